@@ -1,0 +1,142 @@
+"""Isotropic energy-norm damage law at the quadrature points (oracle).
+
+The law (of the benchmark workloads; the paper's own tensile-masking law of
+its Appendix A is not used) is
+
+    sigma = (1 - d) C : eps,      eps = sym(H),
+    kappa_t = sqrt(eps : C : eps / E),
+    d(kappa) = kf/kappa * (kappa - k0)/(kf - k0), clamped to [0, 1],
+
+with C isotropic (Lame constants from E, nu; plane strain in 2D, eps_zz = 0)
+and the history kappa_hist frozen during a load step. A point is loading iff
+kappa_t > kappa_hist (strict); then d = d(kappa_t), else d = d(kappa_hist).
+
+The paper's Newton linearisation (eq. project_stress_linear) and energy
+Hessian (eq. graient_and_hessian) use the consistent tangent:
+
+    dsigma = a C : sym(dH) - c' (s : dH) s,    s = C : eps, a = 1 - d,
+    c' = d'(kappa_t) / (E kappa_t) while loading with 0 < d < 1, else 0.
+
+The exact stored energy for a frozen history (used only to pin the FAIEF
+estimate of eq. incr_energy_func) is w = F(kappa_t) while loading, else
+F(kappa_hist) + (1 - d(kappa_hist)) E (kappa_t^2 - kappa_hist^2) / 2, with
+F(kappa) = int_0^kappa E k (1 - d(k)) dk.
+
+Pinned by: central finite differences of the stress (tangent) and of the
+energy (stress), the small-strain elastic limit, uniaxial-stress compliance
+(``tests/test_oracle_material.py``).
+"""
+import numpy as np
+
+
+def lame(E, nu):
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+def damage_of_kappa(kappa, k0, kf):
+    """d(kappa) clamped to [0, 1]; kappa must be > 0 where k0 > 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d = kf / kappa * (kappa - k0) / (kf - k0)
+    return np.clip(np.nan_to_num(d, nan=0.0), 0.0, 1.0)
+
+
+class MaterialField:
+    """Per-quadrature-point material parameters from a phase map.
+
+    ``phase`` has the grid shape, ``materials[p]`` is a dict with keys kind
+    ('elastic' | 'damage'), E, nu, kappa0, kappaf. Arrays have shape (*grid, nq).
+    """
+
+    def __init__(self, phase, materials, nq):
+        phase = np.asarray(phase)
+        self.grid = phase.shape
+        self.nq = nq
+        self.dim = phase.ndim
+
+        def per_qp(key, conv=float):
+            table = np.array([conv(m[key]) for m in materials])
+            return np.repeat(table[phase][..., None], nq, axis=-1)
+
+        self.E = per_qp("E")
+        nu = per_qp("nu")
+        self.lam, self.mu = lame(self.E, nu)
+        self.damage = per_qp("kind", conv=lambda k: 1.0 if k == "damage" else 0.0) > 0.5
+        self.k0 = np.where(self.damage, per_qp("kappa0"), 0.0)
+        self.kf = np.where(self.damage, per_qp("kappaf"), 1.0)
+
+    def initial_history(self):
+        """kappa_hist := kappa0 on damage points (no damage yet), 0 elsewhere."""
+        return np.where(self.damage, self.k0, 0.0)
+
+
+def sym(H):
+    return 0.5 * (H + np.swapaxes(H, -1, -2))
+
+
+def _c_contract(mat, eps):
+    """C : eps for the in-plane (2D) or full (3D) strain."""
+    dim = eps.shape[-1]
+    tr = np.trace(eps, axis1=-2, axis2=-1)
+    return mat.lam[..., None, None] * tr[..., None, None] * np.eye(dim) \
+        + 2.0 * mat.mu[..., None, None] * eps
+
+
+def evaluate(mat, H, kappa_hist):
+    """Stress and tangent data at the full-gradient field H (*grid, nq, d, d)."""
+    eps = sym(H)
+    s = _c_contract(mat, eps)
+    ecs = np.sum(eps * s, axis=(-2, -1))
+    kappa_t = np.sqrt(np.maximum(ecs, 0.0) / mat.E)
+    loading = mat.damage & (kappa_t > kappa_hist)
+    kappa_eff = np.where(loading, kappa_t, kappa_hist)
+    d = np.where(mat.damage, damage_of_kappa(np.where(mat.damage, kappa_eff, 1.0),
+                                             mat.k0, mat.kf), 0.0)
+    a = 1.0 - d
+    softening = loading & (d > 0.0) & (d < 1.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dprime = mat.kf * mat.k0 / ((mat.kf - mat.k0) * kappa_t ** 2)
+        cprime = np.where(softening, dprime / (mat.E * kappa_t), 0.0)
+    sigma = a[..., None, None] * s
+    tr = np.trace(eps, axis1=-2, axis2=-1)
+    sigma_zz = a * mat.lam * tr if H.shape[-1] == 2 else None
+    return {"eps": eps, "s": s, "sigma": sigma, "a": a, "cprime": cprime,
+            "kappa_t": kappa_t, "loading": loading, "d": d, "sigma_zz": sigma_zz}
+
+
+def apply_tangent(mat, state, dH):
+    """dsigma = a C : sym(dH) - c' (s : dH) s at every quadrature point."""
+    deps = sym(dH)
+    out = state["a"][..., None, None] * _c_contract(mat, deps)
+    sde = np.sum(state["s"] * deps, axis=(-2, -1))
+    out -= (state["cprime"] * sde)[..., None, None] * state["s"]
+    return out
+
+
+def _F(mat, kappa):
+    """int_0^kappa E k (1 - d(k)) dk for the damage law (elastic: E kappa^2/2)."""
+    E, k0, kf = mat.E, mat.k0, mat.kf
+    el = 0.5 * E * kappa ** 2
+    k = np.minimum(kappa, kf)
+    soft = 0.5 * E * k0 ** 2 + E * (0.5 * (k ** 2 - k0 ** 2)
+                                    - kf / (kf - k0) * 0.5 * (k - k0) ** 2)
+    dmg = np.where(kappa <= k0, el, soft)
+    return np.where(mat.damage, dmg, el)
+
+
+def energy(mat, H, kappa_hist):
+    """Exact stored energy W = sum over points of w (frozen history)."""
+    st = evaluate(mat, H, kappa_hist)
+    kt = st["kappa_t"]
+    a_h = 1.0 - np.where(mat.damage,
+                         damage_of_kappa(np.where(mat.damage, kappa_hist, 1.0),
+                                         mat.k0, mat.kf), 0.0)
+    unload = _F(mat, kappa_hist) + 0.5 * a_h * mat.E * (kt ** 2 - kappa_hist ** 2)
+    w = np.where(mat.damage & ~(kt > kappa_hist), unload, _F(mat, kt))
+    return float(np.sum(w))
+
+
+def committed_history(mat, state, kappa_hist):
+    """kappa_hist <- max(kappa_hist, kappa_t) on damage points."""
+    return np.where(mat.damage, np.maximum(kappa_hist, state["kappa_t"]), kappa_hist)

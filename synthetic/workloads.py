@@ -1,0 +1,80 @@
+"""Named synthetic workloads: grid, element, microstructure, materials, loads.
+
+Materials: a damaging matrix (E=1, nu=0.3, isotropic damage driven by the
+energy-norm equivalent strain, linear softening between kappa0=1e-3 and
+kappaf=5e-3) with stiff linear-elastic inclusions (E=10, nu=0.3). Loads are
+strain controlled: equal increments of the macroscopic strain component
+``E_xx``, every other component held at zero.
+"""
+from dataclasses import dataclass, field
+import numpy as np
+
+from .microstructure import inclusion_microstructure
+
+# material records: plain dicts so both sides can read them without sharing code
+MATRIX_DAMAGE = {"kind": "damage", "E": 1.0, "nu": 0.3, "kappa0": 1e-3, "kappaf": 5e-3}
+INCLUSION_ELASTIC = {"kind": "elastic", "E": 10.0, "nu": 0.3, "kappa0": 0.0, "kappaf": 0.0}
+
+
+def uniaxial_load_path(dim, total, steps):
+    """``steps`` equal increments of ``E_xx`` summing to ``total``.
+
+    Returns an array ``(steps, 3, 3)`` of macroscopic strain increments (the
+    3x3 form is used for 2D plane strain as well; only the in-plane block is
+    read there).
+    """
+    inc = np.zeros((steps, 3, 3))
+    inc[:, 0, 0] = total / steps
+    return inc
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    shape: tuple          # (ny, nx) or (nz, ny, nx)
+    element: str          # "p1pair" (2D, two linear triangles per pixel) or "q1" (3D)
+    phase: np.ndarray
+    materials: list       # indexed by phase id
+    load_path: np.ndarray  # (steps, 3, 3)
+    info: dict = field(default_factory=dict)
+
+    @property
+    def nvox(self):
+        return int(np.prod(self.shape))
+
+    @property
+    def nq(self):
+        return 2 if self.element == "p1pair" else 8
+
+
+def workload(name, steps=None):
+    """Build one of the named workloads.
+
+    ``c0_2d32``   2D plane strain 32x32, circles r 3..5 px, vf 0.3, seed 0,
+                  20 steps of E_xx to 0.5%.
+    ``c1_3d64``   3D 64^3, spheres r 4..8 vox, vf 0.25, seed 1,
+                  30 steps of E_xx to 0.6%.
+    ``c1_3dN``    (N in 8..128) the same recipe on an N^3 grid with radii
+                  scaled by N/64 (small parity and large bandwidth cases),
+                  seed 3 for N=128, else seed 1.
+    ``steps`` truncates the load path (the increment size is kept).
+    """
+    if name == "c0_2d32":
+        shape, (rmin, rmax), vf, seed = (32, 32), (3.0, 5.0), 0.3, 0
+        total, nsteps, element = 5e-3, 20, "p1pair"
+    elif name.startswith("c1_3d"):
+        n = int(name[len("c1_3d"):])
+        scale = n / 64.0
+        shape, (rmin, rmax), vf = (n, n, n), (4.0 * scale, 8.0 * scale), 0.25
+        seed = 3 if n == 128 else 1
+        total, nsteps, element = 6e-3, 30, "q1"
+    else:
+        raise KeyError(name)
+    phase, info = inclusion_microstructure(shape, rmin, rmax, vf, seed)
+    path = uniaxial_load_path(len(shape), total, nsteps)
+    if steps is not None:
+        path = path[:steps]
+    return Workload(name=name, dim=len(shape), shape=shape, element=element,
+                    phase=phase, materials=[dict(MATRIX_DAMAGE), dict(INCLUSION_ELASTIC)],
+                    load_path=path, info=info)

@@ -1,0 +1,240 @@
+"""Pins of the oracle's cell solver (Algorithm 2 around Algorithm 1 with the
+projector of eq. proj_operator and the FAIEF ratio of eq. rho_bar).
+
+* Homogeneous elastic cell: the fluctuation stays zero, the step converges
+  without Newton iterations, Sigma = C : E.
+* Homogeneous damage cell: Sigma = (1 - d(kappa(E))) C : E on the linear
+  softening line.
+* Laminates normal to x (grid-aligned interfaces, so the FE solution is exact):
+  the classical harmonic/arithmetic means.
+* Heterogeneous elasticity: the dense FE solution of
+  min 1/2 <D u + E, C (D u + E)> (the projection scheme solves the same FE
+  problem, Sec. 1 and 2.1).
+* FAIEF: rho_bar = 1 to rounding on linear problems; third-order error against
+  the exact stored energy for damage (eq. energy_estim, eq. incr_energy_func).
+* The projected Hessian is the derivative of the projected residual.
+* Invariants of a damage trajectory: mean strain = E, monotone history,
+  0 <= d <= 1, invariance of Sigma under periodic shifts of the cell.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fe, material
+from oracle.solver import CellSolver, inner, INTERIOR
+from synthetic import laminate_microstructure, MATRIX_DAMAGE, INCLUSION_ELASTIC
+from tests.test_oracle_fe import _dense_gradient_matrix
+
+TIGHT = {"eta_eq": 1e-13, "eta_nr": 1e-15, "eta_cg": 1e-13, "j_cg_max": 5000}
+EL1 = {"kind": "elastic", "E": 1.0, "nu": 0.3, "kappa0": 0.0, "kappaf": 0.0}
+EL2 = {"kind": "elastic", "E": 7.0, "nu": 0.2, "kappa0": 0.0, "kappaf": 0.0}
+
+
+def _lame(m):
+    E, nu = m["E"], m["nu"]
+    return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+
+
+def _C_E(m, Emac):
+    lam, mu = _lame(m)
+    return lam * np.trace(Emac) * np.eye(3) + 2 * mu * Emac
+
+
+@pytest.mark.parametrize("element,grid", [("q1", (3, 4, 5)), ("p1pair", (6, 5))])
+def test_homogeneous_elastic(element, grid):
+    phase = np.zeros(grid, dtype=np.uint8)
+    s = CellSolver(phase, [EL2], element)
+    dE = np.array([[1e-3, 2e-4, 0], [2e-4, -3e-4, 1e-4], [0, 1e-4, 5e-4]])
+    if len(grid) == 2:
+        dE[2, :] = dE[:, 2] = 0.0
+    r = s.apply_load_step(dE)
+    assert r < 1e-14
+    rep = s.solve_increment(TIGHT)
+    assert rep["converged"] and rep["newton_iters"] == 0
+    np.testing.assert_allclose(s.homogenized_stress(), _C_E(EL2, dE), rtol=1e-13, atol=1e-18)
+
+
+def test_homogeneous_damage_on_softening_line():
+    phase = np.zeros((4, 4), dtype=np.uint8)
+    s = CellSolver(phase, [MATRIX_DAMAGE], "p1pair")
+    e = 2.5e-3
+    dE = np.zeros((3, 3))
+    dE[0, 0] = e
+    s.apply_load_step(dE)
+    rep = s.solve_increment(TIGHT)
+    assert rep["converged"]
+    lam, mu = _lame(MATRIX_DAMAGE)
+    kap = math.sqrt((lam + 2 * mu) * e * e / MATRIX_DAMAGE["E"])
+    k0, kf = MATRIX_DAMAGE["kappa0"], MATRIX_DAMAGE["kappaf"]
+    # equivalent stress on the straight softening line through (k0, E k0), (kf, 0)
+    seq = MATRIX_DAMAGE["E"] * k0 * (kf - kap) / (kf - k0)
+    one_minus_d = seq / (MATRIX_DAMAGE["E"] * kap)
+    Sig = s.homogenized_stress()
+    np.testing.assert_allclose(Sig[0, 0], one_minus_d * (lam + 2 * mu) * e, rtol=1e-12)
+    np.testing.assert_allclose(Sig[2, 2], one_minus_d * lam * e, rtol=1e-12)
+    np.testing.assert_allclose(s.damage(), 1.0 - one_minus_d, rtol=1e-12)
+
+
+def _laminate_means(mats, frac):
+    lam = np.array([_lame(m)[0] for m in mats])
+    mu = np.array([_lame(m)[1] for m in mats])
+    M = lam + 2 * mu
+    avg = lambda v: float(np.sum(frac * v))
+    Cxxxx = 1.0 / avg(1.0 / M)
+    Cyyxx = avg(lam / M) / avg(1.0 / M)
+    mu_xy = 1.0 / avg(1.0 / mu)
+    return Cxxxx, Cyyxx, mu_xy
+
+
+@pytest.mark.parametrize("element,grid", [("q1", (3, 2, 8)), ("p1pair", (3, 8))])
+def test_laminate_closed_form(element, grid):
+    layers = np.array([0, 0, 1, 1, 1, 0, 1, 0], dtype=np.uint8)
+    phase = laminate_microstructure(grid, layers)
+    mats = [EL1, EL2]
+    frac = np.array([np.mean(layers == 0), np.mean(layers == 1)])
+    Cxxxx, Cyyxx, mu_xy = _laminate_means(mats, frac)
+    for comp in ("xx", "xy"):
+        s = CellSolver(phase, mats, element)
+        dE = np.zeros((3, 3))
+        if comp == "xx":
+            dE[0, 0] = 1e-3
+        else:
+            dE[0, 1] = dE[1, 0] = 1e-3
+        s.apply_load_step(dE)
+        rep = s.solve_increment(TIGHT)
+        assert rep["converged"]
+        Sig = s.homogenized_stress()
+        if comp == "xx":
+            np.testing.assert_allclose(Sig[0, 0], Cxxxx * 1e-3, rtol=1e-11)
+            np.testing.assert_allclose(Sig[1, 1], Cyyxx * 1e-3, rtol=1e-11)
+        else:
+            np.testing.assert_allclose(Sig[0, 1], 2 * mu_xy * 1e-3, rtol=1e-11)
+
+
+def _dense_fe_solution(phase, mats, element, dE):
+    grid = phase.shape
+    dim = fe.element_dim(element)
+    nq = fe.shape_gradients(element).shape[0]
+    D = _dense_gradient_matrix(grid, element)
+    n_pts = int(np.prod(grid)) * nq
+    # per-point elasticity acting on the full gradient (minor symmetries)
+    C = np.zeros((n_pts * dim * dim, n_pts * dim * dim))
+    flat_phase = np.repeat(phase.reshape(-1), nq)
+    for p in range(n_pts):
+        lam, mu = _lame(mats[flat_phase[p]])
+        for i in range(dim):
+            for j in range(dim):
+                for k in range(dim):
+                    for l in range(dim):
+                        v = lam * (i == j) * (k == l) + mu * ((i == k) * (j == l) + (i == l) * (j == k))
+                        C[p * dim * dim + i * dim + j, p * dim * dim + k * dim + l] = v
+    Ef = np.tile(dE[:dim, :dim].reshape(-1), n_pts)
+    K = D.T @ C @ D
+    f = -D.T @ C @ Ef
+    u, *_ = np.linalg.lstsq(K, f, rcond=None)
+    return (D @ u + Ef).reshape(grid + (nq, dim, dim))
+
+
+@pytest.mark.parametrize("element,grid", [("q1", (3, 2, 3)), ("p1pair", (5, 6))])
+def test_heterogeneous_elastic_matches_dense_fe(element, grid):
+    rng = np.random.default_rng(7)
+    phase = (rng.random(grid) < 0.4).astype(np.uint8)
+    mats = [EL1, EL2]
+    dE = np.zeros((3, 3))
+    dE[0, 0], dE[0, 1], dE[1, 0], dE[1, 1] = 1e-3, 3e-4, 3e-4, -2e-4
+    s = CellSolver(phase, mats, element)
+    s.apply_load_step(dE)
+    rep = s.solve_increment(TIGHT)
+    assert rep["converged"]
+    H_ref = _dense_fe_solution(phase, mats, element, dE)
+    np.testing.assert_allclose(s.H, H_ref, rtol=0, atol=1e-12 * np.abs(H_ref).max())
+    # FAIEF is exact on a quadratic energy: every accepted step has rho = 1
+    assert all(abs(r - 1.0) < 1e-9 for r in rep["rho"])
+
+
+def test_faief_third_order_for_damage():
+    rng = np.random.default_rng(8)
+    grid = (4, 4)
+    phase = np.zeros(grid, dtype=np.uint8)
+    mf = material.MaterialField(phase, [MATRIX_DAMAGE], 2)
+    H = 2.5e-3 * np.ones(grid + (2, 2, 2)) * np.array([[1.0, 0.2], [0.1, -0.3]])
+    kh = mf.initial_history()
+    P = rng.normal(size=H.shape) * 2e-4
+    errs = []
+    for t in (1.0, 0.5, 0.25):
+        p = t * P
+        st0 = material.evaluate(mf, H, kh)
+        st1 = material.evaluate(mf, H + p, kh)
+        dW_bar = 0.5 * (inner(st0["sigma"], p) + inner(st1["sigma"], p))
+        dW = material.energy(mf, H + p, kh) - material.energy(mf, H, kh)
+        errs.append(abs(dW_bar - dW))
+    # halving the step divides the error by ~8
+    assert errs[0] / errs[1] > 6.0 and errs[1] / errs[2] > 6.0
+
+
+def test_projected_hessian_is_derivative_of_projected_residual():
+    rng = np.random.default_rng(9)
+    grid = (6, 5)
+    phase = (rng.random(grid) < 0.3).astype(np.uint8)
+    s = CellSolver(phase, [MATRIX_DAMAGE, INCLUSION_ELASTIC], "p1pair")
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 2e-3
+    s.apply_load_step(dE)
+    u = rng.normal(size=(2,) + grid) * 1e-4
+    s.H = s.H + fe.gradient(u, "p1pair")
+    s._set_state(s._evaluate(s.H))
+    v = rng.normal(size=(2,) + grid) * 1e-4
+    X = fe.gradient(v, "p1pair")
+    h = 1e-4
+    gp = s.G(material.evaluate(s.mat, s.H + h * X, s.kappa_hist)["sigma"])
+    gm = s.G(material.evaluate(s.mat, s.H - h * X, s.kappa_hist)["sigma"])
+    fd = (gp - gm) / (2 * h)
+    an = s.apply_hessian(X)
+    assert np.max(np.abs(fd - an)) <= 1e-5 * np.max(np.abs(an))
+    # symmetric on compatible fields
+    Y = fe.gradient(rng.normal(size=(2,) + grid), "p1pair")
+    assert abs(inner(Y, s.apply_hessian(X)) - inner(X, s.apply_hessian(Y))) < 1e-10 * abs(inner(Y, s.apply_hessian(X)))
+
+
+def test_large_radius_gives_newton_cg():
+    # convex problem, inactive trust region: every Steihaug exit is interior
+    # and the first Newton step already solves the linear problem
+    rng = np.random.default_rng(11)
+    phase = (rng.random((4, 3, 4)) < 0.4).astype(np.uint8)
+    s = CellSolver(phase, [EL1, EL2], "q1", R0=1e6, Rmax=1e7)
+    dE = np.zeros((3, 3))
+    dE[1, 1] = 1e-3
+    s.apply_load_step(dE)
+    rep = s.solve_increment(TIGHT)
+    assert rep["converged"] and rep["newton_iters"] == 1
+    assert rep["flags"] == [INTERIOR]
+
+
+def _damage_run(phase, steps, element="p1pair"):
+    s = CellSolver(phase, [MATRIX_DAMAGE, INCLUSION_ELASTIC], element)
+    hist = []
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 3e-4
+    for _ in range(steps):
+        s.apply_load_step(dE)
+        s.solve_increment({"i_nr_max": 30, "j_cg_max": 400})
+        hist.append((s.kappa_hist.copy(), s.homogenized_stress(), s.damage()))
+    return s, hist
+
+
+def test_damage_trajectory_invariants():
+    rng = np.random.default_rng(12)
+    phase = (rng.random((8, 8)) < 0.25).astype(np.uint8)
+    s, hist = _damage_run(phase, 3)
+    for a, b in zip(hist[:-1], hist[1:]):
+        assert np.all(b[0] >= a[0])
+    for _, _, d in hist:
+        assert np.all(d >= 0.0) and np.all(d <= 1.0)
+    # mean of the full gradient is the macroscopic strain
+    np.testing.assert_allclose(s.H.mean(axis=(0, 1, 2)), s.E[:2, :2], atol=1e-15)
+    # a periodic shift of the microstructure shifts the fields, not Sigma
+    s2, hist2 = _damage_run(np.roll(phase, (3, 5), axis=(0, 1)), 3)
+    assert hist[-1][2].max() > 0.5          # damage has localised somewhere
+    for (_, S1, _), (_, S2, _) in zip(hist, hist2):
+        np.testing.assert_allclose(S2, S1, rtol=1e-7, atol=1e-9 * np.abs(S1).max())
