@@ -1,0 +1,165 @@
+"""Benchmark: projected-Hessian throughput and time per load step on one GPU.
+
+Workload: the 3D periodic cell of 64^3 voxels (trilinear hexahedra, 8 Gauss
+points per voxel) with random non-overlapping spherical inclusions (radius 4-8
+voxels, volume fraction 0.25, E = 10) in a damaging matrix (E = 1, nu = 0.3,
+energy-norm damage with linear softening, kappa0 = 1e-3, kappaf = 5e-3),
+loaded in 30 equal uniaxial macro-strain steps to 0.6%, FP64 trust-region +
+Steihaug-CG solver at tolerance 1e-8. Inputs are synthetic and seeded.
+
+One step = one load increment (apply_load_step + solve_increment), which runs
+every stage of the hot path. `--warmup W` increments run untimed, then `--steps
+K` increments are timed. The headline value is
+    Gvoxel-matvec/s = N_voxels x (projected-Hessian applications) / s / 1e9
+over the timed increments (whole-solver throughput, inputs resident in HBM).
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes per launch over its average duration, timed with HIP events on the
+library's stream during the timed region) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c1_3d64"
+
+
+def algorithmic_bytes(name, shape):
+    """Bytes per launch that each kernel must move at minimum (FP64, 3D Q1)."""
+    nz, ny, nx = shape
+    N = nx * ny * nz
+    spec = 48.0 * (nx // 2 + 1) / nx          # 3 half-spectrum fields, B / voxel
+    per_vox = {
+        # d, u (tangent direction s = C:eps), a and c' at 8 points, phase, K d
+        "stiffness": 24 + 24 + 128 + 1 + 24,
+        # 3 real fields in, 3 half spectra out (and back)
+        "fft_plane_fwd": 24 + spec,
+        "fft_pencil_green": 2 * spec,
+        "fft_plane_inv": spec + 24,
+        # u, kappa_hist, phase in; a, c' and D^T sigma out
+        "residual": 24 + 64 + 1 + 128 + 24,
+        # u, z, kappa_hist, old a/c', phase in; trial a/c', D^T sigma_t out
+        "trial": 24 + 24 + 64 + 128 + 1 + 128 + 24,
+    }
+    if name not in per_vox:
+        return None
+    return per_vox[name] * N
+
+
+def cpu_baseline(w, n_matvec):
+    """Time the oracle's projected Hessian (strain space) on the host."""
+    from oracle import fe, material
+    from oracle.projection import Projector
+    rng = np.random.default_rng(0)
+    P = Projector(w.shape, "q1")
+    mf = material.MaterialField(w.phase, w.materials, 8)
+    E = np.zeros((3, 3))
+    E[0, 0] = 2e-3
+    u = 4e-4 * rng.normal(size=(3,) + w.shape)
+    st = material.evaluate(mf, fe.gradient(u, "q1") + E, mf.initial_history())
+    d = rng.normal(size=(3,) + w.shape)
+    t0 = time.perf_counter()
+    for _ in range(n_matvec):
+        P(material.apply_tangent(mf, st, fe.gradient(d, "q1")))
+    dt = time.perf_counter() - t0
+    return {"value": w.nvox * n_matvec / dt / 1e9, "unit": "Gvoxel-matvec/s",
+            "cores": 1, "kind": "oracle",
+            "sample": "%d projected-Hessian applications of the FP64 strain-space oracle "
+                      "(numpy, one thread) at 64^3 on a damaged state, %.1f s" % (n_matvec, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-matvecs", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver is single-GPU (a batch of cells "
+              "would shard across GPUs with no communication); --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2207_10657_amd import Solver
+    from synthetic import workload
+
+    w = workload(WORKLOAD)
+    W, K = args.warmup, args.steps
+    if W + K > len(w.load_path):
+        K = len(w.load_path) - W
+    s = Solver(w.shape, w.element)
+    s.setup(w.phase, w.materials)
+    for n in range(W):
+        s.apply_load_step(w.load_path[n])
+        s.solve_increment()
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    matvecs = newton = cg = 0
+    converged = 0
+    for n in range(W, W + K):
+        s.apply_load_step(w.load_path[n])
+        rep = s.solve_increment()
+        matvecs += rep["matvecs"]
+        newton += rep["newton_iters"]
+        cg += rep["cg_iters"]
+        converged += int(rep["converged"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = s.kernel_stats()
+    s.set_profiling(False)
+
+    # dominant kernel: largest total time in the timed region
+    kern = max(stats.items(), key=lambda kv: kv[1][1])
+    kname, (kcount, kms) = kern
+    avg_s = kms / max(kcount, 1) / 1e3
+    alg = algorithmic_bytes(kname, w.shape)
+    roof = None
+    if alg is not None and avg_s > 0:
+        achieved = alg / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                "avg_launch_us": avg_s * 1e6, "launches": kcount}
+    value = w.nvox * matvecs / dt / 1e9
+    out = {
+        "metric": "projected-Hessian Gvoxel-matvec/s (% HBM peak); time/load step at 1e-8 resid",
+        "value": value,
+        "unit": "Gvoxel-matvec/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D 64^3 Q1 inclusion cell (vf 0.25, seed 1), damage matrix, "
+                               "uniaxial 30 x 2e-4 load path, FP64 TR+Steihaug tol 1e-8",
+                   "load_steps_timed": [W, W + K - 1], "matvecs": matvecs,
+                   "newton_iters": newton, "cg_iters": cg, "converged_steps": converged},
+        "roofline": roof,
+        "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * hfe.h - C ABI of the MI355X FE-projection homogenization solver.
+ *
+ * The library solves the periodic cell problem of small-strain homogenization
+ * (Sec. 2: strain split into a prescribed macroscopic strain E and a periodic
+ * fluctuation, eq. strain_decomp; equilibrium and compatibility, eq.
+ * equilibrium / eq. compatibility) with the FE-projection scheme of Sec. 2.1
+ * (projector built from the discrete derivative of linear finite elements,
+ * eq. proj_operator) and the trust-region Newton solver of Sec. 2.2 with the
+ * first-order approximate incremental energy (eq. incr_energy_func, eq.
+ * rho_bar; Algorithm 2) around Steihaug's truncated CG with restart
+ * (Algorithm 1, eq. 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid: nx x ny (x nz) unit voxels, periodic. Node and element indices
+ *     are n = x + nx*(y + ny*z) (x fastest). Nodes sit at voxel corners, so
+ *     there are as many nodes as voxels.
+ *   - Elements: HFE_Q1 = trilinear hexahedron, 2x2x2 Gauss points
+ *     (1/2 -+ 1/(2 sqrt 3)), point index q = qx + 2 qy + 4 qz (3D only);
+ *     HFE_P1_PAIR = two linear triangles per pixel, one point each,
+ *     T1 = corners (0,0),(1,0),(0,1), T2 = (1,1),(0,1),(1,0) (2D only,
+ *     plane strain).
+ *   - Tensors crossing the ABI are 3x3 row-major doubles (9 values).
+ *   - Host pointers are owned by the caller and only read or written during
+ *     the call. Device pointers (the workspace, and the device arguments of
+ *     the operator entry points) are borrowed: the caller keeps them alive
+ *     for as long as the context, or the call, uses them.
+ *   - Every call returns an hfe_status; nothing throws across the ABI. A
+ *     negative status is an error and leaves the context as it was (its
+ *     text is available from hfe_last_error). Calls out of the documented
+ *     order return HFE_ESTATE.
+ *   - All device work is enqueued on the stream given at creation; calls
+ *     that return host data synchronise with that stream before returning.
+ */
+#ifndef HFE_H
+#define HFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hfe_ctx hfe_ctx;
+
+typedef enum {
+  HFE_OK = 0,
+  HFE_EINVAL = -1,    /* invalid argument (grid, phase id, material, size) */
+  HFE_ENOMEM = -2,    /* workspace too small */
+  HFE_EDEVICE = -3,   /* a HIP call failed */
+  HFE_ENUMERIC = -4,  /* non-finite values in the state */
+  HFE_ESTATE = -5     /* call out of order */
+} hfe_status;
+
+/* Positive outcome codes of hfe_solve_increment (stored in report.status). */
+enum { HFE_CONVERGED = 0, HFE_NOT_CONVERGED = 1 };
+
+enum { HFE_P1_PAIR = 1, HFE_Q1 = 2 };
+enum { HFE_ELASTIC = 0, HFE_DAMAGE_ENERGY_NORM = 1 };
+enum { HFE_MAX_PHASES = 8 };
+
+/* Fields readable through hfe_get_field (sizes per entry). */
+enum {
+  HFE_FIELD_U = 0,       /* nodal fluctuation displacement, [dim][N]            */
+  HFE_FIELD_GRAD = 1,    /* full gradient H = E + D u at points, [N][nq][dim][dim] */
+  HFE_FIELD_STRESS = 2,  /* stress at points, [N][nq][dim][dim]                  */
+  HFE_FIELD_DAMAGE = 3,  /* committed damage d(kappa_hist), [N][nq]              */
+  HFE_FIELD_KAPPA = 4    /* committed history kappa_hist, [N][nq]                */
+};
+
+/* Exit flags of the truncated CG (Algorithm 1), as logged per Newton step. */
+enum { HFE_CG_INTERIOR = 1, HFE_CG_BOUNDARY = 2, HFE_CG_NEGCURV = 3, HFE_CG_MAXITER = 4 };
+
+typedef struct {
+  int dim;       /* 2 or 3 */
+  int n[3];      /* nx, ny, nz (nz = 1 in 2D); every n even-or-odd as below   */
+  int element;   /* HFE_P1_PAIR (dim 2) or HFE_Q1 (dim 3)                       */
+} hfe_grid;
+/* Supported sizes: nx even; nx/2, ny and nz each in
+ * {1,2,3,4,6,8,12,16,24,32,48,64,96,128}; (nx/2+1)*ny*16 bytes <= 160 KiB
+ * (one spectral plane fits in LDS); nz = 1 exactly when dim = 2. */
+
+typedef struct {
+  int kind;        /* HFE_ELASTIC or HFE_DAMAGE_ENERGY_NORM */
+  double E, nu;    /* Young's modulus > 0, Poisson ratio in (-1, 1/2)          */
+  double kappa0;   /* damage threshold of the equivalent strain (damage only) */
+  double kappaf;   /* equivalent strain at full damage, > kappa0             */
+} hfe_material;
+/* Damage law (per point): kappa_t = sqrt(eps : C : eps / E),
+ * loading iff kappa_t > kappa_hist, d = clamp(kf/k (k - k0)/(kf - k0), 0, 1)
+ * with k = kappa_t when loading else kappa_hist, sigma = (1 - d) C : eps.
+ * Consistent tangent B = (1-d) C - c' (C:eps) (x) (C:eps),
+ * c' = d'(kappa_t)/(E kappa_t) while loading with 0 < d < 1, else 0. */
+
+typedef struct {
+  double eta_eq;   /* equilibrium tolerance on ||G sigma|| / ||sigma||        */
+  double eta_nr;   /* Newton tolerance on ||delta eps|| / ||eps||             */
+  double eta_cg;   /* CG tolerance relative to the initial model gradient    */
+  double eta_up;   /* step accepted iff rho_bar > eta_up                       */
+  double R0;       /* initial trust radius (<= 0: 10 sqrt(N_qp) ||dE_1||_F)   */
+  double Rmax;     /* maximum trust radius (<= 0: 1000 sqrt(N_qp) ||dE_1||_F)  */
+  int i_nr_max;    /* maximum Newton iterations per load step                */
+  int j_cg_max;    /* maximum CG iterations per Newton step                  */
+} hfe_solver_params;
+
+typedef struct {
+  int status;          /* HFE_CONVERGED or HFE_NOT_CONVERGED                       */
+  int newton_iters, rejected, cg_iters, restarts, boundary_exits, negcurv_exits;
+  int matvecs;         /* projected-Hessian applications (CG + restarts)          */
+  double r_eq, r_nr, R, rho_last;
+  double time_ms;      /* wall time of the call                                    */
+} hfe_solve_report;
+
+/* Per-Newton-step record (lockstep logs against the oracle). */
+typedef struct {
+  int flag, cg_iters, restarts, accepted;
+  double dm, dW, rho, R_before;
+} hfe_newton_record;
+
+/* Bytes of device workspace needed for a grid; 0 if the grid is unsupported. */
+size_t hfe_workspace_bytes(const hfe_grid* grid);
+
+/* Create a context on the current HIP device. `workspace` is a device buffer of
+ * at least hfe_workspace_bytes(grid) bytes, 256-byte aligned; `hip_stream` is a
+ * hipStream_t (NULL = default stream). Both are borrowed. On success *out
+ * holds the new context. Sec. 2 (cell problem), Algorithm 2 (initialisation). */
+hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes,
+                      void* hip_stream, hfe_ctx** out);
+hfe_status hfe_destroy(hfe_ctx* ctx);
+
+/* Phase id per voxel (host array of N bytes, x fastest), ids < n_phases <=
+ * HFE_MAX_PHASES. Resets the state (u = 0, E = 0, history = kappa0). */
+hfe_status hfe_set_microstructure(hfe_ctx* ctx, const uint8_t* phase, int n_phases);
+
+/* Material of one phase (call once per phase before the first load step). */
+hfe_status hfe_set_material(hfe_ctx* ctx, int phase, const hfe_material* mat);
+
+/* Algorithm 2, start of a load increment: E <- E + dE (dE a host 3x3,
+ * symmetric; in 2D only the in-plane block is used), keep the fluctuation of
+ * the previous step as initial guess, evaluate sigma and B with the history
+ * frozen, the right-hand side -G sigma and its relative norm. */
+hfe_status hfe_apply_load_step(hfe_ctx* ctx, const double dE[9]);
+
+/* Algorithm 2 (Newton / trust-region loop with Algorithm 1 inside) for the
+ * current increment. Commits the damage history iff it converges. `params`
+ * may be NULL (defaults: eta_eq = eta_nr = 1e-8, eta_cg = 1e-6, eta_up = 0.15,
+ * i_nr_max = 50, j_cg_max = 2000, radii from the first increment). `out`
+ * may be NULL. */
+hfe_status hfe_solve_increment(hfe_ctx* ctx, const hfe_solver_params* params,
+                               hfe_solve_report* out);
+
+/* Mean stress over all quadrature points (3x3; in 2D includes sigma_zz of
+ * plane strain) at the last evaluated state. */
+hfe_status hfe_homogenized_stress(const hfe_ctx* ctx, double out[9]);
+
+/* Copy a field (HFE_FIELD_*) to host memory; n = number of doubles in out. */
+hfe_status hfe_get_field(const hfe_ctx* ctx, int which, double* host_out, size_t n);
+
+/* Per-Newton-step records of the last solve; *count receives the number
+ * written (at most max). */
+hfe_status hfe_get_newton_log(const hfe_ctx* ctx, hfe_newton_record* out, int max, int* count);
+
+/* Replace the nodal fluctuation u (host, [dim][N]) and re-evaluate the state
+ * at the current E without committing (operator tests and restarts). */
+hfe_status hfe_set_displacement(hfe_ctx* ctx, const double* host_u);
+
+/* Projected Hessian in displacement coordinates at the current state
+ * (eq. project_stress_linear): out = L^+ K d with K = D^T B D and
+ * L = D^T D (the FE Green's operator of eq. proj_operator), so that
+ * D out = G : B : (D d). `dev_in`, `dev_out` are device arrays [dim][N]
+ * (distinct). dots (host, may be NULL) receives {d.Kd, sum |D d|^2}. */
+hfe_status hfe_apply_projected_hessian(hfe_ctx* ctx, const double* dev_in,
+                                       double* dev_out, double dots[2]);
+
+/* The two halves of the matvec, for operator tests: out = K d (device
+ * arrays [dim][N]), and out = L^+ f (zero mean; the k = 0 mode removed). */
+hfe_status hfe_apply_stiffness(hfe_ctx* ctx, const double* dev_in, double* dev_out);
+hfe_status hfe_apply_green(hfe_ctx* ctx, const double* dev_in, double* dev_out);
+
+/* 3D real-to-complex FFT of dim fields (device in [dim][N]) to the half
+ * spectrum, device out [dim][nz][ny][nx/2+1] complex (interleaved doubles),
+ * unscaled, exponent sign -1; and its inverse (unscaled, sign +1). The
+ * transforms of eq. conv_to_fourier. */
+hfe_status hfe_fft_forward(hfe_ctx* ctx, const double* dev_in, double* dev_out_spec);
+hfe_status hfe_fft_inverse(hfe_ctx* ctx, const double* dev_in_spec, double* dev_out);
+
+/* Kernel timing: when on, every launch is bracketed with HIP events on the
+ * context's stream. hfe_kernel_stats writes, for up to max kernels, the name
+ * pointer, launch count and total milliseconds since the last reset. */
+hfe_status hfe_set_profiling(hfe_ctx* ctx, int on);
+hfe_status hfe_kernel_stats(hfe_ctx* ctx, const char** names, int* counts, double* total_ms,
+                            int max, int* n_kernels);
+
+/* Text of the last error on this context (never NULL). */
+const char* hfe_last_error(const hfe_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFE_H */

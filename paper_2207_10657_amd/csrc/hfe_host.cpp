@@ -1,0 +1,878 @@
+// Host side of the library: context and workspace management, the C ABI, and
+// the scalar logic of the trust-region Newton solver (Algorithm 2) and of the
+// truncated CG (Algorithm 1). Every vector operation runs in the kernels of
+// k_element.hip, k_fft.hip and k_vec.hip; the host only sees reduced scalars.
+//
+// Displacement coordinates. The paper iterates on compatible strain fields
+// with the projector G = D (D^T D)^+ D^T (Sec. 2.1). Every such field is D u
+// for a nodal field u, so the CG of Algorithm 1 is run on nodal vectors:
+//   model gradient  G sigma          <->  g = D^T sigma (nodal), y = L^+ g
+//   Hessian action  G B (D d)        <->  K d = D^T B D d, then L^+ (K d)
+//   <r, r>                           =    y . g
+//   <d, G B d>                       =    d . K d
+//   <r_{j+1}, r_j>  (restart test)   =    y_j . g_{j+1}
+//   <r, d>                           =    g . d
+//   ||d||^2                          =    sum over points of |D d|^2
+// with L = D^T D the FE Laplacian. <z, d> and ||z||^2 follow from
+// L d_{j+1} = -g_{j+1} + beta L d_j:
+//   <z_{j+1}, d_{j+1}> = -z_{j+1}.g_{j+1} + beta (<z_j, d_j> + alpha ||d_j||^2)
+//   ||z_{j+1}||^2      = ||z_j||^2 + 2 alpha <z_j, d_j> + alpha^2 ||d_j||^2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hfe_internal.h"
+
+using hfe::Grid;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t u, z, d, g, y, Kd, w, g0, y0, gt, tmp;      // nodal [dim][N]
+  size_t a, cp, at, cpt, kh;                          // per point [nq][N]
+  size_t phase;                                       // N bytes
+  size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
+  size_t partials;                                    // rows * 16 doubles
+  size_t scal;                                        // 64 doubles
+  size_t tw;                                          // twiddles
+  size_t stab;                                        // sin^2 tables
+  size_t total;
+  int partial_rows;
+  int n_tw, n_stab;
+};
+
+bool grid_ok(const hfe_grid* gr, std::string* why) {
+  if (!gr) { *why = "grid is NULL"; return false; }
+  const int nx = gr->n[0], ny = gr->n[1], nz = gr->n[2];
+  if (gr->dim == 2) {
+    if (gr->element != HFE_P1_PAIR) { *why = "2D grids use the HFE_P1_PAIR element"; return false; }
+    if (nz != 1) { *why = "2D grids have nz = 1"; return false; }
+  } else if (gr->dim == 3) {
+    if (gr->element != HFE_Q1) { *why = "3D grids use the HFE_Q1 element"; return false; }
+  } else {
+    *why = "dim must be 2 or 3";
+    return false;
+  }
+  if (nx < 2 || ny < 1 || nz < 1 || (nx & 1)) { *why = "nx must be even and >= 2, ny, nz >= 1"; return false; }
+  if (!hfe::fft_length_supported(nx / 2) || !hfe::fft_length_supported(ny) ||
+      !hfe::fft_length_supported(nz)) {
+    *why = "nx/2, ny and nz must each be one of 1,2,3,4,6,8,12,16,24,32,48,64,96,128";
+    return false;
+  }
+  if ((size_t)(nx / 2 + 1) * ny * 16 > 160 * 1024) { *why = "a spectral x-y plane must fit in 160 KiB of LDS"; return false; }
+  return true;
+}
+
+Grid make_grid(const hfe_grid* gr) {
+  Grid g;
+  g.nx = gr->n[0];
+  g.ny = gr->n[1];
+  g.nz = gr->n[2];
+  g.dim = gr->dim;
+  g.element = gr->element;
+  g.nq = gr->element == HFE_Q1 ? 8 : 2;
+  g.na = gr->element == HFE_Q1 ? 8 : 4;
+  g.N = (long long)g.nx * g.ny * g.nz;
+  return g;
+}
+
+Layout make_layout(const Grid& g) {
+  Layout L;
+  size_t off = 0;
+  const size_t nod = (size_t)g.dim * g.N * sizeof(double);
+  const size_t pts = (size_t)g.nq * g.N * sizeof(double);
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  L.u = take(nod); L.z = take(nod); L.d = take(nod); L.g = take(nod); L.y = take(nod);
+  L.Kd = take(nod); L.w = take(nod); L.g0 = take(nod); L.y0 = take(nod); L.gt = take(nod);
+  L.tmp = take(nod);
+  L.a = take(pts); L.cp = take(pts); L.at = take(pts); L.cpt = take(pts); L.kh = take(pts);
+  L.phase = take((size_t)g.N);
+  L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
+  L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
+  L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
+  L.scal = take(64 * sizeof(double));
+  L.n_tw = g.nx / 2 + g.ny + g.nz + (g.nx / 2 + 1);
+  L.tw = take((size_t)L.n_tw * sizeof(double2));
+  L.n_stab = (g.nx / 2 + 1) + g.ny + g.nz;
+  L.stab = take((size_t)L.n_stab * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// e^{-2 pi i k / n} and 4 sin^2(pi k / n), evaluated in long double.
+void twiddles(int n, int count, std::vector<double2>& out) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < count; ++k) {
+    const long double a = 2.0L * pi * (long double)k / (long double)n;
+    out.push_back(make_double2((double)cosl(a), (double)(-sinl(a))));
+  }
+}
+void sin2_table(int n, int count, std::vector<double>& out) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < count; ++k) {
+    const long double s = sinl(pi * (long double)k / (long double)n);
+    out.push_back((double)(4.0L * s * s));
+  }
+}
+
+struct ProfEvent { int kernel; hipEvent_t start, stop; };
+
+}  // namespace
+
+struct hfe_ctx {
+  Grid g;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // device views
+  double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *gt, *tmp;
+  double *a, *cp, *at, *cpt, *kh;
+  uint8_t* phase;
+  double2* spec;
+  double* partials;
+  double* scal;
+  hfe::FftTables tabs;
+  double* hscal = nullptr;  // pinned host mirror of scal
+  // host state
+  hfe::MatTable mat;
+  bool mat_set[hfe::kMaxPhases] = {};
+  int n_phases = 0;
+  bool have_micro = false, have_state = false, history_ready = false;
+  double E[9] = {0};
+  bool R_init = false;
+  double R = 0, Rmax = 0, R0_default = 0, Rmax_default = 0;
+  double r_eq = 0, sig_norm2 = 0, rr0 = 0;
+  double sigma_sum[6] = {0};
+  std::vector<hfe_newton_record> log;
+  std::string err;
+  // profiling
+  bool profiling = false;
+  std::vector<std::string> knames;
+  std::vector<int> kcount;
+  std::vector<double> kms;
+  std::vector<ProfEvent> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+hfe_status fail(hfe_ctx* c, hfe_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, HFE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int kernel_id(hfe_ctx* c, const char* name) {
+  for (size_t i = 0; i < c->knames.size(); ++i)
+    if (c->knames[i] == name) return (int)i;
+  c->knames.push_back(name);
+  c->kcount.push_back(0);
+  c->kms.push_back(0.0);
+  return (int)c->knames.size() - 1;
+}
+
+hipEvent_t take_event(hfe_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket a group of launches with events when profiling is on.
+struct Prof {
+  hfe_ctx* c;
+  int id = -1;
+  hipEvent_t s = nullptr;
+  Prof(hfe_ctx* ctx, const char* name) : c(ctx) {
+    if (!c->profiling) return;
+    id = kernel_id(c, name);
+    s = take_event(c);
+    if (s) hipEventRecord(s, c->stream);
+  }
+  ~Prof() {
+    if (!c->profiling || !s) return;
+    hipEvent_t e = take_event(c);
+    if (!e) return;
+    hipEventRecord(e, c->stream);
+    c->pending.push_back({id, s, e});
+  }
+};
+
+// Collect finished event pairs (call after a stream synchronisation).
+void prof_drain(hfe_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      c->kcount[p.kernel] += 1;
+      c->kms[p.kernel] += ms;
+    }
+    c->pool.push_back(p.start);
+    c->pool.push_back(p.stop);
+  }
+  c->pending.clear();
+}
+
+hfe_status sync_read(hfe_ctx* c, int first, int count) {
+  HIPCHK(c, hipMemcpyAsync(c->hscal + first, c->scal + first, count * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->profiling) prof_drain(c);
+  return HFE_OK;
+}
+
+hfe::ElemArgs elem_args(hfe_ctx* c) {
+  hfe::ElemArgs A;
+  A.g = c->g;
+  A.mat = c->mat;
+  for (int k = 0; k < 9; ++k) A.E.e[k] = c->E[k];
+  A.phase = c->phase;
+  A.khist = c->kh;
+  A.a = c->a;
+  A.cp = c->cp;
+  A.a_out = nullptr;
+  A.cp_out = nullptr;
+  A.u = c->u;
+  A.v = nullptr;
+  A.f = nullptr;
+  A.partials = c->partials;
+  return A;
+}
+
+long long ndof(const hfe_ctx* c) { return (long long)c->g.dim * c->g.N; }
+
+// y = L^+ x
+hfe_status green(hfe_ctx* c, const double* x, double* y) {
+  if (c->g.dim == 2) {
+    Prof p(c, "fft_green2d");
+    HIPCHK(c, hfe::fft_plane_green2d(c->g, c->tabs, x, y, c->spec, c->stream));
+    return HFE_OK;
+  }
+  {
+    Prof p(c, "fft_plane_fwd");
+    HIPCHK(c, hfe::fft_plane_forward(c->g, c->tabs, x, c->spec, c->stream));
+  }
+  {
+    Prof p(c, "fft_pencil_green");
+    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream));
+  }
+  {
+    Prof p(c, "fft_plane_inv");
+    HIPCHK(c, hfe::fft_plane_inverse(c->g, c->tabs, c->spec, y, c->stream));
+  }
+  return HFE_OK;
+}
+
+// out = K v at the current state; dots (d.Kd, |Dd|^2) reduced into scal[off..off+1]
+hfe_status stiffness(hfe_ctx* c, const double* v, double* out, int off) {
+  hfe::ElemArgs A = elem_args(c);
+  A.v = v;
+  A.f = out;
+  int nb = 0;
+  {
+    Prof p(c, "stiffness");
+    HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
+  }
+  HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::HES_NV, c->scal + off, c->stream));
+  return HFE_OK;
+}
+
+// Residual at (u, E): g0 = D^T sigma, tangent scalars, y0 = L^+ g0, r_eq.
+hfe_status evaluate_state(hfe_ctx* c) {
+  hfe::ElemArgs A = elem_args(c);
+  A.a_out = c->a;
+  A.cp_out = c->cp;
+  A.f = c->g0;
+  int nb = 0;
+  {
+    Prof p(c, "residual");
+    HIPCHK(c, hfe::launch_residual(A, c->stream, &nb));
+  }
+  HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::RES_NV, c->scal + 16, c->stream));
+  hfe_status st = green(c, c->g0, c->y0);
+  if (st) return st;
+  HIPCHK(c, hfe::vec_dot(ndof(c), c->y0, c->g0, c->partials, c->stream, &nb));
+  HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 24, c->stream));
+  st = sync_read(c, 16, 9);
+  if (st) return st;
+  const double* h = c->hscal;
+  for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[16 + k];
+  c->sig_norm2 = h[16 + hfe::RES_SS];
+  c->rr0 = h[24];
+  if (!std::isfinite(c->rr0) || !std::isfinite(c->sig_norm2))
+    return fail(c, HFE_ENUMERIC, "non-finite stress or residual");
+  c->r_eq = c->sig_norm2 > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(c->sig_norm2) : 0.0;
+  c->have_state = true;
+  return HFE_OK;
+}
+
+void roots(double zz, double zd, double dd, double R, double* tm, double* tp) {
+  const double b = 2.0 * zd, cc = zz - R * R;
+  const double disc = std::sqrt(std::max(b * b - 4.0 * dd * cc, 0.0));
+  const double qq = -0.5 * (b + std::copysign(disc, b));
+  const double t1 = qq / dd;
+  const double t2 = qq != 0.0 ? cc / qq : -t1;
+  *tm = std::min(t1, t2);
+  *tp = std::max(t1, t2);
+}
+
+struct CgInfo { int iters = 0, restarts = 0, matvecs = 0; };
+
+// Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
+hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, CgInfo* info) {
+  const long long n = ndof(c);
+  const size_t bytes = (size_t)n * sizeof(double);
+  HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gv, c->g0, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->y, c->y0, bytes, hipMemcpyDeviceToDevice, c->stream));
+  const double rr0 = c->rr0;
+  double rr = rr0;
+  *flag = HFE_CG_INTERIOR;
+  if (rr0 == 0.0) return HFE_OK;
+  int nb = 0;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_d(n, 0.0, c->y, c->d, c->gv, c->z, c->partials, c->stream, &nb));
+  }
+  HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 4, c->stream));
+  double zz = 0.0, zd = 0.0;
+  for (int j = 0; j < j_max; ++j) {
+    hfe_status st = stiffness(c, c->d, c->Kd, 0);
+    if (st) return st;
+    info->matvecs += 1;
+    info->iters = j + 1;
+    st = sync_read(c, 0, 6);
+    if (st) return st;
+    const double kap = c->hscal[0], dd = c->hscal[1], rd = c->hscal[4];
+    if (!std::isfinite(kap) || !std::isfinite(dd)) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
+    if (kap <= 0.0) {
+      double tm, tp;
+      roots(zz, zd, dd, R, &tm, &tp);
+      const double mm = tm * rd + 0.5 * tm * tm * kap;
+      const double mp = tp * rd + 0.5 * tp * tp * kap;
+      const double tau = mm < mp ? tm : tp;
+      HIPCHK(c, hfe::vec_axpy(n, tau, c->d, c->z, c->stream));
+      *flag = HFE_CG_NEGCURV;
+      return HFE_OK;
+    }
+    const double alpha = rr / kap;
+    const double zz_new = zz + 2.0 * alpha * zd + alpha * alpha * dd;
+    if (std::sqrt(zz_new) >= R) {
+      double tm, tp;
+      roots(zz, zd, dd, R, &tm, &tp);
+      HIPCHK(c, hfe::vec_axpy(n, tp, c->d, c->z, c->stream));
+      *flag = HFE_CG_BOUNDARY;
+      return HFE_OK;
+    }
+    {
+      Prof p(c, "cg_vec");
+      HIPCHK(c, hfe::cg_step_zg(n, alpha, c->d, c->Kd, c->z, c->gv, c->stream));
+    }
+    st = green(c, c->Kd, c->w);
+    if (st) return st;
+    {
+      Prof p(c, "cg_vec");
+      HIPCHK(c, hfe::cg_step_y(n, alpha, c->w, c->y, c->gv, c->partials, c->stream, &nb));
+    }
+    HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 2, c->stream));
+    st = sync_read(c, 2, 2);
+    if (st) return st;
+    double rr_new = c->hscal[2];
+    const double pw = c->hscal[3];
+    if (std::sqrt(std::max(rr_new, 0.0)) <= eta_cg * std::sqrt(rr0)) {
+      *flag = HFE_CG_INTERIOR;
+      return HFE_OK;
+    }
+    double beta;
+    if (std::fabs(pw) > 0.2 * rr_new) {
+      // restart: true residual at the new iterate, steepest-descent direction
+      st = stiffness(c, c->z, c->tmp, 8);
+      if (st) return st;
+      info->matvecs += 1;
+      info->restarts += 1;
+      HIPCHK(c, hfe::vec_axpy_to(n, c->tmp, 1.0, c->g0, c->gv, c->stream));
+      st = green(c, c->gv, c->y);
+      if (st) return st;
+      HIPCHK(c, hfe::vec_dot(n, c->y, c->gv, c->partials, c->stream, &nb));
+      HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 2, c->stream));
+      st = sync_read(c, 2, 1);
+      if (st) return st;
+      rr_new = c->hscal[2];
+      beta = 0.0;
+    } else {
+      beta = rr_new / rr;
+    }
+    const double zd_old_dir = zd + alpha * dd;  // <z_{j+1}, d_j>
+    {
+      Prof p(c, "cg_vec");
+      HIPCHK(c, hfe::cg_step_d(n, beta, c->y, c->d, c->gv, c->z, c->partials, c->stream, &nb));
+    }
+    HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 4, c->stream));
+    st = sync_read(c, 4, 2);
+    if (st) return st;
+    const double zg = c->hscal[5];
+    zd = -zg + beta * zd_old_dir;
+    zz = zz_new;
+    rr = rr_new;
+  }
+  *flag = HFE_CG_MAXITER;
+  return HFE_OK;
+}
+
+hfe_status commit(hfe_ctx* c) {
+  hfe::ElemArgs A = elem_args(c);
+  A.a_out = c->kh;
+  Prof p(c, "commit");
+  HIPCHK(c, hfe::launch_commit(A, c->stream));
+  return HFE_OK;
+}
+
+hfe_status reset_state(hfe_ctx* c) {
+  const size_t nod = (size_t)ndof(c) * sizeof(double);
+  HIPCHK(c, hipMemsetAsync(c->u, 0, nod, c->stream));
+  for (int k = 0; k < 9; ++k) c->E[k] = 0.0;
+  c->R_init = false;
+  c->have_state = false;
+  c->history_ready = false;
+  c->log.clear();
+  return HFE_OK;
+}
+
+bool materials_ready(const hfe_ctx* c) {
+  for (int p = 0; p < c->n_phases; ++p)
+    if (!c->mat_set[p]) return false;
+  return c->have_micro;
+}
+
+hfe_status ensure_history(hfe_ctx* c) {
+  if (c->history_ready) return HFE_OK;
+  hfe::ElemArgs A = elem_args(c);
+  A.a_out = c->kh;
+  HIPCHK(c, hfe::launch_init_history(A, c->stream));
+  c->history_ready = true;
+  return HFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hfe_workspace_bytes(const hfe_grid* grid) {
+  std::string why;
+  if (!grid_ok(grid, &why)) return 0;
+  return make_layout(make_grid(grid)).total;
+}
+
+hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, void* hip_stream,
+                      hfe_ctx** out) {
+  if (!out) return HFE_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!grid_ok(grid, &why)) return HFE_EINVAL;
+  const Grid g = make_grid(grid);
+  const Layout L = make_layout(g);
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HFE_EINVAL;
+  if (ws_bytes < L.total) return HFE_ENOMEM;
+  hfe_ctx* c = new hfe_ctx();
+  c->g = g;
+  c->L = L;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  auto D = [&](size_t off) { return (double*)(c->ws + off); };
+  c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
+  c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);
+  c->tmp = D(L.tmp);
+  c->a = D(L.a); c->cp = D(L.cp); c->at = D(L.at); c->cpt = D(L.cpt); c->kh = D(L.kh);
+  c->phase = (uint8_t*)(c->ws + L.phase);
+  c->spec = (double2*)(c->ws + L.spec);
+  c->partials = D(L.partials);
+  c->scal = D(L.scal);
+  std::memset(&c->mat, 0, sizeof(c->mat));
+  // FFT tables
+  std::vector<double2> tw;
+  const int M = g.nx / 2;
+  c->tabs.off_x = 0;
+  twiddles(M, M, tw);
+  c->tabs.off_y = (int)tw.size();
+  twiddles(g.ny, g.ny, tw);
+  c->tabs.off_z = (int)tw.size();
+  twiddles(g.nz, g.nz, tw);
+  c->tabs.off_post = (int)tw.size();
+  twiddles(g.nx, M + 1, tw);
+  std::vector<double> st;
+  sin2_table(g.nx, M + 1, st);
+  sin2_table(g.ny, g.ny, st);
+  sin2_table(g.nz, g.nz, st);
+  double2* dtw = (double2*)(c->ws + L.tw);
+  double* dst = D(L.stab);
+  c->tabs.tw = dtw;
+  c->tabs.sx = dst;
+  c->tabs.sy = dst + (M + 1);
+  c->tabs.sz = dst + (M + 1) + g.ny;
+  hipError_t e = hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    if (c->hscal) hipHostFree(c->hscal);
+    delete c;
+    return HFE_EDEVICE;
+  }
+  *out = c;
+  return HFE_OK;
+}
+
+hfe_status hfe_destroy(hfe_ctx* c) {
+  if (!c) return HFE_EINVAL;
+  hipStreamSynchronize(c->stream);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->hscal) hipHostFree(c->hscal);
+  delete c;
+  return HFE_OK;
+}
+
+hfe_status hfe_set_microstructure(hfe_ctx* c, const uint8_t* phase, int n_phases) {
+  if (!c) return HFE_EINVAL;
+  if (!phase) return fail(c, HFE_EINVAL, "phase is NULL");
+  if (n_phases < 1 || n_phases > hfe::kMaxPhases) return fail(c, HFE_EINVAL, "n_phases out of range");
+  for (long long i = 0; i < c->g.N; ++i)
+    if (phase[i] >= n_phases) return fail(c, HFE_EINVAL, "phase id >= n_phases");
+  HIPCHK(c, hipMemcpyAsync(c->phase, phase, (size_t)c->g.N, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_phases = n_phases;
+  for (int p = 0; p < hfe::kMaxPhases; ++p) c->mat_set[p] = false;
+  c->have_micro = true;
+  return reset_state(c);
+}
+
+hfe_status hfe_set_material(hfe_ctx* c, int phase, const hfe_material* m) {
+  if (!c) return HFE_EINVAL;
+  if (!c->have_micro) return fail(c, HFE_ESTATE, "set the microstructure first");
+  if (c->have_state) return fail(c, HFE_ESTATE, "materials are fixed once loading started");
+  if (!m || phase < 0 || phase >= c->n_phases) return fail(c, HFE_EINVAL, "bad phase or material");
+  if (!(m->E > 0.0) || !(m->nu > -1.0 && m->nu < 0.5)) return fail(c, HFE_EINVAL, "E > 0 and -1 < nu < 1/2 required");
+  if (m->kind != HFE_ELASTIC && m->kind != HFE_DAMAGE_ENERGY_NORM) return fail(c, HFE_EINVAL, "unknown material kind");
+  if (m->kind == HFE_DAMAGE_ENERGY_NORM && !(m->kappa0 > 0.0 && m->kappaf > m->kappa0))
+    return fail(c, HFE_EINVAL, "damage needs 0 < kappa0 < kappaf");
+  const double E = m->E, nu = m->nu;
+  c->mat.lam[phase] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  c->mat.mu[phase] = E / (2.0 * (1.0 + nu));
+  c->mat.E[phase] = E;
+  c->mat.damage[phase] = m->kind == HFE_DAMAGE_ENERGY_NORM;
+  c->mat.k0[phase] = c->mat.damage[phase] ? m->kappa0 : 0.0;
+  c->mat.kf[phase] = c->mat.damage[phase] ? m->kappaf : 1.0;
+  c->mat_set[phase] = true;
+  c->history_ready = false;  // kappa0 may have changed: re-initialise before the first step
+  return HFE_OK;
+}
+
+hfe_status hfe_apply_load_step(hfe_ctx* c, const double dE[9]) {
+  if (!c) return HFE_EINVAL;
+  if (!dE) return fail(c, HFE_EINVAL, "dE is NULL");
+  if (!materials_ready(c)) return fail(c, HFE_ESTATE, "microstructure and every material must be set");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(dE[k])) return fail(c, HFE_EINVAL, "non-finite dE");
+  const int D = c->g.dim;
+  double inc[9] = {0};
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) inc[3 * i + j] = dE[3 * i + j];
+  hfe_status st = ensure_history(c);
+  if (st) return st;
+  const double Eold[9] = {c->E[0], c->E[1], c->E[2], c->E[3], c->E[4], c->E[5], c->E[6], c->E[7], c->E[8]};
+  for (int k = 0; k < 9; ++k) c->E[k] += inc[k];
+  if (!c->R_init) {
+    double nrm = 0.0;
+    for (int k = 0; k < 9; ++k) nrm += inc[k] * inc[k];
+    const double s = std::sqrt((double)c->g.N * c->g.nq) * std::sqrt(nrm);
+    c->R0_default = 10.0 * s;
+    c->Rmax_default = 1000.0 * s;
+  }
+  st = evaluate_state(c);
+  if (st) {
+    for (int k = 0; k < 9; ++k) c->E[k] = Eold[k];
+    return st;
+  }
+  c->log.clear();
+  return HFE_OK;
+}
+
+hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_solve_report* out) {
+  if (!c) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "apply a load step first");
+  const auto t0 = std::chrono::steady_clock::now();
+  hfe_solver_params p;
+  p.eta_eq = 1e-8; p.eta_nr = 1e-8; p.eta_cg = 1e-6; p.eta_up = 0.15;
+  p.R0 = 0.0; p.Rmax = 0.0; p.i_nr_max = 50; p.j_cg_max = 2000;
+  if (prm) p = *prm;
+  if (!c->R_init) {
+    c->R = p.R0 > 0.0 ? p.R0 : c->R0_default;
+    c->Rmax = p.Rmax > 0.0 ? p.Rmax : c->Rmax_default;
+    c->R_init = true;
+  } else if (p.Rmax > 0.0) {
+    c->Rmax = p.Rmax;
+  }
+  hfe_solve_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  rep.status = HFE_NOT_CONVERGED;
+  c->log.clear();
+  const long long n = ndof(c);
+  hfe_status st = HFE_OK;
+  bool converged = false;
+  if (c->r_eq <= p.eta_eq) {
+    converged = true;
+  } else {
+    for (int it = 0; it < p.i_nr_max && !converged; ++it) {
+      rep.newton_iters = it + 1;
+      int flag = 0;
+      CgInfo info;
+      st = steihaug(c, c->R, p.eta_cg, p.j_cg_max, &flag, &info);
+      if (st) return st;
+      rep.cg_iters += info.iters;
+      rep.restarts += info.restarts;
+      rep.matvecs += info.matvecs;
+      if (flag == HFE_CG_BOUNDARY) rep.boundary_exits++;
+      if (flag == HFE_CG_NEGCURV) rep.negcurv_exits++;
+      // trial evaluation at u + z (Algorithm 2: model change, trial stress, FAIEF)
+      hfe::ElemArgs A = elem_args(c);
+      A.v = c->z;
+      A.a_out = c->at;
+      A.cp_out = c->cpt;
+      A.f = c->gt;
+      int nb = 0;
+      {
+        Prof pr(c, "trial");
+        HIPCHK(c, hfe::launch_trial(A, c->stream, &nb));
+      }
+      HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::TRI_NV, c->scal + 32, c->stream));
+      st = sync_read(c, 32, hfe::TRI_NV);
+      if (st) return st;
+      const double* h = c->hscal + 32;
+      const double sp = h[hfe::TRI_SP], pbp = h[hfe::TRI_PBP], stp = h[hfe::TRI_STP];
+      const double dm = sp + 0.5 * pbp;
+      const double dW = 0.5 * (sp + stp);
+      double rho = -INFINITY;
+      if (dm < 0.0 && std::isfinite(dm) && std::isfinite(dW)) rho = dW / dm;
+      if (!std::isfinite(rho)) rho = -INFINITY;
+      hfe_newton_record rec;
+      rec.flag = flag;
+      rec.cg_iters = info.iters;
+      rec.restarts = info.restarts;
+      rec.dm = dm;
+      rec.dW = dW;
+      rec.rho = rho;
+      rec.R_before = c->R;
+      rec.accepted = 0;
+      rep.rho_last = rho;
+      const bool on_boundary = flag == HFE_CG_BOUNDARY || flag == HFE_CG_NEGCURV;
+      if (rho < 0.25) c->R = 0.25 * c->R;
+      else if (rho > 0.75 && on_boundary) c->R = std::min(2.0 * c->R, c->Rmax);
+      if (rho > p.eta_up) {
+        rec.accepted = 1;
+        HIPCHK(c, hfe::vec_axpy(n, 1.0, c->z, c->u, c->stream));
+        std::swap(c->a, c->at);
+        std::swap(c->cp, c->cpt);
+        std::swap(c->g0, c->gt);
+        const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH], ss = h[hfe::TRI_SS];
+        for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[hfe::TRI_S0 + k];
+        c->sig_norm2 = ss;
+        st = green(c, c->g0, c->y0);
+        if (st) return st;
+        HIPCHK(c, hfe::vec_dot(n, c->y0, c->g0, c->partials, c->stream, &nb));
+        HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 24, c->stream));
+        st = sync_read(c, 24, 1);
+        if (st) return st;
+        c->rr0 = c->hscal[24];
+        c->r_eq = ss > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(ss) : 0.0;
+        const double r_nr = hh > 0.0 ? std::sqrt(pp) / std::sqrt(hh) : 0.0;
+        rep.r_nr = r_nr;
+        if (!on_boundary && (c->r_eq <= p.eta_eq || r_nr <= p.eta_nr)) converged = true;
+      } else {
+        rep.rejected++;
+      }
+      c->log.push_back(rec);
+    }
+  }
+  if (converged) {
+    st = commit(c);
+    if (st) return st;
+    rep.status = HFE_CONVERGED;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->profiling) prof_drain(c);
+  rep.r_eq = c->r_eq;
+  rep.R = c->R;
+  rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = rep;
+  return HFE_OK;
+}
+
+hfe_status hfe_homogenized_stress(const hfe_ctx* cc, double out[9]) {
+  hfe_ctx* c = const_cast<hfe_ctx*>(cc);
+  if (!c || !out) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+  const double inv = 1.0 / ((double)c->g.N * c->g.nq);
+  const double* s = c->sigma_sum;
+  // (xx, yy, zz, xy, xz, yz) -> 3x3
+  out[0] = s[0] * inv; out[4] = s[1] * inv; out[8] = s[2] * inv;
+  out[1] = out[3] = s[3] * inv;
+  out[2] = out[6] = s[4] * inv;
+  out[5] = out[7] = s[5] * inv;
+  return HFE_OK;
+}
+
+hfe_status hfe_get_field(const hfe_ctx* cc, int which, double* host_out, size_t n) {
+  hfe_ctx* c = const_cast<hfe_ctx*>(cc);
+  if (!c || !host_out) return HFE_EINVAL;
+  if (!c->have_micro) return fail(c, HFE_ESTATE, "no microstructure");
+  const Grid& g = c->g;
+  size_t need = 0;
+  switch (which) {
+    case HFE_FIELD_U: need = (size_t)g.dim * g.N; break;
+    case HFE_FIELD_GRAD: case HFE_FIELD_STRESS: need = (size_t)g.N * g.nq * g.dim * g.dim; break;
+    case HFE_FIELD_DAMAGE: case HFE_FIELD_KAPPA: need = (size_t)g.N * g.nq; break;
+    default: return fail(c, HFE_EINVAL, "unknown field");
+  }
+  if (n < need) return fail(c, HFE_EINVAL, "output buffer too small");
+  if (which == HFE_FIELD_U) {
+    HIPCHK(c, hipMemcpyAsync(host_out, c->u, need * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HFE_OK;
+  }
+  hfe_status st = ensure_history(c);
+  if (st) return st;
+  double* tmp = nullptr;
+  HIPCHK(c, hipMalloc((void**)&tmp, need * sizeof(double)));
+  hfe::ElemArgs A = elem_args(c);
+  hipError_t e = hfe::launch_fields(A, which == HFE_FIELD_GRAD ? tmp : nullptr,
+                                    which == HFE_FIELD_STRESS ? tmp : nullptr,
+                                    which == HFE_FIELD_DAMAGE ? tmp : nullptr,
+                                    which == HFE_FIELD_KAPPA ? tmp : nullptr, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host_out, tmp, need * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(c, HFE_EDEVICE, std::string("get_field: ") + hipGetErrorString(e));
+  return HFE_OK;
+}
+
+hfe_status hfe_get_newton_log(const hfe_ctx* c, hfe_newton_record* out, int max, int* count) {
+  if (!c || !count || (max > 0 && !out)) return HFE_EINVAL;
+  const int n = std::min<int>(max, (int)c->log.size());
+  for (int i = 0; i < n; ++i) out[i] = c->log[i];
+  *count = n;
+  return HFE_OK;
+}
+
+hfe_status hfe_set_displacement(hfe_ctx* c, const double* host_u) {
+  if (!c || !host_u) return HFE_EINVAL;
+  if (!materials_ready(c)) return fail(c, HFE_ESTATE, "microstructure and every material must be set");
+  hfe_status st = ensure_history(c);
+  if (st) return st;
+  HIPCHK(c, hipMemcpyAsync(c->u, host_u, (size_t)ndof(c) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  return evaluate_state(c);
+}
+
+hfe_status hfe_apply_projected_hessian(hfe_ctx* c, const double* in, double* out, double dots[2]) {
+  if (!c || !in || !out || in == out) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+  hfe_status st = stiffness(c, in, c->Kd, 0);
+  if (st) return st;
+  st = green(c, c->Kd, out);
+  if (st) return st;
+  if (dots) {
+    st = sync_read(c, 0, 2);
+    if (st) return st;
+    dots[0] = c->hscal[0];
+    dots[1] = c->hscal[1];
+  }
+  return HFE_OK;
+}
+
+hfe_status hfe_apply_stiffness(hfe_ctx* c, const double* in, double* out) {
+  if (!c || !in || !out || in == out) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+  return stiffness(c, in, out, 0);
+}
+
+hfe_status hfe_apply_green(hfe_ctx* c, const double* in, double* out) {
+  if (!c || !in || !out) return HFE_EINVAL;
+  return green(c, in, out);
+}
+
+hfe_status hfe_fft_forward(hfe_ctx* c, const double* in, double* out_spec) {
+  if (!c || !in || !out_spec) return HFE_EINVAL;
+  HIPCHK(c, hfe::fft_forward(c->g, c->tabs, in, c->spec, c->stream));
+  const size_t bytes = (size_t)c->g.dim * c->g.nz * c->g.ny * (c->g.nx / 2 + 1) * sizeof(double2);
+  HIPCHK(c, hipMemcpyAsync(out_spec, c->spec, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return HFE_OK;
+}
+
+hfe_status hfe_fft_inverse(hfe_ctx* c, const double* in_spec, double* out) {
+  if (!c || !in_spec || !out) return HFE_EINVAL;
+  const size_t bytes = (size_t)c->g.dim * c->g.nz * c->g.ny * (c->g.nx / 2 + 1) * sizeof(double2);
+  HIPCHK(c, hipMemcpyAsync(c->spec, in_spec, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hfe::fft_inverse(c->g, c->tabs, c->spec, out, c->stream));
+  return HFE_OK;
+}
+
+hfe_status hfe_set_profiling(hfe_ctx* c, int on) {
+  if (!c) return HFE_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_drain(c);
+  c->profiling = on != 0;
+  for (size_t i = 0; i < c->kcount.size(); ++i) {
+    c->kcount[i] = 0;
+    c->kms[i] = 0.0;
+  }
+  return HFE_OK;
+}
+
+hfe_status hfe_kernel_stats(hfe_ctx* c, const char** names, int* counts, double* total_ms, int max,
+                            int* n_kernels) {
+  if (!c || !n_kernels) return HFE_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_drain(c);
+  const int n = std::min<int>(max, (int)c->knames.size());
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = c->knames[i].c_str();
+    if (counts) counts[i] = c->kcount[i];
+    if (total_ms) total_ms[i] = c->kms[i];
+  }
+  *n_kernels = n;
+  return HFE_OK;
+}
+
+const char* hfe_last_error(const hfe_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal declarations shared by the kernel translation units and the host
+// driver. Not part of the public ABI (include/hfe.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/hfe.h"
+
+namespace hfe {
+
+constexpr int kMaxPhases = HFE_MAX_PHASES;
+constexpr int kBlock = 256;        // threads per block of the element / vector kernels
+constexpr int kMaxPartials = 16;   // doubles per block in a partial-sum row
+
+// Per-phase constants, passed by value to the kernels (no __constant__ state,
+// so several contexts can live on one device).
+struct MatTable {
+  double lam[kMaxPhases], mu[kMaxPhases], E[kMaxPhases];
+  double k0[kMaxPhases], kf[kMaxPhases];
+  int damage[kMaxPhases];
+};
+
+struct Grid {
+  int nx, ny, nz;     // nz = 1 in 2D
+  int dim, nq, na;    // displacement components, points and nodes per element
+  int element;        // HFE_Q1 or HFE_P1_PAIR
+  long long N;        // nodes = elements
+};
+
+struct Macro {        // macroscopic strain E, full 3x3 row-major
+  double e[9];
+};
+
+// ---- element kernels (k_element.hip) -------------------------------------
+
+// Partial-sum layouts written by the element kernels (one row per block).
+enum { RES_S0 = 0 /* 6 stress sums xx,yy,zz,xy,xz,yz */, RES_SS = 6, RES_HH = 7, RES_NV = 8 };
+enum { TRI_SP = 0, TRI_PBP = 1, TRI_STP = 2, TRI_PP = 3, TRI_HH = 4, TRI_SS = 5,
+       TRI_S0 = 6 /* 6 stress sums */, TRI_NV = 12 };
+enum { HES_DKD = 0, HES_DD = 1, HES_NV = 2 };
+
+struct ElemArgs {
+  Grid g;
+  MatTable mat;
+  Macro E;
+  const uint8_t* phase;
+  const double* khist;   // [nq][N]
+  const double* a;       // [nq][N] current tangent scalars
+  const double* cp;
+  double* a_out;         // [nq][N] written by residual / trial
+  double* cp_out;
+  const double* u;       // [dim][N]
+  const double* v;       // second nodal input: z (trial) or the direction (Hessian)
+  double* f;             // nodal output [dim][N]
+  double* partials;      // [blocks][nv]
+};
+
+// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, sums RES_*.
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), sums TRI_*.
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Hessian: f = D^T B D v at the state (u, a, cp), sums HES_*.
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Commit: khist <- max(khist, kappa_t(E + D u)) on damage points (khist is
+// written through the const-cast pointer a_out).
+hipError_t launch_commit(const ElemArgs& A, hipStream_t s);
+// khist := kappa0 on damage points, 0 elsewhere (written through a_out).
+hipError_t launch_init_history(const ElemArgs& A, hipStream_t s);
+// Fields at points: grad (H) and stress into out_h / out_s ([N][nq][dim][dim]),
+// damage and kappa into out_d / out_k ([N][nq]); any may be null.
+hipError_t launch_fields(const ElemArgs& A, double* out_h, double* out_s, double* out_d,
+                         double* out_k, hipStream_t s);
+
+// ---- FFT / Green kernels (k_fft.hip) ---------------------------------------
+
+struct FftTables {
+  const double2* tw;      // concatenated twiddle tables, see offsets
+  int off_x, off_y, off_z, off_post;   // offsets (in double2) of the Lx=nx/2, ny, nz
+                                       // tables and of e^{-2 pi i k/nx}, k <= nx/2
+  const double* sx;       // 4 sin^2(pi k / n) per axis (the 1D FE Laplacian symbol)
+  const double* sy;
+  const double* sz;
+};
+
+bool fft_length_supported(int L);
+size_t fft_plane_lds_bytes(const Grid& g);
+// Pipeline entry points. `in`/`out` are [dim][N] doubles, `spec` is the
+// [dim][nz][ny][nx/2+1] double2 work buffer.
+hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
+                       double2* spec, hipStream_t s);
+// The three passes of green_apply (3D) and the single 2D pass, launched
+// separately so that each can be timed.
+hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+                             hipStream_t s);
+hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s);
+hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+                             hipStream_t s);
+hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
+                             double2* spec, hipStream_t s);
+hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+                       hipStream_t s);
+hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+                       hipStream_t s);
+
+// ---- vector kernels (k_vec.hip) --------------------------------------------
+
+// x += alpha * y over n doubles
+hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipStream_t s);
+// out = x + alpha * y
+hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
+                       hipStream_t s);
+// dots: partials rows of {x.y}
+hipError_t vec_dot(long long n, const double* x, const double* y, double* partials,
+                   hipStream_t s, int* nblocks);
+// CG update 1: z += alpha d ; g += alpha Kd
+hipError_t cg_step_zg(long long n, double alpha, const double* d, const double* Kd, double* z,
+                      double* g, hipStream_t s);
+// CG update 2: y_new = y + alpha w ; partials {y_new.g, y_old.g}
+hipError_t cg_step_y(long long n, double alpha, const double* w, double* y, const double* g,
+                     double* partials, hipStream_t s, int* nblocks);
+// CG update 3: d = -y + beta d ; partials {g.d, z.g}
+hipError_t cg_step_d(long long n, double beta, const double* y, double* d, const double* g,
+                     const double* z, double* partials, hipStream_t s, int* nblocks);
+// Deterministic final reduction of `nblocks` rows of `nv` partials into out[nv].
+hipError_t reduce_partials(const double* partials, int nblocks, int nv, double* out,
+                           hipStream_t s);
+
+}  // namespace hfe

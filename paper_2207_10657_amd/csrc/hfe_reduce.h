@@ -1,0 +1,38 @@
+// Deterministic block reductions: every block writes one row of NV partial
+// sums; a single-block kernel later adds the rows in a fixed order. The order
+// of every addition is fixed by the launch shape, so repeated runs give the
+// same bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hfe {
+
+// Sum over the 64 lanes of a wavefront (butterfly with xor shuffles).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce acc[NV] over the block (blockDim.x a multiple of 64, at most 1024)
+// and store the block's row partials[blockIdx.x * NV + k].
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* partials) {
+  __shared__ double red[16][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += red[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+}  // namespace hfe

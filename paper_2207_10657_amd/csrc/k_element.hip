@@ -1,0 +1,504 @@
+// Element-level kernels of the FE-projection scheme: discrete gradient at
+// the quadrature points (Sec. 2.1, the FE derivative operator evaluated at
+// quadrature points), the damage law and its consistent tangent at every
+// point (the Hessian of eq. graient_and_hessian used in eq.
+// project_stress_linear), and the FE divergence D^T that brings point
+// stresses back to the nodes.
+//
+// One thread per node gathers the contributions of the elements around it;
+// the element whose lowest corner is the node also writes the per-point
+// state and adds the per-point terms of the reductions, so every point is
+// counted once.
+#include "hfe_internal.h"
+#include "hfe_reduce.h"
+
+namespace hfe {
+namespace {
+
+// Gauss abscissae of the 2-point rule on [0,1]: 1/2 -+ 1/(2 sqrt 3).
+constexpr double kG0 = 0.21132486540518711775;
+constexpr double kG1 = 0.78867513459481288225;
+
+template <int EL> struct ET;
+template <> struct ET<HFE_Q1> { static constexpr int D = 3, NQ = 8, NA = 8; };
+template <> struct ET<HFE_P1_PAIR> { static constexpr int D = 2, NQ = 2, NA = 4; };
+
+// dN_a/dx_j at point q of a unit element. Local node a = ax + 2 ay (+ 4 az).
+template <int EL>
+__device__ __forceinline__ double shape_grad(int q, int a, int j);
+
+template <>
+__device__ __forceinline__ double shape_grad<HFE_Q1>(int q, int a, int j) {
+  const int o0 = a & 1, o1 = (a >> 1) & 1, o2 = (a >> 2) & 1;
+  const double x0 = (q & 1) ? kG1 : kG0, x1 = (q & 2) ? kG1 : kG0, x2 = (q & 4) ? kG1 : kG0;
+  const double l0 = o0 ? x0 : 1.0 - x0, l1 = o1 ? x1 : 1.0 - x1, l2 = o2 ? x2 : 1.0 - x2;
+  if (j == 0) return (o0 ? 1.0 : -1.0) * l1 * l2;
+  if (j == 1) return (o1 ? 1.0 : -1.0) * l0 * l2;
+  return (o2 ? 1.0 : -1.0) * l0 * l1;
+}
+
+// Two linear triangles per pixel: T1 = (0,0),(1,0),(0,1); T2 = (1,1),(0,1),(1,0).
+template <>
+__device__ __forceinline__ double shape_grad<HFE_P1_PAIR>(int q, int a, int j) {
+  if (q == 0) {
+    if (a == 0) return -1.0;
+    if (a == 1) return j == 0 ? 1.0 : 0.0;
+    if (a == 2) return j == 1 ? 1.0 : 0.0;
+    return 0.0;
+  }
+  if (a == 3) return 1.0;
+  if (a == 2) return j == 0 ? -1.0 : 0.0;
+  if (a == 1) return j == 1 ? -1.0 : 0.0;
+  return 0.0;
+}
+
+// Symmetric tensors are held as (xx, yy, zz, xy, xz, yz); in 2D zz, xz, yz of
+// a strain are zero (plane strain).
+struct Sym { double v[6]; };
+
+__device__ __forceinline__ double sym_dot(const Sym& a, const Sym& b) {
+  return a.v[0] * b.v[0] + a.v[1] * b.v[1] + a.v[2] * b.v[2] +
+         2.0 * (a.v[3] * b.v[3] + a.v[4] * b.v[4] + a.v[5] * b.v[5]);
+}
+
+// sym part of a full gradient H[i][j] (d x d, row i = displacement component)
+template <int D>
+__device__ __forceinline__ Sym sym_of(const double (&H)[3][3]) {
+  Sym e;
+  e.v[0] = H[0][0];
+  e.v[1] = H[1][1];
+  e.v[2] = D == 3 ? H[2][2] : 0.0;
+  e.v[3] = 0.5 * (H[0][1] + H[1][0]);
+  e.v[4] = D == 3 ? 0.5 * (H[0][2] + H[2][0]) : 0.0;
+  e.v[5] = D == 3 ? 0.5 * (H[1][2] + H[2][1]) : 0.0;
+  return e;
+}
+
+__device__ __forceinline__ Sym c_contract(const Sym& e, double lam, double mu) {
+  const double tr = e.v[0] + e.v[1] + e.v[2];
+  Sym s;
+  s.v[0] = lam * tr + 2.0 * mu * e.v[0];
+  s.v[1] = lam * tr + 2.0 * mu * e.v[1];
+  s.v[2] = lam * tr + 2.0 * mu * e.v[2];
+  s.v[3] = 2.0 * mu * e.v[3];
+  s.v[4] = 2.0 * mu * e.v[4];
+  s.v[5] = 2.0 * mu * e.v[5];
+  return s;
+}
+
+// Norm^2 of the d x d block of a symmetric tensor (the plane-strain zz
+// component is not part of the unknowns' inner product in 2D).
+template <int D>
+__device__ __forceinline__ double sym_norm2(const Sym& s) {
+  if (D == 3) return sym_dot(s, s);
+  return s.v[0] * s.v[0] + s.v[1] * s.v[1] + 2.0 * s.v[3] * s.v[3];
+}
+
+struct PointLaw {
+  Sym s;        // C : eps
+  double a;     // 1 - d
+  double cp;    // c' of the rank-one softening term
+  double kt;    // equivalent strain kappa_t
+};
+
+// Damage law at one point with the history kappa_hist frozen.
+__device__ __forceinline__ PointLaw eval_law(const Sym& eps, double lam, double mu, double E,
+                                             int damage, double k0, double kf, double kh) {
+  PointLaw P;
+  P.s = c_contract(eps, lam, mu);
+  const double ecs = sym_dot(eps, P.s);
+  P.kt = sqrt(fmax(ecs, 0.0) / E);
+  double d = 0.0, cp = 0.0;
+  if (damage) {
+    const bool loading = P.kt > kh;
+    const double ke = loading ? P.kt : kh;
+    d = kf / ke * (ke - k0) / (kf - k0);
+    d = fmin(fmax(d, 0.0), 1.0);
+    if (loading && d > 0.0 && d < 1.0) {
+      const double dprime = kf * k0 / ((kf - k0) * (P.kt * P.kt));
+      cp = dprime / (E * P.kt);
+    }
+  }
+  P.a = 1.0 - d;
+  P.cp = cp;
+  return P;
+}
+
+// Tangent applied to a perturbation: a C:deps - c' (s:deps) s.
+__device__ __forceinline__ Sym apply_tangent(const Sym& de, double a, double cp, const Sym& s,
+                                             double lam, double mu) {
+  Sym t = c_contract(de, lam, mu);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t.v[k] *= a;
+  if (cp != 0.0) {
+    const double sde = sym_dot(s, de);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) t.v[k] -= cp * sde * s.v[k];
+  }
+  return t;
+}
+
+__device__ __forceinline__ double sym_at(const Sym& s, int i, int j) {
+  if (i == j) return s.v[i];
+  const int k = (i + j == 1) ? 3 : ((i + j == 2) ? 4 : 5);
+  return s.v[k];
+}
+
+struct Pos { int x, y, z; };
+
+__device__ __forceinline__ long long lin(const Grid& g, int x, int y, int z) {
+  return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+template <int EL>
+__device__ __forceinline__ long long elem_node(const Grid& g, const Pos& e, int a) {
+  int x = e.x + (a & 1), y = e.y + ((a >> 1) & 1), z = e.z + ((a >> 2) & 1);
+  if (x >= g.nx) x -= g.nx;
+  if (y >= g.ny) y -= g.ny;
+  if (ET<EL>::D == 2) z = 0; else if (z >= g.nz) z -= g.nz;
+  return lin(g, x, y, z);
+}
+
+template <int EL>
+__device__ __forceinline__ void load_nodal(const Grid& g, const double* __restrict__ f,
+                                           const Pos& e, double (&v)[3][ET<EL>::NA]) {
+  constexpr int D = ET<EL>::D, NA = ET<EL>::NA;
+#pragma unroll
+  for (int b = 0; b < NA; ++b) {
+    const long long n = elem_node<EL>(g, e, b);
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i][b] = f[i * g.N + n];
+  }
+}
+
+// Full gradient at point q of a nodal field (element-local values).
+template <int EL>
+__device__ __forceinline__ void grad_at(int q, const double (&v)[3][ET<EL>::NA], double (&H)[3][3]) {
+  constexpr int D = ET<EL>::D, NA = ET<EL>::NA;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H[i][j] = 0.0;
+#pragma unroll
+  for (int b = 0; b < NA; ++b)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double w = shape_grad<EL>(q, b, j);
+#pragma unroll
+      for (int i = 0; i < D; ++i) H[i][j] += w * v[i][b];
+    }
+}
+
+template <int EL>
+__device__ __forceinline__ Pos elem_of(const Grid& g, int x, int y, int z, int al) {
+  Pos e;
+  e.x = x - (al & 1);
+  e.y = y - ((al >> 1) & 1);
+  e.z = (ET<EL>::D == 3) ? z - ((al >> 2) & 1) : 0;
+  if (e.x < 0) e.x += g.nx;
+  if (e.y < 0) e.y += g.ny;
+  if (e.z < 0) e.z += g.nz;
+  return e;
+}
+
+enum { MODE_RESIDUAL = 0, MODE_TRIAL = 1, MODE_HESSIAN = 2 };
+
+template <int EL, int MODE, int NV>
+__global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
+  constexpr int D = ET<EL>::D, NQ = ET<EL>::NQ, NA = ET<EL>::NA;
+  const Grid& g = A.g;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  if (n < g.N) {
+    const int x = (int)(n % g.nx);
+    const int y = (int)((n / g.nx) % g.ny);
+    const int z = (int)(n / ((long long)g.nx * g.ny));
+    double fo[3] = {0.0, 0.0, 0.0};
+    double Em[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Em[i][j] = (i < D && j < D) ? A.E.e[3 * i + j] : 0.0;
+#pragma unroll 1
+    for (int al = 0; al < NA; ++al) {
+      const Pos e = elem_of<EL>(g, x, y, z, al);
+      const long long ei = lin(g, e.x, e.y, e.z);
+      const int ph = A.phase[ei];
+      const double lam = A.mat.lam[ph], mu = A.mat.mu[ph], Ey = A.mat.E[ph];
+      const int dmg = A.mat.damage[ph];
+      const double k0 = A.mat.k0[ph], kf = A.mat.kf[ph];
+      const bool owner = (al == 0);
+      double un[3][NA], vn[3][NA];
+      if (MODE == MODE_HESSIAN) {
+        bool need_s = false;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) need_s |= (A.cp[q * g.N + ei] != 0.0);
+        load_nodal<EL>(g, A.v, e, vn);
+        if (need_s) load_nodal<EL>(g, A.u, e, un);
+        else {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int b = 0; b < NA; ++b) un[i][b] = 0.0;
+        }
+      } else {
+        load_nodal<EL>(g, A.u, e, un);
+        if (MODE == MODE_TRIAL) load_nodal<EL>(g, A.v, e, vn);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        Sym tau;
+        if (MODE == MODE_HESSIAN) {
+          double dH[3][3];
+          grad_at<EL>(q, vn, dH);
+          const double aq = A.a[q * g.N + ei], cq = A.cp[q * g.N + ei];
+          Sym s;
+          if (cq != 0.0) {
+            double H[3][3];
+            grad_at<EL>(q, un, H);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
+            s = c_contract(sym_of<D>(H), lam, mu);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
+          }
+          tau = apply_tangent(sym_of<D>(dH), aq, cq, s, lam, mu);
+          if (owner) {
+            double dd = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+              for (int j = 0; j < D; ++j) dd += dH[i][j] * dH[i][j];
+            acc[HES_DD] += dd;
+          }
+        } else if (MODE == MODE_RESIDUAL) {
+          double H[3][3];
+          grad_at<EL>(q, un, H);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
+          const Sym eps = sym_of<D>(H);
+          const double kh = A.khist[q * g.N + ei];
+          const PointLaw P = eval_law(eps, lam, mu, Ey, dmg, k0, kf, kh);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
+          if (owner) {
+            A.a_out[q * g.N + ei] = P.a;
+            A.cp_out[q * g.N + ei] = P.cp;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[RES_S0 + k] += tau.v[k];
+            acc[RES_SS] += sym_norm2<D>(tau);
+            double hh = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+              for (int j = 0; j < D; ++j) hh += H[i][j] * H[i][j];
+            acc[RES_HH] += hh;
+          }
+        } else {  // MODE_TRIAL
+          double H[3][3], p[3][3];
+          grad_at<EL>(q, un, H);
+          grad_at<EL>(q, vn, p);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
+          double Ht[3][3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
+          const double kh = A.khist[q * g.N + ei];
+          const PointLaw P = eval_law(sym_of<D>(Ht), lam, mu, Ey, dmg, k0, kf, kh);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
+          if (owner) {
+            A.a_out[q * g.N + ei] = P.a;
+            A.cp_out[q * g.N + ei] = P.cp;
+            const double ao = A.a[q * g.N + ei], co = A.cp[q * g.N + ei];
+            const Sym so = c_contract(sym_of<D>(H), lam, mu);
+            const Sym ps = sym_of<D>(p);
+            double sig_p = 0.0;  // sigma_old : p
+            {
+              Sym sig;
+#pragma unroll
+              for (int k = 0; k < 6; ++k) sig.v[k] = ao * so.v[k];
+              sig_p = sym_dot(sig, ps);
+            }
+            const Sym Bp = apply_tangent(ps, ao, co, so, lam, mu);
+            acc[TRI_SP] += sig_p;
+            acc[TRI_PBP] += sym_dot(Bp, ps);
+            acc[TRI_STP] += sym_dot(tau, ps);
+            double pp = 0.0, hh = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+              for (int j = 0; j < D; ++j) {
+                pp += p[i][j] * p[i][j];
+                hh += Ht[i][j] * Ht[i][j];
+              }
+            acc[TRI_PP] += pp;
+            acc[TRI_HH] += hh;
+            acc[TRI_SS] += sym_norm2<D>(tau);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[TRI_S0 + k] += tau.v[k];
+          }
+        }
+        // divergence: contribution of this point to the element's local node al
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const double w = shape_grad<EL>(q, al, j);
+#pragma unroll
+          for (int i = 0; i < D; ++i) fo[i] += w * sym_at(tau, i, j);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) A.f[i * g.N + n] = fo[i];
+    if (MODE == MODE_HESSIAN) {
+      double dk = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) dk += A.v[i * g.N + n] * fo[i];
+      acc[HES_DKD] += dk;
+    }
+  }
+  block_reduce_store<NV>(acc, A.partials);
+}
+
+template <int EL>
+__global__ void __launch_bounds__(kBlock) k_commit(ElemArgs A) {
+  constexpr int D = ET<EL>::D, NQ = ET<EL>::NQ, NA = ET<EL>::NA;
+  const Grid& g = A.g;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int ph = A.phase[n];
+  if (!A.mat.damage[ph]) return;
+  Pos e;
+  e.x = (int)(n % g.nx);
+  e.y = (int)((n / g.nx) % g.ny);
+  e.z = (int)(n / ((long long)g.nx * g.ny));
+  double un[3][NA];
+  load_nodal<EL>(g, A.u, e, un);
+  double* kh = A.a_out;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double H[3][3];
+    grad_at<EL>(q, un, H);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) H[i][j] += A.E.e[3 * i + j];
+    const Sym eps = sym_of<D>(H);
+    const Sym s = c_contract(eps, A.mat.lam[ph], A.mat.mu[ph]);
+    const double kt = sqrt(fmax(sym_dot(eps, s), 0.0) / A.mat.E[ph]);
+    const long long idx = q * g.N + n;
+    kh[idx] = fmax(kh[idx], kt);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_init_history(ElemArgs A) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= A.g.N) return;
+  const int ph = A.phase[n];
+  const double v = A.mat.damage[ph] ? A.mat.k0[ph] : 0.0;
+  for (int q = 0; q < A.g.nq; ++q) A.a_out[q * A.g.N + n] = v;
+}
+
+template <int EL>
+__global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, double* out_s,
+                                                  double* out_d, double* out_k) {
+  constexpr int D = ET<EL>::D, NQ = ET<EL>::NQ, NA = ET<EL>::NA;
+  const Grid& g = A.g;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int ph = A.phase[n];
+  Pos e;
+  e.x = (int)(n % g.nx);
+  e.y = (int)((n / g.nx) % g.ny);
+  e.z = (int)(n / ((long long)g.nx * g.ny));
+  double un[3][NA];
+  load_nodal<EL>(g, A.u, e, un);
+  for (int q = 0; q < NQ; ++q) {
+    double H[3][3];
+    grad_at<EL>(q, un, H);
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) H[i][j] += A.E.e[3 * i + j];
+    const long long base = (n * NQ + q) * D * D;
+    if (out_h)
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) out_h[base + i * D + j] = H[i][j];
+    if (out_s) {
+      const Sym eps = sym_of<D>(H);
+      const double kh = A.khist[q * g.N + n];
+      const PointLaw P = eval_law(eps, A.mat.lam[ph], A.mat.mu[ph], A.mat.E[ph],
+                                  A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh);
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) out_s[base + i * D + j] = P.a * sym_at(P.s, i, j);
+    }
+    const double kh = A.khist[q * g.N + n];
+    if (out_k) out_k[n * NQ + q] = kh;
+    if (out_d) {
+      double d = 0.0;
+      if (A.mat.damage[ph]) {
+        const double k0 = A.mat.k0[ph], kf = A.mat.kf[ph];
+        d = fmin(fmax(kf / kh * (kh - k0) / (kf - k0), 0.0), 1.0);
+      }
+      out_d[n * NQ + q] = d;
+    }
+  }
+}
+
+template <int MODE, int NV>
+hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
+  if (nblocks) *nblocks = nb;
+  if (A.g.element == HFE_Q1)
+    hipLaunchKernelGGL((k_gather<HFE_Q1, MODE, NV>), dim3(nb), dim3(kBlock), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_gather<HFE_P1_PAIR, MODE, NV>), dim3(nb), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
+}
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
+}
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
+}
+hipError_t launch_commit(const ElemArgs& A, hipStream_t s) {
+  const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
+  if (A.g.element == HFE_Q1)
+    hipLaunchKernelGGL(k_commit<HFE_Q1>, dim3(nb), dim3(kBlock), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_commit<HFE_P1_PAIR>, dim3(nb), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_init_history(const ElemArgs& A, hipStream_t s) {
+  const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_init_history, dim3(nb), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_fields(const ElemArgs& A, double* out_h, double* out_s, double* out_d,
+                         double* out_k, hipStream_t s) {
+  const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
+  if (A.g.element == HFE_Q1)
+    hipLaunchKernelGGL(k_fields<HFE_Q1>, dim3(nb), dim3(kBlock), 0, s, A, out_h, out_s, out_d,
+                       out_k);
+  else
+    hipLaunchKernelGGL(k_fields<HFE_P1_PAIR>, dim3(nb), dim3(kBlock), 0, s, A, out_h, out_s,
+                       out_d, out_k);
+  return hipGetLastError();
+}
+
+}  // namespace hfe

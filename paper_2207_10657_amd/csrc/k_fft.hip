@@ -1,0 +1,405 @@
+// Hand-written FP64 FFT and FE Green's operator for gfx950.
+//
+// The projector of Sec. 2.1 is block diagonal in the wave vector (eq.
+// conv_to_fourier). In displacement coordinates its only non-trivial part is
+// the inverse of the FE Laplacian L = D^T D, whose Fourier symbol is
+// S(k) = sum_{q,j} |Dhat_qj(k)|^2 (the denominator of eq. proj_operator), with
+// the k = 0 mode set to zero (ghat(0) = 0). The 3D transform runs in three
+// passes over HBM:
+//   k_plane<FWD>   per z-plane and component: real-to-complex along x (two
+//                  real samples packed per complex value, a half-length
+//                  complex FFT and a split step), then a complex FFT along y,
+//                  all in LDS;
+//   k_pencil       per (ky, kx-chunk, component): FFT along z, multiply by
+//                  1/(S(k) N), inverse FFT along z, all in LDS;
+//   k_plane<INV>   the inverse of the first pass.
+// In 2D a single k_plane<GREEN2D> does forward, multiply and inverse.
+//
+// The 1D transforms are Stockham autosort passes (radix 4, then 3, then 2)
+// on lines held in LDS, with every thread staging its butterflies in
+// registers between two barriers so that one LDS buffer suffices.
+#include "hfe_internal.h"
+
+namespace hfe {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 mul_mi(double2 a) {
+  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+constexpr int radix_of(int rem) { return rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2); }
+
+template <int R, bool INV> struct Bfly;
+template <bool INV> struct Bfly<2, INV> {
+  __device__ static void run(double2 (&v)[2]) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+template <bool INV> struct Bfly<3, INV> {
+  __device__ static void run(double2 (&v)[3]) {
+    constexpr double kS = 0.86602540378443864676;  // sin(2 pi / 3)
+    const double2 a = v[0], b = v[1], c = v[2];
+    const double2 t1 = cadd(b, c);
+    const double2 t2 = make_double2(a.x - 0.5 * t1.x, a.y - 0.5 * t1.y);
+    const double2 d = csub(b, c);
+    const double2 t3 = make_double2(kS * d.x, kS * d.y);
+    v[0] = cadd(a, t1);
+    v[1] = cadd(t2, mul_mi<INV>(t3));
+    v[2] = csub(t2, mul_mi<INV>(t3));
+  }
+};
+template <bool INV> struct Bfly<4, INV> {
+  __device__ static void run(double2 (&v)[4]) {
+    const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const double2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, mul_mi<INV>(t3));
+    v[3] = csub(t1, mul_mi<INV>(t3));
+  }
+};
+
+// One Stockham pass of radix R on `nlines` lines of length L; element k of
+// line l is buf[l*ls + k*es]. `tw` holds e^{-2 pi i k / L}, k < L.
+template <int L, int R, int NS, bool INV>
+__device__ __forceinline__ void fft_pass(double2* buf, int nlines, int ls, int es,
+                                         const double2* __restrict__ tw) {
+  constexpr int NB = L / R;       // butterflies per line
+  constexpr int MAXB = 16 / R;    // butterflies staged per thread (caller guarantees enough threads)
+  double2 v[MAXB][R];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int total = nlines * NB;
+#pragma unroll
+  for (int it = 0; it < MAXB; ++it) {
+    const int b = tid + it * nt;
+    if (b < total) {
+      const int line = b / NB, j = b - line * NB;
+      const int k = j % NS;
+      const double2* base = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double2 x = base[(j + r * NB) * es];
+        if (NS > 1 && r > 0) {
+          double2 w = tw[k * r * (L / (NS * R))];
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[it][r] = x;
+      }
+      Bfly<R, INV>::run(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MAXB; ++it) {
+    const int b = tid + it * nt;
+    if (b < total) {
+      const int line = b / NB, j = b - line * NB;
+      const int k = j % NS;
+      const int idx = (j / NS) * NS * R + k;
+      double2* base = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[(idx + r * NS) * es] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int REM, int NS, bool INV>
+struct Passes {
+  __device__ static void run(double2* buf, int nl, int ls, int es, const double2* tw) {
+    constexpr int R = radix_of(REM);
+    fft_pass<L, R, NS, INV>(buf, nl, ls, es, tw);
+    Passes<L, REM / R, NS * R, INV>::run(buf, nl, ls, es, tw);
+  }
+};
+template <int L, int NS, bool INV>
+struct Passes<L, 1, NS, INV> {
+  __device__ static void run(double2*, int, int, int, const double2*) {}
+};
+
+// In-place transform of nl lines of runtime length L (uniform over the block).
+template <bool INV>
+__device__ void lds_fft(int L, double2* buf, int nl, int ls, int es, const double2* tw) {
+  switch (L) {
+    case 2: Passes<2, 2, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 3: Passes<3, 3, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 4: Passes<4, 4, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 6: Passes<6, 6, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 8: Passes<8, 8, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 12: Passes<12, 12, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 16: Passes<16, 16, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 24: Passes<24, 24, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 32: Passes<32, 32, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 48: Passes<48, 48, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 64: Passes<64, 64, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 96: Passes<96, 96, 1, INV>::run(buf, nl, ls, es, tw); break;
+    case 128: Passes<128, 128, 1, INV>::run(buf, nl, ls, es, tw); break;
+    default: break;  // L = 1: identity
+  }
+}
+
+// Split step of the packed real transform along x: row y holds
+// Z[m] = FFT_M(x[2m] + i x[2m+1]) in columns 0..M-1; afterwards columns
+// 0..M hold X[k] = sum_n x[n] e^{-2 pi i k n / nx}. W[k] = e^{-2 pi i k / nx}.
+__device__ void split_r2c(double2* buf, int M, int ny, int P, const double2* __restrict__ W) {
+  const int npair = M / 2 + 1;
+  for (int i = threadIdx.x; i < ny * npair; i += blockDim.x) {
+    const int y = i / npair, k = i - y * npair;
+    double2* row = buf + y * P;
+    if (k == 0) {
+      const double2 z0 = row[0];
+      row[0] = make_double2(z0.x + z0.y, 0.0);
+      row[M] = make_double2(z0.x - z0.y, 0.0);
+    } else {
+      const int k2 = M - k;
+      const double2 A = row[k], B = row[k2];
+      // X[k] = (A + B*)/2 - i W^k (A - B*)/2
+      {
+        const double2 Bc = cconj(B);
+        const double2 s = cadd(A, Bc), d = csub(A, Bc);
+        const double2 wd = cmul(W[k], d);
+        row[k] = make_double2(0.5 * (s.x + wd.y), 0.5 * (s.y - wd.x));
+      }
+      if (k2 != k) {
+        const double2 Ac = cconj(A);
+        const double2 s = cadd(B, Ac), d = csub(B, Ac);
+        const double2 wd = cmul(W[k2], d);
+        row[k2] = make_double2(0.5 * (s.x + wd.y), 0.5 * (s.y - wd.x));
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of split_r2c, scaled so that the unscaled inverse FFT of length M
+// that follows returns nx times the real samples (packed in pairs).
+__device__ void merge_c2r(double2* buf, int M, int ny, int P, const double2* __restrict__ W) {
+  const int npair = M / 2 + 1;
+  for (int i = threadIdx.x; i < ny * npair; i += blockDim.x) {
+    const int y = i / npair, k = i - y * npair;
+    double2* row = buf + y * P;
+    if (k == 0) {
+      const double2 X0 = row[0], XM = cconj(row[M]);
+      const double2 s = cadd(X0, XM), d = csub(X0, XM);
+      row[0] = make_double2(s.x - d.y, s.y + d.x);
+    } else {
+      const int k2 = M - k;
+      const double2 A = row[k], B = row[k2];
+      // Z[k] = (A + B*) + i W^{-k} (A - B*)
+      {
+        const double2 Bc = cconj(B);
+        const double2 s = cadd(A, Bc), d = csub(A, Bc);
+        const double2 wd = cmul(cconj(W[k]), d);
+        row[k] = make_double2(s.x - wd.y, s.y + wd.x);
+      }
+      if (k2 != k) {
+        const double2 Ac = cconj(A);
+        const double2 s = cadd(B, Ac), d = csub(B, Ac);
+        const double2 wd = cmul(cconj(W[k2]), d);
+        row[k2] = make_double2(s.x - wd.y, s.y + wd.x);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// 1 / (S(k) N) from the per-axis 1D symbols s_m = 2 - 2 cos(theta_m); 0 at k = 0.
+__device__ __forceinline__ double green_q1(double sx, double sy, double sz) {
+  const double px = 3.0 - 0.5 * sx, py = 3.0 - 0.5 * sy, pz = 3.0 - 0.5 * sz;
+  return (8.0 / 9.0) * (sx * py * pz + sy * px * pz + sz * px * py);
+}
+__device__ __forceinline__ double green_p1(double sx, double sy) { return 2.0 * (sx + sy); }
+
+enum { PLANE_FWD = 0, PLANE_INV = 1, PLANE_GREEN2D = 2 };
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const double* __restrict__ in,
+                                                double* __restrict__ out, double2* __restrict__ spec,
+                                                double scale) {
+  extern __shared__ double2 lds[];
+  const int nx = g.nx, ny = g.ny, M = nx / 2, P = M + 1;
+  const int z = blockIdx.x, c = blockIdx.y;
+  const long long plane = (long long)c * g.N + (long long)z * nx * ny;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double2* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
+  if (MODE != PLANE_INV) {
+    const double2* src = reinterpret_cast<const double2*>(in + plane);
+    for (int i = tid; i < M * ny; i += nt) {
+      const int y = i / M, m = i - y * M;
+      lds[y * P + m] = src[i];
+    }
+    __syncthreads();
+    lds_fft<false>(M, lds, ny, P, 1, t.tw + t.off_x);
+    split_r2c(lds, M, ny, P, t.tw + t.off_post);
+    lds_fft<false>(ny, lds, P, 1, P, t.tw + t.off_y);
+    if (MODE == PLANE_FWD) {
+      for (int i = tid; i < P * ny; i += nt) sp[i] = lds[i];
+      return;
+    }
+    // 2D: multiply by the FE Green's function
+    for (int i = tid; i < P * ny; i += nt) {
+      const int ky = i / P, kx = i - ky * P;
+      const double S = green_p1(t.sx[kx], t.sy[ky]);
+      const double m = (kx == 0 && ky == 0) ? 0.0 : scale / S;
+      lds[i] = make_double2(lds[i].x * m, lds[i].y * m);
+    }
+    __syncthreads();
+  } else {
+    for (int i = tid; i < P * ny; i += nt) lds[i] = sp[i];
+    __syncthreads();
+  }
+  lds_fft<true>(ny, lds, P, 1, P, t.tw + t.off_y);
+  merge_c2r(lds, M, ny, P, t.tw + t.off_post);
+  lds_fft<true>(M, lds, ny, P, 1, t.tw + t.off_x);
+  double2* dst = reinterpret_cast<double2*>(out + plane);
+  for (int i = tid; i < M * ny; i += nt) {
+    const int y = i / M, m = i - y * M;
+    dst[i] = lds[y * P + m];
+  }
+}
+
+enum { PENCIL_GREEN = 0, PENCIL_FWD = 1, PENCIL_INV = 2 };
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __restrict__ spec,
+                                               int C, double scale) {
+  extern __shared__ double2 lds[];
+  const int P = g.nx / 2 + 1, ny = g.ny, nz = g.nz;
+  const int kx0 = blockIdx.x * C;
+  const int cv = min(C, P - kx0);
+  const int ky = blockIdx.y, c = blockIdx.z;
+  double2* base = spec + (long long)c * nz * ny * P + (long long)ky * P + kx0;
+  const long long zs = (long long)ny * P;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < nz * cv; i += nt) {
+    const int zz = i / cv, j = i - zz * cv;
+    lds[zz * C + j] = base[zz * zs + j];
+  }
+  __syncthreads();
+  if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, C, t.tw + t.off_z);
+  if (MODE == PENCIL_GREEN) {
+    const double syv = t.sy[ky];
+    for (int i = tid; i < nz * cv; i += nt) {
+      const int kz = i / cv, j = i - kz * cv;
+      const int kx = kx0 + j;
+      const double S = green_q1(t.sx[kx], syv, t.sz[kz]);
+      const double m = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / S;
+      const double2 v = lds[kz * C + j];
+      lds[kz * C + j] = make_double2(v.x * m, v.y * m);
+    }
+    __syncthreads();
+  }
+  if (MODE != PENCIL_FWD) lds_fft<true>(nz, lds, cv, 1, C, t.tw + t.off_z);
+  for (int i = tid; i < nz * cv; i += nt) {
+    const int zz = i / cv, j = i - zz * cv;
+    base[zz * zs + j] = lds[zz * C + j];
+  }
+}
+
+constexpr int kPencilC = 16;
+
+int plane_threads(const Grid& g) {
+  // a thread stages at most 15 complex values per Stockham pass (radix 3:
+  // 5 butterflies), so a block of T threads covers 15 T cells
+  const int cells = (g.nx / 2 + 1) * g.ny;
+  return cells <= 15 * 256 ? 256 : 1024;
+}
+
+template <int MODE>
+hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, double* out,
+                        double2* spec, double scale, hipStream_t s) {
+  const size_t lds = fft_plane_lds_bytes(g);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_plane<MODE>, dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t, in,
+                     out, spec, scale);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, double scale,
+                         hipStream_t s) {
+  const int P = g.nx / 2 + 1;
+  const int nchunk = (P + kPencilC - 1) / kPencilC;
+  const size_t lds = (size_t)kPencilC * g.nz * sizeof(double2);
+  hipLaunchKernelGGL(k_pencil<MODE>, dim3(nchunk, g.ny, g.dim), dim3(256), lds, s, g, t, spec,
+                     kPencilC, scale);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_length_supported(int L) {
+  switch (L) {
+    case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32:
+    case 48: case 64: case 96: case 128:
+      return true;
+    default:
+      return false;
+  }
+}
+
+size_t fft_plane_lds_bytes(const Grid& g) {
+  return (size_t)(g.nx / 2 + 1) * g.ny * sizeof(double2);
+}
+
+hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+                             hipStream_t s) {
+  return launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s);
+}
+
+hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+                             hipStream_t s) {
+  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s);
+}
+
+hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s) {
+  return launch_pencil<PENCIL_GREEN>(g, t, spec, 1.0 / (double)g.N, s);
+}
+
+hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
+                             double2* spec, hipStream_t s) {
+  return launch_plane<PLANE_GREEN2D>(g, t, in, out, spec, 1.0 / (double)g.N, s);
+}
+
+hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
+                       double2* spec, hipStream_t s) {
+  if (g.dim == 2) return fft_plane_green2d(g, t, in, out, spec, s);
+  hipError_t e = fft_plane_forward(g, t, in, spec, s);
+  if (e != hipSuccess) return e;
+  e = fft_pencil_green(g, t, spec, s);
+  if (e != hipSuccess) return e;
+  return fft_plane_inverse(g, t, spec, out, s);
+}
+
+hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+                       hipStream_t s) {
+  hipError_t e = launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s);
+  if (e != hipSuccess || g.nz == 1) return e;
+  return launch_pencil<PENCIL_FWD>(g, t, spec, 1.0, s);
+}
+
+hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+                       hipStream_t s) {
+  if (g.nz > 1) {
+    hipError_t e = launch_pencil<PENCIL_INV>(g, t, spec, 1.0, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s);
+}
+
+}  // namespace hfe

@@ -1,0 +1,309 @@
+"""ctypes binding of libhfe.so (the C ABI declared in include/hfe.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides the device workspace and the stream. Importing this module
+without the built library raises ImportError (there is no fallback path).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfe.so")
+
+HFE_P1_PAIR, HFE_Q1 = 1, 2
+HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM = 0, 1
+FIELD_U, FIELD_GRAD, FIELD_STRESS, FIELD_DAMAGE, FIELD_KAPPA = range(5)
+CG_INTERIOR, CG_BOUNDARY, CG_NEGCURV, CG_MAXITER = 1, 2, 3, 4
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE"}
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("element", ctypes.c_int)]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("E", ctypes.c_double), ("nu", ctypes.c_double),
+                ("kappa0", ctypes.c_double), ("kappaf", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eta_eq", ctypes.c_double), ("eta_nr", ctypes.c_double),
+                ("eta_cg", ctypes.c_double), ("eta_up", ctypes.c_double),
+                ("R0", ctypes.c_double), ("Rmax", ctypes.c_double),
+                ("i_nr_max", ctypes.c_int), ("j_cg_max", ctypes.c_int)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int),
+                ("rejected", ctypes.c_int), ("cg_iters", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("boundary_exits", ctypes.c_int),
+                ("negcurv_exits", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("r_eq", ctypes.c_double), ("r_nr", ctypes.c_double),
+                ("R", ctypes.c_double), ("rho_last", ctypes.c_double),
+                ("time_ms", ctypes.c_double)]
+
+
+class _Record(ctypes.Structure):
+    _fields_ = [("flag", ctypes.c_int), ("cg_iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("accepted", ctypes.c_int), ("dm", ctypes.c_double), ("dW", ctypes.c_double),
+                ("rho", ctypes.c_double), ("R_before", ctypes.c_double)]
+
+
+EXPORTS = {
+    "hfe_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_Grid)]),
+    "hfe_create": (ctypes.c_int, [ctypes.POINTER(_Grid), ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "hfe_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "hfe_set_microstructure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "hfe_set_material": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Material)]),
+    "hfe_apply_load_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_solve_increment": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params),
+                                           ctypes.POINTER(_Report)]),
+    "hfe_homogenized_stress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_get_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]),
+    "hfe_get_newton_log": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Record), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]),
+    "hfe_set_displacement": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_apply_projected_hessian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_apply_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_apply_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_fft_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_fft_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hfe_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
+                                        ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
+    "hfe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhfe.so and declare its exports. Raises ImportError if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhfe.so not built (%s); run paper_2207_10657_amd.build.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HfeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+def _grid(shape, element):
+    shape = tuple(int(s) for s in shape)
+    g = _Grid()
+    if len(shape) == 2:
+        g.dim = 2
+        g.n[0], g.n[1], g.n[2] = shape[1], shape[0], 1
+    else:
+        g.dim = 3
+        g.n[0], g.n[1], g.n[2] = shape[2], shape[1], shape[0]
+    g.element = {"q1": HFE_Q1, "p1pair": HFE_P1_PAIR}[element]
+    return g
+
+
+def workspace_bytes(shape, element):
+    lib = load_library()
+    return int(lib.hfe_workspace_bytes(ctypes.byref(_grid(shape, element))))
+
+
+DEFAULT_PARAMS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "eta_cg": 1e-6, "eta_up": 0.15,
+                  "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000}
+
+
+class Solver:
+    """One periodic cell on one GPU.
+
+    ``shape`` is (ny, nx) for 2D (element ``p1pair``) or (nz, ny, nx) for 3D
+    (element ``q1``). Nodal fields are numpy arrays (dim, *shape); point fields
+    (*shape, nq, dim, dim) or (*shape, nq).
+    """
+
+    def __init__(self, shape, element, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.shape = tuple(int(s) for s in shape)
+        self.element = element
+        self.dim = len(self.shape)
+        self.nq = 8 if element == "q1" else 2
+        self.N = int(np.prod(self.shape))
+        self.device = torch.device(device)
+        g = _grid(self.shape, element)
+        nbytes = int(self.lib.hfe_workspace_bytes(ctypes.byref(g)))
+        if nbytes == 0:
+            raise HfeError(-1, "unsupported grid %s / %s" % (self.shape, element))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.hfe_create(ctypes.byref(g), ctypes.c_void_p(self.workspace.data_ptr()),
+                                 nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(ctx))
+        if st != 0:
+            raise HfeError(st, "hfe_create failed")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hfe_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise HfeError(st, self.lib.hfe_last_error(self.ctx).decode())
+
+    # -- problem definition ---------------------------------------------
+    def set_microstructure(self, phase, n_phases):
+        ph = np.ascontiguousarray(phase, dtype=np.uint8)
+        if ph.shape != self.shape:
+            raise ValueError("phase map shape %s != grid %s" % (ph.shape, self.shape))
+        self._check(self.lib.hfe_set_microstructure(self.ctx, ph.ctypes.data_as(ctypes.c_void_p),
+                                                    int(n_phases)))
+
+    def set_material(self, phase, mat):
+        m = _Material()
+        m.kind = HFE_DAMAGE_ENERGY_NORM if mat["kind"] == "damage" else HFE_ELASTIC
+        m.E, m.nu = float(mat["E"]), float(mat["nu"])
+        m.kappa0 = float(mat.get("kappa0", 0.0))
+        m.kappaf = float(mat.get("kappaf", 0.0))
+        self._check(self.lib.hfe_set_material(self.ctx, int(phase), ctypes.byref(m)))
+
+    def setup(self, phase, materials):
+        self.set_microstructure(phase, len(materials))
+        for p, m in enumerate(materials):
+            self.set_material(p, m)
+
+    # -- Algorithm 2 -----------------------------------------------------
+    def apply_load_step(self, dE):
+        a = np.ascontiguousarray(np.asarray(dE, dtype=np.float64).reshape(3, 3))
+        self._check(self.lib.hfe_apply_load_step(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def solve_increment(self, params=None):
+        p = dict(DEFAULT_PARAMS)
+        if params:
+            p.update({k: v for k, v in params.items() if v is not None and k in p})
+        cp = _Params(**{k: p[k] for k in DEFAULT_PARAMS})
+        rep = _Report()
+        self._check(self.lib.hfe_solve_increment(self.ctx, ctypes.byref(cp), ctypes.byref(rep)))
+        out = {name: getattr(rep, name) for name, _ in _Report._fields_}
+        out["converged"] = rep.status == 0
+        return out
+
+    def newton_log(self, max_records=10000):
+        recs = (_Record * max_records)()
+        cnt = ctypes.c_int()
+        self._check(self.lib.hfe_get_newton_log(self.ctx, recs, max_records, ctypes.byref(cnt)))
+        return [{name: getattr(recs[i], name) for name, _ in _Record._fields_}
+                for i in range(cnt.value)]
+
+    def homogenized_stress(self):
+        out = np.zeros(9)
+        self._check(self.lib.hfe_homogenized_stress(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(3, 3)
+
+    def field(self, which):
+        d, nq = self.dim, self.nq
+        shapes = {FIELD_U: (d,) + self.shape,
+                  FIELD_GRAD: self.shape + (nq, d, d),
+                  FIELD_STRESS: self.shape + (nq, d, d),
+                  FIELD_DAMAGE: self.shape + (nq,),
+                  FIELD_KAPPA: self.shape + (nq,)}
+        out = np.zeros(shapes[which])
+        self._check(self.lib.hfe_get_field(self.ctx, which, out.ctypes.data_as(ctypes.c_void_p),
+                                           out.size))
+        return out
+
+    def displacement(self):
+        return self.field(FIELD_U)
+
+    def gradient(self):
+        return self.field(FIELD_GRAD)
+
+    def damage(self):
+        return self.field(FIELD_DAMAGE)
+
+    def set_displacement(self, u):
+        a = np.ascontiguousarray(u, dtype=np.float64)
+        if a.shape != (self.dim,) + self.shape:
+            raise ValueError("displacement shape")
+        self._check(self.lib.hfe_set_displacement(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
+
+    # -- operators on device tensors ([dim][N] float64, contiguous) -------
+    def _dev(self, t):
+        torch = self.torch
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("expected a contiguous float64 device tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def new_nodal(self):
+        return self.torch.zeros((self.dim,) + self.shape, dtype=self.torch.float64,
+                                device=self.device)
+
+    def apply_projected_hessian(self, d, out=None):
+        out = self.new_nodal() if out is None else out
+        dots = np.zeros(2)
+        self._check(self.lib.hfe_apply_projected_hessian(self.ctx, self._dev(d), self._dev(out),
+                                                         dots.ctypes.data_as(ctypes.c_void_p)))
+        return out, dots
+
+    def apply_stiffness(self, d, out=None):
+        out = self.new_nodal() if out is None else out
+        self._check(self.lib.hfe_apply_stiffness(self.ctx, self._dev(d), self._dev(out)))
+        return out
+
+    def apply_green(self, f, out=None):
+        out = self.new_nodal() if out is None else out
+        self._check(self.lib.hfe_apply_green(self.ctx, self._dev(f), self._dev(out)))
+        return out
+
+    def _spec_shape(self):
+        if self.dim == 2:
+            ny, nx = self.shape
+            return (2, 1, ny, nx // 2 + 1, 2)
+        nz, ny, nx = self.shape
+        return (3, nz, ny, nx // 2 + 1, 2)
+
+    def fft_forward(self, f):
+        out = self.torch.zeros(self._spec_shape(), dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.hfe_fft_forward(self.ctx, self._dev(f), self._dev(out)))
+        return out
+
+    def fft_inverse(self, spec):
+        out = self.new_nodal()
+        self._check(self.lib.hfe_fft_inverse(self.ctx, self._dev(spec), self._dev(out)))
+        return out
+
+    # -- profiling -------------------------------------------------------
+    def set_profiling(self, on):
+        self._check(self.lib.hfe_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_stats(self, max_kernels=32):
+        names = (ctypes.c_char_p * max_kernels)()
+        counts = (ctypes.c_int * max_kernels)()
+        ms = (ctypes.c_double * max_kernels)()
+        n = ctypes.c_int()
+        self._check(self.lib.hfe_kernel_stats(self.ctx, names, counts, ms, max_kernels,
+                                              ctypes.byref(n)))
+        return {names[i].decode(): (counts[i], ms[i]) for i in range(n.value)}

@@ -1,0 +1,58 @@
+"""Host-only checks of the C ABI: the built library loads and exports every
+entry point include/hfe.h declares; grid validation and workspace sizing run
+without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hfe.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hfe_[a-z_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_2207_10657_amd import hfe
+    if not os.path.exists(hfe.LIB_PATH):
+        pytest.skip("libhfe.so not built")
+    return hfe, hfe.load_library()
+
+
+def test_every_declared_symbol_is_exported():
+    hfe, lib = _lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares exactly these
+    assert sorted(hfe.EXPORTS) == names
+
+
+def test_workspace_sizing_and_grid_validation():
+    hfe, lib = _lib()
+    assert hfe.workspace_bytes((64, 64, 64), "q1") > 64 ** 3 * 8 * 3 * 11
+    assert hfe.workspace_bytes((32, 32), "p1pair") > 0
+    # unsupported: odd nx, lengths outside the FFT set, plane too large for LDS
+    assert hfe.workspace_bytes((8, 8, 7), "q1") == 0
+    assert hfe.workspace_bytes((8, 8, 10), "q1") == 0
+    assert hfe.workspace_bytes((8, 256, 256), "q1") == 0
+    # element / dimension mismatch
+    g = hfe._grid((8, 8), "q1")
+    assert lib.hfe_workspace_bytes(ctypes.byref(g)) == 0
+
+
+def test_create_rejects_bad_arguments_without_gpu():
+    hfe, lib = _lib()
+    g = hfe._grid((8, 8, 8), "q1")
+    out = ctypes.c_void_p()
+    # null workspace / misaligned workspace are rejected before any device call
+    assert lib.hfe_create(ctypes.byref(g), None, 1 << 30, None, ctypes.byref(out)) == -1
+    assert lib.hfe_create(ctypes.byref(g), ctypes.c_void_p(8), 1 << 30, None, ctypes.byref(out)) == -1
+    # too small a workspace
+    assert lib.hfe_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == -2
+    assert lib.hfe_last_error(None) == b"null context"
