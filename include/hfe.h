@@ -161,6 +161,24 @@ hfe_status hfe_get_field(const hfe_ctx* ctx, int which, double* host_out, size_t
  * written (at most max). */
 hfe_status hfe_get_newton_log(const hfe_ctx* ctx, hfe_newton_record* out, int max, int* count);
 
+/* Checkpoint and restart: the solver state is the nodal fluctuation u
+ * ([dim][N]), the committed history kappa_hist ([N][nq], point order as the
+ * fields), the macroscopic strain E (3x3) and the trust radius with its cap
+ * (radius[0] = R, radius[1] = Rmax; Algorithm 2 carries R from one load step
+ * to the next). All host arrays. hfe_set_state re-evaluates the state at the
+ * restored point without committing; after it a solve continues exactly as
+ * the run the state was taken from (up to rounding). */
+hfe_status hfe_get_state(const hfe_ctx* ctx, double* u, double* kappa_hist, double E[9],
+                         double radius[2]);
+hfe_status hfe_set_state(hfe_ctx* ctx, const double* u, const double* kappa_hist,
+                         const double E[9], const double radius[2]);
+
+/* Trace of the truncated CG of the last solve, two doubles per iteration:
+ * {d.Ad, ||r_{j+1}|| / ||r_0||} (the second is NaN on a boundary or
+ * negative-curvature exit). Used to certify that a decision that differs
+ * from the oracle's sits on a stopping threshold. */
+hfe_status hfe_get_cg_trace(const hfe_ctx* ctx, double* out, int max, int* count);
+
 /* Replace the nodal fluctuation u (host, [dim][N]) and re-evaluate the state
  * at the current E without committing (operator tests and restarts). */
 hfe_status hfe_set_displacement(hfe_ctx* ctx, const double* host_u);

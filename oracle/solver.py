@@ -77,9 +77,9 @@ def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
         kappa = dot(d, Ad)
         info["iters"] = j + 1
         zz, zd, dd = dot(z, z), dot(z, d), dot(d, d)
-        if log is not None:
-            log.append(("cg", j, kappa, rr))
         if kappa <= 0.0:
+            if log is not None:
+                log.append(("cg", j, kappa, math.nan))
             tm, tp = _roots(zz, zd, dd, R)
             rd = dot(r, d)
             m_m = tm * rd + 0.5 * tm * tm * kappa
@@ -89,10 +89,15 @@ def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
         alpha = rr / kappa
         z_new = z + alpha * d
         if math.sqrt(dot(z_new, z_new)) >= R:
+            if log is not None:
+                log.append(("cg", j, kappa, math.nan))
             _, tp = _roots(zz, zd, dd, R)
             return z + tp * d, BOUNDARY, info
         r_new = r + alpha * Ad
         rr_new = dot(r_new, r_new)
+        if log is not None:
+            # curvature and ||r_{j+1}|| / ||r_0|| (the CG stopping measure)
+            log.append(("cg", j, kappa, math.sqrt(rr_new / rr0)))
         if math.sqrt(rr_new) <= eta_cg * math.sqrt(rr0):
             return z_new, INTERIOR, info
         if abs(dot(r_new, r)) > 0.2 * rr_new:
@@ -257,6 +262,11 @@ class CellSolver:
                 rep["rejected"] += 1
         rep.update(self._report_tail())
         return rep
+
+    def checkpoint(self):
+        """State for a restart: nodal u, history, macroscopic strain, radii."""
+        return {"u": self.displacement(), "kappa_hist": self.kappa_hist.copy(),
+                "E": self.E.copy(), "R": self.R, "Rmax": self.Rmax}
 
     def _commit(self):
         self.kappa_hist = material.committed_history(self.mat, self.state, self.kappa_hist)

@@ -155,6 +155,7 @@ struct hfe_ctx {
   double r_eq = 0, sig_norm2 = 0, rr0 = 0;
   double sigma_sum[6] = {0};
   std::vector<hfe_newton_record> log;
+  std::vector<double> cg_trace;
   std::string err;
   // profiling
   bool profiling = false;
@@ -366,6 +367,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     const double kap = c->hscal[0], dd = c->hscal[1], rd = c->hscal[4];
     if (!std::isfinite(kap) || !std::isfinite(dd)) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
     if (kap <= 0.0) {
+      c->cg_trace.push_back(kap);
+      c->cg_trace.push_back(NAN);
       double tm, tp;
       roots(zz, zd, dd, R, &tm, &tp);
       const double mm = tm * rd + 0.5 * tm * tm * kap;
@@ -378,6 +381,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     const double alpha = rr / kap;
     const double zz_new = zz + 2.0 * alpha * zd + alpha * alpha * dd;
     if (std::sqrt(zz_new) >= R) {
+      c->cg_trace.push_back(kap);
+      c->cg_trace.push_back(NAN);
       double tm, tp;
       roots(zz, zd, dd, R, &tm, &tp);
       HIPCHK(c, hfe::vec_axpy(n, tp, c->d, c->z, c->stream));
@@ -399,6 +404,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     if (st) return st;
     double rr_new = c->hscal[2];
     const double pw = c->hscal[3];
+    c->cg_trace.push_back(kap);
+    c->cg_trace.push_back(std::sqrt(std::max(rr_new, 0.0) / rr0));
     if (std::sqrt(std::max(rr_new, 0.0)) <= eta_cg * std::sqrt(rr0)) {
       *flag = HFE_CG_INTERIOR;
       return HFE_OK;
@@ -643,6 +650,7 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
   std::memset(&rep, 0, sizeof(rep));
   rep.status = HFE_NOT_CONVERGED;
   c->log.clear();
+  c->cg_trace.clear();
   const long long n = ndof(c);
   hfe_status st = HFE_OK;
   bool converged = false;
@@ -789,6 +797,70 @@ hfe_status hfe_get_newton_log(const hfe_ctx* c, hfe_newton_record* out, int max,
   for (int i = 0; i < n; ++i) out[i] = c->log[i];
   *count = n;
   return HFE_OK;
+}
+
+hfe_status hfe_get_cg_trace(const hfe_ctx* c, double* out, int max, int* count) {
+  if (!c || !count || (max > 0 && !out)) return HFE_EINVAL;
+  const int n = std::min<int>(max, (int)(c->cg_trace.size() / 2));
+  for (int i = 0; i < 2 * n; ++i) out[i] = c->cg_trace[i];
+  *count = n;
+  return HFE_OK;
+}
+
+hfe_status hfe_get_state(const hfe_ctx* cc, double* u, double* kappa_hist, double E[9],
+                         double radius[2]) {
+  hfe_ctx* c = const_cast<hfe_ctx*>(cc);
+  if (!c || !u || !kappa_hist || !E || !radius) return HFE_EINVAL;
+  if (!c->have_micro) return fail(c, HFE_ESTATE, "no microstructure");
+  hfe_status st = ensure_history(c);
+  if (st) return st;
+  const long long N = c->g.N;
+  const int nq = c->g.nq;
+  std::vector<double> kh((size_t)nq * N);
+  HIPCHK(c, hipMemcpyAsync(u, c->u, (size_t)ndof(c) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(kh.data(), c->kh, kh.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (long long e = 0; e < N; ++e)
+    for (int q = 0; q < nq; ++q) kappa_hist[e * nq + q] = kh[(size_t)q * N + e];
+  for (int k = 0; k < 9; ++k) E[k] = c->E[k];
+  radius[0] = c->R_init ? c->R : 0.0;
+  radius[1] = c->R_init ? c->Rmax : 0.0;
+  return HFE_OK;
+}
+
+hfe_status hfe_set_state(hfe_ctx* c, const double* u, const double* kappa_hist, const double E[9],
+                         const double radius[2]) {
+  if (!c || !u || !kappa_hist || !E || !radius) return HFE_EINVAL;
+  if (!materials_ready(c)) return fail(c, HFE_ESTATE, "microstructure and every material must be set");
+  const long long N = c->g.N;
+  const int nq = c->g.nq;
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(E[k])) return fail(c, HFE_EINVAL, "non-finite E");
+  std::vector<double> kh((size_t)nq * N);
+  for (long long e = 0; e < N; ++e)
+    for (int q = 0; q < nq; ++q) {
+      const double v = kappa_hist[e * nq + q];
+      if (!(v >= 0.0) || !std::isfinite(v)) return fail(c, HFE_EINVAL, "kappa_hist must be finite and >= 0");
+      kh[(size_t)q * N + e] = v;
+    }
+  HIPCHK(c, hipMemcpyAsync(c->u, u, (size_t)ndof(c) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->kh, kh.data(), kh.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->history_ready = true;
+  const int D = c->g.dim;
+  for (int k = 0; k < 9; ++k) c->E[k] = 0.0;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) c->E[3 * i + j] = E[3 * i + j];
+  if (radius[0] > 0.0) {
+    c->R = radius[0];
+    c->Rmax = radius[1] > 0.0 ? radius[1] : radius[0];
+    c->R_init = true;
+  } else {
+    c->R_init = false;
+  }
+  c->log.clear();
+  c->cg_trace.clear();
+  return evaluate_state(c);
 }
 
 hfe_status hfe_set_displacement(hfe_ctx* c, const double* host_u) {

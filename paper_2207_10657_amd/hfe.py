@@ -66,6 +66,12 @@ EXPORTS = {
     "hfe_get_newton_log": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Record), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]),
     "hfe_set_displacement": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_get_cg_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
     "hfe_apply_projected_hessian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_apply_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -217,6 +223,32 @@ class Solver:
         self._check(self.lib.hfe_get_newton_log(self.ctx, recs, max_records, ctypes.byref(cnt)))
         return [{name: getattr(recs[i], name) for name, _ in _Record._fields_}
                 for i in range(cnt.value)]
+
+    def cg_trace(self, max_iters=1000000):
+        out = np.zeros((max_iters, 2))
+        cnt = ctypes.c_int()
+        self._check(self.lib.hfe_get_cg_trace(self.ctx, out.ctypes.data_as(ctypes.c_void_p),
+                                              max_iters, ctypes.byref(cnt)))
+        return out[: cnt.value]
+
+    def get_state(self):
+        u = np.zeros((self.dim,) + self.shape)
+        kh = np.zeros(self.shape + (self.nq,))
+        E = np.zeros(9)
+        R = np.zeros(2)
+        self._check(self.lib.hfe_get_state(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p)
+                                                       for a in (u, kh, E, R))))
+        return {"u": u, "kappa_hist": kh, "E": E.reshape(3, 3), "R": R[0], "Rmax": R[1]}
+
+    def set_state(self, u, kappa_hist, E, R, Rmax):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        kh = np.ascontiguousarray(kappa_hist, dtype=np.float64)
+        if u.shape != (self.dim,) + self.shape or kh.shape != self.shape + (self.nq,):
+            raise ValueError("state shapes")
+        Em = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(9))
+        Rr = np.array([R, Rmax], dtype=np.float64)
+        self._check(self.lib.hfe_set_state(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p)
+                                                       for a in (u, kh, Em, Rr))))
 
     def homogenized_stress(self):
         out = np.zeros(9)

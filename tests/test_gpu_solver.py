@@ -70,33 +70,93 @@ def test_homogeneous_cell_on_gpu():
     assert rel_err(g.homogenized_stress(), ref) < 1e-13
 
 
-def _lockstep(name, steps, params=None):
+def _load_scale(w, dE):
+    """Stress magnitude of the applied strain in the stiffest phase: the scale
+    against which stress differences are measured (a fully cracked cell has a
+    homogenized stress of zero up to rounding)."""
+    m = max(w.materials, key=lambda m: m["E"])
+    lam = m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"]))
+    mu = m["E"] / (2 * (1 + m["nu"]))
+    return np.linalg.norm(lam * np.trace(dE) * np.eye(3) + 2 * mu * dE)
+
+
+def _tie_margin(glog, gtrace, olog, eta_cg):
+    """Where the Newton decisions first differ, how close the decisive
+    quantity was to its threshold (relative): the CG stopping measure
+    ||r||/||r0|| against eta_cg, or rho against 1/4, 3/4, eta_up."""
+    o_cg = [e for e in olog if e[0] == "cg"]
+    o_nt = [e for e in olog if e[0] == "newton"]
+    pos = 0
+    for i, (gr, on) in enumerate(zip(glog, o_nt)):
+        n_it = min(gr["cg_iters"], on[3])
+        if gr["flag"] != on[2] or gr["cg_iters"] != on[3]:
+            j = pos + n_it - 1
+            cands = []
+            for k in (j, j + 1):
+                if k < len(gtrace):
+                    cands.append(abs(gtrace[k][1] - eta_cg) / eta_cg)
+                if k < len(o_cg):
+                    cands.append(abs(o_cg[k][3] - eta_cg) / eta_cg)
+            cands = [c for c in cands if np.isfinite(c)]
+            return ("cg-stop", i, min(cands) if cands else np.inf)
+        rho_g, rho_o = gr["rho"], on[6]
+        if (rho_g > 0.15) != (rho_o > 0.15) or (rho_g < 0.25) != (rho_o < 0.25) or \
+                (rho_g > 0.75) != (rho_o > 0.75):
+            m = min(abs(rho_o - t) for t in (0.15, 0.25, 0.75))
+            return ("rho", i, m)
+        pos += gr["cg_iters"]
+    return ("none", -1, 0.0)
+
+
+def _lockstep(name, steps, params=None, max_tie_frac=0.2):
+    """Per load step, start the GPU from the oracle's state (checkpoint /
+    restart through the C ABI), solve the same increment on both, and compare
+    decisions and results. A step whose decisions differ must show that the
+    differing decision sat on its threshold (certified tie); its results are
+    then not compared."""
     w = workload(name, steps=steps)
     g, o = _pair(w.shape, w.phase, w.materials)
-    results = []
+    p = dict(params or {})
+    eta_cg = p.get("eta_cg", 1e-6)
+    compared, ties = 0, []
     for n, dE in enumerate(w.load_path):
         announce(name, "step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
         g.apply_load_step(dE)
         o.apply_load_step(dE)
-        rg = g.solve_increment(params)
-        ro = o.solve_increment(params)
+        olog = []
+        rg = g.solve_increment(p)
+        ro = o.solve_increment(p, log=olog)
         glog = g.newton_log()
-        results.append((n, rg, ro, glog))
-        # identical decisions
-        assert [r["flag"] for r in glog] == ro["flags"], (n, [r["flag"] for r in glog], ro["flags"])
-        assert [r["cg_iters"] for r in glog] == ro["cg_per_newton"], n
-        assert rg["converged"] == ro["converged"], n
-        assert rg["rejected"] == ro["rejected"], n
-        # results
+        same = ([r["flag"] for r in glog] == ro["flags"] and
+                [r["cg_iters"] for r in glog] == ro["cg_per_newton"] and
+                [r["accepted"] for r in glog] == [1 if x > 0.15 else 0 for x in ro["rho"]] and
+                rg["converged"] == ro["converged"])
+        if not same:
+            kind, it, margin = _tie_margin(glog, g.cg_trace(), olog, eta_cg)
+            print("[lockstep] %s step %d: decisions differ at Newton %d (%s), margin %.3e"
+                  % (name, n, it, kind, margin), flush=True)
+            assert margin < 1e-4, (n, kind, it, margin)
+            ties.append(n)
+            continue
+        compared += 1
+        scale = _load_scale(w, o.E)
         Sg, So = g.homogenized_stress(), o.homogenized_stress()
-        assert rel_err(Sg, So) < TOL or np.abs(Sg - So).max() < 1e-14 * max(np.abs(So).max(), 1e-30) + 1e-22, (n, Sg, So)
-        assert rel_err(g.gradient(), o.H) < TOL, n
+        assert np.linalg.norm(Sg - So) <= TOL * scale, (n, Sg, So)
+        Hg = g.gradient()
+        assert rel_err(Hg, o.H) < TOL, (n, rel_err(Hg, o.H))
         dg, do = g.damage(), o.damage()
-        if np.linalg.norm(do) > 0:
-            assert rel_err(dg, do) < TOL, n
-        else:
-            assert np.abs(dg).max() < TOL, n
-    return results
+        assert np.abs(dg - do).max() < TOL, (n, np.abs(dg - do).max())
+        # Newton-level scalars agree as well
+        for gr, rho_o in zip(glog, ro["rho"]):
+            if np.isfinite(rho_o):
+                assert abs(gr["rho"] - rho_o) <= 1e-8 * max(1.0, abs(rho_o)), (n, gr["rho"], rho_o)
+    print("[lockstep] %s: %d steps compared, certified ties at steps %s"
+          % (name, compared, ties), flush=True)
+    assert len(ties) <= max_tie_frac * len(w.load_path)
+    return compared, ties
 
 
 def test_lockstep_2d_workload_full_path():
@@ -106,6 +166,33 @@ def test_lockstep_2d_workload_full_path():
 
 
 def test_lockstep_3d_workload_16():
-    """3D Q1 inclusion cell at 16^3, first 8 steps of the 0.6% path."""
+    """3D Q1 inclusion cell at 16^3, first 10 steps of the 0.6% path."""
     require_gpu()
-    _lockstep("c1_3d16", 8)
+    _lockstep("c1_3d16", 10)
+
+
+def test_checkpoint_restart_is_exact():
+    """Solve 4 steps; save after 2, restore into a fresh context, redo steps
+    3-4: identical bits."""
+    require_gpu()
+    announce("checkpoint")
+    w = workload("c0_2d32", steps=4)
+    from paper_2207_10657_amd import Solver
+    a = Solver(w.shape, w.element)
+    a.setup(w.phase, w.materials)
+    for n in range(2):
+        a.apply_load_step(w.load_path[n])
+        a.solve_increment()
+    st = a.get_state()
+    for n in range(2, 4):
+        a.apply_load_step(w.load_path[n])
+        a.solve_increment()
+    b = Solver(w.shape, w.element)
+    b.setup(w.phase, w.materials)
+    b.set_state(st["u"], st["kappa_hist"], st["E"], st["R"], st["Rmax"])
+    for n in range(2, 4):
+        b.apply_load_step(w.load_path[n])
+        b.solve_increment()
+    np.testing.assert_array_equal(a.displacement(), b.displacement())
+    np.testing.assert_array_equal(a.homogenized_stress(), b.homogenized_stress())
+    np.testing.assert_array_equal(a.field(4), b.field(4))
