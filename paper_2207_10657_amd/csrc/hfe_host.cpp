@@ -34,6 +34,8 @@ using hfe::Grid;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kTraceCap = 1 << 16;    // CG trace entries kept per solve
+constexpr int kCgBatch = 8;           // CG iterations enqueued between host polls
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -43,7 +45,9 @@ struct Layout {
   size_t phase;                                       // N bytes
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
-  size_t scal;                                        // 64 doubles
+  size_t counter;                                     // reduction ticket counters
+  size_t cgstate;                                     // device CgState
+  size_t trace;                                       // CG trace, 2 doubles per entry
   size_t tw;                                          // twiddles
   size_t stab;                                        // sin^2 tables
   size_t total;
@@ -100,7 +104,9 @@ Layout make_layout(const Grid& g) {
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
-  L.scal = take(64 * sizeof(double));
+  L.counter = take(16 * sizeof(unsigned int));
+  L.cgstate = take(sizeof(hfe::CgState));
+  L.trace = take((size_t)2 * kTraceCap * sizeof(double));
   L.n_tw = g.nx / 2 + g.ny + g.nz + (g.nx / 2 + 1);
   L.tw = take((size_t)L.n_tw * sizeof(double2));
   L.n_stab = (g.nx / 2 + 1) + g.ny + g.nz;
@@ -141,9 +147,13 @@ struct hfe_ctx {
   uint8_t* phase;
   double2* spec;
   double* partials;
-  double* scal;
+  unsigned int* counter;
+  hfe::CgState* cg;          // device CG state
+  double* trace;             // device CG trace
   hfe::FftTables tabs;
-  double* hscal = nullptr;  // pinned host mirror of scal
+  double* hscal = nullptr;   // pinned, device-mapped: reduction totals land here
+  double* dscal = nullptr;   // device alias of hscal
+  hfe::CgState* hcg = nullptr;  // pinned host copy of the CG state
   // host state
   hfe::MatTable mat;
   bool mat_set[hfe::kMaxPhases] = {};
@@ -234,12 +244,18 @@ void prof_drain(hfe_ctx* c) {
   c->pending.clear();
 }
 
-hfe_status sync_read(hfe_ctx* c, int first, int count) {
-  HIPCHK(c, hipMemcpyAsync(c->hscal + first, c->scal + first, count * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream));
+// Wait for the stream; reduction totals are then visible in hscal.
+hfe_status sync(hfe_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->profiling) prof_drain(c);
   return HFE_OK;
+}
+
+hfe::Reducer reducer(hfe_ctx* c) {
+  hfe::Reducer r;
+  r.partials = c->partials;
+  r.counter = c->counter;
+  return r;
 }
 
 hfe::ElemArgs elem_args(hfe_ctx* c) {
@@ -256,45 +272,61 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.u = c->u;
   A.v = nullptr;
   A.f = nullptr;
-  A.partials = c->partials;
+  A.red = reducer(c);
+  A.out = nullptr;
+  A.cg = nullptr;
+  A.trace = nullptr;
   return A;
 }
 
 long long ndof(const hfe_ctx* c) { return (long long)c->g.dim * c->g.N; }
 
-// y = L^+ x
-hfe_status green(hfe_ctx* c, const double* x, double* y) {
+// Offsets of the reduction totals in hscal.
+enum { S_HES = 0, S_RES = 8, S_RR0 = 16, S_TRI = 24, S_DOT = 40 };
+
+// y = L^+ x (the passes are skipped once skip->done is set)
+hfe_status green(hfe_ctx* c, const double* x, double* y, const hfe::CgState* skip = nullptr) {
   if (c->g.dim == 2) {
     Prof p(c, "fft_green2d");
-    HIPCHK(c, hfe::fft_plane_green2d(c->g, c->tabs, x, y, c->spec, c->stream));
+    HIPCHK(c, hfe::fft_plane_green2d(c->g, c->tabs, x, y, c->spec, c->stream, skip));
     return HFE_OK;
   }
   {
     Prof p(c, "fft_plane_fwd");
-    HIPCHK(c, hfe::fft_plane_forward(c->g, c->tabs, x, c->spec, c->stream));
+    HIPCHK(c, hfe::fft_plane_forward(c->g, c->tabs, x, c->spec, c->stream, skip));
   }
   {
     Prof p(c, "fft_pencil_green");
-    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream));
+    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream, skip));
   }
   {
     Prof p(c, "fft_plane_inv");
-    HIPCHK(c, hfe::fft_plane_inverse(c->g, c->tabs, c->spec, y, c->stream));
+    HIPCHK(c, hfe::fft_plane_inverse(c->g, c->tabs, c->spec, y, c->stream, skip));
   }
   return HFE_OK;
 }
 
-// out = K v at the current state; dots (d.Kd, |Dd|^2) reduced into scal[off..off+1]
-hfe_status stiffness(hfe_ctx* c, const double* v, double* out, int off) {
+// out = K v at the current state. Totals (d.Kd, |Dd|^2) to hscal[S_HES..], or,
+// inside the CG, the curvature decision on the device state.
+hfe_status stiffness(hfe_ctx* c, const double* v, double* out, bool in_cg) {
   hfe::ElemArgs A = elem_args(c);
   A.v = v;
   A.f = out;
-  int nb = 0;
-  {
-    Prof p(c, "stiffness");
-    HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
+  if (in_cg) {
+    A.cg = c->cg;
+    A.trace = c->trace;
+  } else {
+    A.out = c->dscal + S_HES;
   }
-  HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::HES_NV, c->scal + off, c->stream));
+  Prof p(c, "stiffness");
+  HIPCHK(c, hfe::launch_hessian(A, c->stream));
+  return HFE_OK;
+}
+
+// x . y into hscal[slot] (device alias), or into a device address
+hfe_status dot(hfe_ctx* c, const double* x, const double* y, double* dev_out) {
+  Prof p(c, "cg_vec");
+  HIPCHK(c, hfe::vec_dot(ndof(c), x, y, reducer(c), dev_out, c->stream));
   return HFE_OK;
 }
 
@@ -304,22 +336,21 @@ hfe_status evaluate_state(hfe_ctx* c) {
   A.a_out = c->a;
   A.cp_out = c->cp;
   A.f = c->g0;
-  int nb = 0;
+  A.out = c->dscal + S_RES;
   {
     Prof p(c, "residual");
-    HIPCHK(c, hfe::launch_residual(A, c->stream, &nb));
+    HIPCHK(c, hfe::launch_residual(A, c->stream));
   }
-  HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::RES_NV, c->scal + 16, c->stream));
   hfe_status st = green(c, c->g0, c->y0);
   if (st) return st;
-  HIPCHK(c, hfe::vec_dot(ndof(c), c->y0, c->g0, c->partials, c->stream, &nb));
-  HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 24, c->stream));
-  st = sync_read(c, 16, 9);
+  st = dot(c, c->y0, c->g0, c->dscal + S_RR0);
+  if (st) return st;
+  st = sync(c);
   if (st) return st;
   const double* h = c->hscal;
-  for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[16 + k];
-  c->sig_norm2 = h[16 + hfe::RES_SS];
-  c->rr0 = h[24];
+  for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[S_RES + k];
+  c->sig_norm2 = h[S_RES + hfe::RES_SS];
+  c->rr0 = h[S_RR0];
   if (!std::isfinite(c->rr0) || !std::isfinite(c->sig_norm2))
     return fail(c, HFE_ENUMERIC, "non-finite stress or residual");
   c->r_eq = c->sig_norm2 > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(c->sig_norm2) : 0.0;
@@ -327,123 +358,104 @@ hfe_status evaluate_state(hfe_ctx* c) {
   return HFE_OK;
 }
 
-void roots(double zz, double zd, double dd, double R, double* tm, double* tp) {
-  const double b = 2.0 * zd, cc = zz - R * R;
-  const double disc = std::sqrt(std::max(b * b - 4.0 * dd * cc, 0.0));
-  const double qq = -0.5 * (b + std::copysign(disc, b));
-  const double t1 = qq / dd;
-  const double t2 = qq != 0.0 ? cc / qq : -t1;
-  *tm = std::min(t1, t2);
-  *tp = std::max(t1, t2);
-}
-
 struct CgInfo { int iters = 0, restarts = 0, matvecs = 0; };
+
+// One CG iteration, all decisions on the device (no host synchronisation).
+hfe_status cg_iteration(hfe_ctx* c) {
+  const long long n = ndof(c);
+  hfe_status st = stiffness(c, c->d, c->Kd, true);
+  if (st) return st;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_zg(n, c->d, c->Kd, c->z, c->gv, c->cg, c->stream));
+  }
+  st = green(c, c->Kd, c->w, c->cg);
+  if (st) return st;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_y(n, c->w, c->y, c->gv, reducer(c), c->cg, c->trace, c->stream));
+  }
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
+  }
+  return HFE_OK;
+}
 
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
 hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, CgInfo* info) {
   const long long n = ndof(c);
   const size_t bytes = (size_t)n * sizeof(double);
   HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
+  *flag = HFE_CG_INTERIOR;
+  if (c->rr0 == 0.0) return HFE_OK;
   HIPCHK(c, hipMemcpyAsync(c->gv, c->g0, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->y, c->y0, bytes, hipMemcpyDeviceToDevice, c->stream));
-  const double rr0 = c->rr0;
-  double rr = rr0;
-  *flag = HFE_CG_INTERIOR;
-  if (rr0 == 0.0) return HFE_OK;
-  int nb = 0;
+  hfe::CgState init;
+  std::memset(&init, 0, sizeof(init));
+  init.rr = init.rr0 = init.rr_new = c->rr0;
+  init.R = R;
+  init.eta_cg = eta_cg;
+  init.jmax = j_max;
+  init.flag = hfe::CG_RUN;
+  init.trace_cap = kTraceCap;
+  *c->hcg = init;
+  HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
+  // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0
   {
     Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_d(n, 0.0, c->y, c->d, c->gv, c->z, c->partials, c->stream, &nb));
+    HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
   }
-  HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 4, c->stream));
-  double zz = 0.0, zd = 0.0;
-  for (int j = 0; j < j_max; ++j) {
-    hfe_status st = stiffness(c, c->d, c->Kd, 0);
-    if (st) return st;
-    info->matvecs += 1;
-    info->iters = j + 1;
-    st = sync_read(c, 0, 6);
-    if (st) return st;
-    const double kap = c->hscal[0], dd = c->hscal[1], rd = c->hscal[4];
-    if (!std::isfinite(kap) || !std::isfinite(dd)) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
-    if (kap <= 0.0) {
-      c->cg_trace.push_back(kap);
-      c->cg_trace.push_back(NAN);
-      double tm, tp;
-      roots(zz, zd, dd, R, &tm, &tp);
-      const double mm = tm * rd + 0.5 * tm * tm * kap;
-      const double mp = tp * rd + 0.5 * tp * tp * kap;
-      const double tau = mm < mp ? tm : tp;
-      HIPCHK(c, hfe::vec_axpy(n, tau, c->d, c->z, c->stream));
-      *flag = HFE_CG_NEGCURV;
-      return HFE_OK;
-    }
-    const double alpha = rr / kap;
-    const double zz_new = zz + 2.0 * alpha * zd + alpha * alpha * dd;
-    if (std::sqrt(zz_new) >= R) {
-      c->cg_trace.push_back(kap);
-      c->cg_trace.push_back(NAN);
-      double tm, tp;
-      roots(zz, zd, dd, R, &tm, &tp);
-      HIPCHK(c, hfe::vec_axpy(n, tp, c->d, c->z, c->stream));
-      *flag = HFE_CG_BOUNDARY;
-      return HFE_OK;
-    }
-    {
-      Prof p(c, "cg_vec");
-      HIPCHK(c, hfe::cg_step_zg(n, alpha, c->d, c->Kd, c->z, c->gv, c->stream));
-    }
-    st = green(c, c->Kd, c->w);
-    if (st) return st;
-    {
-      Prof p(c, "cg_vec");
-      HIPCHK(c, hfe::cg_step_y(n, alpha, c->w, c->y, c->gv, c->partials, c->stream, &nb));
-    }
-    HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 2, c->stream));
-    st = sync_read(c, 2, 2);
-    if (st) return st;
-    double rr_new = c->hscal[2];
-    const double pw = c->hscal[3];
-    c->cg_trace.push_back(kap);
-    c->cg_trace.push_back(std::sqrt(std::max(rr_new, 0.0) / rr0));
-    if (std::sqrt(std::max(rr_new, 0.0)) <= eta_cg * std::sqrt(rr0)) {
-      *flag = HFE_CG_INTERIOR;
-      return HFE_OK;
-    }
-    double beta;
-    if (std::fabs(pw) > 0.2 * rr_new) {
-      // restart: true residual at the new iterate, steepest-descent direction
-      st = stiffness(c, c->z, c->tmp, 8);
+  int restarts = 0;
+  int batch = 2;
+  for (;;) {
+    for (int k = 0; k < batch; ++k) {
+      hfe_status st = cg_iteration(c);
       if (st) return st;
-      info->matvecs += 1;
-      info->restarts += 1;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
+    hfe_status st = sync(c);
+    if (st) return st;
+    const hfe::CgState h = *c->hcg;
+    if (!h.done) {
+      batch = std::min(batch * 2, kCgBatch);
+      continue;
+    }
+    if (h.flag == hfe::CG_NUMERIC) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
+    if (h.restart) {
+      // Powell's test: recompute the true residual at the new iterate and
+      // restart along steepest descent (beta = 0)
+      restarts += 1;
+      st = stiffness(c, c->z, c->tmp, false);
+      if (st) return st;
       HIPCHK(c, hfe::vec_axpy_to(n, c->tmp, 1.0, c->g0, c->gv, c->stream));
       st = green(c, c->gv, c->y);
       if (st) return st;
-      HIPCHK(c, hfe::vec_dot(n, c->y, c->gv, c->partials, c->stream, &nb));
-      HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 2, c->stream));
-      st = sync_read(c, 2, 1);
+      st = dot(c, c->y, c->gv, &c->cg->rr_new);
       if (st) return st;
-      rr_new = c->hscal[2];
-      beta = 0.0;
-    } else {
-      beta = rr_new / rr;
+      HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
+      {
+        Prof p(c, "cg_vec");
+        HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
+      }
+      batch = 2;
+      continue;
     }
-    const double zd_old_dir = zd + alpha * dd;  // <z_{j+1}, d_j>
-    {
-      Prof p(c, "cg_vec");
-      HIPCHK(c, hfe::cg_step_d(n, beta, c->y, c->d, c->gv, c->z, c->partials, c->stream, &nb));
+    info->iters = h.iters;
+    info->restarts = restarts;
+    info->matvecs = h.iters + restarts;
+    *flag = h.flag;
+    // keep the trace of this solve
+    const int nt = std::min(h.ntrace, kTraceCap);
+    if (nt > 0) {
+      const size_t off = c->cg_trace.size();
+      c->cg_trace.resize(off + 2 * (size_t)nt);
+      HIPCHK(c, hipMemcpyAsync(c->cg_trace.data() + off, c->trace, 2 * (size_t)nt * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    HIPCHK(c, hfe::reduce_partials(c->partials, nb, 2, c->scal + 4, c->stream));
-    st = sync_read(c, 4, 2);
-    if (st) return st;
-    const double zg = c->hscal[5];
-    zd = -zg + beta * zd_old_dir;
-    zz = zz_new;
-    rr = rr_new;
+    return HFE_OK;
   }
-  *flag = HFE_CG_MAXITER;
-  return HFE_OK;
 }
 
 hfe_status commit(hfe_ctx* c) {
@@ -514,7 +526,9 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
-  c->scal = D(L.scal);
+  c->counter = (unsigned int*)(c->ws + L.counter);
+  c->cg = (hfe::CgState*)(c->ws + L.cgstate);
+  c->trace = D(L.trace);
   std::memset(&c->mat, 0, sizeof(c->mat));
   // FFT tables
   std::vector<double2> tw;
@@ -537,7 +551,10 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs.sx = dst;
   c->tabs.sy = dst + (M + 1);
   c->tabs.sz = dst + (M + 1) + g.ny;
-  hipError_t e = hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&c->hscal, 64 * sizeof(double),
+                               hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dscal, c->hscal, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hcg, sizeof(hfe::CgState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream);
@@ -546,6 +563,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     if (c->hscal) hipHostFree(c->hscal);
+    if (c->hcg) hipHostFree(c->hcg);
     delete c;
     return HFE_EDEVICE;
   }
@@ -562,6 +580,7 @@ hfe_status hfe_destroy(hfe_ctx* c) {
   }
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->hscal) hipHostFree(c->hscal);
+  if (c->hcg) hipHostFree(c->hcg);
   delete c;
   return HFE_OK;
 }
@@ -674,15 +693,15 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       A.a_out = c->at;
       A.cp_out = c->cpt;
       A.f = c->gt;
-      int nb = 0;
+      A.out = c->dscal + S_TRI;
       {
         Prof pr(c, "trial");
-        HIPCHK(c, hfe::launch_trial(A, c->stream, &nb));
+        HIPCHK(c, hfe::launch_trial(A, c->stream));
       }
-      HIPCHK(c, hfe::reduce_partials(c->partials, nb, hfe::TRI_NV, c->scal + 32, c->stream));
-      st = sync_read(c, 32, hfe::TRI_NV);
+      st = sync(c);
       if (st) return st;
-      const double* h = c->hscal + 32;
+      double h[hfe::TRI_NV];
+      for (int k = 0; k < hfe::TRI_NV; ++k) h[k] = c->hscal[S_TRI + k];
       const double sp = h[hfe::TRI_SP], pbp = h[hfe::TRI_PBP], stp = h[hfe::TRI_STP];
       const double dm = sp + 0.5 * pbp;
       const double dW = 0.5 * (sp + stp);
@@ -713,11 +732,11 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
         c->sig_norm2 = ss;
         st = green(c, c->g0, c->y0);
         if (st) return st;
-        HIPCHK(c, hfe::vec_dot(n, c->y0, c->g0, c->partials, c->stream, &nb));
-        HIPCHK(c, hfe::reduce_partials(c->partials, nb, 1, c->scal + 24, c->stream));
-        st = sync_read(c, 24, 1);
+        st = dot(c, c->y0, c->g0, c->dscal + S_RR0);
         if (st) return st;
-        c->rr0 = c->hscal[24];
+        st = sync(c);
+        if (st) return st;
+        c->rr0 = c->hscal[S_RR0];
         c->r_eq = ss > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(ss) : 0.0;
         const double r_nr = hh > 0.0 ? std::sqrt(pp) / std::sqrt(hh) : 0.0;
         rep.r_nr = r_nr;
@@ -875,15 +894,15 @@ hfe_status hfe_set_displacement(hfe_ctx* c, const double* host_u) {
 hfe_status hfe_apply_projected_hessian(hfe_ctx* c, const double* in, double* out, double dots[2]) {
   if (!c || !in || !out || in == out) return HFE_EINVAL;
   if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
-  hfe_status st = stiffness(c, in, c->Kd, 0);
+  hfe_status st = stiffness(c, in, c->Kd, false);
   if (st) return st;
   st = green(c, c->Kd, out);
   if (st) return st;
   if (dots) {
-    st = sync_read(c, 0, 2);
+    st = sync(c);
     if (st) return st;
-    dots[0] = c->hscal[0];
-    dots[1] = c->hscal[1];
+    dots[0] = c->hscal[S_HES];
+    dots[1] = c->hscal[S_HES + 1];
   }
   return HFE_OK;
 }
@@ -891,7 +910,7 @@ hfe_status hfe_apply_projected_hessian(hfe_ctx* c, const double* in, double* out
 hfe_status hfe_apply_stiffness(hfe_ctx* c, const double* in, double* out) {
   if (!c || !in || !out || in == out) return HFE_EINVAL;
   if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
-  return stiffness(c, in, out, 0);
+  return stiffness(c, in, out, false);
 }
 
 hfe_status hfe_apply_green(hfe_ctx* c, const double* in, double* out) {

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/hfe.h"
+#include "hfe_cg.h"
 
 namespace hfe {
 
@@ -33,6 +34,13 @@ struct Macro {        // macroscopic strain E, full 3x3 row-major
   double e[9];
 };
 
+// Partial-sum rows plus a ticket counter: the last block of a reducing kernel
+// adds all rows in a fixed order and acts on the totals.
+struct Reducer {
+  double* partials;        // [blocks][nv]
+  unsigned int* counter;   // zero between kernels
+};
+
 // ---- element kernels (k_element.hip) -------------------------------------
 
 // Partial-sum layouts written by the element kernels (one row per block).
@@ -54,15 +62,19 @@ struct ElemArgs {
   const double* u;       // [dim][N]
   const double* v;       // second nodal input: z (trial) or the direction (Hessian)
   double* f;             // nodal output [dim][N]
-  double* partials;      // [blocks][nv]
+  Reducer red;
+  double* out;           // grid totals of the reductions (device or host-mapped)
+  CgState* cg;           // Hessian in a CG iteration: decide on the totals instead
+  double* trace;         // CG trace (with cg)
 };
 
-// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, sums RES_*.
-hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks);
-// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), sums TRI_*.
-hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
-// Hessian: f = D^T B D v at the state (u, a, cp), sums HES_*.
-hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, totals RES_* to out.
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s);
+// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), totals TRI_*.
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s);
+// Hessian: f = D^T B D v at the state (u, a, cp); totals HES_* to out, or, with
+// A.cg set, the curvature decision of the CG iteration (no-op once cg->done).
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s);
 // Commit: khist <- max(khist, kappa_t(E + D u)) on damage points (khist is
 // written through the const-cast pointer a_out).
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s);
@@ -88,17 +100,19 @@ bool fft_length_supported(int L);
 size_t fft_plane_lds_bytes(const Grid& g);
 // Pipeline entry points. `in`/`out` are [dim][N] doubles, `spec` is the
 // [dim][nz][ny][nx/2+1] double2 work buffer.
+// `skip` (may be null): the passes return at entry once skip->done is set.
 hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
-                       double2* spec, hipStream_t s);
+                       double2* spec, hipStream_t s, const CgState* skip = nullptr);
 // The three passes of green_apply (3D) and the single 2D pass, launched
 // separately so that each can be timed.
 hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
-                             hipStream_t s);
-hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s);
+                             hipStream_t s, const CgState* skip = nullptr);
+hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s,
+                            const CgState* skip = nullptr);
 hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
-                             hipStream_t s);
+                             hipStream_t s, const CgState* skip = nullptr);
 hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
-                             double2* spec, hipStream_t s);
+                             double2* spec, hipStream_t s, const CgState* skip = nullptr);
 hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
                        hipStream_t s);
 hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
@@ -111,20 +125,20 @@ hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipSt
 // out = x + alpha * y
 hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
                        hipStream_t s);
-// dots: partials rows of {x.y}
-hipError_t vec_dot(long long n, const double* x, const double* y, double* partials,
-                   hipStream_t s, int* nblocks);
-// CG update 1: z += alpha d ; g += alpha Kd
-hipError_t cg_step_zg(long long n, double alpha, const double* d, const double* Kd, double* z,
-                      double* g, hipStream_t s);
-// CG update 2: y_new = y + alpha w ; partials {y_new.g, y_old.g}
-hipError_t cg_step_y(long long n, double alpha, const double* w, double* y, const double* g,
-                     double* partials, hipStream_t s, int* nblocks);
-// CG update 3: d = -y + beta d ; partials {g.d, z.g}
-hipError_t cg_step_d(long long n, double beta, const double* y, double* d, const double* g,
-                     const double* z, double* partials, hipStream_t s, int* nblocks);
-// Deterministic final reduction of `nblocks` rows of `nv` partials into out[nv].
-hipError_t reduce_partials(const double* partials, int nblocks, int nv, double* out,
-                           hipStream_t s);
+// *out = x . y (fixed-order reduction)
+hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r, double* out,
+                   hipStream_t s);
+// CG, after the curvature decision: z += alpha d ; g += alpha Kd, or, when the
+// CG has just stopped on the trust-region sphere, z += tau d.
+hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z, double* g,
+                      CgState* st, hipStream_t s);
+// CG: y += alpha w, totals {y_new.g, y_old.g} -> residual decision (trace written)
+hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
+                     CgState* st, double* trace, hipStream_t s);
+// CG: d = -y + beta d, totals {g.d, z.g} -> direction decision
+hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
+                     const Reducer& r, CgState* st, hipStream_t s);
+// After the host recomputed the residual of a restart: beta = 0, run again.
+hipError_t cg_resume(CgState* st, hipStream_t s);
 
 }  // namespace hfe

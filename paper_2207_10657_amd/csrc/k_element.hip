@@ -23,6 +23,25 @@ template <int EL> struct ET;
 template <> struct ET<HFE_Q1> { static constexpr int D = 3, NQ = 8, NA = 8; };
 template <> struct ET<HFE_P1_PAIR> { static constexpr int D = 2, NQ = 2, NA = 4; };
 
+// dN_a/dx_j at the Gauss points of the Q1 element, as a table in constant
+// memory for loops over points that are not unrolled (the index is uniform
+// over the wavefront, so the values come through scalar loads).
+struct Q1Table {
+  double v[8][8][3];
+  constexpr Q1Table() : v{} {
+    for (int q = 0; q < 8; ++q)
+      for (int a = 0; a < 8; ++a) {
+        const int o0 = a & 1, o1 = (a >> 1) & 1, o2 = (a >> 2) & 1;
+        const double x0 = (q & 1) ? kG1 : kG0, x1 = (q & 2) ? kG1 : kG0, x2 = (q & 4) ? kG1 : kG0;
+        const double l0 = o0 ? x0 : 1.0 - x0, l1 = o1 ? x1 : 1.0 - x1, l2 = o2 ? x2 : 1.0 - x2;
+        v[q][a][0] = (o0 ? 1.0 : -1.0) * l1 * l2;
+        v[q][a][1] = (o1 ? 1.0 : -1.0) * l0 * l2;
+        v[q][a][2] = (o2 ? 1.0 : -1.0) * l0 * l1;
+      }
+  }
+};
+__constant__ Q1Table kQ1B = Q1Table();
+
 // dN_a/dx_j at point q of a unit element. Local node a = ax + 2 ay (+ 4 az).
 template <int EL>
 __device__ __forceinline__ double shape_grad(int q, int a, int j);
@@ -207,6 +226,7 @@ template <int EL, int MODE, int NV>
 __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
   constexpr int D = ET<EL>::D, NQ = ET<EL>::NQ, NA = ET<EL>::NA;
   const Grid& g = A.g;
+  if (MODE == MODE_HESSIAN && A.cg && A.cg->done) return;
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double acc[NV];
 #pragma unroll
@@ -368,7 +388,13 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
       acc[HES_DKD] += dk;
     }
   }
-  block_reduce_store<NV>(acc, A.partials);
+  double tot[NV];
+  if (block_reduce_last<NV>(acc, A.red, tot) && threadIdx.x == 0) {
+    if (MODE == MODE_HESSIAN && A.cg)
+      cg_decide_curvature(A.cg, A.trace, tot[HES_DKD], tot[HES_DD]);
+    else if (A.out)
+      for (int k = 0; k < NV; ++k) A.out[k] = tot[k];
+  }
 }
 
 template <int EL>
@@ -454,10 +480,190 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
   }
 }
 
+// ---- brick stiffness kernel (Q1) ---------------------------------------
+//
+// K d = D^T B D d for a block of kBx x kBy x kBz nodes. The block computes the
+// (kB+1)^3 elements whose nodes include its own (one layer of halo elements
+// on the low side of each axis, recomputed by the neighbouring block as
+// well), one element per thread, with the nodal inputs staged in LDS. The
+// element forces are added to the owned nodes in eight phases, one per local
+// node a: within a phase the map element -> node e + o_a is one-to-one, so no
+// two threads touch the same accumulator and the order of the additions is
+// fixed.
+constexpr int kBx = 8, kBy = 8, kBz = 8;
+constexpr int kTile = (kBx + 2) * (kBy + 2) * (kBz + 2);   // staged nodes
+constexpr int kOwn = kBx * kBy * kBz;                       // owned nodes
+constexpr int kBrickThreads = 768;                          // >= (kB+1)^3 = 729
+
+__global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
+  const Grid& g = A.g;
+  if (A.cg && A.cg->done) return;
+  __shared__ double sd[3][kTile];
+  __shared__ double su[3][kTile];
+  __shared__ double acc[3][kOwn];
+  __shared__ int need_u_flag;
+  const int nbx = (g.nx + kBx - 1) / kBx, nby = (g.ny + kBy - 1) / kBy;
+  const int bxi = blockIdx.x % nbx, byi = (blockIdx.x / nbx) % nby, bzi = blockIdx.x / (nbx * nby);
+  const int x0 = bxi * kBx, y0 = byi * kBy, z0 = bzi * kBz;
+  const int bx = min(kBx, g.nx - x0), by = min(kBy, g.ny - y0), bz = min(kBz, g.nz - z0);
+  const int tx = bx + 2, ty = by + 2, tz = bz + 2;          // staged node tile
+  const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;    // element brick
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) need_u_flag = 0;
+  // stage d on the node tile: local l <-> global (origin - 1 + l) mod n
+  for (int i = tid; i < tx * ty * tz; i += nt) {
+    const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
+    int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+    gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+    gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
+    const long long n = lin(g, gx, gy, gz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sd[c][i] = A.v[c * g.N + n];
+  }
+  for (int i = tid; i < bx * by * bz; i += nt) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c][i] = 0.0;
+  }
+  // this thread's element
+  const int ne = ex_n * ey_n * ez_n;
+  const bool active = tid < ne;
+  const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
+  long long eg = 0;
+  int ph = 0;
+  if (active) {
+    int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
+    gx = gx < 0 ? gx + g.nx : gx;
+    gy = gy < 0 ? gy + g.ny : gy;
+    gz = gz < 0 ? gz + g.nz : gz;
+    eg = lin(g, gx, gy, gz);
+    ph = A.phase[eg];
+    bool mine_u = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != 0.0;
+    if (mine_u) need_u_flag = 1;
+  }
+  __syncthreads();
+  const bool need_u = need_u_flag != 0;
+  if (need_u) {
+    for (int i = tid; i < tx * ty * tz; i += nt) {
+      const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
+      int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+      gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+      gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+      gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
+      const long long n = lin(g, gx, gy, gz);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) su[c][i] = A.u[c * g.N + n];
+    }
+    __syncthreads();
+  }
+  double f[3][8];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) f[i][a] = 0.0;
+  double dd_acc = 0.0;
+  if (active) {
+    const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
+    const int t0 = ex + tx * (ey + ty * ez);
+    const int sy = tx, sz = tx * ty;
+    const bool owned_elem = ex >= 1 && ey >= 1 && ez >= 1;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+      const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
+      double dH[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
+        const double v0 = sd[0][ti], v1 = sd[1][ti], v2 = sd[2][ti];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double w = kQ1B.v[q][a][j];
+          dH[0][j] += w * v0;
+          dH[1][j] += w * v1;
+          dH[2][j] += w * v2;
+        }
+      }
+      Sym s;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
+      if (cq != 0.0) {
+        double H[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) H[i][j] = A.E.e[3 * i + j];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
+          const double v0 = su[0][ti], v1 = su[1][ti], v2 = su[2][ti];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const double w = kQ1B.v[q][a][j];
+            H[0][j] += w * v0;
+            H[1][j] += w * v1;
+            H[2][j] += w * v2;
+          }
+        }
+        s = c_contract(sym_of<3>(H), lam, mu);
+      }
+      const Sym tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
+      if (owned_elem) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) dd_acc += dH[i][j] * dH[i][j];
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double w = kQ1B.v[q][a][j];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) f[i][a] += w * sym_at(tau, i, j);
+        }
+    }
+  }
+  // assembly into the owned nodes, one local node per phase
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    __syncthreads();
+    if (active) {
+      const int lx = ex + (a & 1) - 1, ly = ey + ((a >> 1) & 1) - 1, lz = ez + ((a >> 2) & 1) - 1;
+      if (lx >= 0 && lx < bx && ly >= 0 && ly < by && lz >= 0 && lz < bz) {
+        const int o = lx + bx * (ly + by * lz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][o] += f[c][a];
+      }
+    }
+  }
+  __syncthreads();
+  double dkd = 0.0;
+  for (int i = tid; i < bx * by * bz; i += nt) {
+    const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
+    const long long n = lin(g, x0 + lx, y0 + ly, z0 + lz);
+    const int ti = (lx + 1) + tx * ((ly + 1) + ty * (lz + 1));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = acc[c][i];
+      A.f[c * g.N + n] = v;
+      dkd += v * sd[c][ti];
+    }
+  }
+  double red[2] = {dkd, dd_acc};
+  double tot[2];
+  if (block_reduce_last<2>(red, A.red, tot) && threadIdx.x == 0) {
+    if (A.cg)
+      cg_decide_curvature(A.cg, A.trace, tot[HES_DKD], tot[HES_DD]);
+    else if (A.out)
+      for (int k = 0; k < 2; ++k) A.out[k] = tot[k];
+  }
+}
+
 template <int MODE, int NV>
-hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
+hipError_t launch_gather(const ElemArgs& A, hipStream_t s) {
   const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
-  if (nblocks) *nblocks = nb;
   if (A.g.element == HFE_Q1)
     hipLaunchKernelGGL((k_gather<HFE_Q1, MODE, NV>), dim3(nb), dim3(kBlock), 0, s, A);
   else
@@ -467,14 +673,17 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 
 }  // namespace
 
-hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s) {
+  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s);
 }
-hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s) {
+  return launch_gather<MODE_TRIAL, TRI_NV>(A, s);
 }
-hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s) {
+  if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s);
+  const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + kBz - 1) / kBz);
+  hipLaunchKernelGGL(k_stiffness_brick, dim3(nb), dim3(kBrickThreads), 0, s, A);
+  return hipGetLastError();
 }
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s) {
   const int nb = (int)((A.g.N + kBlock - 1) / kBlock);

@@ -226,7 +226,8 @@ enum { PLANE_FWD = 0, PLANE_INV = 1, PLANE_GREEN2D = 2 };
 template <int MODE>
 __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const double* __restrict__ in,
                                                 double* __restrict__ out, double2* __restrict__ spec,
-                                                double scale) {
+                                                double scale, const CgState* skip) {
+  if (skip && skip->done) return;
   extern __shared__ double2 lds[];
   const int nx = g.nx, ny = g.ny, M = nx / 2, P = M + 1;
   const int z = blockIdx.x, c = blockIdx.y;
@@ -273,7 +274,8 @@ enum { PENCIL_GREEN = 0, PENCIL_FWD = 1, PENCIL_INV = 2 };
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __restrict__ spec,
-                                               int C, double scale) {
+                                               int C, double scale, const CgState* skip) {
+  if (skip && skip->done) return;
   extern __shared__ double2 lds[];
   const int P = g.nx / 2 + 1, ny = g.ny, nz = g.nz;
   const int kx0 = blockIdx.x * C;
@@ -318,7 +320,7 @@ int plane_threads(const Grid& g) {
 
 template <int MODE>
 hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, double* out,
-                        double2* spec, double scale, hipStream_t s) {
+                        double2* spec, double scale, hipStream_t s, const CgState* skip = nullptr) {
   const size_t lds = fft_plane_lds_bytes(g);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE>,
@@ -326,18 +328,18 @@ hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, dou
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_plane<MODE>, dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t, in,
-                     out, spec, scale);
+                     out, spec, scale, skip);
   return hipGetLastError();
 }
 
 template <int MODE>
 hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, double scale,
-                         hipStream_t s) {
+                         hipStream_t s, const CgState* skip = nullptr) {
   const int P = g.nx / 2 + 1;
   const int nchunk = (P + kPencilC - 1) / kPencilC;
   const size_t lds = (size_t)kPencilC * g.nz * sizeof(double2);
   hipLaunchKernelGGL(k_pencil<MODE>, dim3(nchunk, g.ny, g.dim), dim3(256), lds, s, g, t, spec,
-                     kPencilC, scale);
+                     kPencilC, scale, skip);
   return hipGetLastError();
 }
 
@@ -358,32 +360,33 @@ size_t fft_plane_lds_bytes(const Grid& g) {
 }
 
 hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
-                             hipStream_t s) {
-  return launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s);
+                             hipStream_t s, const CgState* skip) {
+  return launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s, skip);
 }
 
 hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
-                             hipStream_t s) {
-  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s);
+                             hipStream_t s, const CgState* skip) {
+  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s, skip);
 }
 
-hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s) {
-  return launch_pencil<PENCIL_GREEN>(g, t, spec, 1.0 / (double)g.N, s);
+hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s,
+                            const CgState* skip) {
+  return launch_pencil<PENCIL_GREEN>(g, t, spec, 1.0 / (double)g.N, s, skip);
 }
 
 hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
-                             double2* spec, hipStream_t s) {
-  return launch_plane<PLANE_GREEN2D>(g, t, in, out, spec, 1.0 / (double)g.N, s);
+                             double2* spec, hipStream_t s, const CgState* skip) {
+  return launch_plane<PLANE_GREEN2D>(g, t, in, out, spec, 1.0 / (double)g.N, s, skip);
 }
 
 hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
-                       double2* spec, hipStream_t s) {
-  if (g.dim == 2) return fft_plane_green2d(g, t, in, out, spec, s);
-  hipError_t e = fft_plane_forward(g, t, in, spec, s);
+                       double2* spec, hipStream_t s, const CgState* skip) {
+  if (g.dim == 2) return fft_plane_green2d(g, t, in, out, spec, s, skip);
+  hipError_t e = fft_plane_forward(g, t, in, spec, s, skip);
   if (e != hipSuccess) return e;
-  e = fft_pencil_green(g, t, spec, s);
+  e = fft_pencil_green(g, t, spec, s, skip);
   if (e != hipSuccess) return e;
-  return fft_plane_inverse(g, t, spec, out, s);
+  return fft_plane_inverse(g, t, spec, out, s, skip);
 }
 
 hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,

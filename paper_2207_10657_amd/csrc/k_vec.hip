@@ -1,7 +1,9 @@
-// Vector kernels of the truncated CG (Algorithm 1): axpy updates of the
-// iterate, residual and direction in displacement coordinates, each fused
-// with the inner products the next scalar decision needs, and the final
-// fixed-order reduction of per-block partial sums.
+// Vector kernels of the truncated CG (Algorithm 1) in displacement
+// coordinates: updates of the iterate, residual and direction, each fused
+// with the inner products the next decision needs. The last block of each
+// reducing kernel takes that decision on the device-resident CgState, so a CG
+// iteration runs without a host round trip.
+#include "hfe_cg.h"
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
 
@@ -34,20 +36,30 @@ __global__ void __launch_bounds__(kBlock) k_axpy_to(long long n, const double* _
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot(long long n, const double* __restrict__ x,
-                                                const double* __restrict__ y,
-                                                double* __restrict__ partials) {
+                                                const double* __restrict__ y, Reducer r,
+                                                double* __restrict__ out) {
   double acc[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     acc[0] += x[i] * y[i];
-  block_reduce_store<1>(acc, partials);
+  double tot[1];
+  if (block_reduce_last<1>(acc, r, tot) && threadIdx.x == 0) out[0] = tot[0];
 }
 
-__global__ void __launch_bounds__(kBlock) k_cg_zg(long long n, double alpha,
-                                                  const double* __restrict__ d,
+__global__ void __launch_bounds__(kBlock) k_cg_zg(long long n, const double* __restrict__ d,
                                                   const double* __restrict__ Kd,
                                                   double* __restrict__ z,
-                                                  double* __restrict__ g) {
+                                                  double* __restrict__ g,
+                                                  const CgState* __restrict__ st) {
+  if (st->done) {
+    if (!st->apply_tau) return;
+    const double tau = st->tau;   // exit on the trust-region sphere: p = z + tau d
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+      z[i] += tau * d[i];
+    return;
+  }
+  const double alpha = st->alpha;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     z[i] += alpha * d[i];
@@ -55,11 +67,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_zg(long long n, double alpha,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_cg_y(long long n, double alpha,
-                                                 const double* __restrict__ w,
+__global__ void __launch_bounds__(kBlock) k_cg_y(long long n, const double* __restrict__ w,
                                                  double* __restrict__ y,
-                                                 const double* __restrict__ g,
-                                                 double* __restrict__ partials) {
+                                                 const double* __restrict__ g, Reducer r,
+                                                 CgState* st, double* trace) {
+  if (st->done) {
+    // the exit step (if any) was formed by k_cg_zg, which has completed
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->apply_tau = 0;
+    return;
+  }
+  const double alpha = st->alpha;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -67,18 +84,21 @@ __global__ void __launch_bounds__(kBlock) k_cg_y(long long n, double alpha,
     const double yn = yo + alpha * w[i];
     y[i] = yn;
     const double gi = g[i];
-    acc[0] += yn * gi;
-    acc[1] += yo * gi;
+    acc[0] += yn * gi;   // <r_{j+1}, r_{j+1}>
+    acc[1] += yo * gi;   // <r_{j+1}, r_j> (restart test)
   }
-  block_reduce_store<2>(acc, partials);
+  double tot[2];
+  if (block_reduce_last<2>(acc, r, tot) && threadIdx.x == 0)
+    cg_decide_residual(st, trace, tot[0], tot[1]);
 }
 
-__global__ void __launch_bounds__(kBlock) k_cg_d(long long n, double beta,
-                                                 const double* __restrict__ y,
+__global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const double* __restrict__ y,
                                                  double* __restrict__ d,
                                                  const double* __restrict__ g,
-                                                 const double* __restrict__ z,
-                                                 double* __restrict__ partials) {
+                                                 const double* __restrict__ z, Reducer r,
+                                                 CgState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -86,29 +106,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, double beta,
     const double dn = beta == 0.0 ? -y[i] : -y[i] + beta * d[i];
     d[i] = dn;
     const double gi = g[i];
-    acc[0] += gi * dn;
-    acc[1] += z[i] * gi;
+    acc[0] += gi * dn;     // <r, d>
+    acc[1] += z[i] * gi;   // z . g for <z, d>
   }
-  block_reduce_store<2>(acc, partials);
+  double tot[2];
+  if (block_reduce_last<2>(acc, r, tot) && threadIdx.x == 0)
+    cg_decide_direction(st, tot[0], tot[1]);
 }
 
-// One block; thread t adds rows t, t + 256, ... in order, then a fixed tree.
-__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials,
-                                                   int nblocks, int nv,
-                                                   double* __restrict__ out) {
-  __shared__ double sh[kBlock];
-  for (int k = 0; k < nv; ++k) {
-    double s = 0.0;
-    for (int r = threadIdx.x; r < nblocks; r += blockDim.x) s += partials[(size_t)r * nv + k];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
-    __syncthreads();
-  }
+__global__ void k_cg_resume(CgState* st) {
+  st->beta = 0.0;
+  st->restart = 0;
+  st->done = 0;
+  st->flag = CG_RUN;
 }
 
 }  // namespace
@@ -124,39 +134,32 @@ hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double*
   return hipGetLastError();
 }
 
-hipError_t vec_dot(long long n, const double* x, const double* y, double* partials,
-                   hipStream_t s, int* nblocks) {
-  const int nb = vec_blocks(n);
-  *nblocks = nb;
-  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlock), 0, s, n, x, y, partials);
+hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r, double* out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y, r, out);
   return hipGetLastError();
 }
 
-hipError_t cg_step_zg(long long n, double alpha, const double* d, const double* Kd, double* z,
-                      double* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_zg, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, alpha, d, Kd, z, g);
+hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z, double* g,
+                      CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_zg, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, d, Kd, z, g, st);
   return hipGetLastError();
 }
 
-hipError_t cg_step_y(long long n, double alpha, const double* w, double* y, const double* g,
-                     double* partials, hipStream_t s, int* nblocks) {
-  const int nb = vec_blocks(n);
-  *nblocks = nb;
-  hipLaunchKernelGGL(k_cg_y, dim3(nb), dim3(kBlock), 0, s, n, alpha, w, y, g, partials);
+hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
+                     CgState* st, double* trace, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_y, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, w, y, g, r, st, trace);
   return hipGetLastError();
 }
 
-hipError_t cg_step_d(long long n, double beta, const double* y, double* d, const double* g,
-                     const double* z, double* partials, hipStream_t s, int* nblocks) {
-  const int nb = vec_blocks(n);
-  *nblocks = nb;
-  hipLaunchKernelGGL(k_cg_d, dim3(nb), dim3(kBlock), 0, s, n, beta, y, d, g, z, partials);
+hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
+                     const Reducer& r, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_d, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
   return hipGetLastError();
 }
 
-hipError_t reduce_partials(const double* partials, int nblocks, int nv, double* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, nv, out);
+hipError_t cg_resume(CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(1), 0, s, st);
   return hipGetLastError();
 }
 
