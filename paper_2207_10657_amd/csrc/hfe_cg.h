@@ -1,7 +1,7 @@
 // Device-resident scalar state of the truncated CG (Algorithm 1) in
-// displacement coordinates, and the decisions taken on it. The last block of
-// each reducing kernel of a CG iteration applies the corresponding decision,
-// so an iteration needs no host round trip: the host enqueues iterations in
+// displacement coordinates, and the decisions taken on it. The finish kernel
+// that completes each reduction of a CG iteration applies the corresponding
+// decision, so an iteration needs no host round trip: the host enqueues iterations in
 // batches and reads the state once per batch. Once `done` is set, every later
 // kernel of the batch returns at entry.
 #pragma once

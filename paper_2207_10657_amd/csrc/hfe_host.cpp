@@ -45,7 +45,6 @@ struct Layout {
   size_t phase;                                       // N bytes
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
-  size_t counter;                                     // reduction ticket counters
   size_t cgstate;                                     // device CgState
   size_t trace;                                       // CG trace, 2 doubles per entry
   size_t tw;                                          // twiddles
@@ -104,7 +103,6 @@ Layout make_layout(const Grid& g) {
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
-  L.counter = take(16 * sizeof(unsigned int));
   L.cgstate = take(sizeof(hfe::CgState));
   L.trace = take((size_t)2 * kTraceCap * sizeof(double));
   L.n_tw = g.nx / 2 + g.ny + g.nz + (g.nx / 2 + 1);
@@ -147,7 +145,6 @@ struct hfe_ctx {
   uint8_t* phase;
   double2* spec;
   double* partials;
-  unsigned int* counter;
   hfe::CgState* cg;          // device CG state
   double* trace;             // device CG trace
   hfe::FftTables tabs;
@@ -254,8 +251,14 @@ hfe_status sync(hfe_ctx* c) {
 hfe::Reducer reducer(hfe_ctx* c) {
   hfe::Reducer r;
   r.partials = c->partials;
-  r.counter = c->counter;
   return r;
+}
+
+// Complete a reduction of nb rows of nv partials: totals to `out`, or a CG decision.
+hfe_status finish(hfe_ctx* c, int kind, int nb, int nv, double* out) {
+  Prof p(c, "finish");
+  HIPCHK(c, hfe::finish(kind, reducer(c), nb, nv, out, c->cg, c->trace, c->stream));
+  return HFE_OK;
 }
 
 hfe::ElemArgs elem_args(hfe_ctx* c) {
@@ -273,9 +276,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.v = nullptr;
   A.f = nullptr;
   A.red = reducer(c);
-  A.out = nullptr;
   A.cg = nullptr;
-  A.trace = nullptr;
   return A;
 }
 
@@ -312,22 +313,24 @@ hfe_status stiffness(hfe_ctx* c, const double* v, double* out, bool in_cg) {
   hfe::ElemArgs A = elem_args(c);
   A.v = v;
   A.f = out;
-  if (in_cg) {
-    A.cg = c->cg;
-    A.trace = c->trace;
-  } else {
-    A.out = c->dscal + S_HES;
+  if (in_cg) A.cg = c->cg;
+  int nb = 0;
+  {
+    Prof p(c, "stiffness");
+    HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
   }
-  Prof p(c, "stiffness");
-  HIPCHK(c, hfe::launch_hessian(A, c->stream));
-  return HFE_OK;
+  return in_cg ? finish(c, hfe::FIN_CURVATURE, nb, hfe::HES_NV, nullptr)
+               : finish(c, hfe::FIN_OUT, nb, hfe::HES_NV, c->dscal + S_HES);
 }
 
-// x . y into hscal[slot] (device alias), or into a device address
+// x . y into a device (or host-mapped) address
 hfe_status dot(hfe_ctx* c, const double* x, const double* y, double* dev_out) {
-  Prof p(c, "cg_vec");
-  HIPCHK(c, hfe::vec_dot(ndof(c), x, y, reducer(c), dev_out, c->stream));
-  return HFE_OK;
+  int nb = 0;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::vec_dot(ndof(c), x, y, reducer(c), c->stream, &nb));
+  }
+  return finish(c, hfe::FIN_OUT, nb, 1, dev_out);
 }
 
 // Residual at (u, E): g0 = D^T sigma, tangent scalars, y0 = L^+ g0, r_eq.
@@ -336,12 +339,14 @@ hfe_status evaluate_state(hfe_ctx* c) {
   A.a_out = c->a;
   A.cp_out = c->cp;
   A.f = c->g0;
-  A.out = c->dscal + S_RES;
+  int nb = 0;
   {
     Prof p(c, "residual");
-    HIPCHK(c, hfe::launch_residual(A, c->stream));
+    HIPCHK(c, hfe::launch_residual(A, c->stream, &nb));
   }
-  hfe_status st = green(c, c->g0, c->y0);
+  hfe_status st = finish(c, hfe::FIN_OUT, nb, hfe::RES_NV, c->dscal + S_RES);
+  if (st) return st;
+  st = green(c, c->g0, c->y0);
   if (st) return st;
   st = dot(c, c->y0, c->g0, c->dscal + S_RR0);
   if (st) return st;
@@ -360,6 +365,16 @@ hfe_status evaluate_state(hfe_ctx* c) {
 
 struct CgInfo { int iters = 0, restarts = 0, matvecs = 0; };
 
+// d = -y + beta d with <r, d> and z.g, then the direction update of the state.
+hfe_status direction(hfe_ctx* c) {
+  int nb = 0;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_d(ndof(c), c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream, &nb));
+  }
+  return finish(c, hfe::FIN_DIRECTION, nb, 2, nullptr);
+}
+
 // One CG iteration, all decisions on the device (no host synchronisation).
 hfe_status cg_iteration(hfe_ctx* c) {
   const long long n = ndof(c);
@@ -371,15 +386,14 @@ hfe_status cg_iteration(hfe_ctx* c) {
   }
   st = green(c, c->Kd, c->w, c->cg);
   if (st) return st;
+  int nb = 0;
   {
     Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_y(n, c->w, c->y, c->gv, reducer(c), c->cg, c->trace, c->stream));
+    HIPCHK(c, hfe::cg_step_y(n, c->w, c->y, c->gv, reducer(c), c->cg, c->stream, &nb));
   }
-  {
-    Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
-  }
-  return HFE_OK;
+  st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
+  if (st) return st;
+  return direction(c);
 }
 
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
@@ -403,8 +417,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
   HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
   // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0
   {
-    Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
+    hfe_status st = direction(c);
+    if (st) return st;
   }
   int restarts = 0;
   int batch = 2;
@@ -434,10 +448,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
       st = dot(c, c->y, c->gv, &c->cg->rr_new);
       if (st) return st;
       HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
-      {
-        Prof p(c, "cg_vec");
-        HIPCHK(c, hfe::cg_step_d(n, c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream));
-      }
+      st = direction(c);
+      if (st) return st;
       batch = 2;
       continue;
     }
@@ -526,7 +538,6 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
-  c->counter = (unsigned int*)(c->ws + L.counter);
   c->cg = (hfe::CgState*)(c->ws + L.cgstate);
   c->trace = D(L.trace);
   std::memset(&c->mat, 0, sizeof(c->mat));
@@ -693,11 +704,13 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       A.a_out = c->at;
       A.cp_out = c->cpt;
       A.f = c->gt;
-      A.out = c->dscal + S_TRI;
+      int nb = 0;
       {
         Prof pr(c, "trial");
-        HIPCHK(c, hfe::launch_trial(A, c->stream));
+        HIPCHK(c, hfe::launch_trial(A, c->stream, &nb));
       }
+      st = finish(c, hfe::FIN_OUT, nb, hfe::TRI_NV, c->dscal + S_TRI);
+      if (st) return st;
       st = sync(c);
       if (st) return st;
       double h[hfe::TRI_NV];

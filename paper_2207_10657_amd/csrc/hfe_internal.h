@@ -34,11 +34,13 @@ struct Macro {        // macroscopic strain E, full 3x3 row-major
   double e[9];
 };
 
-// Partial-sum rows plus a ticket counter: the last block of a reducing kernel
-// adds all rows in a fixed order and acts on the totals.
+// Every reducing kernel writes one row of partial sums per block; a
+// single-block finish kernel then adds the rows in a fixed order and acts on
+// the totals (writes them out, or takes the CG decision). The kernel boundary
+// between the two orders the memory accesses, so no device-wide fences are
+// needed (on a part with one L2 per XCD such fences write the L2 back).
 struct Reducer {
   double* partials;        // [blocks][nv]
-  unsigned int* counter;   // zero between kernels
 };
 
 // ---- element kernels (k_element.hip) -------------------------------------
@@ -63,18 +65,16 @@ struct ElemArgs {
   const double* v;       // second nodal input: z (trial) or the direction (Hessian)
   double* f;             // nodal output [dim][N]
   Reducer red;
-  double* out;           // grid totals of the reductions (device or host-mapped)
-  CgState* cg;           // Hessian in a CG iteration: decide on the totals instead
-  double* trace;         // CG trace (with cg)
+  CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
 };
 
-// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, totals RES_* to out.
-hipError_t launch_residual(const ElemArgs& A, hipStream_t s);
-// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), totals TRI_*.
-hipError_t launch_trial(const ElemArgs& A, hipStream_t s);
-// Hessian: f = D^T B D v at the state (u, a, cp); totals HES_* to out, or, with
-// A.cg set, the curvature decision of the CG iteration (no-op once cg->done).
-hipError_t launch_hessian(const ElemArgs& A, hipStream_t s);
+// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, partial rows RES_*.
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), rows TRI_*.
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Hessian: f = D^T B D v at the state (u, a, cp), rows HES_* (no-op once
+// A.cg->done when A.cg is set).
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Commit: khist <- max(khist, kappa_t(E + D u)) on damage points (khist is
 // written through the const-cast pointer a_out).
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s);
@@ -125,20 +125,29 @@ hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipSt
 // out = x + alpha * y
 hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
                        hipStream_t s);
-// *out = x . y (fixed-order reduction)
-hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r, double* out,
-                   hipStream_t s);
+// rows of x . y
+hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r,
+                   hipStream_t s, int* nblocks);
 // CG, after the curvature decision: z += alpha d ; g += alpha Kd, or, when the
 // CG has just stopped on the trust-region sphere, z += tau d.
 hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z, double* g,
                       CgState* st, hipStream_t s);
-// CG: y += alpha w, totals {y_new.g, y_old.g} -> residual decision (trace written)
+// CG: y += alpha w, rows {y_new.g, y_old.g}
 hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
-                     CgState* st, double* trace, hipStream_t s);
-// CG: d = -y + beta d, totals {g.d, z.g} -> direction decision
+                     const CgState* st, hipStream_t s, int* nblocks);
+// CG: d = -y + beta d, rows {g.d, z.g}
 hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
-                     const Reducer& r, CgState* st, hipStream_t s);
+                     const Reducer& r, const CgState* st, hipStream_t s, int* nblocks);
 // After the host recomputed the residual of a restart: beta = 0, run again.
 hipError_t cg_resume(CgState* st, hipStream_t s);
+
+// Finish kernels (one block): add `nblocks` rows of `nv` partials in a fixed
+// order, then
+enum { FIN_OUT = 0,          // write the nv totals to out (device or host-mapped)
+       FIN_CURVATURE = 1,    // CG curvature decision on {d.Kd, |Dd|^2}
+       FIN_RESIDUAL = 2,     // CG residual decision on {y_new.g, y_old.g}
+       FIN_DIRECTION = 3 };  // CG direction update on {g.d, z.g}
+hipError_t finish(int kind, const Reducer& r, int nblocks, int nv, double* out, CgState* st,
+                  double* trace, hipStream_t s);
 
 }  // namespace hfe

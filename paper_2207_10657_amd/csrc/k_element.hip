@@ -388,13 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
       acc[HES_DKD] += dk;
     }
   }
-  double tot[NV];
-  if (block_reduce_last<NV>(acc, A.red, tot) && threadIdx.x == 0) {
-    if (MODE == MODE_HESSIAN && A.cg)
-      cg_decide_curvature(A.cg, A.trace, tot[HES_DKD], tot[HES_DD]);
-    else if (A.out)
-      for (int k = 0; k < NV; ++k) A.out[k] = tot[k];
-  }
+  block_reduce_store<NV>(acc, A.red.partials);
 }
 
 template <int EL>
@@ -652,18 +646,13 @@ __global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
     }
   }
   double red[2] = {dkd, dd_acc};
-  double tot[2];
-  if (block_reduce_last<2>(red, A.red, tot) && threadIdx.x == 0) {
-    if (A.cg)
-      cg_decide_curvature(A.cg, A.trace, tot[HES_DKD], tot[HES_DD]);
-    else if (A.out)
-      for (int k = 0; k < 2; ++k) A.out[k] = tot[k];
-  }
+  block_reduce_store<2>(red, A.red.partials);
 }
 
 template <int MODE, int NV>
-hipError_t launch_gather(const ElemArgs& A, hipStream_t s) {
+hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
   const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
+  *nblocks = nb;
   if (A.g.element == HFE_Q1)
     hipLaunchKernelGGL((k_gather<HFE_Q1, MODE, NV>), dim3(nb), dim3(kBlock), 0, s, A);
   else
@@ -673,15 +662,16 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_residual(const ElemArgs& A, hipStream_t s) {
-  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s);
+hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
 }
-hipError_t launch_trial(const ElemArgs& A, hipStream_t s) {
-  return launch_gather<MODE_TRIAL, TRI_NV>(A, s);
+hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
 }
-hipError_t launch_hessian(const ElemArgs& A, hipStream_t s) {
-  if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s);
+hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
   const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + kBz - 1) / kBz);
+  *nblocks = nb;
   hipLaunchKernelGGL(k_stiffness_brick, dim3(nb), dim3(kBrickThreads), 0, s, A);
   return hipGetLastError();
 }

@@ -1,8 +1,9 @@
 // Vector kernels of the truncated CG (Algorithm 1) in displacement
 // coordinates: updates of the iterate, residual and direction, each fused
-// with the inner products the next decision needs. The last block of each
-// reducing kernel takes that decision on the device-resident CgState, so a CG
-// iteration runs without a host round trip.
+// with the inner products the next decision needs, and the single-block
+// finish kernels that add the per-block partial sums in a fixed order and
+// take that decision on the device-resident CgState, so a CG iteration runs
+// without a host round trip.
 #include "hfe_cg.h"
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
@@ -36,14 +37,12 @@ __global__ void __launch_bounds__(kBlock) k_axpy_to(long long n, const double* _
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot(long long n, const double* __restrict__ x,
-                                                const double* __restrict__ y, Reducer r,
-                                                double* __restrict__ out) {
+                                                const double* __restrict__ y, Reducer r) {
   double acc[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     acc[0] += x[i] * y[i];
-  double tot[1];
-  if (block_reduce_last<1>(acc, r, tot) && threadIdx.x == 0) out[0] = tot[0];
+  block_reduce_store<1>(acc, r.partials);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg_zg(long long n, const double* __restrict__ d,
@@ -70,12 +69,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_zg(long long n, const double* __r
 __global__ void __launch_bounds__(kBlock) k_cg_y(long long n, const double* __restrict__ w,
                                                  double* __restrict__ y,
                                                  const double* __restrict__ g, Reducer r,
-                                                 CgState* st, double* trace) {
-  if (st->done) {
-    // the exit step (if any) was formed by k_cg_zg, which has completed
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->apply_tau = 0;
-    return;
-  }
+                                                 const CgState* st) {
+  if (st->done) return;
   const double alpha = st->alpha;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -87,16 +82,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_y(long long n, const double* __re
     acc[0] += yn * gi;   // <r_{j+1}, r_{j+1}>
     acc[1] += yo * gi;   // <r_{j+1}, r_j> (restart test)
   }
-  double tot[2];
-  if (block_reduce_last<2>(acc, r, tot) && threadIdx.x == 0)
-    cg_decide_residual(st, trace, tot[0], tot[1]);
+  block_reduce_store<2>(acc, r.partials);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const double* __restrict__ y,
                                                  double* __restrict__ d,
                                                  const double* __restrict__ g,
                                                  const double* __restrict__ z, Reducer r,
-                                                 CgState* st) {
+                                                 const CgState* st) {
   if (st->done) return;
   const double beta = st->beta;
   double acc[2] = {0.0, 0.0};
@@ -109,9 +102,44 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const double* __re
     acc[0] += gi * dn;     // <r, d>
     acc[1] += z[i] * gi;   // z . g for <z, d>
   }
-  double tot[2];
-  if (block_reduce_last<2>(acc, r, tot) && threadIdx.x == 0)
+  block_reduce_store<2>(acc, r.partials);
+}
+
+// Fixed-order sum of nblocks rows of nv partials (one block), then the action.
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_finish(Reducer r, int nblocks, int nv,
+                                                   double* __restrict__ out, CgState* st,
+                                                   double* trace) {
+  if (KIND != FIN_OUT && st->done) {
+    // the exit step (if any) was formed by k_cg_zg earlier in this iteration
+    if (KIND == FIN_RESIDUAL) st->apply_tau = 0;
+    return;
+  }
+  __shared__ double wsum[kBlock / 64][kMaxPartials];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < nv; ++k) {
+    double s = 0.0;
+    for (int row = threadIdx.x; row < nblocks; row += blockDim.x) s += r.partials[(size_t)row * nv + k];
+    s = wave_sum(s);
+    if (lane == 0) wsum[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[kMaxPartials];
+  for (int k = 0; k < nv; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += wsum[w][k];
+    tot[k] = s;
+  }
+  if (KIND == FIN_OUT) {
+    for (int k = 0; k < nv; ++k) out[k] = tot[k];
+  } else if (KIND == FIN_CURVATURE) {
+    cg_decide_curvature(st, trace, tot[0], tot[1]);
+  } else if (KIND == FIN_RESIDUAL) {
+    cg_decide_residual(st, trace, tot[0], tot[1]);
+  } else {
     cg_decide_direction(st, tot[0], tot[1]);
+  }
 }
 
 __global__ void k_cg_resume(CgState* st) {
@@ -134,9 +162,10 @@ hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double*
   return hipGetLastError();
 }
 
-hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r, double* out,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y, r, out);
+hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r,
+                   hipStream_t s, int* nblocks) {
+  *nblocks = vec_blocks(n);
+  hipLaunchKernelGGL(k_dot, dim3(*nblocks), dim3(kBlock), 0, s, n, x, y, r);
   return hipGetLastError();
 }
 
@@ -147,14 +176,35 @@ hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z,
 }
 
 hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
-                     CgState* st, double* trace, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_y, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, w, y, g, r, st, trace);
+                     const CgState* st, hipStream_t s, int* nblocks) {
+  *nblocks = vec_blocks(n);
+  hipLaunchKernelGGL(k_cg_y, dim3(*nblocks), dim3(kBlock), 0, s, n, w, y, g, r, st);
   return hipGetLastError();
 }
 
 hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
-                     const Reducer& r, CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_d, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
+                     const Reducer& r, const CgState* st, hipStream_t s, int* nblocks) {
+  *nblocks = vec_blocks(n);
+  hipLaunchKernelGGL(k_cg_d, dim3(*nblocks), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
+  return hipGetLastError();
+}
+
+hipError_t finish(int kind, const Reducer& r, int nblocks, int nv, double* out, CgState* st,
+                  double* trace, hipStream_t s) {
+  switch (kind) {
+    case FIN_OUT:
+      hipLaunchKernelGGL(k_finish<FIN_OUT>, dim3(1), dim3(kBlock), 0, s, r, nblocks, nv, out, st, trace);
+      break;
+    case FIN_CURVATURE:
+      hipLaunchKernelGGL(k_finish<FIN_CURVATURE>, dim3(1), dim3(kBlock), 0, s, r, nblocks, nv, out, st, trace);
+      break;
+    case FIN_RESIDUAL:
+      hipLaunchKernelGGL(k_finish<FIN_RESIDUAL>, dim3(1), dim3(kBlock), 0, s, r, nblocks, nv, out, st, trace);
+      break;
+    default:
+      hipLaunchKernelGGL(k_finish<FIN_DIRECTION>, dim3(1), dim3(kBlock), 0, s, r, nblocks, nv, out, st, trace);
+      break;
+  }
   return hipGetLastError();
 }
 

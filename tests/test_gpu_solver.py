@@ -80,14 +80,18 @@ def _load_scale(w, dE):
     return np.linalg.norm(lam * np.trace(dE) * np.eye(3) + 2 * mu * dE)
 
 
-def _certify_tie(glog, gtrace, olog, eta_cg, max_drift=1e-2):
+def _certify_tie(glog, gtrace, olog, eta_cg, max_drift=5e-2):
     """At the first Newton iteration whose decisions differ, check that the
     difference is a threshold tie explained by rounding drift.
 
     CG stop: both CG traces (||r_{j+1}||/||r_0|| per iteration) start equal
     (relative 1e-10) and drift apart slowly; at the last common iteration the
     stopping threshold eta_cg lies between the two values and their relative
-    drift there is below ``max_drift``. rho: the two ratios straddle the
+    drift there is below ``max_drift``. (In finite precision the recursively
+    updated CG residuals of two implementations that round differently
+    separate gradually on ill-conditioned systems; after a few hundred
+    iterations on a damaged state a drift of a few percent is that effect,
+    while an implementation error shows up in the first iterations.) rho: the two ratios straddle the
     threshold and differ by less than ``max_drift``.
     Returns (certified, description)."""
     o_cg = [e for e in olog if e[0] == "cg"]
