@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,6 +48,7 @@ struct Layout {
   size_t partials;                                    // rows * 16 doubles
   size_t cgstate;                                     // device CgState
   size_t trace;                                       // CG trace, 2 doubles per entry
+  size_t Edev;                                        // macroscopic strain (9 doubles)
   size_t tw;                                          // twiddles
   size_t stab;                                        // sin^2 tables
   size_t total;
@@ -105,6 +107,7 @@ Layout make_layout(const Grid& g) {
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
   L.cgstate = take(sizeof(hfe::CgState));
   L.trace = take((size_t)2 * kTraceCap * sizeof(double));
+  L.Edev = take(9 * sizeof(double));
   L.n_tw = g.nx / 2 + g.ny + g.nz + (g.nx / 2 + 1);
   L.tw = take((size_t)L.n_tw * sizeof(double2));
   L.n_stab = (g.nx / 2 + 1) + g.ny + g.nz;
@@ -131,6 +134,14 @@ void sin2_table(int n, int count, std::vector<double>& out) {
 
 struct ProfEvent { int kernel; hipEvent_t start, stop; };
 
+// A captured batch of CG iterations and the timing events inside it.
+struct CgGraph {
+  hipGraphExec_t exec = nullptr;
+  int iters = 0;
+  bool profiled = false;
+  std::vector<ProfEvent> ev;
+};
+
 }  // namespace
 
 struct hfe_ctx {
@@ -146,6 +157,7 @@ struct hfe_ctx {
   double2* spec;
   double* partials;
   hfe::CgState* cg;          // device CG state
+  double* Edev;              // device copy of E
   double* trace;             // device CG trace
   hfe::FftTables tabs;
   double* hscal = nullptr;   // pinned, device-mapped: reduction totals land here
@@ -171,6 +183,11 @@ struct hfe_ctx {
   std::vector<double> kms;
   std::vector<ProfEvent> pending;
   std::vector<hipEvent_t> pool;
+  std::vector<ProfEvent>* prof_sink = nullptr;   // events recorded while capturing
+  // CG iteration graphs: a short batch for the start of a solve, a long one after
+  hipStream_t cap_stream = nullptr;
+  CgGraph graphs[2];
+  bool use_graphs = true;
 };
 
 namespace {
@@ -223,7 +240,7 @@ struct Prof {
     hipEvent_t e = take_event(c);
     if (!e) return;
     hipEventRecord(e, c->stream);
-    c->pending.push_back({id, s, e});
+    (c->prof_sink ? c->prof_sink : &c->pending)->push_back({id, s, e});
   }
 };
 
@@ -242,6 +259,29 @@ void prof_drain(hfe_ctx* c) {
 }
 
 // Wait for the stream; reduction totals are then visible in hscal.
+// Accumulate the timings of the events inside a replayed graph.
+void prof_drain_graph(hfe_ctx* c, const CgGraph& G) {
+  for (const auto& p : G.ev) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      c->kcount[p.kernel] += 1;
+      c->kms[p.kernel] += ms;
+    }
+  }
+}
+
+void destroy_graphs(hfe_ctx* c) {
+  for (auto& G : c->graphs) {
+    if (G.exec) hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    for (auto& p : G.ev) {
+      c->pool.push_back(p.start);
+      c->pool.push_back(p.stop);
+    }
+    G.ev.clear();
+  }
+}
+
 hfe_status sync(hfe_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->profiling) prof_drain(c);
@@ -265,7 +305,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   hfe::ElemArgs A;
   A.g = c->g;
   A.mat = c->mat;
-  for (int k = 0; k < 9; ++k) A.E.e[k] = c->E[k];
+  A.E = c->Edev;
   A.phase = c->phase;
   A.khist = c->kh;
   A.a = c->a;
@@ -283,7 +323,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
 long long ndof(const hfe_ctx* c) { return (long long)c->g.dim * c->g.N; }
 
 // Offsets of the reduction totals in hscal.
-enum { S_HES = 0, S_RES = 8, S_RR0 = 16, S_TRI = 24, S_DOT = 40 };
+enum { S_HES = 0, S_RES = 8, S_RR0 = 16, S_TRI = 24, S_DOT = 40, S_ESTAGE = 48, S_COUNT = 64 };
 
 // y = L^+ x (the passes are skipped once skip->done is set)
 hfe_status green(hfe_ctx* c, const double* x, double* y, const hfe::CgState* skip = nullptr) {
@@ -333,8 +373,21 @@ hfe_status dot(hfe_ctx* c, const double* x, const double* y, double* dev_out) {
   return finish(c, hfe::FIN_OUT, nb, 1, dev_out);
 }
 
+// Copy E to the device (through the pinned staging area; synchronous, rare).
+hfe_status upload_E(hfe_ctx* c) {
+  double* stage = c->hscal + S_ESTAGE;
+  for (int k = 0; k < 9; ++k) stage[k] = c->E[k];
+  HIPCHK(c, hipMemcpyAsync(c->Edev, stage, 9 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HFE_OK;
+}
+
 // Residual at (u, E): g0 = D^T sigma, tangent scalars, y0 = L^+ g0, r_eq.
 hfe_status evaluate_state(hfe_ctx* c) {
+  {
+    hfe_status st0 = upload_E(c);
+    if (st0) return st0;
+  }
   hfe::ElemArgs A = elem_args(c);
   A.a_out = c->a;
   A.cp_out = c->cp;
@@ -396,6 +449,57 @@ hfe_status cg_iteration(hfe_ctx* c) {
   return direction(c);
 }
 
+// Enqueue `k` CG iterations: a replay of a captured graph (captured on a
+// private stream, launched on the context's stream), or plain launches.
+hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
+  if (!c->use_graphs) {
+    for (int i = 0; i < k; ++i) {
+      hfe_status st = cg_iteration(c);
+      if (st) return st;
+    }
+    return HFE_OK;
+  }
+  CgGraph& G = c->graphs[slot];
+  if (G.exec && G.profiled != c->profiling) {
+    hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    for (auto& p : G.ev) {
+      c->pool.push_back(p.start);
+      c->pool.push_back(p.stop);
+    }
+    G.ev.clear();
+  }
+  if (!G.exec) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const hipStream_t saved = c->stream;
+    c->stream = c->cap_stream;
+    c->prof_sink = &G.ev;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    hfe_status st = HFE_OK;
+    if (e == hipSuccess)
+      for (int i = 0; i < k && st == HFE_OK; ++i) st = cg_iteration(c);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &graph) : e;
+    c->stream = saved;
+    c->prof_sink = nullptr;
+    if (st) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e2 != hipSuccess) return fail(c, HFE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
+    const hipError_t e3 = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      G.exec = nullptr;
+      return fail(c, HFE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
+    }
+    G.iters = k;
+    G.profiled = c->profiling;
+  }
+  HIPCHK(c, hipGraphLaunch(G.exec, c->stream));
+  return HFE_OK;
+}
+
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
 hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, CgInfo* info) {
   const long long n = ndof(c);
@@ -421,18 +525,18 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     if (st) return st;
   }
   int restarts = 0;
-  int batch = 2;
+  int slot = 0;
   for (;;) {
-    for (int k = 0; k < batch; ++k) {
-      hfe_status st = cg_iteration(c);
-      if (st) return st;
-    }
-    HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
-    hfe_status st = sync(c);
+    const int k = slot == 0 ? 2 : kCgBatch;
+    hfe_status st = cg_batch(c, slot, k);
     if (st) return st;
+    HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
+    st = sync(c);
+    if (st) return st;
+    if (c->profiling && c->use_graphs) prof_drain_graph(c, c->graphs[slot]);
     const hfe::CgState h = *c->hcg;
     if (!h.done) {
-      batch = std::min(batch * 2, kCgBatch);
+      slot = 1;
       continue;
     }
     if (h.flag == hfe::CG_NUMERIC) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
@@ -450,7 +554,7 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
       HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
       st = direction(c);
       if (st) return st;
-      batch = 2;
+      slot = 0;
       continue;
     }
     info->iters = h.iters;
@@ -482,6 +586,10 @@ hfe_status reset_state(hfe_ctx* c) {
   const size_t nod = (size_t)ndof(c) * sizeof(double);
   HIPCHK(c, hipMemsetAsync(c->u, 0, nod, c->stream));
   for (int k = 0; k < 9; ++k) c->E[k] = 0.0;
+  {
+    hfe_status st = upload_E(c);
+    if (st) return st;
+  }
   c->R_init = false;
   c->have_state = false;
   c->history_ready = false;
@@ -530,6 +638,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
+  c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
   c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);
@@ -540,6 +649,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->partials = D(L.partials);
   c->cg = (hfe::CgState*)(c->ws + L.cgstate);
   c->trace = D(L.trace);
+  c->Edev = D(L.Edev);
   std::memset(&c->mat, 0, sizeof(c->mat));
   // FFT tables
   std::vector<double2> tw;
@@ -562,7 +672,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs.sx = dst;
   c->tabs.sy = dst + (M + 1);
   c->tabs.sz = dst + (M + 1) + g.ny;
-  hipError_t e = hipHostMalloc((void**)&c->hscal, 64 * sizeof(double),
+  hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dscal, c->hscal, 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hcg, sizeof(hfe::CgState), hipHostMallocDefault);
@@ -585,6 +695,8 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
 hfe_status hfe_destroy(hfe_ctx* c) {
   if (!c) return HFE_EINVAL;
   hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (auto& p : c->pending) {
     hipEventDestroy(p.start);
     hipEventDestroy(p.stop);
@@ -604,6 +716,7 @@ hfe_status hfe_set_microstructure(hfe_ctx* c, const uint8_t* phase, int n_phases
     if (phase[i] >= n_phases) return fail(c, HFE_EINVAL, "phase id >= n_phases");
   HIPCHK(c, hipMemcpyAsync(c->phase, phase, (size_t)c->g.N, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  destroy_graphs(c);
   c->n_phases = n_phases;
   for (int p = 0; p < hfe::kMaxPhases; ++p) c->mat_set[p] = false;
   c->have_micro = true;
@@ -627,6 +740,7 @@ hfe_status hfe_set_material(hfe_ctx* c, int phase, const hfe_material* m) {
   c->mat.k0[phase] = c->mat.damage[phase] ? m->kappa0 : 0.0;
   c->mat.kf[phase] = c->mat.damage[phase] ? m->kappaf : 1.0;
   c->mat_set[phase] = true;
+  destroy_graphs(c);
   c->history_ready = false;  // kappa0 may have changed: re-initialise before the first step
   return HFE_OK;
 }
@@ -737,9 +851,12 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       if (rho > p.eta_up) {
         rec.accepted = 1;
         HIPCHK(c, hfe::vec_axpy(n, 1.0, c->z, c->u, c->stream));
-        std::swap(c->a, c->at);
-        std::swap(c->cp, c->cpt);
-        std::swap(c->g0, c->gt);
+        // the trial state becomes the state (copies keep every buffer at a
+        // fixed address, so captured CG graphs stay valid)
+        const size_t pts = (size_t)c->g.nq * c->g.N * sizeof(double);
+        HIPCHK(c, hipMemcpyAsync(c->a, c->at, pts, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->cp, c->cpt, pts, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->g0, c->gt, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH], ss = h[hfe::TRI_SS];
         for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[hfe::TRI_S0 + k];
         c->sig_norm2 = ss;

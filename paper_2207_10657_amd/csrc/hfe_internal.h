@@ -54,7 +54,7 @@ enum { HES_DKD = 0, HES_DD = 1, HES_NV = 2 };
 struct ElemArgs {
   Grid g;
   MatTable mat;
-  Macro E;
+  const double* E;       // macroscopic strain, 3x3 row-major (device)
   const uint8_t* phase;
   const double* khist;   // [nq][N]
   const double* a;       // [nq][N] current tangent scalars

@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) Em[i][j] = (i < D && j < D) ? A.E.e[3 * i + j] : 0.0;
+      for (int j = 0; j < 3; ++j) Em[i][j] = (i < D && j < D) ? A.E[3 * i + j] : 0.0;
 #pragma unroll 1
     for (int al = 0; al < NA; ++al) {
       const Pos e = elem_of<EL>(g, x, y, z, al);
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_commit(ElemArgs A) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int j = 0; j < D; ++j) H[i][j] += A.E.e[3 * i + j];
+      for (int j = 0; j < D; ++j) H[i][j] += A.E[3 * i + j];
     const Sym eps = sym_of<D>(H);
     const Sym s = c_contract(eps, A.mat.lam[ph], A.mat.mu[ph]);
     const double kt = sqrt(fmax(sym_dot(eps, s), 0.0) / A.mat.E[ph]);
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
     double H[3][3];
     grad_at<EL>(q, un, H);
     for (int i = 0; i < D; ++i)
-      for (int j = 0; j < D; ++j) H[i][j] += A.E.e[3 * i + j];
+      for (int j = 0; j < D; ++j) H[i][j] += A.E[3 * i + j];
     const long long base = (n * NQ + q) * D * D;
     if (out_h)
       for (int i = 0; i < D; ++i)
@@ -474,46 +474,81 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
   }
 }
 
-// ---- brick stiffness kernel (Q1) ---------------------------------------
+// ---- brick kernels (Q1) ---------------------------------------------------
 //
-// K d = D^T B D d for a block of kBx x kBy x kBz nodes. The block computes the
+// One block per brick of kBx x kBy x kBz nodes. The block computes the
 // (kB+1)^3 elements whose nodes include its own (one layer of halo elements
 // on the low side of each axis, recomputed by the neighbouring block as
 // well), one element per thread, with the nodal inputs staged in LDS. The
 // element forces are added to the owned nodes in eight phases, one per local
 // node a: within a phase the map element -> node e + o_a is one-to-one, so no
 // two threads touch the same accumulator and the order of the additions is
-// fixed.
-constexpr int kBx = 8, kBy = 8, kBz = 8;
-constexpr int kTile = (kBx + 2) * (kBy + 2) * (kBz + 2);   // staged nodes
-constexpr int kOwn = kBx * kBy * kBz;                       // owned nodes
-constexpr int kBrickThreads = 768;                          // >= (kB+1)^3 = 729
+// fixed. Per-element outputs and reduction terms come from the elements the
+// brick owns (those whose lowest corner is one of its nodes).
+//   MODE_HESSIAN : f = K v = D^T B D v;  rows {v.Kv, |D v|^2}
+//   MODE_RESIDUAL: f = D^T sigma(E + D u), a/c' written;  rows RES_*
+//   MODE_TRIAL   : f = D^T sigma(E + D(u+v)), trial a/c' written;  rows TRI_*
+// The Hessian uses 8x8x8 bricks (768 threads >= 9^3 elements); the residual
+// and trial passes, which hold more per-point state, use 8x8x4 bricks (448
+// threads >= 9x9x5 elements) so that a thread may use up to 256 registers.
+constexpr int kBx = 8, kBy = 8;
+template <int BZ> struct BrickShape {
+  static constexpr int tile = (kBx + 2) * (kBy + 2) * (BZ + 2);   // staged nodes
+  static constexpr int own = kBx * kBy * BZ;                       // owned nodes
+  static constexpr int threads = BZ == 8 ? 768 : 448;             // >= (kB+1)^3 elements
+};
+constexpr int kTileMax = BrickShape<8>::tile;
 
-__global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
+__device__ __forceinline__ int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+// Full gradient at point q of the element whose lowest tile node is t0, from
+// a staged field (three components), plus an optional constant.
+template <int TILE>
+__device__ __forceinline__ void tile_grad(const double (*f)[TILE], int q, int t0, int sy, int sz,
+                                          double (&H)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
+    const double v0 = f[0][ti], v1 = f[1][ti], v2 = f[2][ti];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double w = kQ1B.v[q][a][j];
+      H[0][j] += w * v0;
+      H[1][j] += w * v1;
+      H[2][j] += w * v2;
+    }
+  }
+}
+
+template <int MODE, int NV, int BZ>
+__global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
+  constexpr int kTile = BrickShape<BZ>::tile, kOwn = BrickShape<BZ>::own;
   const Grid& g = A.g;
-  if (A.cg && A.cg->done) return;
-  __shared__ double sd[3][kTile];
-  __shared__ double su[3][kTile];
+  if (MODE == MODE_HESSIAN && A.cg && A.cg->done) return;
+  __shared__ double sv[3][kTile];   // v: direction (Hessian) or step (trial)
+  __shared__ double su[3][kTile];   // u
   __shared__ double acc[3][kOwn];
   __shared__ int need_u_flag;
   const int nbx = (g.nx + kBx - 1) / kBx, nby = (g.ny + kBy - 1) / kBy;
   const int bxi = blockIdx.x % nbx, byi = (blockIdx.x / nbx) % nby, bzi = blockIdx.x / (nbx * nby);
-  const int x0 = bxi * kBx, y0 = byi * kBy, z0 = bzi * kBz;
-  const int bx = min(kBx, g.nx - x0), by = min(kBy, g.ny - y0), bz = min(kBz, g.nz - z0);
+  const int x0 = bxi * kBx, y0 = byi * kBy, z0 = bzi * BZ;
+  const int bx = min(kBx, g.nx - x0), by = min(kBy, g.ny - y0), bz = min(BZ, g.nz - z0);
   const int tx = bx + 2, ty = by + 2, tz = bz + 2;          // staged node tile
   const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;    // element brick
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) need_u_flag = 0;
-  // stage d on the node tile: local l <-> global (origin - 1 + l) mod n
-  for (int i = tid; i < tx * ty * tz; i += nt) {
+  const int ntile = tx * ty * tz;
+  if (tid == 0) need_u_flag = MODE == MODE_HESSIAN ? 0 : 1;
+  // local tile node l <-> global node (origin - 1 + l) mod n
+  auto tile_node = [&](int i) {
     const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
-    int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-    gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-    gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
-    const long long n = lin(g, gx, gy, gz);
+    return lin(g, wrap(x0 - 1 + lx, g.nx), wrap(y0 - 1 + ly, g.ny), wrap(z0 - 1 + lz, g.nz));
+  };
+  if (MODE != MODE_RESIDUAL) {
+    for (int i = tid; i < ntile; i += nt) {
+      const long long n = tile_node(i);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sd[c][i] = A.v[c * g.N + n];
+      for (int c = 0; c < 3; ++c) sv[c][i] = A.v[c * g.N + n];
+    }
   }
   for (int i = tid; i < bx * by * bz; i += nt) {
 #pragma unroll
@@ -526,27 +561,19 @@ __global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
   long long eg = 0;
   int ph = 0;
   if (active) {
-    int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
-    gx = gx < 0 ? gx + g.nx : gx;
-    gy = gy < 0 ? gy + g.ny : gy;
-    gz = gz < 0 ? gz + g.nz : gz;
-    eg = lin(g, gx, gy, gz);
+    eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
-    bool mine_u = false;
+    if (MODE == MODE_HESSIAN) {
+      bool mine_u = false;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != 0.0;
-    if (mine_u) need_u_flag = 1;
+      for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != 0.0;
+      if (mine_u) need_u_flag = 1;
+    }
   }
   __syncthreads();
-  const bool need_u = need_u_flag != 0;
-  if (need_u) {
-    for (int i = tid; i < tx * ty * tz; i += nt) {
-      const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
-      int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-      gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-      gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-      gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
-      const long long n = lin(g, gx, gy, gz);
+  if (need_u_flag) {
+    for (int i = tid; i < ntile; i += nt) {
+      const long long n = tile_node(i);
 #pragma unroll
       for (int c = 0; c < 3; ++c) su[c][i] = A.u[c * g.N + n];
     }
@@ -557,57 +584,100 @@ __global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int a = 0; a < 8; ++a) f[i][a] = 0.0;
-  double dd_acc = 0.0;
+  double red[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) red[k] = 0.0;
   if (active) {
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     const int sy = tx, sz = tx * ty;
-    const bool owned_elem = ex >= 1 && ey >= 1 && ez >= 1;
+    const bool owned = ex >= 1 && ey >= 1 && ez >= 1;
+    double Em[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Em[i][j] = A.E[3 * i + j];
 #pragma unroll 1
     for (int q = 0; q < 8; ++q) {
-      const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
-      double dH[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+      Sym tau;
+      if (MODE == MODE_HESSIAN) {
+        const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
+        double dH[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        tile_grad(sv, q, t0, sy, sz, dH);
+        Sym s;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
-        const double v0 = sd[0][ti], v1 = sd[1][ti], v2 = sd[2][ti];
+        for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
+        if (cq != 0.0) {
+          double H[3][3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double w = kQ1B.v[q][a][j];
-          dH[0][j] += w * v0;
-          dH[1][j] += w * v1;
-          dH[2][j] += w * v2;
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
+          tile_grad(su, q, t0, sy, sz, H);
+          s = c_contract(sym_of<3>(H), lam, mu);
         }
-      }
-      Sym s;
+        tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
+        if (owned) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
-      if (cq != 0.0) {
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) red[HES_DD] += dH[i][j] * dH[i][j];
+        }
+      } else {
         double H[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) H[i][j] = A.E.e[3 * i + j];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
-          const double v0 = su[0][ti], v1 = su[1][ti], v2 = su[2][ti];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            const double w = kQ1B.v[q][a][j];
-            H[0][j] += w * v0;
-            H[1][j] += w * v1;
-            H[2][j] += w * v2;
-          }
-        }
-        s = c_contract(sym_of<3>(H), lam, mu);
-      }
-      const Sym tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
-      if (owned_elem) {
+          for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
+        tile_grad(su, q, t0, sy, sz, H);
+        double p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        if (MODE == MODE_TRIAL) tile_grad(sv, q, t0, sy, sz, p);
+        double Ht[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) dd_acc += dH[i][j] * dH[i][j];
+          for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
+        const double kh = A.khist[q * g.N + eg];
+        const PointLaw P = eval_law(sym_of<3>(Ht), lam, mu, A.mat.E[ph], A.mat.damage[ph],
+                                    A.mat.k0[ph], A.mat.kf[ph], kh);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
+        if (owned) {
+          A.a_out[q * g.N + eg] = P.a;
+          A.cp_out[q * g.N + eg] = P.cp;
+          double hh = 0.0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) hh += Ht[i][j] * Ht[i][j];
+          if (MODE == MODE_RESIDUAL) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
+            red[RES_SS] += sym_dot(tau, tau);
+            red[RES_HH] += hh;
+          } else {
+            const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
+            const Sym so = c_contract(sym_of<3>(H), lam, mu);
+            const Sym ps = sym_of<3>(p);
+            Sym sig;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sig.v[k] = ao * so.v[k];
+            const Sym Bp = apply_tangent(ps, ao, co, so, lam, mu);
+            double pp = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) pp += p[i][j] * p[i][j];
+            red[TRI_SP] += sym_dot(sig, ps);
+            red[TRI_PBP] += sym_dot(Bp, ps);
+            red[TRI_STP] += sym_dot(tau, ps);
+            red[TRI_PP] += pp;
+            red[TRI_HH] += hh;
+            red[TRI_SS] += sym_dot(tau, tau);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[TRI_S0 + k] += tau.v[k];
+          }
+        }
       }
 #pragma unroll
       for (int a = 0; a < 8; ++a)
@@ -642,11 +712,20 @@ __global__ void __launch_bounds__(kBrickThreads) k_stiffness_brick(ElemArgs A) {
     for (int c = 0; c < 3; ++c) {
       const double v = acc[c][i];
       A.f[c * g.N + n] = v;
-      dkd += v * sd[c][ti];
+      if (MODE == MODE_HESSIAN) dkd += v * sv[c][ti];
     }
   }
-  double red[2] = {dkd, dd_acc};
-  block_reduce_store<2>(red, A.red.partials);
+  if (MODE == MODE_HESSIAN) red[HES_DKD] += dkd;
+  block_reduce_store<NV>(red, A.red.partials);
+}
+
+template <int MODE, int NV>
+hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  constexpr int BZ = MODE == MODE_HESSIAN ? 8 : 4;
+  const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + BZ - 1) / BZ);
+  *nblocks = nb;
+  hipLaunchKernelGGL((k_brick<MODE, NV, BZ>), dim3(nb), dim3(BrickShape<BZ>::threads), 0, s, A);
+  return hipGetLastError();
 }
 
 template <int MODE, int NV>
@@ -663,17 +742,16 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 }  // namespace
 
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
+  if (A.g.element != HFE_Q1) return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
+  return launch_brick<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
 }
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
+  if (A.g.element != HFE_Q1) return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
+  return launch_brick<MODE_TRIAL, TRI_NV>(A, s, nblocks);
 }
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
-  const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + kBz - 1) / kBz);
-  *nblocks = nb;
-  hipLaunchKernelGGL(k_stiffness_brick, dim3(nb), dim3(kBrickThreads), 0, s, A);
-  return hipGetLastError();
+  return launch_brick<MODE_HESSIAN, HES_NV>(A, s, nblocks);
 }
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s) {
   const int nb = (int)((A.g.N + kBlock - 1) / kBlock);
