@@ -452,7 +452,9 @@ hfe_status cg_iteration(hfe_ctx* c) {
 // Enqueue `k` CG iterations: a replay of a captured graph (captured on a
 // private stream, launched on the context's stream), or plain launches.
 hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
-  if (!c->use_graphs) {
+  // timing events cannot be recorded inside a captured graph on this
+  // runtime, so a profiled solve launches the kernels one by one
+  if (!c->use_graphs || c->profiling) {
     for (int i = 0; i < k; ++i) {
       hfe_status st = cg_iteration(c);
       if (st) return st;
@@ -533,7 +535,7 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
     st = sync(c);
     if (st) return st;
-    if (c->profiling && c->use_graphs) prof_drain_graph(c, c->graphs[slot]);
+
     const hfe::CgState h = *c->hcg;
     if (!h.done) {
       slot = 1;

@@ -238,3 +238,41 @@ def test_damage_trajectory_invariants():
     assert hist[-1][2].max() > 0.5          # damage has localised somewhere
     for (_, S1, _), (_, S2, _) in zip(hist, hist2):
         np.testing.assert_allclose(S2, S1, rtol=1e-7, atol=1e-9 * np.abs(S1).max())
+
+
+@pytest.mark.slow
+def test_rounding_sensitivity_of_the_method():
+    """The oracle against itself with only the summation order of its inner
+    products changed: on the 3D inclusion cell the CG traces separate by more
+    than 1e-2 (relative) within four load steps. This is the rounding noise
+    against which a GPU/oracle difference in a stopping decision is judged."""
+    import oracle.solver as S
+    from synthetic import workload
+    w = workload("c1_3d16", steps=4)
+    orig = S.steihaug
+
+    def run(dot):
+        def st(apply_A, g, R, eta, jmax, dot_=None, log=None):
+            return orig(apply_A, g, R, eta, jmax, dot=dot, log=log)
+        S.steihaug = st
+        try:
+            o = CellSolver(w.phase, w.materials, w.element)
+            traces = []
+            for dE in w.load_path:
+                o.apply_load_step(dE)
+                log = []
+                o.solve_increment(log=log)
+                traces.append(np.array([e[3] for e in log if e[0] == "cg"]))
+            return traces
+        finally:
+            S.steihaug = orig
+
+    a = run(lambda X, Y: float(np.sum(X * Y)))
+    b = run(lambda X, Y: float(np.sum((X * Y).ravel()[::-1])))
+    drift = 0.0
+    for ta, tb in zip(a, b):
+        m = min(len(ta), len(tb))
+        ok = np.isfinite(ta[:m]) & np.isfinite(tb[:m])
+        if ok.any():
+            drift = max(drift, float(np.max(np.abs(ta[:m][ok] - tb[:m][ok]) / np.abs(ta[:m][ok]))))
+    assert drift > 1e-2, drift
