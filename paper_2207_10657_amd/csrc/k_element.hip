@@ -656,20 +656,21 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
             red[RES_SS] += sym_dot(tau, tau);
             red[RES_HH] += hh;
           } else {
+            // sigma_old : p = a (s:p) and p : B_old : p = a (p:C:p) - c' (s:p)^2,
+            // with s = C : eps(u) at the current state
             const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
-            const Sym so = c_contract(sym_of<3>(H), lam, mu);
             const Sym ps = sym_of<3>(p);
-            Sym sig;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) sig.v[k] = ao * so.v[k];
-            const Sym Bp = apply_tangent(ps, ao, co, so, lam, mu);
+            const Sym so = c_contract(sym_of<3>(H), lam, mu);
+            const double s_p = sym_dot(so, ps);
+            const double trp = ps.v[0] + ps.v[1] + ps.v[2];
+            const double pCp = lam * trp * trp + 2.0 * mu * sym_dot(ps, ps);
             double pp = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
               for (int j = 0; j < 3; ++j) pp += p[i][j] * p[i][j];
-            red[TRI_SP] += sym_dot(sig, ps);
-            red[TRI_PBP] += sym_dot(Bp, ps);
+            red[TRI_SP] += ao * s_p;
+            red[TRI_PBP] += ao * pCp - co * s_p * s_p;
             red[TRI_STP] += sym_dot(tau, ps);
             red[TRI_PP] += pp;
             red[TRI_HH] += hh;
