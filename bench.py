@@ -78,6 +78,35 @@ def cpu_baseline(w, n_matvec):
                       "(numpy, one thread) at 64^3 on a damaged state, %.1f s" % (n_matvec, dt)}
 
 
+COPY_BYTES = 1 << 28
+
+
+def probe(n):
+    """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
+
+    One load step of the workload recipe at n^3, then 5 projected-Hessian
+    applications at that state and 5 device-to-device copies of COPY_BYTES
+    (the copy kernel calibrates the counters: it reads and writes exactly
+    COPY_BYTES per launch)."""
+    import torch
+    from paper_2207_10657_amd import Solver
+    from synthetic import workload
+    w = workload("c1_3d%d" % n)
+    s = Solver(w.shape, w.element)
+    s.setup(w.phase, w.materials)
+    s.apply_load_step(w.load_path[0] * 5)      # a damaged state (E_xx = 1e-3)
+    rng = np.random.default_rng(0)
+    d = torch.tensor(rng.normal(size=(3,) + w.shape), device="cuda")
+    for _ in range(5):
+        s.apply_projected_hessian(d)
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("probe done: %d^3, copy %d bytes" % (n, COPY_BYTES), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +114,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-matvecs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="short run for hardware-counter passes: after one load step, a few "
+                         "projected-Hessian applications and a calibration copy of known size")
+    ap.add_argument("--grid", type=int, default=64,
+                    help="cell size of the --probe run (the 64^3 workload recipe at N^3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is single-GPU (a batch of cells "
@@ -98,6 +132,9 @@ def main():
     from paper_2207_10657_amd import Solver
     from synthetic import workload
 
+    if args.probe:
+        probe(args.grid)
+        return
     w = workload(WORKLOAD)
     W, K = args.warmup, args.steps
     if W + K > len(w.load_path):

@@ -188,6 +188,7 @@ struct hfe_ctx {
   hipStream_t cap_stream = nullptr;
   CgGraph graphs[2];
   bool use_graphs = true;
+  int hessian_brick_z = 4;   // Hessian brick depth (HFE_HESSIAN_BRICK_Z=8 selects 8x8x8)
 };
 
 namespace {
@@ -317,6 +318,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.f = nullptr;
   A.red = reducer(c);
   A.cg = nullptr;
+  A.brick_z = c->hessian_brick_z;
   return A;
 }
 
@@ -641,6 +643,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
   c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
+  if (const char* bz = std::getenv("HFE_HESSIAN_BRICK_Z")) c->hessian_brick_z = std::atoi(bz) == 8 ? 8 : 4;
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
   c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);

@@ -474,6 +474,128 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
   }
 }
 
+// ---- sum-factorised Q1 gradient and divergence --------------------------
+//
+// With the 2-point rule, dN_a/dx at a point is (+-1) times the 1D linear
+// interpolation weights in y and z, so the x-derivative at the 8 points
+// takes 4 differences along x and two interpolations (y, then z) and has
+// only 4 distinct values (it does not depend on the x Gauss point); the same
+// holds for y and z. G[c][j][m][n] is the derivative of component c along j
+// at the two remaining Gauss coordinates (m, n) in increasing axis order:
+// j = x: (gy, gz); j = y: (gx, gz); j = z: (gx, gy).
+// The divergence is the transpose: point values summed over the Gauss
+// coordinate along j, then the transposed interpolations, then +-1 onto the
+// two node layers along j.
+
+// 1D interpolation of (f0 at node 0, f1 at node 1) to Gauss point g.
+__device__ __forceinline__ double interp(double f0, double f1, int g) {
+  const double w1 = g ? kG1 : kG0;        // weight of node 1 at point g
+  return f0 + w1 * (f1 - f0);
+}
+
+// v[a], a = ax + 2 ay + 4 az  ->  G[j][m][n]
+__device__ __forceinline__ void q1_grad_sf(const double (&v)[8], double (&G)[3][2][2]) {
+  // along x: differences over (ay, az), interpolate y then z
+  {
+    double t[2][2];
+#pragma unroll
+    for (int az = 0; az < 2; ++az)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy)
+        t[gy][az] = interp(v[1 + 4 * az] - v[0 + 4 * az], v[3 + 4 * az] - v[2 + 4 * az], gy);
+#pragma unroll
+    for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) G[0][gy][gz] = interp(t[gy][0], t[gy][1], gz);
+  }
+  // along y: differences over (ax, az), interpolate x then z
+  {
+    double t[2][2];
+#pragma unroll
+    for (int az = 0; az < 2; ++az)
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx)
+        t[gx][az] = interp(v[2 + 4 * az] - v[0 + 4 * az], v[3 + 4 * az] - v[1 + 4 * az], gx);
+#pragma unroll
+    for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) G[1][gx][gz] = interp(t[gx][0], t[gx][1], gz);
+  }
+  // along z: differences over (ax, ay), interpolate x then y
+  {
+    double t[2][2];
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx)
+        t[gx][ay] = interp(v[4 + 2 * ay] - v[0 + 2 * ay], v[5 + 2 * ay] - v[1 + 2 * ay], gx);
+#pragma unroll
+    for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy) G[2][gx][gy] = interp(t[gx][0], t[gx][1], gy);
+  }
+}
+
+// Transpose of interp: a value r at Gauss point g adds (1-w) r to node 0 and
+// w r to node 1.
+__device__ __forceinline__ void interp_t(double r, int g, double& f0, double& f1) {
+  const double w1 = g ? kG1 : kG0;
+  f1 += w1 * r;
+  f0 += r - w1 * r;
+}
+
+// T[j][m][n] (point values summed over the Gauss coordinate along j) -> f[a]
+__device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f)[8]) {
+  // x: T[0][gy][gz] -> (ay, az) by transposed z then y interpolation -> +-1 along x
+  {
+    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gy][az]
+#pragma unroll
+    for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) interp_t(T[0][gy][gz], gz, u[gy][0], u[gy][1]);
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+      double w0 = 0.0, w1 = 0.0;                  // (ay = 0, 1)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy) interp_t(u[gy][az], gy, w0, w1);
+      f[1 + 4 * az] += w0; f[0 + 4 * az] -= w0;
+      f[3 + 4 * az] += w1; f[2 + 4 * az] -= w1;
+    }
+  }
+  // y: T[1][gx][gz]
+  {
+    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gx][az]
+#pragma unroll
+    for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) interp_t(T[1][gx][gz], gz, u[gx][0], u[gx][1]);
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+      double w0 = 0.0, w1 = 0.0;                  // (ax = 0, 1)
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][az], gx, w0, w1);
+      f[2 + 4 * az] += w0; f[0 + 4 * az] -= w0;
+      f[3 + 4 * az] += w1; f[1 + 4 * az] -= w1;
+    }
+  }
+  // z: T[2][gx][gy]
+  {
+    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gx][ay]
+#pragma unroll
+    for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy) interp_t(T[2][gx][gy], gy, u[gx][0], u[gx][1]);
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay) {
+      double w0 = 0.0, w1 = 0.0;                  // (ax = 0, 1)
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][ay], gx, w0, w1);
+      f[4 + 2 * ay] += w0; f[0 + 2 * ay] -= w0;
+      f[5 + 2 * ay] += w1; f[1 + 2 * ay] -= w1;
+    }
+  }
+}
+
 // ---- brick kernels (Q1) ---------------------------------------------------
 //
 // One block per brick of kBx x kBy x kBz nodes. The block computes the
@@ -587,7 +709,71 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
   double red[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) red[k] = 0.0;
-  if (active) {
+  if (MODE == MODE_HESSIAN && active) {
+    // sum-factorised gradient of the direction, tangent per point, and the
+    // transposed (factorised) divergence
+    const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
+    const int t0 = ex + tx * (ey + ty * ez);
+    const int sy = tx, sz = tx * ty;
+    const bool owned = ex >= 1 && ey >= 1 && ez >= 1;
+    double G[3][3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        v[a] = sv[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
+      q1_grad_sf(v, G[c]);
+    }
+    double T[3][3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) T[c][j][m][k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
+      double dH[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dH[c][0] = G[c][0][gy][gz];
+        dH[c][1] = G[c][1][gx][gz];
+        dH[c][2] = G[c][2][gx][gy];
+      }
+      const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
+      Sym s;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
+      if (cq != 0.0) {
+        double H[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) H[i][j] = A.E[3 * i + j];
+        tile_grad<kTile>(su, q, t0, sy, sz, H);
+        s = c_contract(sym_of<3>(H), lam, mu);
+      }
+      const Sym tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
+      if (owned) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) red[HES_DD] += dH[i][j] * dH[i][j];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T[c][0][gy][gz] += sym_at(tau, c, 0);
+        T[c][1][gx][gz] += sym_at(tau, c, 1);
+        T[c][2][gx][gy] += sym_at(tau, c, 2);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
+  } else if (MODE != MODE_HESSIAN && active) {
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     const int sy = tx, sz = tx * ty;
@@ -600,30 +786,7 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
 #pragma unroll 1
     for (int q = 0; q < 8; ++q) {
       Sym tau;
-      if (MODE == MODE_HESSIAN) {
-        const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
-        double dH[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-        tile_grad(sv, q, t0, sy, sz, dH);
-        Sym s;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
-        if (cq != 0.0) {
-          double H[3][3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
-          tile_grad(su, q, t0, sy, sz, H);
-          s = c_contract(sym_of<3>(H), lam, mu);
-        }
-        tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
-        if (owned) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) red[HES_DD] += dH[i][j] * dH[i][j];
-        }
-      } else {
+      {
         double H[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -720,13 +883,18 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
   block_reduce_store<NV>(red, A.red.partials);
 }
 
-template <int MODE, int NV>
-hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  constexpr int BZ = MODE == MODE_HESSIAN ? 8 : 4;
+template <int MODE, int NV, int BZ>
+hipError_t launch_brick_bz(const ElemArgs& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
   hipLaunchKernelGGL((k_brick<MODE, NV, BZ>), dim3(nb), dim3(BrickShape<BZ>::threads), 0, s, A);
   return hipGetLastError();
+}
+
+template <int MODE, int NV>
+hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  if (MODE == MODE_HESSIAN && A.brick_z == 8) return launch_brick_bz<MODE, NV, 8>(A, s, nblocks);
+  return launch_brick_bz<MODE, NV, 4>(A, s, nblocks);
 }
 
 template <int MODE, int NV>
