@@ -188,7 +188,7 @@ struct hfe_ctx {
   hipStream_t cap_stream = nullptr;
   CgGraph graphs[2];
   bool use_graphs = true;
-  int hessian_brick_z = 4;   // Hessian brick depth (HFE_HESSIAN_BRICK_Z=8 selects 8x8x8)
+  int brick_shape = 0;       // Q1 brick shape (HFE_BRICK_SHAPE=0..3 overrides)
 };
 
 namespace {
@@ -318,7 +318,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.f = nullptr;
   A.red = reducer(c);
   A.cg = nullptr;
-  A.brick_z = c->hessian_brick_z;
+  A.brick_shape = c->brick_shape;
   return A;
 }
 
@@ -643,7 +643,10 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
   c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
-  if (const char* bz = std::getenv("HFE_HESSIAN_BRICK_Z")) c->hessian_brick_z = std::atoi(bz) == 8 ? 8 : 4;
+  if (const char* bs = std::getenv("HFE_BRICK_SHAPE")) {
+    const int v = std::atoi(bs);
+    if (v >= 0 && v <= 3) c->brick_shape = v;
+  }
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
   c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);

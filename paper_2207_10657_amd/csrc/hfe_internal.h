@@ -66,7 +66,7 @@ struct ElemArgs {
   double* f;             // nodal output [dim][N]
   Reducer red;
   CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
-  int brick_z;           // depth of the Hessian brick (8: 768 threads, 4: 448 threads)
+  int brick_shape;       // brick shape of the Q1 element passes (see launch_brick)
 };
 
 // Residual: f = D^T sigma(E + D u), writes a_out/cp_out, partial rows RES_*.

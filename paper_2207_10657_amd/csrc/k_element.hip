@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         Sym tau;
-        if (MODE == MODE_HESSIAN) {
+        if constexpr (MODE == MODE_HESSIAN) {
           double dH[3][3];
           grad_at<EL>(q, vn, dH);
           const double aq = A.a[q * g.N + ei], cq = A.cp[q * g.N + ei];
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
               for (int j = 0; j < D; ++j) dd += dH[i][j] * dH[i][j];
             acc[HES_DD] += dd;
           }
-        } else if (MODE == MODE_RESIDUAL) {
+        } else if constexpr (MODE == MODE_RESIDUAL) {
           double H[3][3];
           grad_at<EL>(q, un, H);
 #pragma unroll
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) A.f[i * g.N + n] = fo[i];
-    if (MODE == MODE_HESSIAN) {
+    if constexpr (MODE == MODE_HESSIAN) {
       double dk = 0.0;
 #pragma unroll
       for (int i = 0; i < D; ++i) dk += A.v[i * g.N + n] * fo[i];
@@ -598,7 +598,7 @@ __device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f
 
 // ---- brick kernels (Q1) ---------------------------------------------------
 //
-// One block per brick of kBx x kBy x kBz nodes. The block computes the
+// One block per brick of BX x BY x BZ nodes. The block computes the
 // (kB+1)^3 elements whose nodes include its own (one layer of halo elements
 // on the low side of each axis, recomputed by the neighbouring block as
 // well), one element per thread, with the nodal inputs staged in LDS. The
@@ -610,16 +610,23 @@ __device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f
 //   MODE_HESSIAN : f = K v = D^T B D v;  rows {v.Kv, |D v|^2}
 //   MODE_RESIDUAL: f = D^T sigma(E + D u), a/c' written;  rows RES_*
 //   MODE_TRIAL   : f = D^T sigma(E + D(u+v)), trial a/c' written;  rows TRI_*
-// The Hessian uses 8x8x8 bricks (768 threads >= 9^3 elements); the residual
-// and trial passes, which hold more per-point state, use 8x8x4 bricks (448
-// threads >= 9x9x5 elements) so that a thread may use up to 256 registers.
-constexpr int kBx = 8, kBy = 8;
-template <int BZ> struct BrickShape {
-  static constexpr int tile = (kBx + 2) * (kBy + 2) * (BZ + 2);   // staged nodes
-  static constexpr int own = kBx * kBy * BZ;                       // owned nodes
-  static constexpr int threads = BZ == 8 ? 768 : 448;             // >= (kB+1)^3 elements
+// Brick shapes (nodes BX x BY x BZ; the block runs one thread per element of
+// the (BX+1)(BY+1)(BZ+1) element brick, rounded up to whole wavefronts).
+template <int BX, int BY, int BZ> struct BrickShape {
+  static constexpr int tile = (BX + 2) * (BY + 2) * (BZ + 2);      // staged nodes
+  static constexpr int own = BX * BY * BZ;                          // owned nodes
+  static constexpr int elems = (BX + 1) * (BY + 1) * (BZ + 1);
+  static constexpr int threads = (elems + 63) / 64 * 64;
 };
-constexpr int kTileMax = BrickShape<8>::tile;
+
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Give every XCD a contiguous run of bricks so that the halos neighbouring
+// bricks share are fetched once into that XCD's L2.
+__device__ __forceinline__ int xcd_brick(int b, int nb) {
+  const int q = nb / 8;
+  if (b >= 8 * q) return b;
+  return (b % 8) * q + b / 8;
+}
 
 __device__ __forceinline__ int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
 
@@ -642,19 +649,20 @@ __device__ __forceinline__ void tile_grad(const double (*f)[TILE], int q, int t0
   }
 }
 
-template <int MODE, int NV, int BZ>
-__global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
-  constexpr int kTile = BrickShape<BZ>::tile, kOwn = BrickShape<BZ>::own;
+template <int MODE, int NV, int BX, int BY, int BZ>
+__global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(ElemArgs A) {
+  constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
   if (MODE == MODE_HESSIAN && A.cg && A.cg->done) return;
   __shared__ double sv[3][kTile];   // v: direction (Hessian) or step (trial)
   __shared__ double su[3][kTile];   // u
   __shared__ double acc[3][kOwn];
   __shared__ int need_u_flag;
-  const int nbx = (g.nx + kBx - 1) / kBx, nby = (g.ny + kBy - 1) / kBy;
-  const int bxi = blockIdx.x % nbx, byi = (blockIdx.x / nbx) % nby, bzi = blockIdx.x / (nbx * nby);
-  const int x0 = bxi * kBx, y0 = byi * kBy, z0 = bzi * BZ;
-  const int bx = min(kBx, g.nx - x0), by = min(kBy, g.ny - y0), bz = min(BZ, g.nz - z0);
+  const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
+  const int brick = xcd_brick(blockIdx.x, gridDim.x);
+  const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
   const int tx = bx + 2, ty = by + 2, tz = bz + 2;          // staged node tile
   const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;    // element brick
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -709,7 +717,8 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
   double red[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) red[k] = 0.0;
-  if (MODE == MODE_HESSIAN && active) {
+  if constexpr (MODE == MODE_HESSIAN) {
+   if (active) {
     // sum-factorised gradient of the direction, tangent per point, and the
     // transposed (factorised) divergence
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
@@ -773,7 +782,8 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
-  } else if (MODE != MODE_HESSIAN && active) {
+   }
+  } else if (active) {
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     const int sy = tx, sz = tx * ty;
@@ -813,7 +823,7 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) hh += Ht[i][j] * Ht[i][j];
-          if (MODE == MODE_RESIDUAL) {
+          if constexpr (MODE == MODE_RESIDUAL) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
             red[RES_SS] += sym_dot(tau, tau);
@@ -879,22 +889,30 @@ __global__ void __launch_bounds__(BrickShape<BZ>::threads) k_brick(ElemArgs A) {
       if (MODE == MODE_HESSIAN) dkd += v * sv[c][ti];
     }
   }
-  if (MODE == MODE_HESSIAN) red[HES_DKD] += dkd;
+  if constexpr (MODE == MODE_HESSIAN) red[HES_DKD] += dkd;
   block_reduce_store<NV>(red, A.red.partials);
 }
 
-template <int MODE, int NV, int BZ>
-hipError_t launch_brick_bz(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  const int nb = ((A.g.nx + kBx - 1) / kBx) * ((A.g.ny + kBy - 1) / kBy) * ((A.g.nz + BZ - 1) / BZ);
+template <int MODE, int NV, int BX, int BY, int BZ>
+hipError_t launch_brick_shape(const ElemArgs& A, hipStream_t s, int* nblocks) {
+  const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
-  hipLaunchKernelGGL((k_brick<MODE, NV, BZ>), dim3(nb), dim3(BrickShape<BZ>::threads), 0, s, A);
+  hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ>), dim3(nb), dim3(BrickShape<BX, BY, BZ>::threads),
+                     0, s, A);
   return hipGetLastError();
 }
 
+// Brick shapes: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768), 2 = 16x8x4 (768),
+// 3 = 16x4x4 (448). The residual and trial passes use 8x8x4 or 16x4x4.
 template <int MODE, int NV>
 hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  if (MODE == MODE_HESSIAN && A.brick_z == 8) return launch_brick_bz<MODE, NV, 8>(A, s, nblocks);
-  return launch_brick_bz<MODE, NV, 4>(A, s, nblocks);
+  const int shape = A.brick_shape;
+  if constexpr (MODE == MODE_HESSIAN) {
+    if (shape == 1) return launch_brick_shape<MODE, NV, 8, 8, 8>(A, s, nblocks);
+    if (shape == 2) return launch_brick_shape<MODE, NV, 16, 8, 4>(A, s, nblocks);
+  }
+  if (shape == 2 || shape == 3) return launch_brick_shape<MODE, NV, 16, 4, 4>(A, s, nblocks);
+  return launch_brick_shape<MODE, NV, 8, 8, 4>(A, s, nblocks);
 }
 
 template <int MODE, int NV>
