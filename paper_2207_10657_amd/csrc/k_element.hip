@@ -673,13 +673,30 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
     return lin(g, wrap(x0 - 1 + lx, g.nx), wrap(y0 - 1 + ly, g.ny), wrap(z0 - 1 + lz, g.nz));
   };
-  if (MODE != MODE_RESIDUAL) {
-    for (int i = tid; i < ntile; i += nt) {
-      const long long n = tile_node(i);
+  // stage a nodal field on the tile: every load of a thread is issued before
+  // its LDS stores
+  constexpr int kIt = (kTile + BrickShape<BX, BY, BZ>::threads - 1) / BrickShape<BX, BY, BZ>::threads;
+  auto stage = [&](const double* __restrict__ src, double (*dst)[kTile]) {
+    double r[kIt][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sv[c][i] = A.v[c * g.N + n];
+    for (int it = 0; it < kIt; ++it) {
+      const int i = tid + it * nt;
+      if (i < ntile) {
+        const long long n = tile_node(i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[it][c] = src[c * g.N + n];
+      }
     }
-  }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = tid + it * nt;
+      if (i < ntile) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c][i] = r[it][c];
+      }
+    }
+  };
+  if (MODE != MODE_RESIDUAL) stage(A.v, sv);
   for (int i = tid; i < bx * by * bz; i += nt) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c][i] = 0.0;
@@ -702,11 +719,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   }
   __syncthreads();
   if (need_u_flag) {
-    for (int i = tid; i < ntile; i += nt) {
-      const long long n = tile_node(i);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) su[c][i] = A.u[c * g.N + n];
-    }
+    stage(A.u, su);
     __syncthreads();
   }
   double f[3][8];

@@ -35,6 +35,27 @@ __device__ __forceinline__ double2 mul_mi(double2 a) {
   return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
+// Copy `total` elements with up to kStage independent loads in flight per
+// thread (all loads of a round are issued before any store).
+constexpr int kStage = 8;
+template <typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int total, Load load, Store store) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int base = 0; base < total; base += kStage * nt) {
+    double2 r[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = base + u * nt + tid;
+      if (i < total) r[u] = load(i);
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = base + u * nt + tid;
+      if (i < total) store(i, r[u]);
+    }
+  }
+}
+
 constexpr int radix_of(int rem) { return rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2); }
 
 template <int R, bool INV> struct Bfly;
@@ -236,10 +257,11 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
   double2* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
   if (MODE != PLANE_INV) {
     const double2* src = reinterpret_cast<const double2*>(in + plane);
-    for (int i = tid; i < M * ny; i += nt) {
-      const int y = i / M, m = i - y * M;
-      lds[y * P + m] = src[i];
-    }
+    staged_copy(M * ny, [&](int i) { return src[i]; },
+                [&](int i, double2 v) {
+                  const int y = i / M, m = i - y * M;
+                  lds[y * P + m] = v;
+                });
     __syncthreads();
     lds_fft<false>(M, lds, ny, P, 1, t.tw + t.off_x);
     split_r2c(lds, M, ny, P, t.tw + t.off_post);
@@ -257,7 +279,7 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
     }
     __syncthreads();
   } else {
-    for (int i = tid; i < P * ny; i += nt) lds[i] = sp[i];
+    staged_copy(P * ny, [&](int i) { return sp[i]; }, [&](int i, double2 v) { lds[i] = v; });
     __syncthreads();
   }
   lds_fft<true>(ny, lds, P, 1, P, t.tw + t.off_y);
@@ -284,12 +306,18 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
   double2* base = spec + (long long)c * nz * ny * P + (long long)ky * P + kx0;
   const long long zs = (long long)ny * P;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < nz * cv; i += nt) {
-    const int zz = i / cv, j = i - zz * cv;
-    lds[zz * C + j] = base[zz * zs + j];
-  }
+  // LDS row pitch C + 1: consecutive z of one kx column fall in different banks
+  const int CP = C + 1;
+  staged_copy(nz * cv, [&](int i) {
+                const int zz = i / cv, j = i - zz * cv;
+                return base[zz * zs + j];
+              },
+              [&](int i, double2 v) {
+                const int zz = i / cv, j = i - zz * cv;
+                lds[zz * CP + j] = v;
+              });
   __syncthreads();
-  if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, C, t.tw + t.off_z);
+  if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, CP, t.tw + t.off_z);
   if (MODE == PENCIL_GREEN) {
     const double syv = t.sy[ky];
     for (int i = tid; i < nz * cv; i += nt) {
@@ -297,15 +325,15 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
       const int kx = kx0 + j;
       const double S = green_q1(t.sx[kx], syv, t.sz[kz]);
       const double m = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / S;
-      const double2 v = lds[kz * C + j];
-      lds[kz * C + j] = make_double2(v.x * m, v.y * m);
+      const double2 v = lds[kz * CP + j];
+      lds[kz * CP + j] = make_double2(v.x * m, v.y * m);
     }
     __syncthreads();
   }
-  if (MODE != PENCIL_FWD) lds_fft<true>(nz, lds, cv, 1, C, t.tw + t.off_z);
+  if (MODE != PENCIL_FWD) lds_fft<true>(nz, lds, cv, 1, CP, t.tw + t.off_z);
   for (int i = tid; i < nz * cv; i += nt) {
     const int zz = i / cv, j = i - zz * cv;
-    base[zz * zs + j] = lds[zz * C + j];
+    base[zz * zs + j] = lds[zz * CP + j];
   }
 }
 
@@ -337,7 +365,7 @@ hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, doubl
                          hipStream_t s, const CgState* skip = nullptr) {
   const int P = g.nx / 2 + 1;
   const int nchunk = (P + kPencilC - 1) / kPencilC;
-  const size_t lds = (size_t)kPencilC * g.nz * sizeof(double2);
+  const size_t lds = (size_t)(kPencilC + 1) * g.nz * sizeof(double2);
   hipLaunchKernelGGL(k_pencil<MODE>, dim3(nchunk, g.ny, g.dim), dim3(256), lds, s, g, t, spec,
                      kPencilC, scale, skip);
   return hipGetLastError();
