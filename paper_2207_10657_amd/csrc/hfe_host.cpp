@@ -74,7 +74,10 @@ bool grid_ok(const hfe_grid* gr, std::string* why) {
     *why = "nx/2, ny and nz must each be one of 1,2,3,4,6,8,12,16,24,32,48,64,96,128";
     return false;
   }
-  if ((size_t)(nx / 2 + 1) * ny * 16 > 160 * 1024) { *why = "a spectral x-y plane must fit in 160 KiB of LDS"; return false; }
+  if (((size_t)(nx / 2 + 1) * ny + nx + 1 + ny) * 16 > 160 * 1024) {
+    *why = "a spectral x-y plane (with its twiddles) must fit in 160 KiB of LDS";
+    return false;
+  }
   return true;
 }
 

@@ -56,7 +56,9 @@ __device__ __forceinline__ void staged_copy(int total, Load load, Store store) {
   }
 }
 
-constexpr int radix_of(int rem) { return rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2); }
+constexpr int radix_of(int rem) {
+  return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2));
+}
 
 template <int R, bool INV> struct Bfly;
 template <bool INV> struct Bfly<2, INV> {
@@ -87,6 +89,32 @@ template <bool INV> struct Bfly<4, INV> {
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, mul_mi<INV>(t3));
     v[3] = csub(t1, mul_mi<INV>(t3));
+  }
+};
+
+template <bool INV> struct Bfly<8, INV> {
+  // 8-point DFT = two 4-point DFTs (even, odd samples) and one radix-2 stage
+  // with the twiddles e^{-+ 2 pi i k / 8}
+  __device__ static void run(double2 (&v)[8]) {
+    constexpr double kR = 0.70710678118654752440;   // 1/sqrt(2)
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<4, INV>::run(e);
+    Bfly<4, INV>::run(o);
+    // w^1 o[1], w^2 o[2], w^3 o[3] with w = e^{-2 pi i/8} (conjugate for INV)
+    const double2 o1 = INV ? make_double2(kR * (o[1].x - o[1].y), kR * (o[1].x + o[1].y))
+                           : make_double2(kR * (o[1].x + o[1].y), kR * (o[1].y - o[1].x));
+    const double2 o2 = mul_mi<INV>(o[2]);
+    const double2 o3 = INV ? make_double2(-kR * (o[3].x + o[3].y), kR * (o[3].x - o[3].y))
+                           : make_double2(kR * (o[3].y - o[3].x), -kR * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
   }
 };
 
@@ -255,6 +283,18 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
   const long long plane = (long long)c * g.N + (long long)z * nx * ny;
   const int tid = threadIdx.x, nt = blockDim.x;
   double2* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
+  // twiddles of the x (length M) and y (length ny) transforms and of the
+  // split step, staged once into LDS behind the plane
+  double2* twx = lds + P * ny;
+  double2* twy = twx + M;
+  double2* twp = twy + ny;
+  for (int i = tid; i < 2 * M + 1 + ny; i += nt) {
+    double2 v;
+    if (i < M) v = t.tw[t.off_x + i];
+    else if (i < M + ny) v = t.tw[t.off_y + i - M];
+    else v = t.tw[t.off_post + i - M - ny];
+    twx[i] = v;
+  }
   if (MODE != PLANE_INV) {
     const double2* src = reinterpret_cast<const double2*>(in + plane);
     staged_copy(M * ny, [&](int i) { return src[i]; },
@@ -263,9 +303,9 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
                   lds[y * P + m] = v;
                 });
     __syncthreads();
-    lds_fft<false>(M, lds, ny, P, 1, t.tw + t.off_x);
-    split_r2c(lds, M, ny, P, t.tw + t.off_post);
-    lds_fft<false>(ny, lds, P, 1, P, t.tw + t.off_y);
+    lds_fft<false>(M, lds, ny, P, 1, twx);
+    split_r2c(lds, M, ny, P, twp);
+    lds_fft<false>(ny, lds, P, 1, P, twy);
     if (MODE == PLANE_FWD) {
       for (int i = tid; i < P * ny; i += nt) sp[i] = lds[i];
       return;
@@ -282,9 +322,9 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
     staged_copy(P * ny, [&](int i) { return sp[i]; }, [&](int i, double2 v) { lds[i] = v; });
     __syncthreads();
   }
-  lds_fft<true>(ny, lds, P, 1, P, t.tw + t.off_y);
-  merge_c2r(lds, M, ny, P, t.tw + t.off_post);
-  lds_fft<true>(M, lds, ny, P, 1, t.tw + t.off_x);
+  lds_fft<true>(ny, lds, P, 1, P, twy);
+  merge_c2r(lds, M, ny, P, twp);
+  lds_fft<true>(M, lds, ny, P, 1, twx);
   double2* dst = reinterpret_cast<double2*>(out + plane);
   for (int i = tid; i < M * ny; i += nt) {
     const int y = i / M, m = i - y * M;
@@ -308,6 +348,8 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
   const int tid = threadIdx.x, nt = blockDim.x;
   // LDS row pitch C + 1: consecutive z of one kx column fall in different banks
   const int CP = C + 1;
+  double2* twz = lds + CP * nz;    // z twiddles staged behind the pencils
+  for (int i = tid; i < nz; i += nt) twz[i] = t.tw[t.off_z + i];
   staged_copy(nz * cv, [&](int i) {
                 const int zz = i / cv, j = i - zz * cv;
                 return base[zz * zs + j];
@@ -317,7 +359,7 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
                 lds[zz * CP + j] = v;
               });
   __syncthreads();
-  if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, CP, t.tw + t.off_z);
+  if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, CP, twz);
   if (MODE == PENCIL_GREEN) {
     const double syv = t.sy[ky];
     for (int i = tid; i < nz * cv; i += nt) {
@@ -330,7 +372,7 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
     }
     __syncthreads();
   }
-  if (MODE != PENCIL_FWD) lds_fft<true>(nz, lds, cv, 1, CP, t.tw + t.off_z);
+  if (MODE != PENCIL_FWD) lds_fft<true>(nz, lds, cv, 1, CP, twz);
   for (int i = tid; i < nz * cv; i += nt) {
     const int zz = i / cv, j = i - zz * cv;
     base[zz * zs + j] = lds[zz * CP + j];
@@ -365,7 +407,7 @@ hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, doubl
                          hipStream_t s, const CgState* skip = nullptr) {
   const int P = g.nx / 2 + 1;
   const int nchunk = (P + kPencilC - 1) / kPencilC;
-  const size_t lds = (size_t)(kPencilC + 1) * g.nz * sizeof(double2);
+  const size_t lds = ((size_t)(kPencilC + 1) * g.nz + g.nz) * sizeof(double2);
   hipLaunchKernelGGL(k_pencil<MODE>, dim3(nchunk, g.ny, g.dim), dim3(256), lds, s, g, t, spec,
                      kPencilC, scale, skip);
   return hipGetLastError();
@@ -384,7 +426,8 @@ bool fft_length_supported(int L) {
 }
 
 size_t fft_plane_lds_bytes(const Grid& g) {
-  return (size_t)(g.nx / 2 + 1) * g.ny * sizeof(double2);
+  const int M = g.nx / 2;
+  return ((size_t)(M + 1) * g.ny + 2 * M + 1 + g.ny) * sizeof(double2);
 }
 
 hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
