@@ -46,6 +46,7 @@ struct Layout {
   size_t phase;                                       // N bytes
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
+  size_t partials2;                                   // second row buffer (direction sums)
   size_t cgstate;                                     // device CgState
   size_t trace;                                       // CG trace, 2 doubles per entry
   size_t Edev;                                        // macroscopic strain (9 doubles)
@@ -108,6 +109,7 @@ Layout make_layout(const Grid& g) {
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
+  L.partials2 = take((size_t)L.partial_rows * 2 * sizeof(double));
   L.cgstate = take(sizeof(hfe::CgState));
   L.trace = take((size_t)2 * kTraceCap * sizeof(double));
   L.Edev = take(9 * sizeof(double));
@@ -159,6 +161,8 @@ struct hfe_ctx {
   uint8_t* phase;
   double2* spec;
   double* partials;
+  double* partials2;
+  int nb_dir = 0;            // rows of the pending direction sums in partials2
   hfe::CgState* cg;          // device CG state
   double* Edev;              // device copy of E
   double* trace;             // device CG trace
@@ -423,33 +427,69 @@ hfe_status evaluate_state(hfe_ctx* c) {
 
 struct CgInfo { int iters = 0, restarts = 0, matvecs = 0; };
 
-// d = -y + beta d with <r, d> and z.g, then the direction update of the state.
+// d = -y + beta d with <r, d> and z.g into the second row buffer; the
+// direction update of the state is applied by the next iteration's finish.
 hfe_status direction(hfe_ctx* c) {
-  int nb = 0;
-  {
-    Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_d(ndof(c), c->y, c->d, c->gv, c->z, reducer(c), c->cg, c->stream, &nb));
-  }
-  return finish(c, hfe::FIN_DIRECTION, nb, 2, nullptr);
+  hfe::Reducer r;
+  r.partials = c->partials2;
+  Prof p(c, "cg_vec");
+  HIPCHK(c, hfe::cg_step_d(ndof(c), c->y, c->d, c->gv, c->z, r, c->cg, c->stream, &c->nb_dir));
+  return HFE_OK;
 }
 
-// One CG iteration, all decisions on the device (no host synchronisation).
+// One CG iteration, all decisions on the device (no host synchronisation):
+// K d, [direction update of the previous iteration + curvature decision],
+// z/g update + forward FFT, Green z-pass, inverse FFT + y update + residual
+// sums, [residual decision], new direction.
 hfe_status cg_iteration(hfe_ctx* c) {
   const long long n = ndof(c);
-  hfe_status st = stiffness(c, c->d, c->Kd, true);
-  if (st) return st;
-  {
-    Prof p(c, "cg_vec");
-    HIPCHK(c, hfe::cg_step_zg(n, c->d, c->Kd, c->z, c->gv, c->cg, c->stream));
-  }
-  st = green(c, c->Kd, c->w, c->cg);
-  if (st) return st;
+  hfe::ElemArgs A = elem_args(c);
+  A.v = c->d;
+  A.f = c->Kd;
+  A.cg = c->cg;
   int nb = 0;
   {
+    Prof p(c, "stiffness");
+    HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
+  }
+  {
+    hfe::Reducer rd;
+    rd.partials = c->partials2;
+    Prof p(c, "finish");
+    HIPCHK(c, hfe::finish_direction_curvature(rd, c->nb_dir, reducer(c), nb, c->cg, c->trace,
+                                              c->stream));
+  }
+  if (c->g.dim == 3) {
+    hfe::CgFuse f;
+    f.st = c->cg;
+    f.d = c->d;
+    f.z = c->z;
+    f.g = c->gv;
+    f.y = c->y;
+    f.partials = c->partials;
+    {
+      Prof p(c, "fft_plane_fwd");
+      HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs, c->Kd, c->spec, f, c->stream));
+    }
+    {
+      Prof p(c, "fft_pencil_green");
+      HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream, c->cg));
+    }
+    {
+      Prof p(c, "fft_plane_inv");
+      HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs, c->spec, f, c->stream, &nb));
+    }
+  } else {
+    {
+      Prof p(c, "cg_vec");
+      HIPCHK(c, hfe::cg_step_zg(n, c->d, c->Kd, c->z, c->gv, c->cg, c->stream));
+    }
+    hfe_status st = green(c, c->Kd, c->w, c->cg);
+    if (st) return st;
     Prof p(c, "cg_vec");
     HIPCHK(c, hfe::cg_step_y(n, c->w, c->y, c->gv, reducer(c), c->cg, c->stream, &nb));
   }
-  st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
+  hfe_status st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
   if (st) return st;
   return direction(c);
 }
@@ -658,6 +698,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
+  c->partials2 = D(L.partials2);
   c->cg = (hfe::CgState*)(c->ws + L.cgstate);
   c->trace = D(L.trace);
   c->Edev = D(L.Edev);

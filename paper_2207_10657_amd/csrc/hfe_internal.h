@@ -114,6 +114,24 @@ hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, d
                              hipStream_t s, const CgState* skip = nullptr);
 hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
                              double2* spec, hipStream_t s, const CgState* skip = nullptr);
+
+// CG iteration passes with the vector updates fused in (3D):
+//  forward plane pass of Kd that also does z += alpha d, g += alpha Kd (or,
+//  when the CG has just stopped on the sphere, z += tau d);
+//  inverse plane pass that, instead of writing w = L^+ Kd, does y += alpha w
+//  and writes partial rows {y_new.g, y_old.g} (one row per plane block).
+struct CgFuse {
+  CgState* st;
+  const double* d;
+  double* z;
+  double* g;
+  double* y;
+  double* partials;
+};
+hipError_t fft_plane_forward_cg(const Grid& g, const FftTables& t, const double* Kd, double2* spec,
+                                const CgFuse& f, hipStream_t s);
+hipError_t fft_plane_inverse_cg(const Grid& g, const FftTables& t, double2* spec, const CgFuse& f,
+                                hipStream_t s, int* nblocks);
 hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
                        hipStream_t s);
 hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
@@ -150,5 +168,9 @@ enum { FIN_OUT = 0,          // write the nv totals to out (device or host-mappe
        FIN_DIRECTION = 3 };  // CG direction update on {g.d, z.g}
 hipError_t finish(int kind, const Reducer& r, int nblocks, int nv, double* out, CgState* st,
                   double* trace, hipStream_t s);
+// Direction update (rows rd of {g.d, z.g}) then curvature decision (rows rc of
+// {d.Kd, |Dd|^2}), one block.
+hipError_t finish_direction_curvature(const Reducer& rd, int nbd, const Reducer& rc, int nbc,
+                                      CgState* st, double* trace, hipStream_t s);
 
 }  // namespace hfe

@@ -20,7 +20,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Reduce acc[NV] over the block (blockDim.x a multiple of 64, at most 1024)
 // and store the block's row partials[blockIdx.x * NV + k].
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* partials) {
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* partials,
+                                                   int row = -1) {
   __shared__ double red[16][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -33,7 +34,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* pa
   if (threadIdx.x < NV) {
     double s = 0.0;
     for (int w = 0; w < nwaves; ++w) s += red[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+    partials[(size_t)(row < 0 ? (int)blockIdx.x : row) * NV + threadIdx.x] = s;
   }
 }
 

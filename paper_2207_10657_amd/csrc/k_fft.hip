@@ -19,6 +19,7 @@
 // on lines held in LDS, with every thread staging its butterflies in
 // registers between two barriers so that one LDS buffer suffices.
 #include "hfe_internal.h"
+#include "hfe_reduce.h"
 
 namespace hfe {
 namespace {
@@ -270,18 +271,27 @@ __device__ __forceinline__ double green_q1(double sx, double sy, double sz) {
 }
 __device__ __forceinline__ double green_p1(double sx, double sy) { return 2.0 * (sx + sy); }
 
-enum { PLANE_FWD = 0, PLANE_INV = 1, PLANE_GREEN2D = 2 };
+enum { PLANE_FWD = 0, PLANE_INV = 1, PLANE_GREEN2D = 2, PLANE_FWD_CG = 3, PLANE_INV_CG = 4 };
 
 template <int MODE>
 __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const double* __restrict__ in,
                                                 double* __restrict__ out, double2* __restrict__ spec,
-                                                double scale, const CgState* skip) {
-  if (skip && skip->done) return;
-  extern __shared__ double2 lds[];
+                                                double scale, const CgState* skip, CgFuse cf) {
   const int nx = g.nx, ny = g.ny, M = nx / 2, P = M + 1;
   const int z = blockIdx.x, c = blockIdx.y;
   const long long plane = (long long)c * g.N + (long long)z * nx * ny;
   const int tid = threadIdx.x, nt = blockDim.x;
+  if (MODE == PLANE_FWD_CG && cf.st->done) {
+    // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
+    if (cf.st->apply_tau) {
+      const double tau = cf.st->tau;
+      for (int i = tid; i < nx * ny; i += nt) cf.z[plane + i] += tau * cf.d[plane + i];
+    }
+    return;
+  }
+  if (MODE == PLANE_INV_CG && cf.st->done) return;
+  if (skip && skip->done) return;
+  extern __shared__ double2 lds[];
   double2* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
   // twiddles of the x (length M) and y (length ny) transforms and of the
   // split step, staged once into LDS behind the plane
@@ -303,10 +313,19 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
                   lds[y * P + m] = v;
                 });
     __syncthreads();
+    if (MODE == PLANE_FWD_CG) {
+      // z += alpha d, g += alpha Kd on this plane (Kd is the transform input)
+      const double alpha = cf.st->alpha;
+      const double* kd = in + plane;
+      for (int i = tid; i < nx * ny; i += nt) {
+        cf.z[plane + i] += alpha * cf.d[plane + i];
+        cf.g[plane + i] += alpha * kd[i];
+      }
+    }
     lds_fft<false>(M, lds, ny, P, 1, twx);
     split_r2c(lds, M, ny, P, twp);
     lds_fft<false>(ny, lds, P, 1, P, twy);
-    if (MODE == PLANE_FWD) {
+    if (MODE == PLANE_FWD || MODE == PLANE_FWD_CG) {
       for (int i = tid; i < P * ny; i += nt) sp[i] = lds[i];
       return;
     }
@@ -325,6 +344,25 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
   lds_fft<true>(ny, lds, P, 1, P, twy);
   merge_c2r(lds, M, ny, P, twp);
   lds_fft<true>(M, lds, ny, P, 1, twx);
+  if (MODE == PLANE_INV_CG) {
+    // y += alpha w and the residual inner products, w never leaves LDS
+    const double alpha = cf.st->alpha;
+    double2* y2 = reinterpret_cast<double2*>(cf.y + plane);
+    const double2* g2 = reinterpret_cast<const double2*>(cf.g + plane);
+    double acc[2] = {0.0, 0.0};
+    for (int i = tid; i < M * ny; i += nt) {
+      const int yy = i / M, m = i - yy * M;
+      const double2 w = lds[yy * P + m];
+      const double2 yo = y2[i];
+      const double2 gi = g2[i];
+      const double2 yn = make_double2(yo.x + alpha * w.x, yo.y + alpha * w.y);
+      y2[i] = yn;
+      acc[0] += yn.x * gi.x + yn.y * gi.y;
+      acc[1] += yo.x * gi.x + yo.y * gi.y;
+    }
+    block_reduce_store<2>(acc, cf.partials, (int)(blockIdx.y * gridDim.x + blockIdx.x));
+    return;
+  }
   double2* dst = reinterpret_cast<double2*>(out + plane);
   for (int i = tid; i < M * ny; i += nt) {
     const int y = i / M, m = i - y * M;
@@ -390,7 +428,8 @@ int plane_threads(const Grid& g) {
 
 template <int MODE>
 hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, double* out,
-                        double2* spec, double scale, hipStream_t s, const CgState* skip = nullptr) {
+                        double2* spec, double scale, hipStream_t s, const CgState* skip = nullptr,
+                        CgFuse cf = CgFuse{}) {
   const size_t lds = fft_plane_lds_bytes(g);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE>,
@@ -398,7 +437,7 @@ hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, dou
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_plane<MODE>, dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t, in,
-                     out, spec, scale, skip);
+                     out, spec, scale, skip, cf);
   return hipGetLastError();
 }
 
@@ -448,6 +487,17 @@ hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hi
 hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
                              double2* spec, hipStream_t s, const CgState* skip) {
   return launch_plane<PLANE_GREEN2D>(g, t, in, out, spec, 1.0 / (double)g.N, s, skip);
+}
+
+hipError_t fft_plane_forward_cg(const Grid& g, const FftTables& t, const double* Kd, double2* spec,
+                                const CgFuse& f, hipStream_t s) {
+  return launch_plane<PLANE_FWD_CG>(g, t, Kd, nullptr, spec, 1.0, s, nullptr, f);
+}
+
+hipError_t fft_plane_inverse_cg(const Grid& g, const FftTables& t, double2* spec, const CgFuse& f,
+                                hipStream_t s, int* nblocks) {
+  *nblocks = g.nz * g.dim;
+  return launch_plane<PLANE_INV_CG>(g, t, nullptr, nullptr, spec, 1.0, s, nullptr, f);
 }
 
 hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,

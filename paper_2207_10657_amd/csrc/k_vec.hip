@@ -142,6 +142,40 @@ __global__ void __launch_bounds__(kBlock) k_finish(Reducer r, int nblocks, int n
   }
 }
 
+// Fixed-order sum of nb rows of 2 partials into thread 0's tot (one block).
+__device__ __forceinline__ void sum_rows2(const double* __restrict__ rows, int nb, double (&tot)[2]) {
+  __shared__ double wsum[kBlock / 64][2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < 2; ++k) {
+    double s = 0.0;
+    for (int row = threadIdx.x; row < nb; row += blockDim.x) s += rows[(size_t)row * 2 + k];
+    s = wave_sum(s);
+    if (lane == 0) wsum[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 2; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) s += wsum[w][k];
+      tot[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// The direction update of the previous iteration, then the curvature decision
+// of this one (both need the state in this order).
+__global__ void __launch_bounds__(kBlock) k_finish_dc(Reducer rd, int nbd, Reducer rc, int nbc,
+                                                      CgState* st, double* trace) {
+  if (st->done) return;
+  double td[2], tc[2];
+  sum_rows2(rd.partials, nbd, td);
+  sum_rows2(rc.partials, nbc, tc);
+  if (threadIdx.x != 0) return;
+  cg_decide_direction(st, td[0], td[1]);
+  cg_decide_curvature(st, trace, tc[0], tc[1]);
+}
+
 __global__ void k_cg_resume(CgState* st) {
   st->beta = 0.0;
   st->restart = 0;
@@ -205,6 +239,12 @@ hipError_t finish(int kind, const Reducer& r, int nblocks, int nv, double* out, 
       hipLaunchKernelGGL(k_finish<FIN_DIRECTION>, dim3(1), dim3(kBlock), 0, s, r, nblocks, nv, out, st, trace);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t finish_direction_curvature(const Reducer& rd, int nbd, const Reducer& rc, int nbc,
+                                      CgState* st, double* trace, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_dc, dim3(1), dim3(kBlock), 0, s, rd, nbd, rc, nbc, st, trace);
   return hipGetLastError();
 }
 
