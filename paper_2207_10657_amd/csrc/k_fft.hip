@@ -305,7 +305,10 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
     else v = t.tw[t.off_post + i - M - ny];
     twx[i] = v;
   }
-  if (MODE != PLANE_INV) {
+  // modes whose input is a real field (forward transform first); the others
+  // start from the half spectrum
+  constexpr bool kRealInput = MODE == PLANE_FWD || MODE == PLANE_FWD_CG || MODE == PLANE_GREEN2D;
+  if (kRealInput) {
     const double2* src = reinterpret_cast<const double2*>(in + plane);
     staged_copy(M * ny, [&](int i) { return src[i]; },
                 [&](int i, double2 v) {
@@ -430,6 +433,13 @@ template <int MODE>
 hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, double* out,
                         double2* spec, double scale, hipStream_t s, const CgState* skip = nullptr,
                         CgFuse cf = CgFuse{}) {
+  // every pointer the mode dereferences must be present (a missing one is an
+  // error here, not a fault on the device)
+  constexpr bool real_in = MODE == PLANE_FWD || MODE == PLANE_FWD_CG || MODE == PLANE_GREEN2D;
+  constexpr bool real_out = MODE == PLANE_INV || MODE == PLANE_GREEN2D;
+  constexpr bool cg = MODE == PLANE_FWD_CG || MODE == PLANE_INV_CG;
+  if ((real_in && !in) || (real_out && !out) || !spec) return hipErrorInvalidValue;
+  if (cg && (!cf.st || !cf.d || !cf.z || !cf.g || !cf.y || !cf.partials)) return hipErrorInvalidValue;
   const size_t lds = fft_plane_lds_bytes(g);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE>,
@@ -444,6 +454,7 @@ hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, dou
 template <int MODE>
 hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, double scale,
                          hipStream_t s, const CgState* skip = nullptr) {
+  if (!spec) return hipErrorInvalidValue;
   const int P = g.nx / 2 + 1;
   const int nchunk = (P + kPencilC - 1) / kPencilC;
   const size_t lds = ((size_t)(kPencilC + 1) * g.nz + g.nz) * sizeof(double2);
