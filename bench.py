@@ -80,6 +80,107 @@ def cpu_baseline(w, n_matvec):
 
 COPY_BYTES = 1 << 28
 
+# Counter summary written by `--pmc-summary`; read back for roofline.traffic.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_64cubed.md")
+CSRC = os.path.join(ROOT, "paper_2207_10657_amd", "csrc")
+# sources each timed kernel is compiled from: a counter reading is void once
+# any of them has changed
+KERNEL_SOURCES = {
+    "stiffness": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "trial": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "residual": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "fft_plane_fwd": ["k_fft.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "fft_pencil_green": ["k_fft.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "fft_plane_inv": ["k_fft.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+}
+# device kernel name (as rocprofv3 prints it) -> timed kernel; the probe runs
+# the Hessian and the plain FFT passes, the solver the CG-fused ones
+PMC_KERNELS = [("k_brick<2,", "stiffness"), ("k_brick<0,", "residual"),
+               ("k_plane<0>", "fft_plane_fwd"), ("k_pencil<0>", "fft_pencil_green"),
+               ("k_plane<1>", "fft_plane_inv"), ("copyBuffer", "copy")]
+
+
+def sources_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_pmc(path):
+    """Per-dispatch counter values from rocprofv3 counter_collection CSVs."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % path)
+    out = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Kernel_Name", "")
+                label = next((lab for key, lab in PMC_KERNELS if key in name.replace(" ", "")), None)
+                if label is None:
+                    continue
+                out.setdefault(label, []).append(float(row["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, grid):
+    """Markdown summary of a FETCH_SIZE and a WRITE_SIZE pass over `--probe`.
+
+    Both counters are in KiB per dispatch. The copy kernel moves COPY_BYTES in
+    and COPY_BYTES out, which fixes one scale factor per counter."""
+    fetch, write = read_pmc(fetch_dir), read_pmc(write_dir)
+    if "copy" not in fetch or "copy" not in write:
+        raise SystemExit("the calibration copy is missing from the counter runs")
+    # the calibration copies are the five largest copy dispatches (the library
+    # and torch issue smaller device copies of their own)
+    kf = COPY_BYTES / (1024.0 * np.median(sorted(fetch["copy"])[-5:]))
+    kw = COPY_BYTES / (1024.0 * np.median(sorted(write["copy"])[-5:]))
+    shape = (grid, grid, grid)
+    rows, table = [], {}
+    for label in ("stiffness", "residual", "fft_plane_fwd", "fft_pencil_green", "fft_plane_inv"):
+        if label not in fetch or label not in write:
+            continue
+        fb = float(np.median(fetch[label])) * 1024.0 * kf
+        wb = float(np.median(write[label])) * 1024.0 * kw
+        alg = algorithmic_bytes(label, shape)
+        table[label] = {"fetch_bytes": fb, "write_bytes": wb, "dispatches": len(fetch[label]),
+                        "algorithmic_bytes": alg, "sources": sources_digest(label)}
+        rows.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (
+            label, len(fetch[label]), fb / 1e6, wb / 1e6, (fb + wb) / 1e6,
+            (fb + wb) / alg if alg else float("nan")))
+    lines = [
+        "| kernel | dispatches | fetch MB | write MB | HBM MB / launch | / algorithmic |",
+        "|---|---|---|---|---|---|"] + rows + [
+        "",
+        "Calibration (copy of %d bytes): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (COPY_BYTES, kf, kw),
+        "",
+        "```json",
+        json.dumps({"grid": grid, "fetch_scale": kf, "write_scale": kw, "kernels": table}, indent=1),
+        "```"]
+    return "\n".join(lines)
+
+
+def load_traffic(kernel, shape):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none for this grid or the kernel's sources changed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    k = blob.get("kernels", {}).get(kernel)
+    if not k or tuple([blob.get("grid")] * 3) != tuple(shape):
+        return None
+    if k.get("sources") != sources_digest(kernel):
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
 
 def probe(n):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
@@ -119,7 +220,13 @@ def main():
                          "projected-Hessian applications and a calibration copy of known size")
     ap.add_argument("--grid", type=int, default=64,
                     help="cell size of the --probe run (the 64^3 workload recipe at N^3)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs of --probe "
+                         "(FETCH_SIZE, then WRITE_SIZE; csv output)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.grid))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is single-GPU (a batch of cells "
               "would shard across GPUs with no communication); --gpus %d is not supported"
@@ -146,8 +253,11 @@ def main():
         s.solve_increment()
     ck = s.get_state()
 
+    detail = []
+
     def timed_steps():
         matvecs = newton = cg = converged = 0
+        detail.clear()
         for n in range(W, W + K):
             s.apply_load_step(w.load_path[n])
             rep = s.solve_increment()
@@ -155,6 +265,9 @@ def main():
             newton += rep["newton_iters"]
             cg += rep["cg_iters"]
             converged += int(rep["converged"])
+            detail.append({k: rep[k] for k in ("newton_iters", "rejected", "cg_iters", "restarts",
+                                               "boundary_exits", "negcurv_exits", "r_eq", "R",
+                                               "converged")})
         return matvecs, newton, cg, converged
 
     # timed region: CG iterations replayed from captured HIP graphs
@@ -163,6 +276,7 @@ def main():
     matvecs, newton, cg, converged = timed_steps()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_detail = list(detail)
     # the same steps again from the same state (restart is bit-exact), every
     # kernel launch bracketed by HIP events on the library's stream
     s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
@@ -187,7 +301,8 @@ def main():
     if alg is not None and avg_s > 0:
         achieved = alg / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname, w.shape),
+                "kernel": kname, "algorithmic_bytes": alg,
                 "avg_launch_us": avg_s * 1e6, "launches": kcount}
     value = w.nvox * matvecs / dt / 1e9
     out = {
@@ -206,7 +321,8 @@ def main():
         "config": {"workload": "3D 64^3 Q1 inclusion cell (vf 0.25, seed 1), damage matrix, "
                                "uniaxial 30 x 2e-4 load path, FP64 TR+Steihaug tol 1e-8",
                    "load_steps_timed": [W, W + K - 1], "matvecs": matvecs,
-                   "newton_iters": newton, "cg_iters": cg, "converged_steps": converged},
+                   "newton_iters": newton, "cg_iters": cg, "converged_steps": converged,
+                   "per_step": step_detail},
         "roofline": roof,
         "kernel_timing": "HIP events around every launch in a replay of the timed steps from the "
                          "same checkpoint (kernel-by-kernel launches, %.1f ms/step)" % (dt_prof / K * 1e3),

@@ -574,7 +574,10 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
   int restarts = 0;
   int slot = 0;
   for (;;) {
-    const int k = slot == 0 ? 2 : kCgBatch;
+    // a profiled solve polls after every iteration, so no launch of a batch
+    // runs after the stop (such launches return at entry and would bias the
+    // per-kernel averages)
+    const int k = c->profiling ? 1 : slot == 0 ? 2 : kCgBatch;
     hfe_status st = cg_batch(c, slot, k);
     if (st) return st;
     HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
