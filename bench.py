@@ -35,25 +35,32 @@ WORKLOAD = "c1_3d64"
 
 
 def algorithmic_bytes(name, shape):
-    """Bytes per launch that each kernel must move at minimum (FP64, 3D Q1)."""
+    """Bytes per launch that each kernel must move at minimum (3D Q1, FP64, or
+    FP32 for the kernels of the mixed-precision CG, names ending in _f32)."""
     nz, ny, nx = shape
     N = nx * ny * nz
-    spec = 48.0 * (nx // 2 + 1) / nx          # 3 half-spectrum fields, B / voxel
+    f32 = name.endswith("_f32")
+    base = name[:-4] if f32 else name
+    r = 4 if f32 else 8                        # bytes per real
+    spec = 6.0 * r * (nx // 2 + 1) / nx         # 3 half-spectrum fields, B / voxel
     per_vox = {
         # d, u (tangent direction s = C:eps), a and c' at 8 points, phase, K d
-        "stiffness": 24 + 24 + 128 + 1 + 24,
+        "stiffness": 3 * r + 3 * r + 16 * r + 1 + 3 * r,
         # 3 real fields in, 3 half spectra out (and back)
-        "fft_plane_fwd": 24 + spec,
+        "fft_plane_fwd": 3 * r + spec,
         "fft_pencil_green": 2 * spec,
-        "fft_plane_inv": spec + 24,
+        "fft_plane_inv": spec + 3 * r,
+        # fused CG passes: + z, d, g in and z, g out / + y, g in and y out
+        "fft_plane_fwd_cg": 3 * r + spec + 15 * r,
+        "fft_plane_inv_cg": spec + 9 * r,
         # u, kappa_hist, phase in; a, c' and D^T sigma out
         "residual": 24 + 64 + 1 + 128 + 24,
         # u, z, kappa_hist, old a/c', phase in; trial a/c', D^T sigma_t out
         "trial": 24 + 24 + 64 + 128 + 1 + 128 + 24,
     }
-    if name not in per_vox:
+    if base not in per_vox or (f32 and base in ("residual", "trial")):
         return None
-    return per_vox[name] * N
+    return per_vox[base] * N
 
 
 def cpu_baseline(w, n_matvec):
@@ -87,6 +94,7 @@ CSRC = os.path.join(ROOT, "paper_2207_10657_amd", "csrc")
 # any of them has changed
 KERNEL_SOURCES = {
     "stiffness": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
+    "stiffness_f32": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
     "trial": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
     "residual": ["k_element.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
     "fft_plane_fwd": ["k_fft.hip", "hfe_internal.h", "hfe_reduce.h", "hfe_cg.h"],
@@ -215,6 +223,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-matvecs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the same steps")
     ap.add_argument("--probe", action="store_true",
                     help="short run for hardware-counter passes: after one load step, a few "
                          "projected-Hessian applications and a calibration copy of known size")
@@ -253,14 +263,15 @@ def main():
         s.solve_increment()
     ck = s.get_state()
 
-    detail = []
+    detail, sigmas = [], []
 
-    def timed_steps():
+    def timed_steps(params=None):
         matvecs = newton = cg = converged = 0
         detail.clear()
+        sigmas.clear()
         for n in range(W, W + K):
             s.apply_load_step(w.load_path[n])
-            rep = s.solve_increment()
+            rep = s.solve_increment(params)
             matvecs += rep["matvecs"]
             newton += rep["newton_iters"]
             cg += rep["cg_iters"]
@@ -268,6 +279,7 @@ def main():
             detail.append({k: rep[k] for k in ("newton_iters", "rejected", "cg_iters", "restarts",
                                                "boundary_exits", "negcurv_exits", "r_eq", "R",
                                                "converged")})
+            sigmas.append(s.homogenized_stress())
         return matvecs, newton, cg, converged
 
     # timed region: CG iterations replayed from captured HIP graphs
@@ -277,6 +289,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     step_detail = list(detail)
+    sig64 = list(sigmas)
     # the same steps again from the same state (restart is bit-exact), every
     # kernel launch bracketed by HIP events on the library's stream
     s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
@@ -291,6 +304,27 @@ def main():
     if replay[0] != matvecs:
         print("warning: event-timed replay differs from the timed run", replay, matvecs,
               file=sys.stderr)
+
+    # the same steps with the mixed-precision CG (FP32 Hessian, FFT and CG
+    # vectors; FP64 residual, trial and energy ratio) from the same state
+    mixed = None
+    if not args.no_mixed:
+        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        mv32, nw32, cg32, conv32 = timed_steps({"precision": "mixed"})
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t2
+        errs = [float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+                for a, b in zip(sigmas, sig64)]
+        mixed = {"value": w.nvox * mv32 / dt32 / 1e9, "unit": "Gvoxel-matvec/s",
+                 "ms_per_step": dt32 / K * 1e3, "speedup_per_step": dt / dt32,
+                 "matvecs": mv32, "newton_iters": nw32, "cg_iters": cg32,
+                 "converged_steps": conv32,
+                 "sigma_rel_err_vs_fp64_per_step": errs,
+                 "per_step": list(detail),
+                 "note": "same load steps from the same checkpoint; the reference is the FP64 "
+                         "GPU solve above (the FP64 path is checked against the oracle)"}
 
     # dominant kernel: largest total time in the timed region
     kern = max(stats.items(), key=lambda kv: kv[1][1])
@@ -327,6 +361,7 @@ def main():
         "kernel_timing": "HIP events around every launch in a replay of the timed steps from the "
                          "same checkpoint (kernel-by-kernel launches, %.1f ms/step)" % (dt_prof / K * 1e3),
         "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats.items()},
+        "mixed_precision": mixed,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)

@@ -59,6 +59,8 @@ enum { HFE_CONVERGED = 0, HFE_NOT_CONVERGED = 1 };
 enum { HFE_P1_PAIR = 1, HFE_Q1 = 2 };
 enum { HFE_ELASTIC = 0, HFE_DAMAGE_ENERGY_NORM = 1 };
 enum { HFE_MAX_PHASES = 8 };
+/* Arithmetic of the CG inside hfe_solve_increment (hfe_solver_params.precision). */
+enum { HFE_FP64 = 0, HFE_MIXED = 1 };
 
 /* Fields readable through hfe_get_field (sizes per entry). */
 enum {
@@ -102,6 +104,13 @@ typedef struct {
   double Rmax;     /* maximum trust radius (<= 0: 1000 sqrt(N_qp) ||dE_1||_F)  */
   int i_nr_max;    /* maximum Newton iterations per load step                */
   int j_cg_max;    /* maximum CG iterations per Newton step                  */
+  int precision;   /* HFE_FP64: everything in FP64. HFE_MIXED (3D only): the
+                    * Hessian, the FFT / Green's operator and the CG vectors
+                    * inside Algorithm 1 in FP32 (CG inner products summed in
+                    * FP64); the residual D^T sigma, the trial evaluation and
+                    * the energy terms of the ratio rho_bar, the history and
+                    * the state stay FP64, so each Newton step starts from an
+                    * FP64 residual and the tolerances keep their meaning.   */
 } hfe_solver_params;
 
 typedef struct {
@@ -190,6 +199,13 @@ hfe_status hfe_set_displacement(hfe_ctx* ctx, const double* host_u);
  * (distinct). dots (host, may be NULL) receives {d.Kd, sum |D d|^2}. */
 hfe_status hfe_apply_projected_hessian(hfe_ctx* ctx, const double* dev_in,
                                        double* dev_out, double dots[2]);
+
+/* The projected Hessian of hfe_apply_projected_hessian in the FP32 arithmetic
+ * of the HFE_MIXED CG (3D only): the state (u, the tangent scalars) rounded to
+ * FP32, FP32 Hessian and FFT, dots summed in FP64. `dev_in`, `dev_out` are
+ * distinct device float arrays [dim][N]. HFE_EINVAL in 2D. */
+hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* ctx, const float* dev_in, float* dev_out,
+                                           double dots[2]);
 
 /* The two halves of the matvec, for operator tests: out = K d (device
  * arrays [dim][N]), and out = L^+ f (zero mean; the k = 0 mode removed). */

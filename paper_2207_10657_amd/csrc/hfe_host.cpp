@@ -52,6 +52,11 @@ struct Layout {
   size_t Edev;                                        // macroscopic strain (9 doubles)
   size_t tw;                                          // twiddles
   size_t stab;                                        // sin^2 tables
+  // FP32 copies for the mixed-precision CG
+  size_t u32, z32, d32, g32, y32, Kd32, tmp32;        // nodal [dim][N] floats
+  size_t a32, cp32;                                   // per point [nq][N] floats
+  size_t spec32;                                      // dim*nz*ny*(nx/2+1) float2
+  size_t tw32, stab32;                                // tables
   size_t total;
   int partial_rows;
   int n_tw, n_stab;
@@ -117,6 +122,14 @@ Layout make_layout(const Grid& g) {
   L.tw = take((size_t)L.n_tw * sizeof(double2));
   L.n_stab = (g.nx / 2 + 1) + g.ny + g.nz;
   L.stab = take((size_t)L.n_stab * sizeof(double));
+  const size_t nod32 = (size_t)g.dim * g.N * sizeof(float);
+  const size_t pts32 = (size_t)g.nq * g.N * sizeof(float);
+  L.u32 = take(nod32); L.z32 = take(nod32); L.d32 = take(nod32); L.g32 = take(nod32);
+  L.y32 = take(nod32); L.Kd32 = take(nod32); L.tmp32 = take(nod32);
+  L.a32 = take(pts32); L.cp32 = take(pts32);
+  L.spec32 = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(float2));
+  L.tw32 = take((size_t)L.n_tw * sizeof(float2));
+  L.stab32 = take((size_t)L.n_stab * sizeof(float));
   L.total = off;
   return L;
 }
@@ -167,6 +180,11 @@ struct hfe_ctx {
   double* Edev;              // device copy of E
   double* trace;             // device CG trace
   hfe::FftTables tabs;
+  // mixed precision: FP32 CG vectors, FP32 copies of the state, FP32 tables
+  float *u32, *z32, *d32, *g32, *y32, *Kd32, *tmp32, *a32, *cp32;
+  float2* spec32;
+  hfe::FftTablesT<float> tabs32;
+  bool state32_fresh = false;  // u32, a32, cp32 match u, a, cp
   double* hscal = nullptr;   // pinned, device-mapped: reduction totals land here
   double* dscal = nullptr;   // device alias of hscal
   hfe::CgState* hcg = nullptr;  // pinned host copy of the CG state
@@ -194,6 +212,7 @@ struct hfe_ctx {
   // CG iteration graphs: a short batch for the start of a solve, a long one after
   hipStream_t cap_stream = nullptr;
   CgGraph graphs[2];
+  int graph_precision = HFE_FP64;   // precision the captured graphs run
   bool use_graphs = true;
   int brick_shape = 0;       // Q1 brick shape (HFE_BRICK_SHAPE=0..3 overrides)
 };
@@ -422,6 +441,7 @@ hfe_status evaluate_state(hfe_ctx* c) {
     return fail(c, HFE_ENUMERIC, "non-finite stress or residual");
   c->r_eq = c->sig_norm2 > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(c->sig_norm2) : 0.0;
   c->have_state = true;
+  c->state32_fresh = false;
   return HFE_OK;
 }
 
@@ -435,6 +455,124 @@ hfe_status direction(hfe_ctx* c) {
   Prof p(c, "cg_vec");
   HIPCHK(c, hfe::cg_step_d(ndof(c), c->y, c->d, c->gv, c->z, r, c->cg, c->stream, &c->nb_dir));
   return HFE_OK;
+}
+
+// ---- mixed precision: the CG of Algorithm 1 on FP32 vectors ----------------
+
+// FP32 copies of the state (u, a, c') read by the FP32 Hessian.
+hfe_status refresh_state32(hfe_ctx* c) {
+  if (c->state32_fresh) return HFE_OK;
+  const long long np = (long long)c->g.nq * c->g.N;
+  {
+    Prof p(c, "convert");
+    HIPCHK(c, hfe::vec_to_f32(ndof(c), c->u, c->u32, c->stream));
+    HIPCHK(c, hfe::vec_to_f32(np, c->a, c->a32, c->stream));
+    HIPCHK(c, hfe::vec_to_f32(np, c->cp, c->cp32, c->stream));
+  }
+  c->state32_fresh = true;
+  return HFE_OK;
+}
+
+hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in_cg) {
+  hfe::HessArgs<float> H;
+  H.g = c->g;
+  H.mat = c->mat;
+  H.E = c->Edev;
+  H.phase = c->phase;
+  H.u = c->u32;
+  H.a = c->a32;
+  H.cp = c->cp32;
+  H.v = v;
+  H.f = out;
+  H.red = reducer(c);
+  H.cg = in_cg ? c->cg : nullptr;
+  H.brick_shape = c->brick_shape;
+  return H;
+}
+
+// out = K v in FP32 (state copies must be fresh); totals as in stiffness().
+hfe_status stiffness32(hfe_ctx* c, const float* v, float* out, bool in_cg) {
+  int nb = 0;
+  {
+    Prof p(c, "stiffness_f32");
+    HIPCHK(c, hfe::launch_hessian_f32(hess_args32(c, v, out, in_cg), c->stream, &nb));
+  }
+  return in_cg ? finish(c, hfe::FIN_CURVATURE, nb, hfe::HES_NV, nullptr)
+               : finish(c, hfe::FIN_OUT, nb, hfe::HES_NV, c->dscal + S_HES);
+}
+
+// y = L^+ x in FP32 (3D)
+hfe_status green32(hfe_ctx* c, const float* x, float* y) {
+  {
+    Prof p(c, "fft_plane_fwd_f32");
+    HIPCHK(c, hfe::fft_plane_forward(c->g, c->tabs32, x, c->spec32, c->stream));
+  }
+  {
+    Prof p(c, "fft_pencil_green_f32");
+    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs32, c->spec32, c->stream));
+  }
+  {
+    Prof p(c, "fft_plane_inv_f32");
+    HIPCHK(c, hfe::fft_plane_inverse(c->g, c->tabs32, c->spec32, y, c->stream));
+  }
+  return HFE_OK;
+}
+
+hfe_status dot32(hfe_ctx* c, const float* x, const float* y, double* dev_out) {
+  int nb = 0;
+  {
+    Prof p(c, "cg_vec_f32");
+    HIPCHK(c, hfe::vec_dot_f32(ndof(c), x, y, reducer(c), c->stream, &nb));
+  }
+  return finish(c, hfe::FIN_OUT, nb, 1, dev_out);
+}
+
+hfe_status direction32(hfe_ctx* c) {
+  hfe::Reducer r;
+  r.partials = c->partials2;
+  Prof p(c, "cg_vec_f32");
+  HIPCHK(c, hfe::cg_step_d<float>(ndof(c), c->y32, c->d32, c->g32, c->z32, r, c->cg, c->stream,
+                                  &c->nb_dir));
+  return HFE_OK;
+}
+
+// The FP64 iteration below with FP32 vectors, Hessian and FFT (3D).
+hfe_status cg_iteration32(hfe_ctx* c) {
+  int nb = 0;
+  {
+    Prof p(c, "stiffness_f32");
+    HIPCHK(c, hfe::launch_hessian_f32(hess_args32(c, c->d32, c->Kd32, true), c->stream, &nb));
+  }
+  {
+    hfe::Reducer rd;
+    rd.partials = c->partials2;
+    Prof p(c, "finish");
+    HIPCHK(c, hfe::finish_direction_curvature(rd, c->nb_dir, reducer(c), nb, c->cg, c->trace,
+                                              c->stream));
+  }
+  hfe::CgFuse<float> f;
+  f.st = c->cg;
+  f.d = c->d32;
+  f.z = c->z32;
+  f.g = c->g32;
+  f.y = c->y32;
+  f.partials = c->partials;
+  {
+    Prof p(c, "fft_plane_fwd_cg_f32");
+    HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs32, (const float*)c->Kd32, c->spec32, f,
+                                        c->stream));
+  }
+  {
+    Prof p(c, "fft_pencil_green_f32");
+    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs32, c->spec32, c->stream, c->cg));
+  }
+  {
+    Prof p(c, "fft_plane_inv_cg_f32");
+    HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs32, c->spec32, f, c->stream, &nb));
+  }
+  hfe_status st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
+  if (st) return st;
+  return direction32(c);
 }
 
 // One CG iteration, all decisions on the device (no host synchronisation):
@@ -460,7 +598,7 @@ hfe_status cg_iteration(hfe_ctx* c) {
                                               c->stream));
   }
   if (c->g.dim == 3) {
-    hfe::CgFuse f;
+    hfe::CgFuse<double> f;
     f.st = c->cg;
     f.d = c->d;
     f.z = c->z;
@@ -468,7 +606,7 @@ hfe_status cg_iteration(hfe_ctx* c) {
     f.y = c->y;
     f.partials = c->partials;
     {
-      Prof p(c, "fft_plane_fwd");
+      Prof p(c, "fft_plane_fwd_cg");
       HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs, c->Kd, c->spec, f, c->stream));
     }
     {
@@ -476,7 +614,7 @@ hfe_status cg_iteration(hfe_ctx* c) {
       HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream, c->cg));
     }
     {
-      Prof p(c, "fft_plane_inv");
+      Prof p(c, "fft_plane_inv_cg");
       HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs, c->spec, f, c->stream, &nb));
     }
   } else {
@@ -499,9 +637,12 @@ hfe_status cg_iteration(hfe_ctx* c) {
 hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
   // timing events cannot be recorded inside a captured graph on this
   // runtime, so a profiled solve launches the kernels one by one
+  auto iteration = [&]() {
+    return c->graph_precision == HFE_MIXED ? cg_iteration32(c) : cg_iteration(c);
+  };
   if (!c->use_graphs || c->profiling) {
     for (int i = 0; i < k; ++i) {
-      hfe_status st = cg_iteration(c);
+      hfe_status st = iteration();
       if (st) return st;
     }
     return HFE_OK;
@@ -524,7 +665,7 @@ hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     hfe_status st = HFE_OK;
     if (e == hipSuccess)
-      for (int i = 0; i < k && st == HFE_OK; ++i) st = cg_iteration(c);
+      for (int i = 0; i < k && st == HFE_OK; ++i) st = iteration();
     hipGraph_t graph = nullptr;
     const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &graph) : e;
     c->stream = saved;
@@ -548,14 +689,29 @@ hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
 }
 
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
-hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, CgInfo* info) {
+hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, int* flag,
+                    CgInfo* info) {
   const long long n = ndof(c);
   const size_t bytes = (size_t)n * sizeof(double);
+  const bool mixed = prec == HFE_MIXED;
   HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
   *flag = HFE_CG_INTERIOR;
   if (c->rr0 == 0.0) return HFE_OK;
-  HIPCHK(c, hipMemcpyAsync(c->gv, c->g0, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->y, c->y0, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->graph_precision != prec) {
+    // captured iterations run one precision's kernels and buffers
+    destroy_graphs(c);
+    c->graph_precision = prec;
+  }
+  if (mixed) {
+    hfe_status st0 = refresh_state32(c);
+    if (st0) return st0;
+    HIPCHK(c, hipMemsetAsync(c->z32, 0, (size_t)n * sizeof(float), c->stream));
+    HIPCHK(c, hfe::vec_to_f32(n, c->g0, c->g32, c->stream));
+    HIPCHK(c, hfe::vec_to_f32(n, c->y0, c->y32, c->stream));
+  } else {
+    HIPCHK(c, hipMemcpyAsync(c->gv, c->g0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->y, c->y0, bytes, hipMemcpyDeviceToDevice, c->stream));
+  }
   hfe::CgState init;
   std::memset(&init, 0, sizeof(init));
   init.rr = init.rr0 = init.rr_new = c->rr0;
@@ -568,7 +724,7 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
   HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
   // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0
   {
-    hfe_status st = direction(c);
+    hfe_status st = mixed ? direction32(c) : direction(c);
     if (st) return st;
   }
   int restarts = 0;
@@ -594,15 +750,27 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
       // Powell's test: recompute the true residual at the new iterate and
       // restart along steepest descent (beta = 0)
       restarts += 1;
-      st = stiffness(c, c->z, c->tmp, false);
-      if (st) return st;
-      HIPCHK(c, hfe::vec_axpy_to(n, c->tmp, 1.0, c->g0, c->gv, c->stream));
-      st = green(c, c->gv, c->y);
-      if (st) return st;
-      st = dot(c, c->y, c->gv, &c->cg->rr_new);
-      if (st) return st;
-      HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
-      st = direction(c);
+      if (mixed) {
+        st = stiffness32(c, c->z32, c->tmp32, false);
+        if (st) return st;
+        HIPCHK(c, hfe::vec_add_f32(n, c->tmp32, c->g0, c->g32, c->stream));
+        st = green32(c, c->g32, c->y32);
+        if (st) return st;
+        st = dot32(c, c->y32, c->g32, &c->cg->rr_new);
+        if (st) return st;
+        HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
+        st = direction32(c);
+      } else {
+        st = stiffness(c, c->z, c->tmp, false);
+        if (st) return st;
+        HIPCHK(c, hfe::vec_axpy_to(n, c->tmp, 1.0, c->g0, c->gv, c->stream));
+        st = green(c, c->gv, c->y);
+        if (st) return st;
+        st = dot(c, c->y, c->gv, &c->cg->rr_new);
+        if (st) return st;
+        HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
+        st = direction(c);
+      }
       if (st) return st;
       slot = 0;
       continue;
@@ -611,6 +779,8 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int* flag, C
     info->restarts = restarts;
     info->matvecs = h.iters + restarts;
     *flag = h.flag;
+    // the step of a mixed-precision solve continues in FP64
+    if (mixed) HIPCHK(c, hfe::vec_to_f64(n, c->z32, c->z, c->stream));
     // keep the trace of this solve
     const int nt = std::min(h.ntrace, kTraceCap);
     if (nt > 0) {
@@ -698,6 +868,11 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);
   c->tmp = D(L.tmp);
   c->a = D(L.a); c->cp = D(L.cp); c->at = D(L.at); c->cpt = D(L.cpt); c->kh = D(L.kh);
+  auto F = [&](size_t off) { return (float*)(c->ws + off); };
+  c->u32 = F(L.u32); c->z32 = F(L.z32); c->d32 = F(L.d32); c->g32 = F(L.g32);
+  c->y32 = F(L.y32); c->Kd32 = F(L.Kd32); c->tmp32 = F(L.tmp32);
+  c->a32 = F(L.a32); c->cp32 = F(L.cp32);
+  c->spec32 = (float2*)(c->ws + L.spec32);
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
@@ -727,6 +902,20 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs.sx = dst;
   c->tabs.sy = dst + (M + 1);
   c->tabs.sz = dst + (M + 1) + g.ny;
+  // the same tables rounded to FP32 for the mixed-precision CG
+  std::vector<float2> tw32(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
+  std::vector<float> st32(st.begin(), st.end());
+  float2* dtw32 = (float2*)(c->ws + L.tw32);
+  float* dst32 = F(L.stab32);
+  c->tabs32.tw = dtw32;
+  c->tabs32.off_x = c->tabs.off_x;
+  c->tabs32.off_y = c->tabs.off_y;
+  c->tabs32.off_z = c->tabs.off_z;
+  c->tabs32.off_post = c->tabs.off_post;
+  c->tabs32.sx = dst32;
+  c->tabs32.sy = dst32 + (M + 1);
+  c->tabs32.sz = dst32 + (M + 1) + g.ny;
   hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dscal, c->hscal, 0);
@@ -736,6 +925,12 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
     e = hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dst, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtw32, tw32.data(), tw32.size() * sizeof(float2), hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst32, st32.data(), st32.size() * sizeof(float), hipMemcpyHostToDevice,
+                       c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     if (c->hscal) hipHostFree(c->hscal);
@@ -836,8 +1031,12 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
   const auto t0 = std::chrono::steady_clock::now();
   hfe_solver_params p;
   p.eta_eq = 1e-8; p.eta_nr = 1e-8; p.eta_cg = 1e-6; p.eta_up = 0.15;
-  p.R0 = 0.0; p.Rmax = 0.0; p.i_nr_max = 50; p.j_cg_max = 2000;
+  p.R0 = 0.0; p.Rmax = 0.0; p.i_nr_max = 50; p.j_cg_max = 2000; p.precision = HFE_FP64;
   if (prm) p = *prm;
+  if (p.precision != HFE_FP64 && p.precision != HFE_MIXED)
+    return fail(c, HFE_EINVAL, "precision must be HFE_FP64 or HFE_MIXED");
+  if (p.precision == HFE_MIXED && c->g.dim != 3)
+    return fail(c, HFE_EINVAL, "HFE_MIXED is implemented for 3D grids");
   if (!c->R_init) {
     c->R = p.R0 > 0.0 ? p.R0 : c->R0_default;
     c->Rmax = p.Rmax > 0.0 ? p.Rmax : c->Rmax_default;
@@ -860,7 +1059,7 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       rep.newton_iters = it + 1;
       int flag = 0;
       CgInfo info;
-      st = steihaug(c, c->R, p.eta_cg, p.j_cg_max, &flag, &info);
+      st = steihaug(c, c->R, p.eta_cg, p.j_cg_max, p.precision, &flag, &info);
       if (st) return st;
       rep.cg_iters += info.iters;
       rep.restarts += info.restarts;
@@ -912,6 +1111,7 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
         HIPCHK(c, hipMemcpyAsync(c->a, c->at, pts, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->cp, c->cpt, pts, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->g0, c->gt, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        c->state32_fresh = false;
         const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH], ss = h[hfe::TRI_SS];
         for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[hfe::TRI_S0 + k];
         c->sig_norm2 = ss;
@@ -1082,6 +1282,26 @@ hfe_status hfe_apply_projected_hessian(hfe_ctx* c, const double* in, double* out
   hfe_status st = stiffness(c, in, c->Kd, false);
   if (st) return st;
   st = green(c, c->Kd, out);
+  if (st) return st;
+  if (dots) {
+    st = sync(c);
+    if (st) return st;
+    dots[0] = c->hscal[S_HES];
+    dots[1] = c->hscal[S_HES + 1];
+  }
+  return HFE_OK;
+}
+
+hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* c, const float* in, float* out,
+                                           double dots[2]) {
+  if (!c || !in || !out || in == out) return HFE_EINVAL;
+  if (c->g.dim != 3) return fail(c, HFE_EINVAL, "the FP32 operator is implemented for 3D grids");
+  if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+  hfe_status st = refresh_state32(c);
+  if (st) return st;
+  st = stiffness32(c, in, c->Kd32, false);
+  if (st) return st;
+  st = green32(c, c->Kd32, out);
   if (st) return st;
   if (dots) {
     st = sync(c);

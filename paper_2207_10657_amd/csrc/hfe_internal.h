@@ -76,6 +76,25 @@ hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Hessian: f = D^T B D v at the state (u, a, cp), rows HES_* (no-op once
 // A.cg->done when A.cg is set).
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Hessian operands in one precision (the FP32 copies of the state serve the
+// mixed-precision CG; Q1 only).
+template <typename R>
+struct HessArgs {
+  Grid g;
+  MatTable mat;
+  const double* E;       // macroscopic strain (device, FP64)
+  const uint8_t* phase;
+  const R* u;            // [dim][N] state displacement (s = C:eps at softening points)
+  const R* a;            // [nq][N] tangent scalars of the state
+  const R* cp;
+  const R* v;            // [dim][N] direction
+  R* f;                  // [dim][N] K v
+  Reducer red;           // rows HES_* (FP64)
+  CgState* cg;           // skipped once cg->done when set
+  int brick_shape;
+};
+// FP32 Hessian f = D^T B D v (rows HES_* in FP64), 3D Q1 only.
+hipError_t launch_hessian_f32(const HessArgs<float>& A, hipStream_t s, int* nblocks);
 // Commit: khist <- max(khist, kappa_t(E + D u)) on damage points (khist is
 // written through the const-cast pointer a_out).
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s);
@@ -88,50 +107,71 @@ hipError_t launch_fields(const ElemArgs& A, double* out_h, double* out_s, double
 
 // ---- FFT / Green kernels (k_fft.hip) ---------------------------------------
 
-struct FftTables {
-  const double2* tw;      // concatenated twiddle tables, see offsets
-  int off_x, off_y, off_z, off_post;   // offsets (in double2) of the Lx=nx/2, ny, nz
-                                       // tables and of e^{-2 pi i k/nx}, k <= nx/2
-  const double* sx;       // 4 sin^2(pi k / n) per axis (the 1D FE Laplacian symbol)
-  const double* sy;
-  const double* sz;
+// Complex type of a real type: double2 for double, float2 for float.
+template <typename R> struct Complex;
+template <> struct Complex<double> { using T = double2; };
+template <> struct Complex<float> { using T = float2; };
+template <typename R> using C2 = typename Complex<R>::T;
+
+// Twiddle and symbol tables of one precision (R = double or float).
+template <typename R>
+struct FftTablesT {
+  const C2<R>* tw;        // concatenated twiddle tables, see offsets
+  int off_x, off_y, off_z, off_post;   // offsets (in complex values) of the Lx=nx/2, ny,
+                                       // nz tables and of e^{-2 pi i k/nx}, k <= nx/2
+  const R* sx;            // 4 sin^2(pi k / n) per axis (the 1D FE Laplacian symbol)
+  const R* sy;
+  const R* sz;
 };
+using FftTables = FftTablesT<double>;
 
 bool fft_length_supported(int L);
-size_t fft_plane_lds_bytes(const Grid& g);
-// Pipeline entry points. `in`/`out` are [dim][N] doubles, `spec` is the
-// [dim][nz][ny][nx/2+1] double2 work buffer.
-// `skip` (may be null): the passes return at entry once skip->done is set.
-hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
-                       double2* spec, hipStream_t s, const CgState* skip = nullptr);
+template <typename R> size_t fft_plane_lds_bytes(const Grid& g);
+// The plane passes of this grid fit one block (LDS and staged values).
+template <typename R> bool fft_plane_fits(const Grid& g);
+// Pipeline entry points, R = double or float. `in`/`out` are [dim][N] reals,
+// `spec` is the [dim][nz][ny][nx/2+1] complex work buffer.
+// Green's operator: out = L^+ in (3D: three passes, 2D: one).
+template <typename R>
+hipError_t green_apply(const Grid& g, const FftTablesT<R>& t, const R* in, R* out, C2<R>* spec,
+                       hipStream_t s, const CgState* skip = nullptr);
 // The three passes of green_apply (3D) and the single 2D pass, launched
 // separately so that each can be timed.
-hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+template <typename R>
+hipError_t fft_plane_forward(const Grid& g, const FftTablesT<R>& t, const R* in, C2<R>* spec,
                              hipStream_t s, const CgState* skip = nullptr);
-hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s,
+template <typename R>
+hipError_t fft_pencil_green(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, hipStream_t s,
                             const CgState* skip = nullptr);
-hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+template <typename R>
+hipError_t fft_plane_inverse(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, R* out,
                              hipStream_t s, const CgState* skip = nullptr);
-hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
-                             double2* spec, hipStream_t s, const CgState* skip = nullptr);
+template <typename R>
+hipError_t fft_plane_green2d(const Grid& g, const FftTablesT<R>& t, const R* in, R* out,
+                             C2<R>* spec, hipStream_t s, const CgState* skip = nullptr);
 
 // CG iteration passes with the vector updates fused in (3D):
 //  forward plane pass of Kd that also does z += alpha d, g += alpha Kd (or,
 //  when the CG has just stopped on the sphere, z += tau d);
 //  inverse plane pass that, instead of writing w = L^+ Kd, does y += alpha w
-//  and writes partial rows {y_new.g, y_old.g} (one row per plane block).
+//  and writes partial rows {y_new.g, y_old.g} (one row per plane block,
+//  accumulated in FP64 in either precision).
+template <typename R>
 struct CgFuse {
   CgState* st;
-  const double* d;
-  double* z;
-  double* g;
-  double* y;
+  const R* d;
+  R* z;
+  R* g;
+  R* y;
   double* partials;
 };
-hipError_t fft_plane_forward_cg(const Grid& g, const FftTables& t, const double* Kd, double2* spec,
-                                const CgFuse& f, hipStream_t s);
-hipError_t fft_plane_inverse_cg(const Grid& g, const FftTables& t, double2* spec, const CgFuse& f,
-                                hipStream_t s, int* nblocks);
+template <typename R>
+hipError_t fft_plane_forward_cg(const Grid& g, const FftTablesT<R>& t, const R* Kd, C2<R>* spec,
+                                const CgFuse<R>& f, hipStream_t s);
+template <typename R>
+hipError_t fft_plane_inverse_cg(const Grid& g, const FftTablesT<R>& t, C2<R>* spec,
+                                const CgFuse<R>& f, hipStream_t s, int* nblocks);
+// Plain transforms (FP64): forward R2C and unscaled inverse C2R (times N).
 hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
                        hipStream_t s);
 hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
@@ -154,9 +194,17 @@ hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z,
 // CG: y += alpha w, rows {y_new.g, y_old.g}
 hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
                      const CgState* st, hipStream_t s, int* nblocks);
-// CG: d = -y + beta d, rows {g.d, z.g}
-hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
-                     const Reducer& r, const CgState* st, hipStream_t s, int* nblocks);
+// CG: d = -y + beta d, rows {g.d, z.g} (R = double or float; sums in FP64)
+template <typename R>
+hipError_t cg_step_d(long long n, const R* y, R* d, const R* g, const R* z, const Reducer& r,
+                     const CgState* st, hipStream_t s, int* nblocks);
+// Mixed precision: rows of x . y over FP32 vectors (FP64 sums); y = (float) x;
+// y = (double) x; out = (float)(x + y).
+hipError_t vec_dot_f32(long long n, const float* x, const float* y, const Reducer& r,
+                       hipStream_t s, int* nblocks);
+hipError_t vec_to_f32(long long n, const double* x, float* y, hipStream_t s);
+hipError_t vec_to_f64(long long n, const float* x, double* y, hipStream_t s);
+hipError_t vec_add_f32(long long n, const float* x, const double* y, float* out, hipStream_t s);
 // After the host recomputed the residual of a restart: beta = 0, run again.
 hipError_t cg_resume(CgState* st, hipStream_t s);
 

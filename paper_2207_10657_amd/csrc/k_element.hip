@@ -26,21 +26,27 @@ template <> struct ET<HFE_P1_PAIR> { static constexpr int D = 2, NQ = 2, NA = 4;
 // dN_a/dx_j at the Gauss points of the Q1 element, as a table in constant
 // memory for loops over points that are not unrolled (the index is uniform
 // over the wavefront, so the values come through scalar loads).
+template <typename R>
 struct Q1Table {
-  double v[8][8][3];
+  R v[8][8][3];
   constexpr Q1Table() : v{} {
     for (int q = 0; q < 8; ++q)
       for (int a = 0; a < 8; ++a) {
         const int o0 = a & 1, o1 = (a >> 1) & 1, o2 = (a >> 2) & 1;
         const double x0 = (q & 1) ? kG1 : kG0, x1 = (q & 2) ? kG1 : kG0, x2 = (q & 4) ? kG1 : kG0;
         const double l0 = o0 ? x0 : 1.0 - x0, l1 = o1 ? x1 : 1.0 - x1, l2 = o2 ? x2 : 1.0 - x2;
-        v[q][a][0] = (o0 ? 1.0 : -1.0) * l1 * l2;
-        v[q][a][1] = (o1 ? 1.0 : -1.0) * l0 * l2;
-        v[q][a][2] = (o2 ? 1.0 : -1.0) * l0 * l1;
+        v[q][a][0] = R((o0 ? 1.0 : -1.0) * l1 * l2);
+        v[q][a][1] = R((o1 ? 1.0 : -1.0) * l0 * l2);
+        v[q][a][2] = R((o2 ? 1.0 : -1.0) * l0 * l1);
       }
   }
 };
-__constant__ Q1Table kQ1B = Q1Table();
+__constant__ Q1Table<double> kQ1B = Q1Table<double>();
+__constant__ Q1Table<float> kQ1Bf = Q1Table<float>();
+
+template <typename R> __device__ __forceinline__ const Q1Table<R>& q1b();
+template <> __device__ __forceinline__ const Q1Table<double>& q1b<double>() { return kQ1B; }
+template <> __device__ __forceinline__ const Q1Table<float>& q1b<float>() { return kQ1Bf; }
 
 // dN_a/dx_j at point q of a unit element. Local node a = ax + 2 ay (+ 4 az).
 template <int EL>
@@ -72,36 +78,39 @@ __device__ __forceinline__ double shape_grad<HFE_P1_PAIR>(int q, int a, int j) {
 }
 
 // Symmetric tensors are held as (xx, yy, zz, xy, xz, yz); in 2D zz, xz, yz of
-// a strain are zero (plane strain).
-struct Sym { double v[6]; };
+// a strain are zero (plane strain). R = double, or float in the FP32 Hessian.
+template <typename R> struct SymT { R v[6]; };
+using Sym = SymT<double>;
 
-__device__ __forceinline__ double sym_dot(const Sym& a, const Sym& b) {
+template <typename R>
+__device__ __forceinline__ R sym_dot(const SymT<R>& a, const SymT<R>& b) {
   return a.v[0] * b.v[0] + a.v[1] * b.v[1] + a.v[2] * b.v[2] +
-         2.0 * (a.v[3] * b.v[3] + a.v[4] * b.v[4] + a.v[5] * b.v[5]);
+         R(2) * (a.v[3] * b.v[3] + a.v[4] * b.v[4] + a.v[5] * b.v[5]);
 }
 
 // sym part of a full gradient H[i][j] (d x d, row i = displacement component)
-template <int D>
-__device__ __forceinline__ Sym sym_of(const double (&H)[3][3]) {
-  Sym e;
+template <int D, typename R>
+__device__ __forceinline__ SymT<R> sym_of(const R (&H)[3][3]) {
+  SymT<R> e;
   e.v[0] = H[0][0];
   e.v[1] = H[1][1];
-  e.v[2] = D == 3 ? H[2][2] : 0.0;
-  e.v[3] = 0.5 * (H[0][1] + H[1][0]);
-  e.v[4] = D == 3 ? 0.5 * (H[0][2] + H[2][0]) : 0.0;
-  e.v[5] = D == 3 ? 0.5 * (H[1][2] + H[2][1]) : 0.0;
+  e.v[2] = D == 3 ? H[2][2] : R(0);
+  e.v[3] = R(0.5) * (H[0][1] + H[1][0]);
+  e.v[4] = D == 3 ? R(0.5) * (H[0][2] + H[2][0]) : R(0);
+  e.v[5] = D == 3 ? R(0.5) * (H[1][2] + H[2][1]) : R(0);
   return e;
 }
 
-__device__ __forceinline__ Sym c_contract(const Sym& e, double lam, double mu) {
-  const double tr = e.v[0] + e.v[1] + e.v[2];
-  Sym s;
-  s.v[0] = lam * tr + 2.0 * mu * e.v[0];
-  s.v[1] = lam * tr + 2.0 * mu * e.v[1];
-  s.v[2] = lam * tr + 2.0 * mu * e.v[2];
-  s.v[3] = 2.0 * mu * e.v[3];
-  s.v[4] = 2.0 * mu * e.v[4];
-  s.v[5] = 2.0 * mu * e.v[5];
+template <typename R>
+__device__ __forceinline__ SymT<R> c_contract(const SymT<R>& e, R lam, R mu) {
+  const R tr = e.v[0] + e.v[1] + e.v[2];
+  SymT<R> s;
+  s.v[0] = lam * tr + R(2) * mu * e.v[0];
+  s.v[1] = lam * tr + R(2) * mu * e.v[1];
+  s.v[2] = lam * tr + R(2) * mu * e.v[2];
+  s.v[3] = R(2) * mu * e.v[3];
+  s.v[4] = R(2) * mu * e.v[4];
+  s.v[5] = R(2) * mu * e.v[5];
   return s;
 }
 
@@ -144,20 +153,22 @@ __device__ __forceinline__ PointLaw eval_law(const Sym& eps, double lam, double 
 }
 
 // Tangent applied to a perturbation: a C:deps - c' (s:deps) s.
-__device__ __forceinline__ Sym apply_tangent(const Sym& de, double a, double cp, const Sym& s,
-                                             double lam, double mu) {
-  Sym t = c_contract(de, lam, mu);
+template <typename R>
+__device__ __forceinline__ SymT<R> apply_tangent(const SymT<R>& de, R a, R cp, const SymT<R>& s,
+                                                 R lam, R mu) {
+  SymT<R> t = c_contract(de, lam, mu);
 #pragma unroll
   for (int k = 0; k < 6; ++k) t.v[k] *= a;
-  if (cp != 0.0) {
-    const double sde = sym_dot(s, de);
+  if (cp != R(0)) {
+    const R sde = sym_dot(s, de);
 #pragma unroll
     for (int k = 0; k < 6; ++k) t.v[k] -= cp * sde * s.v[k];
   }
   return t;
 }
 
-__device__ __forceinline__ double sym_at(const Sym& s, int i, int j) {
+template <typename R>
+__device__ __forceinline__ R sym_at(const SymT<R>& s, int i, int j) {
   if (i == j) return s.v[i];
   const int k = (i + j == 1) ? 3 : ((i + j == 2) ? 4 : 5);
   return s.v[k];
@@ -488,16 +499,18 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
 // two node layers along j.
 
 // 1D interpolation of (f0 at node 0, f1 at node 1) to Gauss point g.
-__device__ __forceinline__ double interp(double f0, double f1, int g) {
-  const double w1 = g ? kG1 : kG0;        // weight of node 1 at point g
+template <typename R>
+__device__ __forceinline__ R interp(R f0, R f1, int g) {
+  const R w1 = g ? R(kG1) : R(kG0);       // weight of node 1 at point g
   return f0 + w1 * (f1 - f0);
 }
 
 // v[a], a = ax + 2 ay + 4 az  ->  G[j][m][n]
-__device__ __forceinline__ void q1_grad_sf(const double (&v)[8], double (&G)[3][2][2]) {
+template <typename R>
+__device__ __forceinline__ void q1_grad_sf(const R (&v)[8], R (&G)[3][2][2]) {
   // along x: differences over (ay, az), interpolate y then z
   {
-    double t[2][2];
+    R t[2][2];
 #pragma unroll
     for (int az = 0; az < 2; ++az)
 #pragma unroll
@@ -510,7 +523,7 @@ __device__ __forceinline__ void q1_grad_sf(const double (&v)[8], double (&G)[3][
   }
   // along y: differences over (ax, az), interpolate x then z
   {
-    double t[2][2];
+    R t[2][2];
 #pragma unroll
     for (int az = 0; az < 2; ++az)
 #pragma unroll
@@ -523,7 +536,7 @@ __device__ __forceinline__ void q1_grad_sf(const double (&v)[8], double (&G)[3][
   }
   // along z: differences over (ax, ay), interpolate x then y
   {
-    double t[2][2];
+    R t[2][2];
 #pragma unroll
     for (int ay = 0; ay < 2; ++ay)
 #pragma unroll
@@ -538,24 +551,26 @@ __device__ __forceinline__ void q1_grad_sf(const double (&v)[8], double (&G)[3][
 
 // Transpose of interp: a value r at Gauss point g adds (1-w) r to node 0 and
 // w r to node 1.
-__device__ __forceinline__ void interp_t(double r, int g, double& f0, double& f1) {
-  const double w1 = g ? kG1 : kG0;
+template <typename R>
+__device__ __forceinline__ void interp_t(R r, int g, R& f0, R& f1) {
+  const R w1 = g ? R(kG1) : R(kG0);
   f1 += w1 * r;
   f0 += r - w1 * r;
 }
 
 // T[j][m][n] (point values summed over the Gauss coordinate along j) -> f[a]
-__device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f)[8]) {
+template <typename R>
+__device__ __forceinline__ void q1_div_sf(const R (&T)[3][2][2], R (&f)[8]) {
   // x: T[0][gy][gz] -> (ay, az) by transposed z then y interpolation -> +-1 along x
   {
-    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gy][az]
+    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gy][az]
 #pragma unroll
     for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
       for (int gz = 0; gz < 2; ++gz) interp_t(T[0][gy][gz], gz, u[gy][0], u[gy][1]);
 #pragma unroll
     for (int az = 0; az < 2; ++az) {
-      double w0 = 0.0, w1 = 0.0;                  // (ay = 0, 1)
+      R w0 = R(0), w1 = R(0);                  // (ay = 0, 1)
 #pragma unroll
       for (int gy = 0; gy < 2; ++gy) interp_t(u[gy][az], gy, w0, w1);
       f[1 + 4 * az] += w0; f[0 + 4 * az] -= w0;
@@ -564,14 +579,14 @@ __device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f
   }
   // y: T[1][gx][gz]
   {
-    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gx][az]
+    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gx][az]
 #pragma unroll
     for (int gx = 0; gx < 2; ++gx)
 #pragma unroll
       for (int gz = 0; gz < 2; ++gz) interp_t(T[1][gx][gz], gz, u[gx][0], u[gx][1]);
 #pragma unroll
     for (int az = 0; az < 2; ++az) {
-      double w0 = 0.0, w1 = 0.0;                  // (ax = 0, 1)
+      R w0 = R(0), w1 = R(0);                  // (ax = 0, 1)
 #pragma unroll
       for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][az], gx, w0, w1);
       f[2 + 4 * az] += w0; f[0 + 4 * az] -= w0;
@@ -580,14 +595,14 @@ __device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f
   }
   // z: T[2][gx][gy]
   {
-    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // u[gx][ay]
+    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gx][ay]
 #pragma unroll
     for (int gx = 0; gx < 2; ++gx)
 #pragma unroll
       for (int gy = 0; gy < 2; ++gy) interp_t(T[2][gx][gy], gy, u[gx][0], u[gx][1]);
 #pragma unroll
     for (int ay = 0; ay < 2; ++ay) {
-      double w0 = 0.0, w1 = 0.0;                  // (ax = 0, 1)
+      R w0 = R(0), w1 = R(0);                  // (ax = 0, 1)
 #pragma unroll
       for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][ay], gx, w0, w1);
       f[4 + 2 * ay] += w0; f[0 + 2 * ay] -= w0;
@@ -607,7 +622,7 @@ __device__ __forceinline__ void q1_div_sf(const double (&T)[3][2][2], double (&f
 // two threads touch the same accumulator and the order of the additions is
 // fixed. Per-element outputs and reduction terms come from the elements the
 // brick owns (those whose lowest corner is one of its nodes).
-//   MODE_HESSIAN : f = K v = D^T B D v;  rows {v.Kv, |D v|^2}
+//   k_hessian    : f = K v = D^T B D v;  rows {v.Kv, |D v|^2}
 //   MODE_RESIDUAL: f = D^T sigma(E + D u), a/c' written;  rows RES_*
 //   MODE_TRIAL   : f = D^T sigma(E + D(u+v)), trial a/c' written;  rows TRI_*
 // Brick shapes (nodes BX x BY x BZ; the block runs one thread per element of
@@ -632,16 +647,16 @@ __device__ __forceinline__ int wrap(int x, int n) { return x < 0 ? x + n : (x >=
 
 // Full gradient at point q of the element whose lowest tile node is t0, from
 // a staged field (three components), plus an optional constant.
-template <int TILE>
-__device__ __forceinline__ void tile_grad(const double (*f)[TILE], int q, int t0, int sy, int sz,
-                                          double (&H)[3][3]) {
+template <int TILE, typename R>
+__device__ __forceinline__ void tile_grad(const R (*f)[TILE], int q, int t0, int sy, int sz,
+                                          R (&H)[3][3]) {
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int ti = t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz;
-    const double v0 = f[0][ti], v1 = f[1][ti], v2 = f[2][ti];
+    const R v0 = f[0][ti], v1 = f[1][ti], v2 = f[2][ti];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double w = kQ1B.v[q][a][j];
+      const R w = q1b<R>().v[q][a][j];
       H[0][j] += w * v0;
       H[1][j] += w * v1;
       H[2][j] += w * v2;
@@ -653,11 +668,9 @@ template <int MODE, int NV, int BX, int BY, int BZ>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(ElemArgs A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
-  if (MODE == MODE_HESSIAN && A.cg && A.cg->done) return;
-  __shared__ double sv[3][kTile];   // v: direction (Hessian) or step (trial)
+  __shared__ double sv[3][kTile];   // v: step (trial)
   __shared__ double su[3][kTile];   // u
   __shared__ double acc[3][kOwn];
-  __shared__ int need_u_flag;
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
@@ -667,7 +680,6 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;    // element brick
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ntile = tx * ty * tz;
-  if (tid == 0) need_u_flag = MODE == MODE_HESSIAN ? 0 : 1;
   // local tile node l <-> global node (origin - 1 + l) mod n
   auto tile_node = [&](int i) {
     const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
@@ -696,7 +708,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
       }
     }
   };
-  if (MODE != MODE_RESIDUAL) stage(A.v, sv);
+  if (MODE == MODE_TRIAL) stage(A.v, sv);
   for (int i = tid; i < bx * by * bz; i += nt) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c][i] = 0.0;
@@ -710,18 +722,9 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
-    if (MODE == MODE_HESSIAN) {
-      bool mine_u = false;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != 0.0;
-      if (mine_u) need_u_flag = 1;
-    }
   }
+  stage(A.u, su);
   __syncthreads();
-  if (need_u_flag) {
-    stage(A.u, su);
-    __syncthreads();
-  }
   double f[3][8];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -730,73 +733,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   double red[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) red[k] = 0.0;
-  if constexpr (MODE == MODE_HESSIAN) {
-   if (active) {
-    // sum-factorised gradient of the direction, tangent per point, and the
-    // transposed (factorised) divergence
-    const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
-    const int t0 = ex + tx * (ey + ty * ez);
-    const int sy = tx, sz = tx * ty;
-    const bool owned = ex >= 1 && ey >= 1 && ez >= 1;
-    double G[3][3][2][2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double v[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        v[a] = sv[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
-      q1_grad_sf(v, G[c]);
-    }
-    double T[3][3][2][2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int k = 0; k < 2; ++k) T[c][j][m][k] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
-      double dH[3][3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        dH[c][0] = G[c][0][gy][gz];
-        dH[c][1] = G[c][1][gx][gz];
-        dH[c][2] = G[c][2][gx][gy];
-      }
-      const double aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
-      Sym s;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
-      if (cq != 0.0) {
-        double H[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) H[i][j] = A.E[3 * i + j];
-        tile_grad<kTile>(su, q, t0, sy, sz, H);
-        s = c_contract(sym_of<3>(H), lam, mu);
-      }
-      const Sym tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
-      if (owned) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) red[HES_DD] += dH[i][j] * dH[i][j];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T[c][0][gy][gz] += sym_at(tau, c, 0);
-        T[c][1][gx][gz] += sym_at(tau, c, 1);
-        T[c][2][gx][gy] += sym_at(tau, c, 2);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
-   }
-  } else if (active) {
+  if (active) {
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     const int sy = tx, sz = tx * ty;
@@ -890,6 +827,172 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     }
   }
   __syncthreads();
+  for (int i = tid; i < bx * by * bz; i += nt) {
+    const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
+    const long long n = lin(g, x0 + lx, y0 + ly, z0 + lz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.f[c * g.N + n] = acc[c][i];
+  }
+  block_reduce_store<NV>(red, A.red.partials);
+}
+
+// Hessian K v = D^T B D v at the state (u, a, c'), in FP64 (R = double) or,
+// for the mixed-precision CG, FP32 (R = float) with the reduction terms
+// {v.Kv, |D v|^2} accumulated in FP64. The same brick scheme as k_brick: the
+// direction is staged on the tile, the displacement only if some element of
+// the brick softens (c' != 0 at one of its points). The gradient of v and the
+// divergence are sum-factorised; s = C : eps(u) is recomputed at softening
+// points only.
+template <typename R, int BX, int BY, int BZ>
+__global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_hessian(HessArgs<R> A) {
+  constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
+  const Grid& g = A.g;
+  if (A.cg && A.cg->done) return;
+  __shared__ R sv[3][kTile];
+  __shared__ R su[3][kTile];
+  __shared__ R acc[3][kOwn];
+  __shared__ int need_u_flag;
+  const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
+  const int brick = xcd_brick(blockIdx.x, gridDim.x);
+  const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
+  const int tx = bx + 2, ty = by + 2, tz = bz + 2;
+  const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ntile = tx * ty * tz;
+  if (tid == 0) need_u_flag = 0;
+  auto tile_node = [&](int i) {
+    const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
+    return lin(g, wrap(x0 - 1 + lx, g.nx), wrap(y0 - 1 + ly, g.ny), wrap(z0 - 1 + lz, g.nz));
+  };
+  constexpr int kIt = (kTile + BrickShape<BX, BY, BZ>::threads - 1) / BrickShape<BX, BY, BZ>::threads;
+  auto stage = [&](const R* __restrict__ src, R (*dst)[kTile]) {
+    R r[kIt][3];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = tid + it * nt;
+      if (i < ntile) {
+        const long long n = tile_node(i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[it][c] = src[c * g.N + n];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = tid + it * nt;
+      if (i < ntile) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c][i] = r[it][c];
+      }
+    }
+  };
+  stage(A.v, sv);
+  for (int i = tid; i < bx * by * bz; i += nt) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c][i] = R(0);
+  }
+  const int ne = ex_n * ey_n * ez_n;
+  const bool active = tid < ne;
+  const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
+  long long eg = 0;
+  int ph = 0;
+  if (active) {
+    eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
+    ph = A.phase[eg];
+    bool mine_u = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != R(0);
+    if (mine_u) need_u_flag = 1;
+  }
+  __syncthreads();
+  if (need_u_flag) {
+    stage(A.u, su);
+    __syncthreads();
+  }
+  R f[3][8];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) f[i][a] = R(0);
+  double dd = 0.0;
+  if (active) {
+    const R lam = (R)A.mat.lam[ph], mu = (R)A.mat.mu[ph];
+    const int t0 = ex + tx * (ey + ty * ez);
+    const int sy = tx, sz = tx * ty;
+    const bool owned = ex >= 1 && ey >= 1 && ez >= 1;
+    R G[3][3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      R v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        v[a] = sv[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
+      q1_grad_sf(v, G[c]);
+    }
+    R T[3][3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) T[c][j][m][k] = R(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
+      R dH[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dH[c][0] = G[c][0][gy][gz];
+        dH[c][1] = G[c][1][gx][gz];
+        dH[c][2] = G[c][2][gx][gy];
+      }
+      const R aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
+      SymT<R> s;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s.v[k] = R(0);
+      if (cq != R(0)) {
+        R H[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) H[i][j] = (R)A.E[3 * i + j];
+        tile_grad<kTile>(su, q, t0, sy, sz, H);
+        s = c_contract(sym_of<3>(H), lam, mu);
+      }
+      const SymT<R> tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
+      if (owned) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) dd += (double)dH[i][j] * (double)dH[i][j];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T[c][0][gy][gz] += sym_at(tau, c, 0);
+        T[c][1][gx][gz] += sym_at(tau, c, 1);
+        T[c][2][gx][gy] += sym_at(tau, c, 2);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
+  }
+  // assembly into the owned nodes, one local node per phase
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    __syncthreads();
+    if (active) {
+      const int lx = ex + (a & 1) - 1, ly = ey + ((a >> 1) & 1) - 1, lz = ez + ((a >> 2) & 1) - 1;
+      if (lx >= 0 && lx < bx && ly >= 0 && ly < by && lz >= 0 && lz < bz) {
+        const int o = lx + bx * (ly + by * lz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][o] += f[c][a];
+      }
+    }
+  }
+  __syncthreads();
   double dkd = 0.0;
   for (int i = tid; i < bx * by * bz; i += nt) {
     const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
@@ -897,13 +1000,15 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     const int ti = (lx + 1) + tx * ((ly + 1) + ty * (lz + 1));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double v = acc[c][i];
+      const R v = acc[c][i];
       A.f[c * g.N + n] = v;
-      if (MODE == MODE_HESSIAN) dkd += v * sv[c][ti];
+      dkd += (double)v * (double)sv[c][ti];
     }
   }
-  if constexpr (MODE == MODE_HESSIAN) red[HES_DKD] += dkd;
-  block_reduce_store<NV>(red, A.red.partials);
+  double red[HES_NV];
+  red[HES_DKD] = dkd;
+  red[HES_DD] = dd;
+  block_reduce_store<HES_NV>(red, A.red.partials);
 }
 
 template <int MODE, int NV, int BX, int BY, int BZ>
@@ -915,17 +1020,36 @@ hipError_t launch_brick_shape(const ElemArgs& A, hipStream_t s, int* nblocks) {
   return hipGetLastError();
 }
 
-// Brick shapes: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768), 2 = 16x8x4 (768),
-// 3 = 16x4x4 (448). The residual and trial passes use 8x8x4 or 16x4x4.
+// Brick shapes of the residual and trial passes: 8x8x4 (448 threads), or
+// 16x4x4 (448) for shapes 2 and 3.
 template <int MODE, int NV>
 hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
   const int shape = A.brick_shape;
-  if constexpr (MODE == MODE_HESSIAN) {
-    if (shape == 1) return launch_brick_shape<MODE, NV, 8, 8, 8>(A, s, nblocks);
-    if (shape == 2) return launch_brick_shape<MODE, NV, 16, 8, 4>(A, s, nblocks);
-  }
   if (shape == 2 || shape == 3) return launch_brick_shape<MODE, NV, 16, 4, 4>(A, s, nblocks);
   return launch_brick_shape<MODE, NV, 8, 8, 4>(A, s, nblocks);
+}
+
+template <typename R, int BX, int BY, int BZ>
+hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
+  const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
+  *nblocks = nb;
+  hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ>), dim3(nb), dim3(BrickShape<BX, BY, BZ>::threads), 0,
+                     s, A);
+  return hipGetLastError();
+}
+
+// Hessian brick shapes: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768),
+// 2 = 16x8x4 (768), 3 = 16x4x4 (448).
+template <typename R>
+hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
+  if (!A.v || !A.f || !A.u || !A.a || !A.cp || !A.phase || !A.E || !A.red.partials)
+    return hipErrorInvalidValue;
+  switch (A.brick_shape) {
+    case 1: return launch_hessian_shape<R, 8, 8, 8>(A, s, nblocks);
+    case 2: return launch_hessian_shape<R, 16, 8, 4>(A, s, nblocks);
+    case 3: return launch_hessian_shape<R, 16, 4, 4>(A, s, nblocks);
+    default: return launch_hessian_shape<R, 8, 8, 4>(A, s, nblocks);
+  }
 }
 
 template <int MODE, int NV>
@@ -951,7 +1075,24 @@ hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
 }
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
-  return launch_brick<MODE_HESSIAN, HES_NV>(A, s, nblocks);
+  HessArgs<double> H;
+  H.g = A.g;
+  H.mat = A.mat;
+  H.E = A.E;
+  H.phase = A.phase;
+  H.u = A.u;
+  H.a = A.a;
+  H.cp = A.cp;
+  H.v = A.v;
+  H.f = A.f;
+  H.red = A.red;
+  H.cg = A.cg;
+  H.brick_shape = A.brick_shape;
+  return launch_hessian_brick<double>(H, s, nblocks);
+}
+hipError_t launch_hessian_f32(const HessArgs<float>& A, hipStream_t s, int* nblocks) {
+  if (A.g.element != HFE_Q1) return hipErrorInvalidValue;
+  return launch_hessian_brick<float>(A, s, nblocks);
 }
 hipError_t launch_commit(const ElemArgs& A, hipStream_t s) {
   const int nb = (int)((A.g.N + kBlock - 1) / kBlock);

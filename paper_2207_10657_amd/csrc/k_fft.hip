@@ -1,4 +1,5 @@
-// Hand-written FP64 FFT and FE Green's operator for gfx950.
+// Hand-written FFT and FE Green's operator for gfx950, in FP64 and (for the
+// mixed-precision CG) FP32.
 //
 // The projector of Sec. 2.1 is block diagonal in the wave vector (eq.
 // conv_to_fourier). In displacement coordinates its only non-trivial part is
@@ -10,12 +11,13 @@
 //                  real samples packed per complex value, a half-length
 //                  complex FFT and a split step), then a complex FFT along y,
 //                  all in LDS;
-//   k_pencil       per (ky, kx-chunk, component): FFT along z, multiply by
-//                  1/(S(k) N), inverse FFT along z, all in LDS;
+//   k_pencil       per chunk of consecutive (ky, kx) columns and component:
+//                  FFT along z, multiply by 1/(S(k) N), inverse FFT along z,
+//                  all in LDS;
 //   k_plane<INV>   the inverse of the first pass.
 // In 2D a single k_plane<GREEN2D> does forward, multiply and inverse.
 //
-// The 1D transforms are Stockham autosort passes (radix 4, then 3, then 2)
+// The 1D transforms are Stockham autosort passes (radix 8, 4, 3, then 2)
 // on lines held in LDS, with every thread staging its butterflies in
 // registers between two barriers so that one LDS buffer suffices.
 #include "hfe_internal.h"
@@ -24,26 +26,39 @@
 namespace hfe {
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex values of either precision: V is double2 or float2, ScalarOf<V> its
+// component type.
+template <typename V> struct ScalarOf;
+template <> struct ScalarOf<double2> { using T = double; };
+template <> struct ScalarOf<float2> { using T = float; };
+
+template <typename V>
+__device__ __forceinline__ V mk(typename ScalarOf<V>::T a, typename ScalarOf<V>::T b) {
+  V v;
+  v.x = a;
+  v.y = b;
+  return v;
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cconj(V a) { return mk<V>(a.x, -a.y); }
 // multiply by -i (forward) or +i (inverse)
-template <bool INV>
-__device__ __forceinline__ double2 mul_mi(double2 a) {
-  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <bool INV, typename V>
+__device__ __forceinline__ V mul_mi(V a) {
+  return INV ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x);
 }
 
 // Copy `total` elements with up to kStage independent loads in flight per
 // thread (all loads of a round are issued before any store).
 constexpr int kStage = 8;
-template <typename Load, typename Store>
+template <typename V, typename Load, typename Store>
 __device__ __forceinline__ void staged_copy(int total, Load load, Store store) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int base = 0; base < total; base += kStage * nt) {
-    double2 r[kStage];
+    V r[kStage];
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int i = base + u * nt + tid;
@@ -63,29 +78,30 @@ constexpr int radix_of(int rem) {
 
 template <int R, bool INV> struct Bfly;
 template <bool INV> struct Bfly<2, INV> {
-  __device__ static void run(double2 (&v)[2]) {
-    const double2 a = v[0], b = v[1];
+  template <typename V> __device__ static void run(V (&v)[2]) {
+    const V a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   }
 };
 template <bool INV> struct Bfly<3, INV> {
-  __device__ static void run(double2 (&v)[3]) {
-    constexpr double kS = 0.86602540378443864676;  // sin(2 pi / 3)
-    const double2 a = v[0], b = v[1], c = v[2];
-    const double2 t1 = cadd(b, c);
-    const double2 t2 = make_double2(a.x - 0.5 * t1.x, a.y - 0.5 * t1.y);
-    const double2 d = csub(b, c);
-    const double2 t3 = make_double2(kS * d.x, kS * d.y);
+  template <typename V> __device__ static void run(V (&v)[3]) {
+    using S = typename ScalarOf<V>::T;
+    const S kS = S(0.86602540378443864676);  // sin(2 pi / 3)
+    const V a = v[0], b = v[1], c = v[2];
+    const V t1 = cadd(b, c);
+    const V t2 = mk<V>(a.x - S(0.5) * t1.x, a.y - S(0.5) * t1.y);
+    const V d = csub(b, c);
+    const V t3 = mk<V>(kS * d.x, kS * d.y);
     v[0] = cadd(a, t1);
     v[1] = cadd(t2, mul_mi<INV>(t3));
     v[2] = csub(t2, mul_mi<INV>(t3));
   }
 };
 template <bool INV> struct Bfly<4, INV> {
-  __device__ static void run(double2 (&v)[4]) {
-    const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const double2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+  template <typename V> __device__ static void run(V (&v)[4]) {
+    const V t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const V t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
     v[0] = cadd(t0, t2);
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, mul_mi<INV>(t3));
@@ -96,18 +112,19 @@ template <bool INV> struct Bfly<4, INV> {
 template <bool INV> struct Bfly<8, INV> {
   // 8-point DFT = two 4-point DFTs (even, odd samples) and one radix-2 stage
   // with the twiddles e^{-+ 2 pi i k / 8}
-  __device__ static void run(double2 (&v)[8]) {
-    constexpr double kR = 0.70710678118654752440;   // 1/sqrt(2)
-    double2 e[4] = {v[0], v[2], v[4], v[6]};
-    double2 o[4] = {v[1], v[3], v[5], v[7]};
+  template <typename V> __device__ static void run(V (&v)[8]) {
+    using S = typename ScalarOf<V>::T;
+    const S kR = S(0.70710678118654752440);   // 1/sqrt(2)
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
     Bfly<4, INV>::run(e);
     Bfly<4, INV>::run(o);
     // w^1 o[1], w^2 o[2], w^3 o[3] with w = e^{-2 pi i/8} (conjugate for INV)
-    const double2 o1 = INV ? make_double2(kR * (o[1].x - o[1].y), kR * (o[1].x + o[1].y))
-                           : make_double2(kR * (o[1].x + o[1].y), kR * (o[1].y - o[1].x));
-    const double2 o2 = mul_mi<INV>(o[2]);
-    const double2 o3 = INV ? make_double2(-kR * (o[3].x + o[3].y), kR * (o[3].x - o[3].y))
-                           : make_double2(kR * (o[3].y - o[3].x), -kR * (o[3].x + o[3].y));
+    const V o1 = INV ? mk<V>(kR * (o[1].x - o[1].y), kR * (o[1].x + o[1].y))
+                     : mk<V>(kR * (o[1].x + o[1].y), kR * (o[1].y - o[1].x));
+    const V o2 = mul_mi<INV>(o[2]);
+    const V o3 = INV ? mk<V>(-kR * (o[3].x + o[3].y), kR * (o[3].x - o[3].y))
+                     : mk<V>(kR * (o[3].y - o[3].x), -kR * (o[3].x + o[3].y));
     v[0] = cadd(e[0], o[0]);
     v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], o1);
@@ -121,12 +138,12 @@ template <bool INV> struct Bfly<8, INV> {
 
 // One Stockham pass of radix R on `nlines` lines of length L; element k of
 // line l is buf[l*ls + k*es]. `tw` holds e^{-2 pi i k / L}, k < L.
-template <int L, int R, int NS, bool INV>
-__device__ __forceinline__ void fft_pass(double2* buf, int nlines, int ls, int es,
-                                         const double2* __restrict__ tw) {
+template <int L, int R, int NS, bool INV, typename V>
+__device__ __forceinline__ void fft_pass(V* buf, int nlines, int ls, int es,
+                                         const V* __restrict__ tw) {
   constexpr int NB = L / R;       // butterflies per line
   constexpr int MAXB = 16 / R;    // butterflies staged per thread (caller guarantees enough threads)
-  double2 v[MAXB][R];
+  V v[MAXB][R];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int total = nlines * NB;
 #pragma unroll
@@ -135,12 +152,12 @@ __device__ __forceinline__ void fft_pass(double2* buf, int nlines, int ls, int e
     if (b < total) {
       const int line = b / NB, j = b - line * NB;
       const int k = j % NS;
-      const double2* base = buf + line * ls;
+      const V* base = buf + line * ls;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double2 x = base[(j + r * NB) * es];
+        V x = base[(j + r * NB) * es];
         if (NS > 1 && r > 0) {
-          double2 w = tw[k * r * (L / (NS * R))];
+          V w = tw[k * r * (L / (NS * R))];
           if (INV) w.y = -w.y;
           x = cmul(x, w);
         }
@@ -157,7 +174,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int nlines, int ls, int e
       const int line = b / NB, j = b - line * NB;
       const int k = j % NS;
       const int idx = (j / NS) * NS * R + k;
-      double2* base = buf + line * ls;
+      V* base = buf + line * ls;
 #pragma unroll
       for (int r = 0; r < R; ++r) base[(idx + r * NS) * es] = v[it][r];
     }
@@ -167,7 +184,8 @@ __device__ __forceinline__ void fft_pass(double2* buf, int nlines, int ls, int e
 
 template <int L, int REM, int NS, bool INV>
 struct Passes {
-  __device__ static void run(double2* buf, int nl, int ls, int es, const double2* tw) {
+  template <typename V>
+  __device__ static void run(V* buf, int nl, int ls, int es, const V* tw) {
     constexpr int R = radix_of(REM);
     fft_pass<L, R, NS, INV>(buf, nl, ls, es, tw);
     Passes<L, REM / R, NS * R, INV>::run(buf, nl, ls, es, tw);
@@ -175,12 +193,13 @@ struct Passes {
 };
 template <int L, int NS, bool INV>
 struct Passes<L, 1, NS, INV> {
-  __device__ static void run(double2*, int, int, int, const double2*) {}
+  template <typename V>
+  __device__ static void run(V*, int, int, int, const V*) {}
 };
 
 // In-place transform of nl lines of runtime length L (uniform over the block).
-template <bool INV>
-__device__ void lds_fft(int L, double2* buf, int nl, int ls, int es, const double2* tw) {
+template <bool INV, typename V>
+__device__ void lds_fft(int L, V* buf, int nl, int ls, int es, const V* tw) {
   switch (L) {
     case 2: Passes<2, 2, 1, INV>::run(buf, nl, ls, es, tw); break;
     case 3: Passes<3, 3, 1, INV>::run(buf, nl, ls, es, tw); break;
@@ -202,30 +221,32 @@ __device__ void lds_fft(int L, double2* buf, int nl, int ls, int es, const doubl
 // Split step of the packed real transform along x: row y holds
 // Z[m] = FFT_M(x[2m] + i x[2m+1]) in columns 0..M-1; afterwards columns
 // 0..M hold X[k] = sum_n x[n] e^{-2 pi i k n / nx}. W[k] = e^{-2 pi i k / nx}.
-__device__ void split_r2c(double2* buf, int M, int ny, int P, const double2* __restrict__ W) {
+template <typename V>
+__device__ void split_r2c(V* buf, int M, int ny, int P, const V* __restrict__ W) {
+  using S = typename ScalarOf<V>::T;
   const int npair = M / 2 + 1;
   for (int i = threadIdx.x; i < ny * npair; i += blockDim.x) {
     const int y = i / npair, k = i - y * npair;
-    double2* row = buf + y * P;
+    V* row = buf + y * P;
     if (k == 0) {
-      const double2 z0 = row[0];
-      row[0] = make_double2(z0.x + z0.y, 0.0);
-      row[M] = make_double2(z0.x - z0.y, 0.0);
+      const V z0 = row[0];
+      row[0] = mk<V>(z0.x + z0.y, S(0));
+      row[M] = mk<V>(z0.x - z0.y, S(0));
     } else {
       const int k2 = M - k;
-      const double2 A = row[k], B = row[k2];
+      const V A = row[k], B = row[k2];
       // X[k] = (A + B*)/2 - i W^k (A - B*)/2
       {
-        const double2 Bc = cconj(B);
-        const double2 s = cadd(A, Bc), d = csub(A, Bc);
-        const double2 wd = cmul(W[k], d);
-        row[k] = make_double2(0.5 * (s.x + wd.y), 0.5 * (s.y - wd.x));
+        const V Bc = cconj(B);
+        const V s = cadd(A, Bc), d = csub(A, Bc);
+        const V wd = cmul(W[k], d);
+        row[k] = mk<V>(S(0.5) * (s.x + wd.y), S(0.5) * (s.y - wd.x));
       }
       if (k2 != k) {
-        const double2 Ac = cconj(A);
-        const double2 s = cadd(B, Ac), d = csub(B, Ac);
-        const double2 wd = cmul(W[k2], d);
-        row[k2] = make_double2(0.5 * (s.x + wd.y), 0.5 * (s.y - wd.x));
+        const V Ac = cconj(A);
+        const V s = cadd(B, Ac), d = csub(B, Ac);
+        const V wd = cmul(W[k2], d);
+        row[k2] = mk<V>(S(0.5) * (s.x + wd.y), S(0.5) * (s.y - wd.x));
       }
     }
   }
@@ -234,49 +255,53 @@ __device__ void split_r2c(double2* buf, int M, int ny, int P, const double2* __r
 
 // Inverse of split_r2c, scaled so that the unscaled inverse FFT of length M
 // that follows returns nx times the real samples (packed in pairs).
-__device__ void merge_c2r(double2* buf, int M, int ny, int P, const double2* __restrict__ W) {
+template <typename V>
+__device__ void merge_c2r(V* buf, int M, int ny, int P, const V* __restrict__ W) {
   const int npair = M / 2 + 1;
   for (int i = threadIdx.x; i < ny * npair; i += blockDim.x) {
     const int y = i / npair, k = i - y * npair;
-    double2* row = buf + y * P;
+    V* row = buf + y * P;
     if (k == 0) {
-      const double2 X0 = row[0], XM = cconj(row[M]);
-      const double2 s = cadd(X0, XM), d = csub(X0, XM);
-      row[0] = make_double2(s.x - d.y, s.y + d.x);
+      const V X0 = row[0], XM = cconj(row[M]);
+      const V s = cadd(X0, XM), d = csub(X0, XM);
+      row[0] = mk<V>(s.x - d.y, s.y + d.x);
     } else {
       const int k2 = M - k;
-      const double2 A = row[k], B = row[k2];
+      const V A = row[k], B = row[k2];
       // Z[k] = (A + B*) + i W^{-k} (A - B*)
       {
-        const double2 Bc = cconj(B);
-        const double2 s = cadd(A, Bc), d = csub(A, Bc);
-        const double2 wd = cmul(cconj(W[k]), d);
-        row[k] = make_double2(s.x - wd.y, s.y + wd.x);
+        const V Bc = cconj(B);
+        const V s = cadd(A, Bc), d = csub(A, Bc);
+        const V wd = cmul(cconj(W[k]), d);
+        row[k] = mk<V>(s.x - wd.y, s.y + wd.x);
       }
       if (k2 != k) {
-        const double2 Ac = cconj(A);
-        const double2 s = cadd(B, Ac), d = csub(B, Ac);
-        const double2 wd = cmul(cconj(W[k2]), d);
-        row[k2] = make_double2(s.x - wd.y, s.y + wd.x);
+        const V Ac = cconj(A);
+        const V s = cadd(B, Ac), d = csub(B, Ac);
+        const V wd = cmul(cconj(W[k2]), d);
+        row[k2] = mk<V>(s.x - wd.y, s.y + wd.x);
       }
     }
   }
   __syncthreads();
 }
 
-// 1 / (S(k) N) from the per-axis 1D symbols s_m = 2 - 2 cos(theta_m); 0 at k = 0.
-__device__ __forceinline__ double green_q1(double sx, double sy, double sz) {
-  const double px = 3.0 - 0.5 * sx, py = 3.0 - 0.5 * sy, pz = 3.0 - 0.5 * sz;
-  return (8.0 / 9.0) * (sx * py * pz + sy * px * pz + sz * px * py);
+// S(k) from the per-axis 1D symbols s_m = 2 - 2 cos(theta_m).
+template <typename R>
+__device__ __forceinline__ R green_q1(R sx, R sy, R sz) {
+  const R px = R(3) - R(0.5) * sx, py = R(3) - R(0.5) * sy, pz = R(3) - R(0.5) * sz;
+  return R(8.0 / 9.0) * (sx * py * pz + sy * px * pz + sz * px * py);
 }
-__device__ __forceinline__ double green_p1(double sx, double sy) { return 2.0 * (sx + sy); }
+template <typename R>
+__device__ __forceinline__ R green_p1(R sx, R sy) { return R(2) * (sx + sy); }
 
 enum { PLANE_FWD = 0, PLANE_INV = 1, PLANE_GREEN2D = 2, PLANE_FWD_CG = 3, PLANE_INV_CG = 4 };
 
-template <int MODE>
-__global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const double* __restrict__ in,
-                                                double* __restrict__ out, double2* __restrict__ spec,
-                                                double scale, const CgState* skip, CgFuse cf) {
+template <int MODE, typename R>
+__global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R* __restrict__ in,
+                                                R* __restrict__ out, C2<R>* __restrict__ spec,
+                                                R scale, const CgState* skip, CgFuse<R> cf) {
+  using V = C2<R>;
   const int nx = g.nx, ny = g.ny, M = nx / 2, P = M + 1;
   const int z = blockIdx.x, c = blockIdx.y;
   const long long plane = (long long)c * g.N + (long long)z * nx * ny;
@@ -284,22 +309,23 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
   if (MODE == PLANE_FWD_CG && cf.st->done) {
     // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
     if (cf.st->apply_tau) {
-      const double tau = cf.st->tau;
+      const R tau = (R)cf.st->tau;
       for (int i = tid; i < nx * ny; i += nt) cf.z[plane + i] += tau * cf.d[plane + i];
     }
     return;
   }
   if (MODE == PLANE_INV_CG && cf.st->done) return;
   if (skip && skip->done) return;
-  extern __shared__ double2 lds[];
-  double2* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  V* lds = reinterpret_cast<V*>(lds_raw);
+  V* sp = spec + ((long long)c * g.nz + z) * (long long)ny * P;
   // twiddles of the x (length M) and y (length ny) transforms and of the
   // split step, staged once into LDS behind the plane
-  double2* twx = lds + P * ny;
-  double2* twy = twx + M;
-  double2* twp = twy + ny;
+  V* twx = lds + P * ny;
+  V* twy = twx + M;
+  V* twp = twy + ny;
   for (int i = tid; i < 2 * M + 1 + ny; i += nt) {
-    double2 v;
+    V v;
     if (i < M) v = t.tw[t.off_x + i];
     else if (i < M + ny) v = t.tw[t.off_y + i - M];
     else v = t.tw[t.off_post + i - M - ny];
@@ -309,17 +335,17 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
   // start from the half spectrum
   constexpr bool kRealInput = MODE == PLANE_FWD || MODE == PLANE_FWD_CG || MODE == PLANE_GREEN2D;
   if (kRealInput) {
-    const double2* src = reinterpret_cast<const double2*>(in + plane);
-    staged_copy(M * ny, [&](int i) { return src[i]; },
-                [&](int i, double2 v) {
-                  const int y = i / M, m = i - y * M;
-                  lds[y * P + m] = v;
-                });
+    const V* src = reinterpret_cast<const V*>(in + plane);
+    staged_copy<V>(M * ny, [&](int i) { return src[i]; },
+                   [&](int i, V v) {
+                     const int y = i / M, m = i - y * M;
+                     lds[y * P + m] = v;
+                   });
     __syncthreads();
     if (MODE == PLANE_FWD_CG) {
       // z += alpha d, g += alpha Kd on this plane (Kd is the transform input)
-      const double alpha = cf.st->alpha;
-      const double* kd = in + plane;
+      const R alpha = (R)cf.st->alpha;
+      const R* kd = in + plane;
       for (int i = tid; i < nx * ny; i += nt) {
         cf.z[plane + i] += alpha * cf.d[plane + i];
         cf.g[plane + i] += alpha * kd[i];
@@ -335,38 +361,39 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
     // 2D: multiply by the FE Green's function
     for (int i = tid; i < P * ny; i += nt) {
       const int ky = i / P, kx = i - ky * P;
-      const double S = green_p1(t.sx[kx], t.sy[ky]);
-      const double m = (kx == 0 && ky == 0) ? 0.0 : scale / S;
-      lds[i] = make_double2(lds[i].x * m, lds[i].y * m);
+      const R S = green_p1(t.sx[kx], t.sy[ky]);
+      const R m = (kx == 0 && ky == 0) ? R(0) : scale / S;
+      lds[i] = mk<V>(lds[i].x * m, lds[i].y * m);
     }
     __syncthreads();
   } else {
-    staged_copy(P * ny, [&](int i) { return sp[i]; }, [&](int i, double2 v) { lds[i] = v; });
+    staged_copy<V>(P * ny, [&](int i) { return sp[i]; }, [&](int i, V v) { lds[i] = v; });
     __syncthreads();
   }
   lds_fft<true>(ny, lds, P, 1, P, twy);
   merge_c2r(lds, M, ny, P, twp);
   lds_fft<true>(M, lds, ny, P, 1, twx);
   if (MODE == PLANE_INV_CG) {
-    // y += alpha w and the residual inner products, w never leaves LDS
-    const double alpha = cf.st->alpha;
-    double2* y2 = reinterpret_cast<double2*>(cf.y + plane);
-    const double2* g2 = reinterpret_cast<const double2*>(cf.g + plane);
+    // y += alpha w and the residual inner products (accumulated in FP64),
+    // w never leaves LDS
+    const R alpha = (R)cf.st->alpha;
+    V* y2 = reinterpret_cast<V*>(cf.y + plane);
+    const V* g2 = reinterpret_cast<const V*>(cf.g + plane);
     double acc[2] = {0.0, 0.0};
     for (int i = tid; i < M * ny; i += nt) {
       const int yy = i / M, m = i - yy * M;
-      const double2 w = lds[yy * P + m];
-      const double2 yo = y2[i];
-      const double2 gi = g2[i];
-      const double2 yn = make_double2(yo.x + alpha * w.x, yo.y + alpha * w.y);
+      const V w = lds[yy * P + m];
+      const V yo = y2[i];
+      const V gi = g2[i];
+      const V yn = mk<V>(yo.x + alpha * w.x, yo.y + alpha * w.y);
       y2[i] = yn;
-      acc[0] += yn.x * gi.x + yn.y * gi.y;
-      acc[1] += yo.x * gi.x + yo.y * gi.y;
+      acc[0] += (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
+      acc[1] += (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
     }
     block_reduce_store<2>(acc, cf.partials, (int)(blockIdx.y * gridDim.x + blockIdx.x));
     return;
   }
-  double2* dst = reinterpret_cast<double2*>(out + plane);
+  V* dst = reinterpret_cast<V*>(out + plane);
   for (int i = tid; i < M * ny; i += nt) {
     const int y = i / M, m = i - y * M;
     dst[i] = lds[y * P + m];
@@ -375,41 +402,51 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTables t, const doubl
 
 enum { PENCIL_GREEN = 0, PENCIL_FWD = 1, PENCIL_INV = 2 };
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __restrict__ spec,
-                                               int C, double scale, const CgState* skip) {
+// Columns per pencil block: runs of 256 bytes per z row.
+template <typename R> constexpr int pencil_cols() { return 256 / (int)sizeof(C2<R>); }
+
+// One block per run of C consecutive columns p = ky (nx/2+1) + kx of one
+// component (the last run may be shorter); the column data of a z row are
+// contiguous in the half spectrum.
+template <int MODE, typename R>
+__global__ void __launch_bounds__(256) k_pencil(Grid g, FftTablesT<R> t, C2<R>* __restrict__ spec,
+                                               R scale, const CgState* skip) {
+  using V = C2<R>;
+  constexpr int C = pencil_cols<R>();
   if (skip && skip->done) return;
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  V* lds = reinterpret_cast<V*>(lds_raw);
   const int P = g.nx / 2 + 1, ny = g.ny, nz = g.nz;
-  const int kx0 = blockIdx.x * C;
-  const int cv = min(C, P - kx0);
-  const int ky = blockIdx.y, c = blockIdx.z;
-  double2* base = spec + (long long)c * nz * ny * P + (long long)ky * P + kx0;
-  const long long zs = (long long)ny * P;
+  const int ncol = P * ny;
+  const int p0 = blockIdx.x * C;
+  const int cv = min(C, ncol - p0);
+  const int c = blockIdx.y;
+  V* base = spec + (long long)c * nz * ncol + p0;
+  const long long zs = ncol;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // LDS row pitch C + 1: consecutive z of one kx column fall in different banks
-  const int CP = C + 1;
-  double2* twz = lds + CP * nz;    // z twiddles staged behind the pencils
+  // LDS row pitch C + 1: consecutive z of one column fall in different banks
+  constexpr int CP = C + 1;
+  V* twz = lds + CP * nz;    // z twiddles staged behind the pencils
   for (int i = tid; i < nz; i += nt) twz[i] = t.tw[t.off_z + i];
-  staged_copy(nz * cv, [&](int i) {
-                const int zz = i / cv, j = i - zz * cv;
-                return base[zz * zs + j];
-              },
-              [&](int i, double2 v) {
-                const int zz = i / cv, j = i - zz * cv;
-                lds[zz * CP + j] = v;
-              });
+  staged_copy<V>(nz * cv, [&](int i) {
+                   const int zz = i / cv, j = i - zz * cv;
+                   return base[zz * zs + j];
+                 },
+                 [&](int i, V v) {
+                   const int zz = i / cv, j = i - zz * cv;
+                   lds[zz * CP + j] = v;
+                 });
   __syncthreads();
   if (MODE != PENCIL_INV) lds_fft<false>(nz, lds, cv, 1, CP, twz);
   if (MODE == PENCIL_GREEN) {
-    const double syv = t.sy[ky];
     for (int i = tid; i < nz * cv; i += nt) {
       const int kz = i / cv, j = i - kz * cv;
-      const int kx = kx0 + j;
-      const double S = green_q1(t.sx[kx], syv, t.sz[kz]);
-      const double m = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / S;
-      const double2 v = lds[kz * CP + j];
-      lds[kz * CP + j] = make_double2(v.x * m, v.y * m);
+      const int p = p0 + j;
+      const int ky = p / P, kx = p - ky * P;
+      const R S = green_q1(t.sx[kx], t.sy[ky], t.sz[kz]);
+      const R m = (kx == 0 && ky == 0 && kz == 0) ? R(0) : scale / S;
+      const V v = lds[kz * CP + j];
+      lds[kz * CP + j] = mk<V>(v.x * m, v.y * m);
     }
     __syncthreads();
   }
@@ -420,8 +457,6 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTables t, double2* __
   }
 }
 
-constexpr int kPencilC = 16;
-
 int plane_threads(const Grid& g) {
   // a thread stages at most 15 complex values per Stockham pass (radix 3:
   // 5 butterflies), so a block of T threads covers 15 T cells
@@ -429,37 +464,42 @@ int plane_threads(const Grid& g) {
   return cells <= 15 * 256 ? 256 : 1024;
 }
 
-template <int MODE>
-hipError_t launch_plane(const Grid& g, const FftTables& t, const double* in, double* out,
-                        double2* spec, double scale, hipStream_t s, const CgState* skip = nullptr,
-                        CgFuse cf = CgFuse{}) {
+template <int MODE, typename R>
+hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* out, C2<R>* spec,
+                        R scale, hipStream_t s, const CgState* skip = nullptr,
+                        CgFuse<R> cf = CgFuse<R>{}) {
   // every pointer the mode dereferences must be present (a missing one is an
   // error here, not a fault on the device)
   constexpr bool real_in = MODE == PLANE_FWD || MODE == PLANE_FWD_CG || MODE == PLANE_GREEN2D;
   constexpr bool real_out = MODE == PLANE_INV || MODE == PLANE_GREEN2D;
   constexpr bool cg = MODE == PLANE_FWD_CG || MODE == PLANE_INV_CG;
-  if ((real_in && !in) || (real_out && !out) || !spec) return hipErrorInvalidValue;
+  if ((real_in && !in) || (real_out && !out) || !spec || !t.tw) return hipErrorInvalidValue;
   if (cg && (!cf.st || !cf.d || !cf.z || !cf.g || !cf.y || !cf.partials)) return hipErrorInvalidValue;
-  const size_t lds = fft_plane_lds_bytes(g);
+  if (!fft_plane_fits<R>(g)) return hipErrorInvalidValue;
+  const size_t lds = fft_plane_lds_bytes<R>(g);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE, R>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_plane<MODE>, dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t, in,
-                     out, spec, scale, skip, cf);
+  hipLaunchKernelGGL((k_plane<MODE, R>), dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t,
+                     in, out, spec, scale, skip, cf);
   return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_pencil(const Grid& g, const FftTables& t, double2* spec, double scale,
+template <int MODE, typename R>
+hipError_t launch_pencil(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, R scale,
                          hipStream_t s, const CgState* skip = nullptr) {
-  if (!spec) return hipErrorInvalidValue;
-  const int P = g.nx / 2 + 1;
-  const int nchunk = (P + kPencilC - 1) / kPencilC;
-  const size_t lds = ((size_t)(kPencilC + 1) * g.nz + g.nz) * sizeof(double2);
-  hipLaunchKernelGGL(k_pencil<MODE>, dim3(nchunk, g.ny, g.dim), dim3(256), lds, s, g, t, spec,
-                     kPencilC, scale, skip);
+  if (!spec || !t.tw) return hipErrorInvalidValue;
+  constexpr int C = pencil_cols<R>();
+  // one Stockham pass stages at most 15 (radix 3) or 16 values per thread
+  if ((long long)C * g.nz > 15LL * 256 && g.nz % 3 == 0) return hipErrorInvalidValue;
+  if ((long long)C * g.nz > 16LL * 256) return hipErrorInvalidValue;
+  const int ncol = (g.nx / 2 + 1) * g.ny;
+  const int nchunk = (ncol + C - 1) / C;
+  const size_t lds = ((size_t)(C + 1) * g.nz + g.nz) * sizeof(C2<R>);
+  hipLaunchKernelGGL((k_pencil<MODE, R>), dim3(nchunk, g.dim), dim3(256), lds, s, g, t, spec,
+                     scale, skip);
   return hipGetLastError();
 }
 
@@ -475,44 +515,58 @@ bool fft_length_supported(int L) {
   }
 }
 
+template <typename R>
 size_t fft_plane_lds_bytes(const Grid& g) {
   const int M = g.nx / 2;
-  return ((size_t)(M + 1) * g.ny + 2 * M + 1 + g.ny) * sizeof(double2);
+  return ((size_t)(M + 1) * g.ny + 2 * M + 1 + g.ny) * sizeof(C2<R>);
 }
 
-hipError_t fft_plane_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
+template <typename R>
+bool fft_plane_fits(const Grid& g) {
+  // LDS of one CU, and at most 15 staged values per thread of a 1024-thread block
+  return fft_plane_lds_bytes<R>(g) <= 160 * 1024 && (long long)(g.nx / 2 + 1) * g.ny <= 15 * 1024;
+}
+
+template <typename R>
+hipError_t fft_plane_forward(const Grid& g, const FftTablesT<R>& t, const R* in, C2<R>* spec,
                              hipStream_t s, const CgState* skip) {
-  return launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s, skip);
+  return launch_plane<PLANE_FWD, R>(g, t, in, nullptr, spec, R(1), s, skip);
 }
 
-hipError_t fft_plane_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
+template <typename R>
+hipError_t fft_plane_inverse(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, R* out,
                              hipStream_t s, const CgState* skip) {
-  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s, skip);
+  return launch_plane<PLANE_INV, R>(g, t, nullptr, out, spec, R(1), s, skip);
 }
 
-hipError_t fft_pencil_green(const Grid& g, const FftTables& t, double2* spec, hipStream_t s,
+template <typename R>
+hipError_t fft_pencil_green(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, hipStream_t s,
                             const CgState* skip) {
-  return launch_pencil<PENCIL_GREEN>(g, t, spec, 1.0 / (double)g.N, s, skip);
+  return launch_pencil<PENCIL_GREEN, R>(g, t, spec, R(1.0 / (double)g.N), s, skip);
 }
 
-hipError_t fft_plane_green2d(const Grid& g, const FftTables& t, const double* in, double* out,
-                             double2* spec, hipStream_t s, const CgState* skip) {
-  return launch_plane<PLANE_GREEN2D>(g, t, in, out, spec, 1.0 / (double)g.N, s, skip);
+template <typename R>
+hipError_t fft_plane_green2d(const Grid& g, const FftTablesT<R>& t, const R* in, R* out,
+                             C2<R>* spec, hipStream_t s, const CgState* skip) {
+  return launch_plane<PLANE_GREEN2D, R>(g, t, in, out, spec, R(1.0 / (double)g.N), s, skip);
 }
 
-hipError_t fft_plane_forward_cg(const Grid& g, const FftTables& t, const double* Kd, double2* spec,
-                                const CgFuse& f, hipStream_t s) {
-  return launch_plane<PLANE_FWD_CG>(g, t, Kd, nullptr, spec, 1.0, s, nullptr, f);
+template <typename R>
+hipError_t fft_plane_forward_cg(const Grid& g, const FftTablesT<R>& t, const R* Kd, C2<R>* spec,
+                                const CgFuse<R>& f, hipStream_t s) {
+  return launch_plane<PLANE_FWD_CG, R>(g, t, Kd, nullptr, spec, R(1), s, nullptr, f);
 }
 
-hipError_t fft_plane_inverse_cg(const Grid& g, const FftTables& t, double2* spec, const CgFuse& f,
-                                hipStream_t s, int* nblocks) {
+template <typename R>
+hipError_t fft_plane_inverse_cg(const Grid& g, const FftTablesT<R>& t, C2<R>* spec,
+                                const CgFuse<R>& f, hipStream_t s, int* nblocks) {
   *nblocks = g.nz * g.dim;
-  return launch_plane<PLANE_INV_CG>(g, t, nullptr, nullptr, spec, 1.0, s, nullptr, f);
+  return launch_plane<PLANE_INV_CG, R>(g, t, nullptr, nullptr, spec, R(1), s, nullptr, f);
 }
 
-hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, double* out,
-                       double2* spec, hipStream_t s, const CgState* skip) {
+template <typename R>
+hipError_t green_apply(const Grid& g, const FftTablesT<R>& t, const R* in, R* out, C2<R>* spec,
+                       hipStream_t s, const CgState* skip) {
   if (g.dim == 2) return fft_plane_green2d(g, t, in, out, spec, s, skip);
   hipError_t e = fft_plane_forward(g, t, in, spec, s, skip);
   if (e != hipSuccess) return e;
@@ -523,18 +577,40 @@ hipError_t green_apply(const Grid& g, const FftTables& t, const double* in, doub
 
 hipError_t fft_forward(const Grid& g, const FftTables& t, const double* in, double2* spec,
                        hipStream_t s) {
-  hipError_t e = launch_plane<PLANE_FWD>(g, t, in, nullptr, spec, 1.0, s);
+  hipError_t e = launch_plane<PLANE_FWD, double>(g, t, in, nullptr, spec, 1.0, s);
   if (e != hipSuccess || g.nz == 1) return e;
-  return launch_pencil<PENCIL_FWD>(g, t, spec, 1.0, s);
+  return launch_pencil<PENCIL_FWD, double>(g, t, spec, 1.0, s);
 }
 
 hipError_t fft_inverse(const Grid& g, const FftTables& t, double2* spec, double* out,
                        hipStream_t s) {
   if (g.nz > 1) {
-    hipError_t e = launch_pencil<PENCIL_INV>(g, t, spec, 1.0, s);
+    hipError_t e = launch_pencil<PENCIL_INV, double>(g, t, spec, 1.0, s);
     if (e != hipSuccess) return e;
   }
-  return launch_plane<PLANE_INV>(g, t, nullptr, out, spec, 1.0, s);
+  return launch_plane<PLANE_INV, double>(g, t, nullptr, out, spec, 1.0, s);
 }
+
+#define HFE_FFT_INSTANTIATE(R)                                                                  \
+  template size_t fft_plane_lds_bytes<R>(const Grid&);                                          \
+  template bool fft_plane_fits<R>(const Grid&);                                                 \
+  template hipError_t fft_plane_forward<R>(const Grid&, const FftTablesT<R>&, const R*, C2<R>*, \
+                                           hipStream_t, const CgState*);                        \
+  template hipError_t fft_plane_inverse<R>(const Grid&, const FftTablesT<R>&, C2<R>*, R*,       \
+                                           hipStream_t, const CgState*);                        \
+  template hipError_t fft_pencil_green<R>(const Grid&, const FftTablesT<R>&, C2<R>*,            \
+                                          hipStream_t, const CgState*);                         \
+  template hipError_t fft_plane_green2d<R>(const Grid&, const FftTablesT<R>&, const R*, R*,     \
+                                           C2<R>*, hipStream_t, const CgState*);                \
+  template hipError_t fft_plane_forward_cg<R>(const Grid&, const FftTablesT<R>&, const R*,      \
+                                              C2<R>*, const CgFuse<R>&, hipStream_t);           \
+  template hipError_t fft_plane_inverse_cg<R>(const Grid&, const FftTablesT<R>&, C2<R>*,        \
+                                              const CgFuse<R>&, hipStream_t, int*);             \
+  template hipError_t green_apply<R>(const Grid&, const FftTablesT<R>&, const R*, R*, C2<R>*,   \
+                                     hipStream_t, const CgState*);
+
+HFE_FFT_INSTANTIATE(double)
+HFE_FFT_INSTANTIATE(float)
+#undef HFE_FFT_INSTANTIATE
 
 }  // namespace hfe

@@ -85,24 +85,52 @@ __global__ void __launch_bounds__(kBlock) k_cg_y(long long n, const double* __re
   block_reduce_store<2>(acc, r.partials);
 }
 
-__global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const double* __restrict__ y,
-                                                 double* __restrict__ d,
-                                                 const double* __restrict__ g,
-                                                 const double* __restrict__ z, Reducer r,
+// d = -y + beta d with the sums {g.d, z.g} (FP64 in either precision)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restrict__ y,
+                                                 R* __restrict__ d, const R* __restrict__ g,
+                                                 const R* __restrict__ z, Reducer r,
                                                  const CgState* st) {
   if (st->done) return;
-  const double beta = st->beta;
+  const R beta = (R)st->beta;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     // beta = 0 starts a new direction without reading the old one
-    const double dn = beta == 0.0 ? -y[i] : -y[i] + beta * d[i];
+    const R dn = beta == R(0) ? -y[i] : -y[i] + beta * d[i];
     d[i] = dn;
     const double gi = g[i];
-    acc[0] += gi * dn;     // <r, d>
-    acc[1] += z[i] * gi;   // z . g for <z, d>
+    acc[0] += gi * (double)dn;     // <r, d>
+    acc[1] += (double)z[i] * gi;   // z . g for <z, d>
   }
   block_reduce_store<2>(acc, r.partials);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_dot_t(long long n, const R* __restrict__ x,
+                                                  const R* __restrict__ y, Reducer r) {
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc[0] += (double)x[i] * (double)y[i];
+  block_reduce_store<1>(acc, r.partials);
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock) k_convert(long long n, const S* __restrict__ x,
+                                                    D* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (D)x[i];
+}
+
+// out = x + y rounded to FP32, the sum taken in FP64
+__global__ void __launch_bounds__(kBlock) k_add_f32(long long n, const float* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    float* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (float)((double)x[i] + y[i]);
 }
 
 // Fixed-order sum of nblocks rows of nv partials (one block), then the action.
@@ -216,10 +244,38 @@ hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, c
   return hipGetLastError();
 }
 
-hipError_t cg_step_d(long long n, const double* y, double* d, const double* g, const double* z,
-                     const Reducer& r, const CgState* st, hipStream_t s, int* nblocks) {
+template <typename R>
+hipError_t cg_step_d(long long n, const R* y, R* d, const R* g, const R* z, const Reducer& r,
+                     const CgState* st, hipStream_t s, int* nblocks) {
   *nblocks = vec_blocks(n);
-  hipLaunchKernelGGL(k_cg_d, dim3(*nblocks), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
+  hipLaunchKernelGGL((k_cg_d<R>), dim3(*nblocks), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
+  return hipGetLastError();
+}
+template hipError_t cg_step_d<double>(long long, const double*, double*, const double*,
+                                      const double*, const Reducer&, const CgState*, hipStream_t,
+                                      int*);
+template hipError_t cg_step_d<float>(long long, const float*, float*, const float*, const float*,
+                                     const Reducer&, const CgState*, hipStream_t, int*);
+
+hipError_t vec_dot_f32(long long n, const float* x, const float* y, const Reducer& r,
+                       hipStream_t s, int* nblocks) {
+  *nblocks = vec_blocks(n);
+  hipLaunchKernelGGL((k_dot_t<float>), dim3(*nblocks), dim3(kBlock), 0, s, n, x, y, r);
+  return hipGetLastError();
+}
+
+hipError_t vec_to_f32(long long n, const double* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t vec_to_f64(long long n, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t vec_add_f32(long long n, const float* x, const double* y, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f32, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, y, out);
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("eta_eq", ctypes.c_double), ("eta_nr", ctypes.c_double),
                 ("eta_cg", ctypes.c_double), ("eta_up", ctypes.c_double),
                 ("R0", ctypes.c_double), ("Rmax", ctypes.c_double),
-                ("i_nr_max", ctypes.c_int), ("j_cg_max", ctypes.c_int)]
+                ("i_nr_max", ctypes.c_int), ("j_cg_max", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
@@ -74,6 +75,8 @@ EXPORTS = {
                                         ctypes.POINTER(ctypes.c_int)]),
     "hfe_apply_projected_hessian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_apply_projected_hessian_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_apply_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_apply_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_fft_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -129,8 +132,10 @@ def workspace_bytes(shape, element):
     return int(lib.hfe_workspace_bytes(ctypes.byref(_grid(shape, element))))
 
 
+# CG arithmetic (hfe_solver_params.precision)
+PRECISIONS = {"fp64": 0, "mixed": 1}
 DEFAULT_PARAMS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "eta_cg": 1e-6, "eta_up": 0.15,
-                  "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000}
+                  "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000, "precision": 0}
 
 
 class Solver:
@@ -210,6 +215,8 @@ class Solver:
         p = dict(DEFAULT_PARAMS)
         if params:
             p.update({k: v for k, v in params.items() if v is not None and k in p})
+        if isinstance(p["precision"], str):
+            p["precision"] = PRECISIONS[p["precision"]]
         cp = _Params(**{k: p[k] for k in DEFAULT_PARAMS})
         rep = _Report()
         self._check(self.lib.hfe_solve_increment(self.ctx, ctypes.byref(cp), ctypes.byref(rep)))
@@ -283,10 +290,11 @@ class Solver:
         self._check(self.lib.hfe_set_displacement(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
 
     # -- operators on device tensors ([dim][N] float64, contiguous) -------
-    def _dev(self, t):
+    def _dev(self, t, dtype=None):
         torch = self.torch
-        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-            raise ValueError("expected a contiguous float64 device tensor")
+        dtype = torch.float64 if dtype is None else dtype
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise ValueError("expected a contiguous %s device tensor" % dtype)
         return ctypes.c_void_p(t.data_ptr())
 
     def new_nodal(self):
@@ -298,6 +306,18 @@ class Solver:
         dots = np.zeros(2)
         self._check(self.lib.hfe_apply_projected_hessian(self.ctx, self._dev(d), self._dev(out),
                                                          dots.ctypes.data_as(ctypes.c_void_p)))
+        return out, dots
+
+    def apply_projected_hessian_f32(self, d, out=None):
+        """The projected Hessian in the FP32 arithmetic of the mixed-precision
+        CG (3D): float32 device tensors [dim][N], dots {d.Kd, |Dd|^2} in FP64."""
+        torch = self.torch
+        out = torch.zeros((self.dim,) + self.shape, dtype=torch.float32,
+                          device=self.device) if out is None else out
+        dots = np.zeros(2)
+        self._check(self.lib.hfe_apply_projected_hessian_f32(
+            self.ctx, self._dev(d, torch.float32), self._dev(out, torch.float32),
+            dots.ctypes.data_as(ctypes.c_void_p)))
         return out, dots
 
     def apply_stiffness(self, d, out=None):

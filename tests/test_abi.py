@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "hfe.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(hfe_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hfe_[a-z0-9_]+)\s*\(", text)))
 
 
 def _lib():

@@ -1,0 +1,139 @@
+"""GPU checks of the mixed-precision CG (FP32 Hessian, FFT and CG vectors
+inside Algorithm 1; residual, trial evaluation, energy ratio, history and
+state in FP64) against the FP64 oracle.
+
+Bounds. One FP32 projected-Hessian application carries the rounding of a
+few hundred FP32 operations per output (unit roundoff 2^-24 = 6e-8): the
+operator tests allow 1e-5 relative to the norm of the result. A solve is an
+inexact Newton iteration whose residual is recomputed in FP64 at every step,
+so a converged load step meets the same FP64 tolerances as the FP64 solver;
+the homogenized stress of a converged step is compared at 1e-7 of the load
+stress scale (elastic cells) and 1e-6 (damage cells, where the Newton paths
+of the two precisions differ and stop at different points inside the
+tolerance).
+"""
+import numpy as np
+import pytest
+
+from oracle import fe, material
+from oracle.projection import Projector
+from oracle.solver import CellSolver
+from synthetic import workload, laminate_microstructure, MATRIX_DAMAGE, INCLUSION_ELASTIC
+from tests.gpu_util import require_gpu, announce, rel_err
+
+pytestmark = pytest.mark.gpu
+
+F32_OP_TOL = 1e-5
+EL1 = {"kind": "elastic", "E": 1.0, "nu": 0.3}
+EL2 = {"kind": "elastic", "E": 7.0, "nu": 0.2}
+
+
+def _damaged_state(shape, seed):
+    rng = np.random.default_rng(seed)
+    phase = (rng.random(shape) < 0.3).astype(np.uint8)
+    mats = [dict(MATRIX_DAMAGE), dict(INCLUSION_ELASTIC)]
+    E = np.zeros((3, 3))
+    E[0, 0] = 1.5e-3
+    E[1, 1] = -2e-4
+    E[0, 1] = E[1, 0] = 3e-4
+    u = 4e-4 * rng.normal(size=(3,) + shape)
+    return phase, mats, E, u
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (16, 12, 8), (32, 32, 32), (64, 64, 64)])
+def test_f32_projected_hessian(shape):
+    torch = require_gpu()
+    announce("f32 projected hessian", shape)
+    from paper_2207_10657_amd import Solver
+    phase, mats, E, u = _damaged_state(shape, 7)
+    s = Solver(shape, "q1")
+    s.setup(phase, mats)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    rng = np.random.default_rng(8)
+    d = rng.normal(size=(3,) + shape)
+    out, dots = s.apply_projected_hessian_f32(torch.tensor(d, dtype=torch.float32, device="cuda"))
+    out = out.double().cpu().numpy()
+    mf = material.MaterialField(phase, mats, 8)
+    st = material.evaluate(mf, fe.gradient(u, "q1") + E, mf.initial_history())
+    assert np.mean(st["cprime"] > 0) > 0.05
+    # the oracle on the same FP32-rounded direction
+    d32 = d.astype(np.float32).astype(np.float64)
+    Dd = fe.gradient(d32, "q1")
+    BDd = material.apply_tangent(mf, st, Dd)
+    ref = Projector(shape, "q1")(BDd)
+    err = rel_err(fe.gradient(out, "q1"), ref)
+    e0 = abs(dots[0] - np.sum(Dd * BDd)) / abs(np.sum(Dd * BDd))
+    e1 = abs(dots[1] - np.sum(Dd * Dd)) / np.sum(Dd * Dd)
+    print("[mixed] f32 projected Hessian %s: rel %.2e, d.Kd %.2e, |Dd|^2 %.2e" % (shape, err, e0, e1),
+          flush=True)
+    assert err < F32_OP_TOL and e0 < F32_OP_TOL and e1 < F32_OP_TOL
+
+
+def test_mixed_laminate_closed_form():
+    require_gpu()
+    announce("mixed laminate")
+    from paper_2207_10657_amd import Solver
+    shape = (8, 8, 16)
+    layers = np.array([0, 0, 1, 1, 1, 0, 1, 0] * 2, dtype=np.uint8)
+    phase = laminate_microstructure(shape, layers)
+    g = Solver(shape, "q1")
+    g.setup(phase, [EL1, EL2])
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 1e-3
+    g.apply_load_step(dE)
+    rep = g.solve_increment({"eta_eq": 1e-10, "eta_nr": 1e-14, "precision": "mixed"})
+    assert rep["converged"]
+    lam = np.array([m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"])) for m in (EL1, EL2)])
+    mu = np.array([m["E"] / (2 * (1 + m["nu"])) for m in (EL1, EL2)])
+    frac = np.array([np.mean(layers == 0), np.mean(layers == 1)])
+    M = lam + 2 * mu
+    Cxxxx = 1.0 / np.sum(frac / M)
+    S = g.homogenized_stress()
+    err = abs(S[0, 0] - Cxxxx * 1e-3) / (Cxxxx * 1e-3)
+    print("[mixed] laminate: Newton %d, CG %d, |dS|/S %.2e" % (rep["newton_iters"], rep["cg_iters"], err),
+          flush=True)
+    assert err < 1e-7
+
+
+def _load_scale(w, E):
+    m = max(w.materials, key=lambda m: m["E"])
+    lam = m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"]))
+    mu = m["E"] / (2 * (1 + m["nu"]))
+    return np.linalg.norm(lam * np.trace(E) * np.eye(3) + 2 * mu * E)
+
+
+@pytest.mark.parametrize("name,steps,tol", [("c1_3d16", 6, 1e-6)])
+def test_mixed_workload_steps_against_oracle(name, steps, tol):
+    """Each load step from the oracle's state (checkpoint / restart): the
+    mixed-precision GPU solve and the FP64 oracle solve of the same increment
+    must both converge, and their homogenized stress and damage agree to
+    `tol` of the load stress scale."""
+    require_gpu()
+    from paper_2207_10657_amd import Solver
+    w = workload(name, steps=steps)
+    g = Solver(w.shape, "q1")
+    g.setup(w.phase, w.materials)
+    o = CellSolver(w.phase, w.materials, "q1")
+    compared = 0
+    for n, dE in enumerate(w.load_path):
+        announce("mixed", name, "step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        g.apply_load_step(dE)
+        o.apply_load_step(dE)
+        rg = g.solve_increment({"precision": "mixed"})
+        ro = o.solve_increment()
+        scale = _load_scale(w, o.E)
+        dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
+        dd = float(np.abs(g.damage() - o.damage()).max())
+        print("[mixed] %s step %d: converged %s/%s, Newton %d/%d, CG %d/%d, |dSigma|/scale %.2e, "
+              "damage %.2e" % (name, n, rg["converged"], ro["converged"], rg["newton_iters"],
+                               len(ro["flags"]), rg["cg_iters"], sum(ro["cg_per_newton"]), dS, dd),
+              flush=True)
+        assert rg["converged"] == ro["converged"]
+        if ro["converged"]:
+            assert dS < tol and dd < tol, (n, dS, dd)
+            compared += 1
+    assert compared >= steps // 2
