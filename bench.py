@@ -317,12 +317,21 @@ def main():
         dt32 = time.perf_counter() - t2
         errs = [float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
                 for a, b in zip(sigmas, sig64)]
+        mixed_detail = list(detail)
+        # per-kernel times of the mixed run (event-timed replay)
+        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        s.set_profiling(True)
+        timed_steps({"precision": "mixed"})
+        torch.cuda.synchronize()
+        stats32 = s.kernel_stats()
+        s.set_profiling(False)
         mixed = {"value": w.nvox * mv32 / dt32 / 1e9, "unit": "Gvoxel-matvec/s",
                  "ms_per_step": dt32 / K * 1e3, "speedup_per_step": dt / dt32,
                  "matvecs": mv32, "newton_iters": nw32, "cg_iters": cg32,
                  "converged_steps": conv32,
                  "sigma_rel_err_vs_fp64_per_step": errs,
-                 "per_step": list(detail),
+                 "per_step": mixed_detail,
+                 "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats32.items()},
                  "note": "same load steps from the same checkpoint; the reference is the FP64 "
                          "GPU solve above (the FP64 path is checked against the oracle)"}
 

@@ -41,8 +41,8 @@ constexpr int kCgBatch = 8;           // CG iterations enqueued between host pol
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u, z, d, g, y, Kd, w, g0, y0, gt, tmp;      // nodal [dim][N]
-  size_t a, cp, at, cpt, kh;                          // per point [nq][N]
+  size_t u, z, d, g, y, Kd, w, g0, y0, tmp;          // nodal [dim][N]
+  size_t a, cp, kh;                                   // per point [nq][N]
   size_t phase;                                       // N bytes
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
@@ -107,9 +107,9 @@ Layout make_layout(const Grid& g) {
   const size_t pts = (size_t)g.nq * g.N * sizeof(double);
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.u = take(nod); L.z = take(nod); L.d = take(nod); L.g = take(nod); L.y = take(nod);
-  L.Kd = take(nod); L.w = take(nod); L.g0 = take(nod); L.y0 = take(nod); L.gt = take(nod);
+  L.Kd = take(nod); L.w = take(nod); L.g0 = take(nod); L.y0 = take(nod);
   L.tmp = take(nod);
-  L.a = take(pts); L.cp = take(pts); L.at = take(pts); L.cpt = take(pts); L.kh = take(pts);
+  L.a = take(pts); L.cp = take(pts); L.kh = take(pts);
   L.phase = take((size_t)g.N);
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
@@ -169,8 +169,8 @@ struct hfe_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   // device views
-  double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *gt, *tmp;
-  double *a, *cp, *at, *cpt, *kh;
+  double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *tmp;
+  double *a, *cp, *kh;
   uint8_t* phase;
   double2* spec;
   double* partials;
@@ -410,12 +410,9 @@ hfe_status upload_E(hfe_ctx* c) {
   return HFE_OK;
 }
 
-// Residual at (u, E): g0 = D^T sigma, tangent scalars, y0 = L^+ g0, r_eq.
-hfe_status evaluate_state(hfe_ctx* c) {
-  {
-    hfe_status st0 = upload_E(c);
-    if (st0) return st0;
-  }
+// Residual at (u, E) with E already on the device: g0 = D^T sigma, tangent
+// scalars, y0 = L^+ g0, the stress sums and r_eq.
+hfe_status evaluate_residual(hfe_ctx* c) {
   hfe::ElemArgs A = elem_args(c);
   A.a_out = c->a;
   A.cp_out = c->cp;
@@ -443,6 +440,12 @@ hfe_status evaluate_state(hfe_ctx* c) {
   c->have_state = true;
   c->state32_fresh = false;
   return HFE_OK;
+}
+
+hfe_status evaluate_state(hfe_ctx* c) {
+  hfe_status st = upload_E(c);
+  if (st) return st;
+  return evaluate_residual(c);
 }
 
 struct CgInfo { int iters = 0, restarts = 0, matvecs = 0; };
@@ -865,9 +868,9 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   }
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
-  c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0); c->gt = D(L.gt);
+  c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0);
   c->tmp = D(L.tmp);
-  c->a = D(L.a); c->cp = D(L.cp); c->at = D(L.at); c->cpt = D(L.cpt); c->kh = D(L.kh);
+  c->a = D(L.a); c->cp = D(L.cp); c->kh = D(L.kh);
   auto F = [&](size_t off) { return (float*)(c->ws + off); };
   c->u32 = F(L.u32); c->z32 = F(L.z32); c->d32 = F(L.d32); c->g32 = F(L.g32);
   c->y32 = F(L.y32); c->Kd32 = F(L.Kd32); c->tmp32 = F(L.tmp32);
@@ -1069,9 +1072,6 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       // trial evaluation at u + z (Algorithm 2: model change, trial stress, FAIEF)
       hfe::ElemArgs A = elem_args(c);
       A.v = c->z;
-      A.a_out = c->at;
-      A.cp_out = c->cpt;
-      A.f = c->gt;
       int nb = 0;
       {
         Prof pr(c, "trial");
@@ -1104,25 +1104,13 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       else if (rho > 0.75 && on_boundary) c->R = std::min(2.0 * c->R, c->Rmax);
       if (rho > p.eta_up) {
         rec.accepted = 1;
+        // the state moves to u + z; its stress, tangent scalars and residual
+        // (g0 = D^T sigma, y0 = L^+ g0) are evaluated there in FP64, in
+        // place, so captured CG graphs stay valid
         HIPCHK(c, hfe::vec_axpy(n, 1.0, c->z, c->u, c->stream));
-        // the trial state becomes the state (copies keep every buffer at a
-        // fixed address, so captured CG graphs stay valid)
-        const size_t pts = (size_t)c->g.nq * c->g.N * sizeof(double);
-        HIPCHK(c, hipMemcpyAsync(c->a, c->at, pts, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->cp, c->cpt, pts, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->g0, c->gt, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        c->state32_fresh = false;
-        const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH], ss = h[hfe::TRI_SS];
-        for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[hfe::TRI_S0 + k];
-        c->sig_norm2 = ss;
-        st = green(c, c->g0, c->y0);
+        st = evaluate_residual(c);
         if (st) return st;
-        st = dot(c, c->y0, c->g0, c->dscal + S_RR0);
-        if (st) return st;
-        st = sync(c);
-        if (st) return st;
-        c->rr0 = c->hscal[S_RR0];
-        c->r_eq = ss > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(ss) : 0.0;
+        const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH];
         const double r_nr = hh > 0.0 ? std::sqrt(pp) / std::sqrt(hh) : 0.0;
         rep.r_nr = r_nr;
         if (!on_boundary && (c->r_eq <= p.eta_eq || r_nr <= p.eta_nr)) converged = true;

@@ -47,8 +47,7 @@ struct Reducer {
 
 // Partial-sum layouts written by the element kernels (one row per block).
 enum { RES_S0 = 0 /* 6 stress sums xx,yy,zz,xy,xz,yz */, RES_SS = 6, RES_HH = 7, RES_NV = 8 };
-enum { TRI_SP = 0, TRI_PBP = 1, TRI_STP = 2, TRI_PP = 3, TRI_HH = 4, TRI_SS = 5,
-       TRI_S0 = 6 /* 6 stress sums */, TRI_NV = 12 };
+enum { TRI_SP = 0, TRI_PBP = 1, TRI_STP = 2, TRI_PP = 3, TRI_HH = 4, TRI_NV = 5 };
 enum { HES_DKD = 0, HES_DD = 1, HES_NV = 2 };
 
 struct ElemArgs {
@@ -71,7 +70,7 @@ struct ElemArgs {
 
 // Residual: f = D^T sigma(E + D u), writes a_out/cp_out, partial rows RES_*.
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks);
-// Trial: f = D^T sigma(E + D(u+v)), writes a_out/cp_out (trial tangent), rows TRI_*.
+// Trial at u + v: sums over points only (rows TRI_*), no nodal or point output.
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Hessian: f = D^T B D v at the state (u, a, cp), rows HES_* (no-op once
 // A.cg->done when A.cg is set).

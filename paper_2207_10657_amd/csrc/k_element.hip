@@ -252,8 +252,11 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Em[i][j] = (i < D && j < D) ? A.E[3 * i + j] : 0.0;
+    // the trial pass only sums over points (no divergence): the element
+    // this node owns is the only one it needs
+    constexpr int kElems = MODE == MODE_TRIAL ? 1 : NA;
 #pragma unroll 1
-    for (int al = 0; al < NA; ++al) {
+    for (int al = 0; al < kElems; ++al) {
       const Pos e = elem_of<EL>(g, x, y, z, al);
       const long long ei = lin(g, e.x, e.y, e.z);
       const int ph = A.phase[ei];
@@ -350,8 +353,6 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
           if (owner) {
-            A.a_out[q * g.N + ei] = P.a;
-            A.cp_out[q * g.N + ei] = P.cp;
             const double ao = A.a[q * g.N + ei], co = A.cp[q * g.N + ei];
             const Sym so = c_contract(sym_of<D>(H), lam, mu);
             const Sym ps = sym_of<D>(p);
@@ -376,22 +377,23 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
               }
             acc[TRI_PP] += pp;
             acc[TRI_HH] += hh;
-            acc[TRI_SS] += sym_norm2<D>(tau);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) acc[TRI_S0 + k] += tau.v[k];
           }
         }
         // divergence: contribution of this point to the element's local node al
+        if (MODE != MODE_TRIAL) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-          const double w = shape_grad<EL>(q, al, j);
+          for (int j = 0; j < D; ++j) {
+            const double w = shape_grad<EL>(q, al, j);
 #pragma unroll
-          for (int i = 0; i < D; ++i) fo[i] += w * sym_at(tau, i, j);
+            for (int i = 0; i < D; ++i) fo[i] += w * sym_at(tau, i, j);
+          }
         }
       }
     }
+    if (MODE != MODE_TRIAL) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) A.f[i * g.N + n] = fo[i];
+      for (int i = 0; i < D; ++i) A.f[i * g.N + n] = fo[i];
+    }
     if constexpr (MODE == MODE_HESSIAN) {
       double dk = 0.0;
 #pragma unroll
@@ -623,8 +625,8 @@ __device__ __forceinline__ void q1_div_sf(const R (&T)[3][2][2], R (&f)[8]) {
 // fixed. Per-element outputs and reduction terms come from the elements the
 // brick owns (those whose lowest corner is one of its nodes).
 //   k_hessian    : f = K v = D^T B D v;  rows {v.Kv, |D v|^2}
-//   MODE_RESIDUAL: f = D^T sigma(E + D u), a/c' written;  rows RES_*
-//   MODE_TRIAL   : f = D^T sigma(E + D(u+v)), trial a/c' written;  rows TRI_*
+//   k_brick      : f = D^T sigma(E + D u), a/c' written;  rows RES_*
+//   k_trial      : sums over the points only (no halo elements): rows TRI_*
 // Brick shapes (nodes BX x BY x BZ; the block runs one thread per element of
 // the (BX+1)(BY+1)(BZ+1) element brick, rounded up to whole wavefronts).
 template <int BX, int BY, int BZ> struct BrickShape {
@@ -668,7 +670,6 @@ template <int MODE, int NV, int BX, int BY, int BZ>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(ElemArgs A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
-  __shared__ double sv[3][kTile];   // v: step (trial)
   __shared__ double su[3][kTile];   // u
   __shared__ double acc[3][kOwn];
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
@@ -708,7 +709,6 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
       }
     }
   };
-  if (MODE == MODE_TRIAL) stage(A.v, sv);
   for (int i = tid; i < bx * by * bz; i += nt) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c][i] = 0.0;
@@ -753,15 +753,8 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
 #pragma unroll
           for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
         tile_grad(su, q, t0, sy, sz, H);
-        double p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-        if (MODE == MODE_TRIAL) tile_grad(sv, q, t0, sy, sz, p);
-        double Ht[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
         const double kh = A.khist[q * g.N + eg];
-        const PointLaw P = eval_law(sym_of<3>(Ht), lam, mu, A.mat.E[ph], A.mat.damage[ph],
+        const PointLaw P = eval_law(sym_of<3>(H), lam, mu, A.mat.E[ph], A.mat.damage[ph],
                                     A.mat.k0[ph], A.mat.kf[ph], kh);
 #pragma unroll
         for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
@@ -772,35 +765,11 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) hh += Ht[i][j] * Ht[i][j];
-          if constexpr (MODE == MODE_RESIDUAL) {
+            for (int j = 0; j < 3; ++j) hh += H[i][j] * H[i][j];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
-            red[RES_SS] += sym_dot(tau, tau);
-            red[RES_HH] += hh;
-          } else {
-            // sigma_old : p = a (s:p) and p : B_old : p = a (p:C:p) - c' (s:p)^2,
-            // with s = C : eps(u) at the current state
-            const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
-            const Sym ps = sym_of<3>(p);
-            const Sym so = c_contract(sym_of<3>(H), lam, mu);
-            const double s_p = sym_dot(so, ps);
-            const double trp = ps.v[0] + ps.v[1] + ps.v[2];
-            const double pCp = lam * trp * trp + 2.0 * mu * sym_dot(ps, ps);
-            double pp = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) pp += p[i][j] * p[i][j];
-            red[TRI_SP] += ao * s_p;
-            red[TRI_PBP] += ao * pCp - co * s_p * s_p;
-            red[TRI_STP] += sym_dot(tau, ps);
-            red[TRI_PP] += pp;
-            red[TRI_HH] += hh;
-            red[TRI_SS] += sym_dot(tau, tau);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) red[TRI_S0 + k] += tau.v[k];
-          }
+          for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
+          red[RES_SS] += sym_dot(tau, tau);
+          red[RES_HH] += hh;
         }
       }
 #pragma unroll
@@ -834,6 +803,102 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     for (int c = 0; c < 3; ++c) A.f[c * g.N + n] = acc[c][i];
   }
   block_reduce_store<NV>(red, A.red.partials);
+}
+
+// Trial evaluation at u + v for the trust-region ratio (eq. rho_bar): per
+// point of the elements the brick owns, with H = E + D u, p = D v and the
+// history frozen,
+//   TRI_SP  sigma(H) : p = a (s:p),      s = C : eps(H)
+//   TRI_PBP p : B(H) : p = a (p:C:p) - c' (s:p)^2
+//   TRI_STP sigma(H + p) : p
+//   TRI_PP  |p|^2,  TRI_HH |H + p|^2
+// No nodal output, so no halo elements: one thread per owned element, the
+// nodes of u and v staged on the (BX+1)(BY+1)(BZ+1) tile.
+template <int BX, int BY, int BZ>
+__global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
+  constexpr int kTile = (BX + 1) * (BY + 1) * (BZ + 1);
+  const Grid& g = A.g;
+  __shared__ double su[3][kTile];
+  __shared__ double sv[3][kTile];
+  const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
+  const int brick = xcd_brick(blockIdx.x, gridDim.x);
+  const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
+  const int tx = bx + 1, ty = by + 1, tz = bz + 1;          // staged node tile
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ntile = tx * ty * tz;
+  for (int i = tid; i < ntile; i += nt) {
+    const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
+    const long long n = lin(g, wrap(x0 + lx, g.nx), wrap(y0 + ly, g.ny), wrap(z0 + lz, g.nz));
+    double r[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = A.u[c * g.N + n];
+      r[3 + c] = A.v[c * g.N + n];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      su[c][i] = r[c];
+      sv[c][i] = r[3 + c];
+    }
+  }
+  __syncthreads();
+  double red[TRI_NV];
+#pragma unroll
+  for (int k = 0; k < TRI_NV; ++k) red[k] = 0.0;
+  const int ex = tid % BX, ey = (tid / BX) % BY, ez = tid / (BX * BY);
+  if (ex < bx && ey < by && ez < bz) {
+    const long long eg = lin(g, x0 + ex, y0 + ey, z0 + ez);
+    const int ph = A.phase[eg];
+    const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
+    const int t0 = ex + tx * (ey + ty * ez);
+    const int sy = tx, sz = tx * ty;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+      double H[3][3], p[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          H[i][j] = A.E[3 * i + j];
+          p[i][j] = 0.0;
+        }
+      tile_grad<kTile>(su, q, t0, sy, sz, H);
+      tile_grad<kTile>(sv, q, t0, sy, sz, p);
+      double Ht[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
+      const double kh = A.khist[q * g.N + eg];
+      const PointLaw P = eval_law(sym_of<3>(Ht), lam, mu, A.mat.E[ph], A.mat.damage[ph],
+                                  A.mat.k0[ph], A.mat.kf[ph], kh);
+      Sym tau;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
+      const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
+      const Sym ps = sym_of<3>(p);
+      const Sym so = c_contract(sym_of<3>(H), lam, mu);
+      const double s_p = sym_dot(so, ps);
+      const double trp = ps.v[0] + ps.v[1] + ps.v[2];
+      const double pCp = lam * trp * trp + 2.0 * mu * sym_dot(ps, ps);
+      double pp = 0.0, hh = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          pp += p[i][j] * p[i][j];
+          hh += Ht[i][j] * Ht[i][j];
+        }
+      red[TRI_SP] += ao * s_p;
+      red[TRI_PBP] += ao * pCp - co * s_p * s_p;
+      red[TRI_STP] += sym_dot(tau, ps);
+      red[TRI_PP] += pp;
+      red[TRI_HH] += hh;
+    }
+  }
+  block_reduce_store<TRI_NV>(red, A.red.partials);
 }
 
 // Hessian K v = D^T B D v at the state (u, a, c'), in FP64 (R = double) or,
@@ -1071,7 +1136,13 @@ hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
 }
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
-  return launch_brick<MODE_TRIAL, TRI_NV>(A, s, nblocks);
+  if (!A.u || !A.v || !A.a || !A.cp || !A.khist || !A.phase || !A.E || !A.red.partials)
+    return hipErrorInvalidValue;
+  constexpr int BX = 8, BY = 8, BZ = 4;
+  const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
+  *nblocks = nb;
+  hipLaunchKernelGGL((k_trial<BX, BY, BZ>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
+  return hipGetLastError();
 }
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
