@@ -87,6 +87,66 @@ def cpu_baseline(w, n_matvec):
 
 COPY_BYTES = 1 << 28
 
+
+def unit_load_cases(mag):
+    """The six macroscopic strain increments xx, yy, zz, xy, xz, yz of size mag."""
+    cases = []
+    for (i, j) in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
+        dE = np.zeros((3, 3))
+        dE[i, j] = dE[j, i] = mag
+        cases.append(dE)
+    return cases
+
+
+def batch_bench(w, steps):
+    """The six unit load cases of the cell, `steps` increments each after one
+    untimed increment: solved one cell after the other, then as one batch
+    (one solver per case on its own stream, hfe_solve_batch), from the same
+    states. Each solver's launch shapes come from the autotuner."""
+    import torch
+    from paper_2207_10657_amd import Solver, solve_batch
+    cases = unit_load_cases(float(w.load_path[0][0, 0]))
+    solvers = [Solver(w.shape, w.element, own_stream=True) for _ in cases]
+    tuned = None
+    for s, dE in zip(solvers, cases):
+        s.setup(w.phase, w.materials)
+        s.apply_load_step(dE)
+        tuned = s.autotune()
+    solve_batch(solvers)
+    cks = [s.get_state() for s in solvers]
+
+    def run(batched):
+        mv = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for s, dE in zip(solvers, cases):
+                s.apply_load_step(dE)
+            if batched:
+                reps = solve_batch(solvers)
+            else:
+                reps = [s.solve_increment() for s in solvers]
+            mv += sum(r["matvecs"] for r in reps)
+        torch.cuda.synchronize()
+        return mv, time.perf_counter() - t0
+
+    mv_seq, dt_seq = run(False)
+    out_seq = [s.homogenized_stress() for s in solvers]
+    for s, ck in zip(solvers, cks):
+        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+    mv_bat, dt_bat = run(True)
+    same = all(np.array_equal(a, s.homogenized_stress()) for a, s in zip(out_seq, solvers))
+    for s in solvers:
+        s.close()
+    return {"cases": 6, "steps_timed": steps,
+            "sequential": {"value": w.nvox * mv_seq / dt_seq / 1e9, "ms": dt_seq * 1e3,
+                           "matvecs": mv_seq},
+            "batched": {"value": w.nvox * mv_bat / dt_bat / 1e9, "ms": dt_bat * 1e3,
+                        "matvecs": mv_bat},
+            "unit": "Gvoxel-matvec/s", "speedup": dt_seq / dt_bat,
+            "same_results_as_sequential": bool(same and mv_seq == mv_bat),
+            "autotuned_launch": tuned}
+
 # Counter summary written by `--pmc-summary`; read back for roofline.traffic.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_64cubed.md")
 CSRC = os.path.join(ROOT, "paper_2207_10657_amd", "csrc")
@@ -103,9 +163,10 @@ KERNEL_SOURCES = {
 }
 # device kernel name (as rocprofv3 prints it) -> timed kernel; the probe runs
 # the Hessian and the plain FFT passes, the solver the CG-fused ones
-PMC_KERNELS = [("k_brick<2,", "stiffness"), ("k_brick<0,", "residual"),
-               ("k_plane<0>", "fft_plane_fwd"), ("k_pencil<0>", "fft_pencil_green"),
-               ("k_plane<1>", "fft_plane_inv"), ("copyBuffer", "copy")]
+PMC_KERNELS = [("k_hessian<double,", "stiffness"), ("k_brick<0,", "residual"),
+               ("k_plane<0,double>", "fft_plane_fwd"), ("k_pencil<0,double>", "fft_pencil_green"),
+               ("k_plane<1,double>", "fft_plane_inv"), ("copyBuffer", "copy")]
+PROBE_REPS = 5
 
 
 def sources_digest(kernel):
@@ -124,19 +185,30 @@ def read_pmc(path):
     files = sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True))
     if not files:
         raise SystemExit("no counter_collection.csv under %s" % path)
-    out = {}
+    rows = []
     for f in files:
         with open(f, newline="") as fh:
             for row in csv.DictReader(fh):
                 name = row.get("Kernel_Name", "")
                 label = next((lab for key, lab in PMC_KERNELS if key in name.replace(" ", "")), None)
-                if label is None:
-                    continue
-                out.setdefault(label, []).append(float(row["Counter_Value"]))
-    return out
+                if label is not None:
+                    rows.append((int(row["Dispatch_Id"]), label, float(row["Counter_Value"])))
+    out = {}
+    for _, label, v in sorted(rows):
+        out.setdefault(label, []).append(v)
+    # the probe's own dispatches are the last PROBE_REPS of each kernel (the
+    # autotuner and the load step launch the same kernels before them)
+    return {k: v[-PROBE_REPS:] for k, v in out.items()}
 
 
-def pmc_summary(fetch_dir, write_dir, grid):
+# which launch-shape fields a kernel's traffic depends on
+SHAPE_KEYS = {"stiffness": ("brick_shape",), "stiffness_f32": ("brick_shape32",),
+              "residual": (), "trial": (),
+              "fft_plane_fwd": ("plane_threads",), "fft_plane_inv": ("plane_threads",),
+              "fft_pencil_green": ("pencil_cols", "pencil_threads")}
+
+
+def pmc_summary(fetch_dir, write_dir, grid, tuning=None):
     """Markdown summary of a FETCH_SIZE and a WRITE_SIZE pass over `--probe`.
 
     Both counters are in KiB per dispatch. The copy kernel moves COPY_BYTES in
@@ -144,10 +216,9 @@ def pmc_summary(fetch_dir, write_dir, grid):
     fetch, write = read_pmc(fetch_dir), read_pmc(write_dir)
     if "copy" not in fetch or "copy" not in write:
         raise SystemExit("the calibration copy is missing from the counter runs")
-    # the calibration copies are the five largest copy dispatches (the library
-    # and torch issue smaller device copies of their own)
-    kf = COPY_BYTES / (1024.0 * np.median(sorted(fetch["copy"])[-5:]))
-    kw = COPY_BYTES / (1024.0 * np.median(sorted(write["copy"])[-5:]))
+    # the calibration copies are the last copy dispatches of the probe
+    kf = COPY_BYTES / (1024.0 * np.median(fetch["copy"]))
+    kw = COPY_BYTES / (1024.0 * np.median(write["copy"]))
     shape = (grid, grid, grid)
     rows, table = [], {}
     for label in ("stiffness", "residual", "fft_plane_fwd", "fft_pencil_green", "fft_plane_inv"):
@@ -157,7 +228,8 @@ def pmc_summary(fetch_dir, write_dir, grid):
         wb = float(np.median(write[label])) * 1024.0 * kw
         alg = algorithmic_bytes(label, shape)
         table[label] = {"fetch_bytes": fb, "write_bytes": wb, "dispatches": len(fetch[label]),
-                        "algorithmic_bytes": alg, "sources": sources_digest(label)}
+                        "algorithmic_bytes": alg, "sources": sources_digest(label),
+                        "launch": {k: tuning[k] for k in SHAPE_KEYS[label]} if tuning else None}
         rows.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (
             label, len(fetch[label]), fb / 1e6, wb / 1e6, (fb + wb) / 1e6,
             (fb + wb) / alg if alg else float("nan")))
@@ -173,9 +245,10 @@ def pmc_summary(fetch_dir, write_dir, grid):
     return "\n".join(lines)
 
 
-def load_traffic(kernel, shape):
+def load_traffic(kernel, shape, tuning):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if there is none for this grid or the kernel's sources changed."""
+    None if there is none for this grid and launch shape or the kernel's
+    sources changed."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -187,15 +260,18 @@ def load_traffic(kernel, shape):
         return None
     if k.get("sources") != sources_digest(kernel):
         return None
+    if k.get("launch") != {key: tuning[key] for key in SHAPE_KEYS.get(kernel, ())}:
+        return None
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def probe(n):
+def probe(n, tuning_out=None):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
 
-    One load step of the workload recipe at n^3, then 5 projected-Hessian
-    applications at that state and 5 device-to-device copies of COPY_BYTES
-    (the copy kernel calibrates the counters: it reads and writes exactly
+    One load step of the workload recipe at n^3, the autotuner (the launch
+    shapes the benchmark uses), then PROBE_REPS projected-Hessian applications
+    at that state and PROBE_REPS device-to-device copies of COPY_BYTES (the
+    copy kernel calibrates the counters: it reads and writes exactly
     COPY_BYTES per launch)."""
     import torch
     from paper_2207_10657_amd import Solver
@@ -204,13 +280,18 @@ def probe(n):
     s = Solver(w.shape, w.element)
     s.setup(w.phase, w.materials)
     s.apply_load_step(w.load_path[0] * 5)      # a damaged state (E_xx = 1e-3)
+    tuned = s.autotune()
+    print("probe launch shapes:", tuned, flush=True)
+    if tuning_out:
+        with open(tuning_out, "w") as fh:
+            json.dump(tuned, fh)
     rng = np.random.default_rng(0)
     d = torch.tensor(rng.normal(size=(3,) + w.shape), device="cuda")
-    for _ in range(5):
+    for _ in range(PROBE_REPS):
         s.apply_projected_hessian(d)
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(5):
+    for _ in range(PROBE_REPS):
         b.copy_(a)
     torch.cuda.synchronize()
     print("probe done: %d^3, copy %d bytes" % (n, COPY_BYTES), flush=True)
@@ -225,6 +306,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same steps")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the six-load-case batch run")
     ap.add_argument("--probe", action="store_true",
                     help="short run for hardware-counter passes: after one load step, a few "
                          "projected-Hessian applications and a calibration copy of known size")
@@ -233,9 +316,15 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc runs of --probe "
                          "(FETCH_SIZE, then WRITE_SIZE; csv output)")
+    ap.add_argument("--probe-tuning", metavar="FILE",
+                    help="--probe: write the launch shapes it used; --pmc-summary: read them")
     args = ap.parse_args()
     if args.pmc_summary:
-        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.grid))
+        tuning = None
+        if args.probe_tuning:
+            with open(args.probe_tuning) as fh:
+                tuning = json.load(fh)
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.grid, tuning))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is single-GPU (a batch of cells "
@@ -250,7 +339,7 @@ def main():
     from synthetic import workload
 
     if args.probe:
-        probe(args.grid)
+        probe(args.grid, args.probe_tuning)
         return
     w = workload(WORKLOAD)
     W, K = args.warmup, args.steps
@@ -261,6 +350,8 @@ def main():
     for n in range(W):
         s.apply_load_step(w.load_path[n])
         s.solve_increment()
+    # launch shapes for this grid and state, chosen by measurement (setup)
+    tuning = s.autotune()
     ck = s.get_state()
 
     detail, sigmas = [], []
@@ -331,7 +422,7 @@ def main():
                  "converged_steps": conv32,
                  "sigma_rel_err_vs_fp64_per_step": errs,
                  "per_step": mixed_detail,
-                 "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats32.items()},
+                 "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats32.items() if c},
                  "note": "same load steps from the same checkpoint; the reference is the FP64 "
                          "GPU solve above (the FP64 path is checked against the oracle)"}
 
@@ -344,7 +435,8 @@ def main():
     if alg is not None and avg_s > 0:
         achieved = alg / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname, w.shape),
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": load_traffic(kname, w.shape, tuning),
                 "kernel": kname, "algorithmic_bytes": alg,
                 "avg_launch_us": avg_s * 1e6, "launches": kcount}
     value = w.nvox * matvecs / dt / 1e9
@@ -365,13 +457,15 @@ def main():
                                "uniaxial 30 x 2e-4 load path, FP64 TR+Steihaug tol 1e-8",
                    "load_steps_timed": [W, W + K - 1], "matvecs": matvecs,
                    "newton_iters": newton, "cg_iters": cg, "converged_steps": converged,
-                   "per_step": step_detail},
+                   "per_step": step_detail, "launch_shapes": tuning},
         "roofline": roof,
         "kernel_timing": "HIP events around every launch in a replay of the timed steps from the "
                          "same checkpoint (kernel-by-kernel launches, %.1f ms/step)" % (dt_prof / K * 1e3),
-        "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats.items()},
+        "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats.items() if c},
         "mixed_precision": mixed,
     }
+    if not args.no_batch:
+        out["batch_six_load_cases"] = batch_bench(w, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)
     print(json.dumps(out), flush=True)

@@ -207,6 +207,38 @@ hfe_status hfe_apply_projected_hessian(hfe_ctx* ctx, const double* dev_in,
 hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* ctx, const float* dev_in, float* dev_out,
                                            double dots[2]);
 
+/* Solve one load increment (as hfe_solve_increment) on each of n distinct
+ * contexts at once: several load cases or cells on one GPU, one host thread
+ * per context. The work of contexts created on distinct streams overlaps on
+ * the device, which fills the chip where one cell cannot. `params` (may be
+ * NULL) applies to all; reports[i] (host, n entries) receives context i's
+ * report. Returns the first non-OK status (every solve still runs). */
+hfe_status hfe_solve_batch(hfe_ctx* const* ctxs, int n, const hfe_solver_params* params,
+                           hfe_solve_report* reports);
+
+/* Launch shapes of the hot kernels, per context. FP64 fields serve the FP64
+ * path, *32 fields the FP32 kernels of the HFE_MIXED CG. */
+typedef struct {
+  int plane_threads;    /* threads of an x-y plane FFT block (64..1024, multiple of 64) */
+  int pencil_cols;      /* z columns per pencil block (1..64)                       */
+  int pencil_threads;   /* threads of a pencil block (64..256, multiple of 64)      */
+  int brick_shape;      /* Q1 Hessian brick: 0 = 8x8x4, 1 = 8x8x8, 2 = 16x8x4, 3 = 16x4x4 */
+  int plane_threads32, pencil_cols32, pencil_threads32, brick_shape32;
+} hfe_tuning;
+
+/* Current launch shapes (defaults at creation). */
+hfe_status hfe_get_tuning(const hfe_ctx* ctx, hfe_tuning* out);
+/* Set launch shapes; HFE_EINVAL (context unchanged) if one does not fit the
+ * grid: a plane block must stage (nx/2+1) ny values at 15 per thread, a
+ * pencil block pencil_cols * nz values at 15 per thread in 64 KiB of LDS. */
+hfe_status hfe_set_tuning(hfe_ctx* ctx, const hfe_tuning* in);
+/* Autotuner: times every valid plane / pencil shape on this grid's Green's
+ * operator (FP64 and FP32) and, once a load step has been applied, every
+ * brick shape on the Hessian at the current state; keeps the fastest and
+ * returns them in `out` (may be NULL). Results do not depend on the shapes
+ * (the arithmetic per value is the same), only the time does. */
+hfe_status hfe_autotune(hfe_ctx* ctx, hfe_tuning* out);
+
 /* The two halves of the matvec, for operator tests: out = K d (device
  * arrays [dim][N]), and out = L^+ f (zero mean; the k = 0 mode removed). */
 hfe_status hfe_apply_stiffness(hfe_ctx* ctx, const double* dev_in, double* dev_out);

@@ -5,4 +5,4 @@ in ``include/hfe.h``); ``hfe`` is its ctypes binding. Importing the package
 does not load the library; ``Solver(...)`` or ``hfe.load_library()`` does,
 and fails with ImportError when it has not been built.
 """
-from .hfe import Solver, HfeError, load_library, workspace_bytes  # noqa: F401
+from .hfe import Solver, HfeError, load_library, solve_batch, workspace_bytes  # noqa: F401

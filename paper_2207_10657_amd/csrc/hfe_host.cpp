@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hfe_internal.h"
@@ -214,7 +215,8 @@ struct hfe_ctx {
   CgGraph graphs[2];
   int graph_precision = HFE_FP64;   // precision the captured graphs run
   bool use_graphs = true;
-  int brick_shape = 0;       // Q1 brick shape (HFE_BRICK_SHAPE=0..3 overrides)
+  int brick_shape = 0;       // Q1 Hessian brick shape, FP64 (HFE_BRICK_SHAPE=0..3 overrides)
+  int brick_shape32 = 0;     // and FP32
 };
 
 namespace {
@@ -489,7 +491,7 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.f = out;
   H.red = reducer(c);
   H.cg = in_cg ? c->cg : nullptr;
-  H.brick_shape = c->brick_shape;
+  H.brick_shape = c->brick_shape32;
   return H;
 }
 
@@ -864,7 +866,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
   if (const char* bs = std::getenv("HFE_BRICK_SHAPE")) {
     const int v = std::atoi(bs);
-    if (v >= 0 && v <= 3) c->brick_shape = v;
+    if (v >= 0 && v <= 3) c->brick_shape = c->brick_shape32 = v;
   }
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
@@ -905,6 +907,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs.sx = dst;
   c->tabs.sy = dst + (M + 1);
   c->tabs.sz = dst + (M + 1) + g.ny;
+  hfe::fft_default_launch(g, &c->tabs.plane_threads, &c->tabs.pencil_cols, &c->tabs.pencil_threads);
   // the same tables rounded to FP32 for the mixed-precision CG
   std::vector<float2> tw32(tw.size());
   for (size_t i = 0; i < tw.size(); ++i) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
@@ -919,6 +922,9 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs32.sx = dst32;
   c->tabs32.sy = dst32 + (M + 1);
   c->tabs32.sz = dst32 + (M + 1) + g.ny;
+  c->tabs32.plane_threads = c->tabs.plane_threads;
+  c->tabs32.pencil_cols = c->tabs.pencil_cols;
+  c->tabs32.pencil_threads = c->tabs.pencil_threads;
   hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dscal, c->hscal, 0);
@@ -1134,6 +1140,26 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
   return HFE_OK;
 }
 
+hfe_status hfe_solve_batch(hfe_ctx* const* ctxs, int n, const hfe_solver_params* params,
+                           hfe_solve_report* reports) {
+  if (!ctxs || !reports || n < 1) return HFE_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return HFE_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return HFE_EINVAL;
+  }
+  std::vector<hfe_status> st(n, HFE_OK);
+  std::vector<std::thread> pool;
+  pool.reserve(n > 1 ? n - 1 : 0);
+  for (int i = 1; i < n; ++i)
+    pool.emplace_back([&, i]() { st[i] = hfe_solve_increment(ctxs[i], params, &reports[i]); });
+  st[0] = hfe_solve_increment(ctxs[0], params, &reports[0]);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i] != HFE_OK) return st[i];
+  return HFE_OK;
+}
+
 hfe_status hfe_homogenized_stress(const hfe_ctx* cc, double out[9]) {
   hfe_ctx* c = const_cast<hfe_ctx*>(cc);
   if (!c || !out) return HFE_EINVAL;
@@ -1298,6 +1324,146 @@ hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* c, const float* in, float* o
     dots[1] = c->hscal[S_HES + 1];
   }
   return HFE_OK;
+}
+
+hfe_status hfe_get_tuning(const hfe_ctx* c, hfe_tuning* out) {
+  if (!c || !out) return HFE_EINVAL;
+  out->plane_threads = c->tabs.plane_threads;
+  out->pencil_cols = c->tabs.pencil_cols;
+  out->pencil_threads = c->tabs.pencil_threads;
+  out->brick_shape = c->brick_shape;
+  out->plane_threads32 = c->tabs32.plane_threads;
+  out->pencil_cols32 = c->tabs32.pencil_cols;
+  out->pencil_threads32 = c->tabs32.pencil_threads;
+  out->brick_shape32 = c->brick_shape32;
+  return HFE_OK;
+}
+
+hfe_status hfe_set_tuning(hfe_ctx* c, const hfe_tuning* in) {
+  if (!c || !in) return HFE_EINVAL;
+  if (!hfe::fft_launch_valid(c->g, in->plane_threads, in->pencil_cols, in->pencil_threads, 8) ||
+      !hfe::fft_launch_valid(c->g, in->plane_threads32, in->pencil_cols32, in->pencil_threads32, 4))
+    return fail(c, HFE_EINVAL, "an FFT launch shape does not fit this grid");
+  if (in->brick_shape < 0 || in->brick_shape > 3 || in->brick_shape32 < 0 || in->brick_shape32 > 3)
+    return fail(c, HFE_EINVAL, "brick_shape must be 0..3");
+  hfe_status st = sync(c);
+  if (st) return st;
+  destroy_graphs(c);
+  c->tabs.plane_threads = in->plane_threads;
+  c->tabs.pencil_cols = in->pencil_cols;
+  c->tabs.pencil_threads = in->pencil_threads;
+  c->brick_shape = in->brick_shape;
+  c->tabs32.plane_threads = in->plane_threads32;
+  c->tabs32.pencil_cols = in->pencil_cols32;
+  c->tabs32.pencil_threads = in->pencil_threads32;
+  c->brick_shape32 = in->brick_shape32;
+  return HFE_OK;
+}
+
+hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
+  if (!c) return HFE_EINVAL;
+  if (c->profiling) return fail(c, HFE_ESTATE, "switch profiling off before tuning");
+  hfe_status st = sync(c);
+  if (st) return st;
+  destroy_graphs(c);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(c, HFE_EDEVICE, "hipEventCreate");
+  }
+  constexpr int kReps = 4, kTrials = 3;
+  // best over kTrials of the average of kReps calls, after one untimed call;
+  // +inf on failure
+  auto time_us = [&](auto&& call) -> double {
+    if (call() != HFE_OK) return INFINITY;
+    double best = INFINITY;
+    for (int t = 0; t < kTrials; ++t) {
+      if (hipEventRecord(e0, c->stream) != hipSuccess) return INFINITY;
+      for (int r = 0; r < kReps; ++r)
+        if (call() != HFE_OK) return INFINITY;
+      if (hipEventRecord(e1, c->stream) != hipSuccess) return INFINITY;
+      if (hipEventSynchronize(e1) != hipSuccess) return INFINITY;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return INFINITY;
+      best = std::min(best, 1e3 * ms / kReps);
+    }
+    return best;
+  };
+  // a candidate replaces the current choice only if it is clearly faster, so
+  // that timing noise does not flip the choice between runs; the default
+  // shape is timed first
+  constexpr double kMargin = 0.97;
+  int dp = 0, dc = 0, dt = 0;
+  hfe::fft_default_launch(c->g, &dp, &dc, &dt);
+  const int planes[] = {dp, 256, 512, 1024};
+  const int pencils[][2] = {{dc, dt}, {4, 64}, {4, 128}, {8, 64}, {8, 128}, {8, 256}, {16, 128},
+                            {16, 256}, {32, 256}};
+  const bool q1 = c->g.dim == 3;
+  for (int prec = 0; prec < (q1 ? 2 : 1); ++prec) {
+    const size_t rb = prec ? 4 : 8;
+    double best = INFINITY;
+    int bp = 0, bc = 0, bt = 0;
+    for (int pt : planes)
+      for (const auto& pc : pencils) {
+        if (!hfe::fft_launch_valid(c->g, pt, pc[0], pc[1], rb)) continue;
+        double t;
+        if (prec == 0) {
+          c->tabs.plane_threads = pt;
+          c->tabs.pencil_cols = pc[0];
+          c->tabs.pencil_threads = pc[1];
+          t = time_us([&]() { return green(c, c->g0, c->w); });
+        } else {
+          c->tabs32.plane_threads = pt;
+          c->tabs32.pencil_cols = pc[0];
+          c->tabs32.pencil_threads = pc[1];
+          t = time_us([&]() { return green32(c, c->Kd32, c->tmp32); });
+        }
+        if (t < kMargin * best) {
+          best = t;
+          bp = pt;
+          bc = pc[0];
+          bt = pc[1];
+        }
+      }
+    if (!(best < INFINITY)) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(c, HFE_EDEVICE, "autotune: no FFT launch shape ran");
+    }
+    hfe::FftTablesT<double>* t64 = &c->tabs;
+    if (prec == 0) {
+      t64->plane_threads = bp;
+      t64->pencil_cols = bc;
+      t64->pencil_threads = bt;
+    } else {
+      c->tabs32.plane_threads = bp;
+      c->tabs32.pencil_cols = bc;
+      c->tabs32.pencil_threads = bt;
+    }
+  }
+  if (q1 && c->have_state) {
+    st = refresh_state32(c);
+    if (st == HFE_OK) {
+      double best = INFINITY, best32 = INFINITY;
+      int bs = 0, bs32 = 0;
+      for (int shape = 0; shape < 4; ++shape) {
+        c->brick_shape = c->brick_shape32 = shape;
+        const double t = time_us([&]() { return stiffness(c, c->g0, c->Kd, false); });
+        const double t32 = time_us([&]() { return stiffness32(c, c->Kd32, c->tmp32, false); });
+        if (t < kMargin * best) { best = t; bs = shape; }
+        if (t32 < kMargin * best32) { best32 = t32; bs32 = shape; }
+      }
+      c->brick_shape = bs;
+      c->brick_shape32 = bs32;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  st = sync(c);
+  if (st) return st;
+  return out ? hfe_get_tuning(c, out) : HFE_OK;
 }
 
 hfe_status hfe_apply_stiffness(hfe_ctx* c, const double* in, double* out) {

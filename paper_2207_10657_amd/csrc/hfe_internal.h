@@ -121,10 +121,17 @@ struct FftTablesT {
   const R* sx;            // 4 sin^2(pi k / n) per axis (the 1D FE Laplacian symbol)
   const R* sy;
   const R* sz;
+  // launch shape: threads of a plane block, columns and threads of a pencil block
+  int plane_threads, pencil_cols, pencil_threads;
 };
 using FftTables = FftTablesT<double>;
 
 bool fft_length_supported(int L);
+// Launch shapes: whether one fits the grid (threads, staged values, LDS of a
+// pencil block for reals of `real_bytes`), and the default one.
+bool fft_launch_valid(const Grid& g, int plane_threads, int pencil_cols, int pencil_threads,
+                      size_t real_bytes);
+void fft_default_launch(const Grid& g, int* plane_threads, int* pencil_cols, int* pencil_threads);
 template <typename R> size_t fft_plane_lds_bytes(const Grid& g);
 // The plane passes of this grid fit one block (LDS and staged values).
 template <typename R> bool fft_plane_fits(const Grid& g);

@@ -908,8 +908,13 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 // the brick softens (c' != 0 at one of its points). The gradient of v and the
 // divergence are sum-factorised; s = C : eps(u) is recomputed at softening
 // points only.
+// FP32: at most 128 VGPRs (4 waves per SIMD), which the FP32 kernel fits
+// without spills; FP64 keeps the compiler's choice.
+template <typename R> constexpr int hessian_waves_per_eu() { return sizeof(R) == 4 ? 4 : 1; }
+
 template <typename R, int BX, int BY, int BZ>
-__global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_hessian(HessArgs<R> A) {
+__global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
+    k_hessian(HessArgs<R> A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
   if (A.cg && A.cg->done) return;

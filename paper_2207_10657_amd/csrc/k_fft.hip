@@ -402,8 +402,8 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
 
 enum { PENCIL_GREEN = 0, PENCIL_FWD = 1, PENCIL_INV = 2 };
 
-// Columns per pencil block: runs of 256 bytes per z row.
-template <typename R> constexpr int pencil_cols() { return 256 / (int)sizeof(C2<R>); }
+// Launch shape of the pencil pass: C columns per block (t.pencil_cols),
+// t.pencil_threads threads; at most 256 threads.
 
 // One block per run of C consecutive columns p = ky (nx/2+1) + kx of one
 // component (the last run may be shorter); the column data of a z row are
@@ -412,7 +412,7 @@ template <int MODE, typename R>
 __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTablesT<R> t, C2<R>* __restrict__ spec,
                                                R scale, const CgState* skip) {
   using V = C2<R>;
-  constexpr int C = pencil_cols<R>();
+  const int C = t.pencil_cols;
   if (skip && skip->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   V* lds = reinterpret_cast<V*>(lds_raw);
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTablesT<R> t, C2<R>* 
   const long long zs = ncol;
   const int tid = threadIdx.x, nt = blockDim.x;
   // LDS row pitch C + 1: consecutive z of one column fall in different banks
-  constexpr int CP = C + 1;
+  const int CP = C + 1;
   V* twz = lds + CP * nz;    // z twiddles staged behind the pencils
   for (int i = tid; i < nz; i += nt) twz[i] = t.tw[t.off_z + i];
   staged_copy<V>(nz * cv, [&](int i) {
@@ -457,12 +457,34 @@ __global__ void __launch_bounds__(256) k_pencil(Grid g, FftTablesT<R> t, C2<R>* 
   }
 }
 
-int plane_threads(const Grid& g) {
-  // a thread stages at most 15 complex values per Stockham pass (radix 3:
-  // 5 butterflies), so a block of T threads covers 15 T cells
+}  // namespace
+
+// A thread stages at most 15 complex values per Stockham pass (radix 3: 5
+// butterflies), so a plane block of T threads covers 15 T cells and a pencil
+// block of T threads 15 T column values.
+bool fft_launch_valid(const Grid& g, int plane_threads, int pencil_cols, int pencil_threads,
+                      size_t real_bytes) {
   const int cells = (g.nx / 2 + 1) * g.ny;
-  return cells <= 15 * 256 ? 256 : 1024;
+  if (plane_threads < 64 || plane_threads > 1024 || plane_threads % 64) return false;
+  if (pencil_threads < 64 || pencil_threads > 256 || pencil_threads % 64) return false;
+  if (pencil_cols < 1 || pencil_cols > 64) return false;
+  if (cells > 15 * plane_threads) return false;
+  if ((long long)pencil_cols * g.nz > 15LL * pencil_threads) return false;
+  return ((size_t)(pencil_cols + 1) * g.nz + g.nz) * 2 * real_bytes <= 65536;
 }
+
+void fft_default_launch(const Grid& g, int* plane_threads, int* pencil_cols, int* pencil_threads) {
+  // more threads than the minimum hide latency on the small planes, and short
+  // runs of columns give the pencil pass enough blocks (measured on 64^3 and
+  // 128^3 cells)
+  const int cells = (g.nx / 2 + 1) * g.ny;
+  *plane_threads = cells <= 15 * 128 ? 256 : (cells <= 15 * 512 ? 512 : 1024);
+  *pencil_cols = 8;
+  *pencil_threads = 128;
+  while ((long long)*pencil_cols * g.nz > 15LL * *pencil_threads && *pencil_cols > 1) *pencil_cols /= 2;
+}
+
+namespace {
 
 template <int MODE, typename R>
 hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* out, C2<R>* spec,
@@ -476,13 +498,15 @@ hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* o
   if ((real_in && !in) || (real_out && !out) || !spec || !t.tw) return hipErrorInvalidValue;
   if (cg && (!cf.st || !cf.d || !cf.z || !cf.g || !cf.y || !cf.partials)) return hipErrorInvalidValue;
   if (!fft_plane_fits<R>(g)) return hipErrorInvalidValue;
+  if (!fft_launch_valid(g, t.plane_threads, t.pencil_cols, t.pencil_threads, sizeof(R)))
+    return hipErrorInvalidValue;
   const size_t lds = fft_plane_lds_bytes<R>(g);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE, R>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_plane<MODE, R>), dim3(g.nz, g.dim), dim3(plane_threads(g)), lds, s, g, t,
+  hipLaunchKernelGGL((k_plane<MODE, R>), dim3(g.nz, g.dim), dim3(t.plane_threads), lds, s, g, t,
                      in, out, spec, scale, skip, cf);
   return hipGetLastError();
 }
@@ -491,15 +515,14 @@ template <int MODE, typename R>
 hipError_t launch_pencil(const Grid& g, const FftTablesT<R>& t, C2<R>* spec, R scale,
                          hipStream_t s, const CgState* skip = nullptr) {
   if (!spec || !t.tw) return hipErrorInvalidValue;
-  constexpr int C = pencil_cols<R>();
-  // one Stockham pass stages at most 15 (radix 3) or 16 values per thread
-  if ((long long)C * g.nz > 15LL * 256 && g.nz % 3 == 0) return hipErrorInvalidValue;
-  if ((long long)C * g.nz > 16LL * 256) return hipErrorInvalidValue;
+  if (!fft_launch_valid(g, t.plane_threads, t.pencil_cols, t.pencil_threads, sizeof(R)))
+    return hipErrorInvalidValue;
+  const int C = t.pencil_cols;
   const int ncol = (g.nx / 2 + 1) * g.ny;
   const int nchunk = (ncol + C - 1) / C;
   const size_t lds = ((size_t)(C + 1) * g.nz + g.nz) * sizeof(C2<R>);
-  hipLaunchKernelGGL((k_pencil<MODE, R>), dim3(nchunk, g.dim), dim3(256), lds, s, g, t, spec,
-                     scale, skip);
+  hipLaunchKernelGGL((k_pencil<MODE, R>), dim3(nchunk, g.dim), dim3(t.pencil_threads), lds, s, g,
+                     t, spec, scale, skip);
   return hipGetLastError();
 }
 

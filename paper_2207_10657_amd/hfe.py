@@ -36,6 +36,12 @@ class _Params(ctypes.Structure):
                 ("precision", ctypes.c_int)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in (
+        "plane_threads", "pencil_cols", "pencil_threads", "brick_shape",
+        "plane_threads32", "pencil_cols32", "pencil_threads32", "brick_shape32")]
+
+
 class _Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int),
                 ("rejected", ctypes.c_int), ("cg_iters", ctypes.c_int),
@@ -78,6 +84,11 @@ EXPORTS = {
     "hfe_apply_projected_hessian_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_apply_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "hfe_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "hfe_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "hfe_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
+                                       ctypes.c_void_p]),
     "hfe_apply_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_fft_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_fft_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -138,6 +149,37 @@ DEFAULT_PARAMS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "eta_cg": 1e-6, "eta_up": 0.15
                   "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000, "precision": 0}
 
 
+def _params(params):
+    p = dict(DEFAULT_PARAMS)
+    if params:
+        p.update({k: v for k, v in params.items() if v is not None and k in p})
+    if isinstance(p["precision"], str):
+        p["precision"] = PRECISIONS[p["precision"]]
+    return _Params(**{k: p[k] for k in DEFAULT_PARAMS})
+
+
+def _report(rep):
+    out = {name: getattr(rep, name) for name, _ in _Report._fields_}
+    out["converged"] = rep.status == 0
+    return out
+
+
+def solve_batch(solvers, params=None):
+    """One load increment on each of several solvers at once
+    (hfe_solve_batch): their work overlaps on the device when each runs on its
+    own stream (``Solver(..., own_stream=True)``). Returns the reports."""
+    lib = load_library()
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[s.ctx.value for s in solvers])
+    cp = _params(params)
+    reps = (_Report * n)()
+    st = lib.hfe_solve_batch(arr, n, ctypes.byref(cp), reps)
+    if st != 0:
+        msgs = "; ".join(lib.hfe_last_error(s.ctx).decode() for s in solvers)
+        raise HfeError(st, msgs)
+    return [_report(reps[i]) for i in range(n)]
+
+
 class Solver:
     """One periodic cell on one GPU.
 
@@ -146,7 +188,10 @@ class Solver:
     (*shape, nq, dim, dim) or (*shape, nq).
     """
 
-    def __init__(self, shape, element, device="cuda:0"):
+    def __init__(self, shape, element, device="cuda:0", own_stream=False):
+        """``own_stream``: run on a new stream of this solver (default
+        priority) instead of torch's current stream, so that the solves of
+        several solvers in ``solve_batch`` overlap on the device."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -161,7 +206,12 @@ class Solver:
         if nbytes == 0:
             raise HfeError(-1, "unsupported grid %s / %s" % (self.shape, element))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
+        self.own_stream = bool(own_stream)
+        if self.own_stream:
+            self.stream = torch.cuda.Stream(self.device)
+            self.workspace.record_stream(self.stream)
+        else:
+            self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         st = self.lib.hfe_create(ctypes.byref(g), ctypes.c_void_p(self.workspace.data_ptr()),
                                  nbytes, ctypes.c_void_p(self.stream.cuda_stream),
@@ -212,17 +262,10 @@ class Solver:
         self._check(self.lib.hfe_apply_load_step(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
 
     def solve_increment(self, params=None):
-        p = dict(DEFAULT_PARAMS)
-        if params:
-            p.update({k: v for k, v in params.items() if v is not None and k in p})
-        if isinstance(p["precision"], str):
-            p["precision"] = PRECISIONS[p["precision"]]
-        cp = _Params(**{k: p[k] for k in DEFAULT_PARAMS})
+        cp = _params(params)
         rep = _Report()
         self._check(self.lib.hfe_solve_increment(self.ctx, ctypes.byref(cp), ctypes.byref(rep)))
-        out = {name: getattr(rep, name) for name, _ in _Report._fields_}
-        out["converged"] = rep.status == 0
-        return out
+        return _report(rep)
 
     def newton_log(self, max_records=10000):
         recs = (_Record * max_records)()
@@ -290,6 +333,15 @@ class Solver:
         self._check(self.lib.hfe_set_displacement(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
 
     # -- operators on device tensors ([dim][N] float64, contiguous) -------
+    def _sync_in(self):
+        """Device-tensor operators: the solver's stream waits for torch's."""
+        if self.own_stream:
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _sync_out(self):
+        if self.own_stream:
+            self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def _dev(self, t, dtype=None):
         torch = self.torch
         dtype = torch.float64 if dtype is None else dtype
@@ -304,8 +356,10 @@ class Solver:
     def apply_projected_hessian(self, d, out=None):
         out = self.new_nodal() if out is None else out
         dots = np.zeros(2)
+        self._sync_in()
         self._check(self.lib.hfe_apply_projected_hessian(self.ctx, self._dev(d), self._dev(out),
                                                          dots.ctypes.data_as(ctypes.c_void_p)))
+        self._sync_out()
         return out, dots
 
     def apply_projected_hessian_f32(self, d, out=None):
@@ -315,19 +369,43 @@ class Solver:
         out = torch.zeros((self.dim,) + self.shape, dtype=torch.float32,
                           device=self.device) if out is None else out
         dots = np.zeros(2)
+        self._sync_in()
         self._check(self.lib.hfe_apply_projected_hessian_f32(
             self.ctx, self._dev(d, torch.float32), self._dev(out, torch.float32),
             dots.ctypes.data_as(ctypes.c_void_p)))
+        self._sync_out()
         return out, dots
+
+    def tuning(self):
+        t = _Tuning()
+        self._check(self.lib.hfe_get_tuning(self.ctx, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = _Tuning(**cur)
+        self._check(self.lib.hfe_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def autotune(self):
+        """Time the launch shapes on this grid (and, after a load step, the
+        Hessian brick shapes at the current state); keep the fastest."""
+        t = _Tuning()
+        self._check(self.lib.hfe_autotune(self.ctx, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in _Tuning._fields_}
 
     def apply_stiffness(self, d, out=None):
         out = self.new_nodal() if out is None else out
+        self._sync_in()
         self._check(self.lib.hfe_apply_stiffness(self.ctx, self._dev(d), self._dev(out)))
+        self._sync_out()
         return out
 
     def apply_green(self, f, out=None):
         out = self.new_nodal() if out is None else out
+        self._sync_in()
         self._check(self.lib.hfe_apply_green(self.ctx, self._dev(f), self._dev(out)))
+        self._sync_out()
         return out
 
     def _spec_shape(self):
@@ -339,12 +417,16 @@ class Solver:
 
     def fft_forward(self, f):
         out = self.torch.zeros(self._spec_shape(), dtype=self.torch.float64, device=self.device)
+        self._sync_in()
         self._check(self.lib.hfe_fft_forward(self.ctx, self._dev(f), self._dev(out)))
+        self._sync_out()
         return out
 
     def fft_inverse(self, spec):
         out = self.new_nodal()
+        self._sync_in()
         self._check(self.lib.hfe_fft_inverse(self.ctx, self._dev(spec), self._dev(out)))
+        self._sync_out()
         return out
 
     # -- profiling -------------------------------------------------------
