@@ -265,7 +265,7 @@ def load_traffic(kernel, shape, tuning):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def probe(n, tuning_out=None):
+def probe(n, tuning_out=None, tuning_in=None):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
 
     One load step of the workload recipe at n^3, the autotuner (the launch
@@ -280,7 +280,12 @@ def probe(n, tuning_out=None):
     s = Solver(w.shape, w.element)
     s.setup(w.phase, w.materials)
     s.apply_load_step(w.load_path[0] * 5)      # a damaged state (E_xx = 1e-3)
-    tuned = s.autotune()
+    if tuning_in:
+        with open(tuning_in) as fh:
+            s.set_tuning(**json.load(fh))
+        tuned = s.tuning()
+    else:
+        tuned = s.autotune()
     print("probe launch shapes:", tuned, flush=True)
     if tuning_out:
         with open(tuning_out, "w") as fh:
@@ -318,6 +323,8 @@ def main():
                          "(FETCH_SIZE, then WRITE_SIZE; csv output)")
     ap.add_argument("--probe-tuning", metavar="FILE",
                     help="--probe: write the launch shapes it used; --pmc-summary: read them")
+    ap.add_argument("--probe-set-tuning", metavar="FILE",
+                    help="--probe: use these launch shapes instead of autotuning")
     args = ap.parse_args()
     if args.pmc_summary:
         tuning = None
@@ -339,7 +346,7 @@ def main():
     from synthetic import workload
 
     if args.probe:
-        probe(args.grid, args.probe_tuning)
+        probe(args.grid, args.probe_tuning, args.probe_set_tuning)
         return
     w = workload(WORKLOAD)
     W, K = args.warmup, args.steps

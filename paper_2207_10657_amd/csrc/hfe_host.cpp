@@ -45,10 +45,12 @@ struct Layout {
   size_t u, z, d, g, y, Kd, w, g0, y0, tmp;          // nodal [dim][N]
   size_t a, cp, kh;                                   // per point [nq][N]
   size_t phase;                                       // N bytes
+  size_t soft;                                        // N bytes: element softens
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
   size_t partials2;                                   // second row buffer (direction sums)
   size_t cgstate;                                     // device CgState
+  size_t cgmid;                                       // its copy between the fused passes
   size_t trace;                                       // CG trace, 2 doubles per entry
   size_t Edev;                                        // macroscopic strain (9 doubles)
   size_t tw;                                          // twiddles
@@ -81,7 +83,7 @@ bool grid_ok(const hfe_grid* gr, std::string* why) {
     *why = "nx/2, ny and nz must each be one of 1,2,3,4,6,8,12,16,24,32,48,64,96,128";
     return false;
   }
-  if (((size_t)(nx / 2 + 1) * ny + nx + 1 + ny) * 16 > 160 * 1024) {
+  if (((size_t)(nx / 2 + 1) * ny + nx + 1 + ny) * 16 > 159 * 1024) {
     *why = "a spectral x-y plane (with its twiddles) must fit in 160 KiB of LDS";
     return false;
   }
@@ -112,11 +114,13 @@ Layout make_layout(const Grid& g) {
   L.tmp = take(nod);
   L.a = take(pts); L.cp = take(pts); L.kh = take(pts);
   L.phase = take((size_t)g.N);
+  L.soft = take((size_t)g.N);
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
   L.partials2 = take((size_t)L.partial_rows * 2 * sizeof(double));
   L.cgstate = take(sizeof(hfe::CgState));
+  L.cgmid = take(sizeof(hfe::CgState));
   L.trace = take((size_t)2 * kTraceCap * sizeof(double));
   L.Edev = take(9 * sizeof(double));
   L.n_tw = g.nx / 2 + g.ny + g.nz + (g.nx / 2 + 1);
@@ -173,11 +177,13 @@ struct hfe_ctx {
   double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *tmp;
   double *a, *cp, *kh;
   uint8_t* phase;
+  uint8_t* soft;             // per element: c' != 0 at some point of the state
   double2* spec;
   double* partials;
   double* partials2;
   int nb_dir = 0;            // rows of the pending direction sums in partials2
-  hfe::CgState* cg;          // device CG state
+  hfe::CgState* cg;          // device CG state (after each iteration)
+  hfe::CgState* cg_mid;      // the state after the forward plane pass's decisions (3D)
   double* Edev;              // device copy of E
   double* trace;             // device CG trace
   hfe::FftTables tabs;
@@ -344,6 +350,8 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.u = c->u;
   A.v = nullptr;
   A.f = nullptr;
+  A.soft = c->soft;
+  A.soft_out = nullptr;
   A.red = reducer(c);
   A.cg = nullptr;
   A.brick_shape = c->brick_shape;
@@ -418,6 +426,7 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   hfe::ElemArgs A = elem_args(c);
   A.a_out = c->a;
   A.cp_out = c->cp;
+  A.soft_out = c->soft;
   A.f = c->g0;
   int nb = 0;
   {
@@ -484,6 +493,7 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.mat = c->mat;
   H.E = c->Edev;
   H.phase = c->phase;
+  H.soft = c->soft;
   H.u = c->u32;
   H.a = c->a32;
   H.cp = c->cp32;
@@ -541,6 +551,28 @@ hfe_status direction32(hfe_ctx* c) {
   return HFE_OK;
 }
 
+// Operands of the fused CG passes of a 3D iteration: the forward pass reads
+// the state after the previous iteration (cg) with the pending direction rows
+// (partials2) and the Hessian rows (partials, nb_hes), and stores its
+// decisions in cg_mid.
+template <typename R>
+hfe::CgFuse<R> fuse_args(hfe_ctx* c, int nb_hes, const R* d, R* z, R* g, R* y) {
+  hfe::CgFuse<R> f;
+  f.st_in = c->cg;
+  f.st_out = c->cg_mid;
+  f.rows_dir = c->partials2;
+  f.nb_dir = c->nb_dir;
+  f.rows_hes = c->partials;
+  f.nb_hes = nb_hes;
+  f.trace = c->trace;
+  f.d = d;
+  f.z = z;
+  f.g = g;
+  f.y = y;
+  f.partials = c->partials;
+  return f;
+}
+
 // The FP64 iteration below with FP32 vectors, Hessian and FFT (3D).
 hfe_status cg_iteration32(hfe_ctx* c) {
   int nb = 0;
@@ -548,20 +580,7 @@ hfe_status cg_iteration32(hfe_ctx* c) {
     Prof p(c, "stiffness_f32");
     HIPCHK(c, hfe::launch_hessian_f32(hess_args32(c, c->d32, c->Kd32, true), c->stream, &nb));
   }
-  {
-    hfe::Reducer rd;
-    rd.partials = c->partials2;
-    Prof p(c, "finish");
-    HIPCHK(c, hfe::finish_direction_curvature(rd, c->nb_dir, reducer(c), nb, c->cg, c->trace,
-                                              c->stream));
-  }
-  hfe::CgFuse<float> f;
-  f.st = c->cg;
-  f.d = c->d32;
-  f.z = c->z32;
-  f.g = c->g32;
-  f.y = c->y32;
-  f.partials = c->partials;
+  hfe::CgFuse<float> f = fuse_args<float>(c, nb, c->d32, c->z32, c->g32, c->y32);
   {
     Prof p(c, "fft_plane_fwd_cg_f32");
     HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs32, (const float*)c->Kd32, c->spec32, f,
@@ -569,21 +588,26 @@ hfe_status cg_iteration32(hfe_ctx* c) {
   }
   {
     Prof p(c, "fft_pencil_green_f32");
-    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs32, c->spec32, c->stream, c->cg));
+    HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs32, c->spec32, c->stream, c->cg_mid));
   }
+  f.st_in = c->cg_mid;
   {
     Prof p(c, "fft_plane_inv_cg_f32");
     HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs32, c->spec32, f, c->stream, &nb));
   }
-  hfe_status st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
-  if (st) return st;
-  return direction32(c);
+  hfe::Reducer r;
+  r.partials = c->partials2;
+  Prof p(c, "cg_vec_f32");
+  HIPCHK(c, hfe::cg_step_d<float>(ndof(c), c->y32, c->d32, c->g32, c->z32, r, c->cg_mid, c->stream,
+                                  &c->nb_dir, c->partials, nb, c->cg, c->trace));
+  return HFE_OK;
 }
 
 // One CG iteration, all decisions on the device (no host synchronisation):
 // K d, [direction update of the previous iteration + curvature decision],
 // z/g update + forward FFT, Green z-pass, inverse FFT + y update + residual
-// sums, [residual decision], new direction.
+// sums, [residual decision], new direction. In 3D the bracketed decisions
+// are taken inside the neighbouring passes (4 launches per iteration).
 hfe_status cg_iteration(hfe_ctx* c) {
   const long long n = ndof(c);
   hfe::ElemArgs A = elem_args(c);
@@ -595,6 +619,32 @@ hfe_status cg_iteration(hfe_ctx* c) {
     Prof p(c, "stiffness");
     HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
   }
+  if (c->g.dim == 3) {
+    // 3D: four launches, the decisions fused into the forward plane pass
+    // (direction + curvature) and into the direction update (residual)
+    hfe::CgFuse<double> f = fuse_args<double>(c, nb, c->d, c->z, c->gv, c->y);
+    {
+      Prof p(c, "fft_plane_fwd_cg");
+      HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs, (const double*)c->Kd, c->spec, f,
+                                          c->stream));
+    }
+    {
+      Prof p(c, "fft_pencil_green");
+      HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream, c->cg_mid));
+    }
+    f.st_in = c->cg_mid;
+    {
+      Prof p(c, "fft_plane_inv_cg");
+      HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs, c->spec, f, c->stream, &nb));
+    }
+    hfe::Reducer r;
+    r.partials = c->partials2;
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_d<double>(n, c->y, c->d, c->gv, c->z, r, c->cg_mid, c->stream,
+                                     &c->nb_dir, c->partials, nb, c->cg, c->trace));
+    return HFE_OK;
+  }
+  // 2D: separate passes and finish kernels
   {
     hfe::Reducer rd;
     rd.partials = c->partials2;
@@ -602,37 +652,17 @@ hfe_status cg_iteration(hfe_ctx* c) {
     HIPCHK(c, hfe::finish_direction_curvature(rd, c->nb_dir, reducer(c), nb, c->cg, c->trace,
                                               c->stream));
   }
-  if (c->g.dim == 3) {
-    hfe::CgFuse<double> f;
-    f.st = c->cg;
-    f.d = c->d;
-    f.z = c->z;
-    f.g = c->gv;
-    f.y = c->y;
-    f.partials = c->partials;
-    {
-      Prof p(c, "fft_plane_fwd_cg");
-      HIPCHK(c, hfe::fft_plane_forward_cg(c->g, c->tabs, c->Kd, c->spec, f, c->stream));
-    }
-    {
-      Prof p(c, "fft_pencil_green");
-      HIPCHK(c, hfe::fft_pencil_green(c->g, c->tabs, c->spec, c->stream, c->cg));
-    }
-    {
-      Prof p(c, "fft_plane_inv_cg");
-      HIPCHK(c, hfe::fft_plane_inverse_cg(c->g, c->tabs, c->spec, f, c->stream, &nb));
-    }
-  } else {
-    {
-      Prof p(c, "cg_vec");
-      HIPCHK(c, hfe::cg_step_zg(n, c->d, c->Kd, c->z, c->gv, c->cg, c->stream));
-    }
-    hfe_status st = green(c, c->Kd, c->w, c->cg);
-    if (st) return st;
+  {
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_step_zg(n, c->d, c->Kd, c->z, c->gv, c->cg, c->stream));
+  }
+  hfe_status st = green(c, c->Kd, c->w, c->cg);
+  if (st) return st;
+  {
     Prof p(c, "cg_vec");
     HIPCHK(c, hfe::cg_step_y(n, c->w, c->y, c->gv, reducer(c), c->cg, c->stream, &nb));
   }
-  hfe_status st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
+  st = finish(c, hfe::FIN_RESIDUAL, nb, 2, nullptr);
   if (st) return st;
   return direction(c);
 }
@@ -879,10 +909,12 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->a32 = F(L.a32); c->cp32 = F(L.cp32);
   c->spec32 = (float2*)(c->ws + L.spec32);
   c->phase = (uint8_t*)(c->ws + L.phase);
+  c->soft = (uint8_t*)(c->ws + L.soft);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
   c->partials2 = D(L.partials2);
   c->cg = (hfe::CgState*)(c->ws + L.cgstate);
+  c->cg_mid = (hfe::CgState*)(c->ws + L.cgmid);
   c->trace = D(L.trace);
   c->Edev = D(L.Edev);
   std::memset(&c->mat, 0, sizeof(c->mat));

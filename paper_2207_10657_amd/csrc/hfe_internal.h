@@ -63,6 +63,8 @@ struct ElemArgs {
   const double* u;       // [dim][N]
   const double* v;       // second nodal input: z (trial) or the direction (Hessian)
   double* f;             // nodal output [dim][N]
+  const uint8_t* soft;   // [N] element softens (c' != 0 at a point); read by the Hessian
+  uint8_t* soft_out;     // written by the residual (Q1)
   Reducer red;
   CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
   int brick_shape;       // brick shape of the Q1 element passes (see launch_brick)
@@ -83,6 +85,7 @@ struct HessArgs {
   MatTable mat;
   const double* E;       // macroscopic strain (device, FP64)
   const uint8_t* phase;
+  const uint8_t* soft;   // [N] element softens at some point (from the residual pass)
   const R* u;            // [dim][N] state displacement (s = C:eps at softening points)
   const R* a;            // [nq][N] tangent scalars of the state
   const R* cp;
@@ -156,15 +159,25 @@ template <typename R>
 hipError_t fft_plane_green2d(const Grid& g, const FftTablesT<R>& t, const R* in, R* out,
                              C2<R>* spec, hipStream_t s, const CgState* skip = nullptr);
 
-// CG iteration passes with the vector updates fused in (3D):
-//  forward plane pass of Kd that also does z += alpha d, g += alpha Kd (or,
-//  when the CG has just stopped on the sphere, z += tau d);
-//  inverse plane pass that, instead of writing w = L^+ Kd, does y += alpha w
-//  and writes partial rows {y_new.g, y_old.g} (one row per plane block,
+// CG iteration passes with the vector updates and decisions fused in (3D):
+//  forward plane pass of Kd: every block adds the rows of the previous
+//  direction update {g.d, z.g} (rows_dir) and of the Hessian {d.Kd, |Dd|^2}
+//  (rows_hes) in a fixed order and takes the direction and curvature
+//  decisions on its own copy of st_in (block (0,0) stores the result in
+//  st_out and writes the trace); then z += alpha d, g += alpha Kd (or, when
+//  the CG has just stopped on the sphere, z += tau d);
+//  inverse plane pass (state st_in): instead of writing w = L^+ Kd, y +=
+//  alpha w and partial rows {y_new.g, y_old.g} (one row per plane block,
 //  accumulated in FP64 in either precision).
 template <typename R>
 struct CgFuse {
-  CgState* st;
+  const CgState* st_in;
+  CgState* st_out;          // forward pass only
+  const double* rows_dir;   // forward pass only
+  int nb_dir;
+  const double* rows_hes;   // forward pass only
+  int nb_hes;
+  double* trace;            // forward pass only
   const R* d;
   R* z;
   R* g;
@@ -200,10 +213,16 @@ hipError_t cg_step_zg(long long n, const double* d, const double* Kd, double* z,
 // CG: y += alpha w, rows {y_new.g, y_old.g}
 hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, const Reducer& r,
                      const CgState* st, hipStream_t s, int* nblocks);
-// CG: d = -y + beta d, rows {g.d, z.g} (R = double or float; sums in FP64)
+// CG: d = -y + beta d, rows {g.d, z.g} (R = double or float; sums in FP64).
+// With rows_res set, every block first adds the nb_res rows {y_new.g,
+// y_old.g} of the inverse plane pass and takes the residual decision on its
+// own copy of st (block 0 stores it in st_out and writes the trace);
+// otherwise it reads beta from st.
 template <typename R>
 hipError_t cg_step_d(long long n, const R* y, R* d, const R* g, const R* z, const Reducer& r,
-                     const CgState* st, hipStream_t s, int* nblocks);
+                     const CgState* st, hipStream_t s, int* nblocks,
+                     const double* rows_res = nullptr, int nb_res = 0, CgState* st_out = nullptr,
+                     double* trace = nullptr);
 // Mixed precision: rows of x . y over FP32 vectors (FP64 sums); y = (float) x;
 // y = (double) x; out = (float)(x + y).
 hipError_t vec_dot_f32(long long n, const float* x, const float* y, const Reducer& r,

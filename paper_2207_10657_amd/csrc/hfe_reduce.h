@@ -38,8 +38,30 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* pa
   }
 }
 
-}  // namespace hfe
-
-namespace hfe {
+// Fixed-order sum of nb rows of NV partials, done by the first 256 threads
+// of the block so that the order of the additions does not depend on the
+// block size (blockDim.x >= 256). The totals end in thread 0's tot. Every
+// thread of the block must call it.
+template <int NV>
+__device__ __forceinline__ void block_sum_rows(const double* __restrict__ rows, int nb,
+                                               double (&tot)[NV]) {
+  __shared__ double ws[4][NV];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < 256) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int r = tid; r < nb; r += 256) s += rows[(size_t)r * NV + k];
+      s = wave_sum(s);
+      if (lane == 0) ws[wave][k] = s;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
+  }
+  __syncthreads();
+}
 
 }  // namespace hfe

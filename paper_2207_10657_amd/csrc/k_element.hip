@@ -743,6 +743,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Em[i][j] = A.E[3 * i + j];
+    bool soft = false;   // some point of this element softens (c' != 0)
 #pragma unroll 1
     for (int q = 0; q < 8; ++q) {
       Sym tau;
@@ -761,6 +762,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
         if (owned) {
           A.a_out[q * g.N + eg] = P.a;
           A.cp_out[q * g.N + eg] = P.cp;
+          soft |= P.cp != 0.0;
           double hh = 0.0;
 #pragma unroll
           for (int i = 0; i < 3; ++i)
@@ -781,6 +783,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
           for (int i = 0; i < 3; ++i) f[i][a] += w * sym_at(tau, i, j);
         }
     }
+    if (owned) A.soft_out[eg] = soft ? 1 : 0;
   }
   // assembly into the owned nodes, one local node per phase
 #pragma unroll
@@ -905,7 +908,8 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 // for the mixed-precision CG, FP32 (R = float) with the reduction terms
 // {v.Kv, |D v|^2} accumulated in FP64. The same brick scheme as k_brick: the
 // direction is staged on the tile, the displacement only if some element of
-// the brick softens (c' != 0 at one of its points). The gradient of v and the
+// the brick softens (c' != 0 at one of its points; a per-element flag written
+// by the residual pass). The gradient of v and the
 // divergence are sum-factorised; s = C : eps(u) is recomputed at softening
 // points only.
 // FP32: at most 128 VGPRs (4 waves per SIMD), which the FP32 kernel fits
@@ -970,10 +974,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
-    bool mine_u = false;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) mine_u |= A.cp[q * g.N + eg] != R(0);
-    if (mine_u) need_u_flag = 1;
+    if (A.soft[eg]) need_u_flag = 1;
   }
   __syncthreads();
   if (need_u_flag) {
@@ -1112,7 +1113,7 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
 // 2 = 16x8x4 (768), 3 = 16x4x4 (448).
 template <typename R>
 hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
-  if (!A.v || !A.f || !A.u || !A.a || !A.cp || !A.phase || !A.E || !A.red.partials)
+  if (!A.v || !A.f || !A.u || !A.a || !A.cp || !A.phase || !A.soft || !A.E || !A.red.partials)
     return hipErrorInvalidValue;
   switch (A.brick_shape) {
     case 1: return launch_hessian_shape<R, 8, 8, 8>(A, s, nblocks);
@@ -1156,6 +1157,7 @@ hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   H.mat = A.mat;
   H.E = A.E;
   H.phase = A.phase;
+  H.soft = A.soft;
   H.u = A.u;
   H.a = A.a;
   H.cp = A.cp;

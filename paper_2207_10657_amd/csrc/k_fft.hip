@@ -306,15 +306,38 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   const int z = blockIdx.x, c = blockIdx.y;
   const long long plane = (long long)c * g.N + (long long)z * nx * ny;
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (MODE == PLANE_FWD_CG && cf.st->done) {
-    // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
-    if (cf.st->apply_tau) {
-      const R tau = (R)cf.st->tau;
-      for (int i = tid; i < nx * ny; i += nt) cf.z[plane + i] += tau * cf.d[plane + i];
+  // CG state of this pass: the forward pass takes the direction and
+  // curvature decisions itself (every block on its own copy, from the same
+  // rows in the same order, so all copies agree); the inverse pass reads it
+  __shared__ CgState sst;
+  if constexpr (MODE == PLANE_FWD_CG) {
+    if (!cf.st_in->done) {
+      double td[2], tc[2];
+      block_sum_rows<2>(cf.rows_dir, cf.nb_dir, td);
+      block_sum_rows<2>(cf.rows_hes, cf.nb_hes, tc);
+      if (tid == 0) {
+        const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+        sst = *cf.st_in;
+        cg_decide_direction(&sst, td[0], td[1]);
+        cg_decide_curvature(&sst, first ? cf.trace : nullptr, tc[0], tc[1]);
+      }
+    } else if (tid == 0) {
+      sst = *cf.st_in;
     }
-    return;
+    __syncthreads();
+    if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) *cf.st_out = sst;
+    if (sst.done) {
+      // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
+      if (sst.apply_tau && !cf.st_in->done) {
+        const R tau = (R)sst.tau;
+        for (int i = tid; i < nx * ny; i += nt) cf.z[plane + i] += tau * cf.d[plane + i];
+      }
+      return;
+    }
   }
-  if (MODE == PLANE_INV_CG && cf.st->done) return;
+  if constexpr (MODE == PLANE_INV_CG) {
+    if (cf.st_in->done) return;
+  }
   if (skip && skip->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   V* lds = reinterpret_cast<V*>(lds_raw);
@@ -344,7 +367,7 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
     __syncthreads();
     if (MODE == PLANE_FWD_CG) {
       // z += alpha d, g += alpha Kd on this plane (Kd is the transform input)
-      const R alpha = (R)cf.st->alpha;
+      const R alpha = (R)sst.alpha;
       const R* kd = in + plane;
       for (int i = tid; i < nx * ny; i += nt) {
         cf.z[plane + i] += alpha * cf.d[plane + i];
@@ -376,7 +399,7 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   if (MODE == PLANE_INV_CG) {
     // y += alpha w and the residual inner products (accumulated in FP64),
     // w never leaves LDS
-    const R alpha = (R)cf.st->alpha;
+    const R alpha = (R)cf.st_in->alpha;
     V* y2 = reinterpret_cast<V*>(cf.y + plane);
     const V* g2 = reinterpret_cast<const V*>(cf.g + plane);
     double acc[2] = {0.0, 0.0};
@@ -496,7 +519,10 @@ hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* o
   constexpr bool real_out = MODE == PLANE_INV || MODE == PLANE_GREEN2D;
   constexpr bool cg = MODE == PLANE_FWD_CG || MODE == PLANE_INV_CG;
   if ((real_in && !in) || (real_out && !out) || !spec || !t.tw) return hipErrorInvalidValue;
-  if (cg && (!cf.st || !cf.d || !cf.z || !cf.g || !cf.y || !cf.partials)) return hipErrorInvalidValue;
+  if (cg && (!cf.st_in || !cf.d || !cf.z || !cf.g || !cf.y || !cf.partials)) return hipErrorInvalidValue;
+  if (MODE == PLANE_FWD_CG && (!cf.st_out || !cf.rows_dir || !cf.rows_hes || cf.nb_dir < 1 ||
+                               cf.nb_hes < 1 || t.plane_threads < 256))
+    return hipErrorInvalidValue;
   if (!fft_plane_fits<R>(g)) return hipErrorInvalidValue;
   if (!fft_launch_valid(g, t.plane_threads, t.pencil_cols, t.pencil_threads, sizeof(R)))
     return hipErrorInvalidValue;

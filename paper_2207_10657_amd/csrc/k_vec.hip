@@ -85,14 +85,36 @@ __global__ void __launch_bounds__(kBlock) k_cg_y(long long n, const double* __re
   block_reduce_store<2>(acc, r.partials);
 }
 
-// d = -y + beta d with the sums {g.d, z.g} (FP64 in either precision)
+// d = -y + beta d with the sums {g.d, z.g} (FP64 in either precision). With
+// rows_res set, every block first takes the residual decision on its own copy
+// of st from the rows of the inverse plane pass (block 0 stores it in st_out).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restrict__ y,
                                                  R* __restrict__ d, const R* __restrict__ g,
                                                  const R* __restrict__ z, Reducer r,
-                                                 const CgState* st) {
-  if (st->done) return;
-  const R beta = (R)st->beta;
+                                                 const CgState* st, const double* rows_res,
+                                                 int nb_res, CgState* st_out, double* trace) {
+  __shared__ CgState sst;
+  if (rows_res) {
+    if (!st->done) {
+      double t[2];
+      block_sum_rows<2>(rows_res, nb_res, t);
+      if (threadIdx.x == 0) {
+        sst = *st;
+        cg_decide_residual(&sst, blockIdx.x == 0 ? trace : nullptr, t[0], t[1]);
+      }
+    } else if (threadIdx.x == 0) {
+      sst = *st;
+      sst.apply_tau = 0;   // the exit step was formed by the forward plane pass
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && blockIdx.x == 0) *st_out = sst;
+  } else if (threadIdx.x == 0) {
+    sst = *st;
+  }
+  __syncthreads();
+  if (sst.done) return;
+  const R beta = (R)sst.beta;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -246,16 +268,20 @@ hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, c
 
 template <typename R>
 hipError_t cg_step_d(long long n, const R* y, R* d, const R* g, const R* z, const Reducer& r,
-                     const CgState* st, hipStream_t s, int* nblocks) {
+                     const CgState* st, hipStream_t s, int* nblocks, const double* rows_res,
+                     int nb_res, CgState* st_out, double* trace) {
+  if (rows_res && (!st_out || nb_res < 1)) return hipErrorInvalidValue;
   *nblocks = vec_blocks(n);
-  hipLaunchKernelGGL((k_cg_d<R>), dim3(*nblocks), dim3(kBlock), 0, s, n, y, d, g, z, r, st);
+  hipLaunchKernelGGL((k_cg_d<R>), dim3(*nblocks), dim3(kBlock), 0, s, n, y, d, g, z, r, st,
+                     rows_res, nb_res, st_out, trace);
   return hipGetLastError();
 }
 template hipError_t cg_step_d<double>(long long, const double*, double*, const double*,
                                       const double*, const Reducer&, const CgState*, hipStream_t,
-                                      int*);
+                                      int*, const double*, int, CgState*, double*);
 template hipError_t cg_step_d<float>(long long, const float*, float*, const float*, const float*,
-                                     const Reducer&, const CgState*, hipStream_t, int*);
+                                     const Reducer&, const CgState*, hipStream_t, int*,
+                                     const double*, int, CgState*, double*);
 
 hipError_t vec_dot_f32(long long n, const float* x, const float* y, const Reducer& r,
                        hipStream_t s, int* nblocks) {
