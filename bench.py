@@ -167,6 +167,12 @@ PMC_KERNELS = [("k_hessian<double,", "stiffness"), ("k_brick<0,", "residual"),
                ("k_plane<0,double>", "fft_plane_fwd"), ("k_pencil<0,double>", "fft_pencil_green"),
                ("k_plane<1,double>", "fft_plane_inv"), ("copyBuffer", "copy")]
 PROBE_REPS = 5
+# Hessian brick shapes (nodes per axis, x y z) by tuning index
+BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4)}
+
+
+def hessian_label(shape_index):
+    return "stiffness:%dx%dx%d" % BRICKS[shape_index]
 
 
 def sources_digest(kernel):
@@ -189,8 +195,12 @@ def read_pmc(path):
     for f in files:
         with open(f, newline="") as fh:
             for row in csv.DictReader(fh):
-                name = row.get("Kernel_Name", "")
-                label = next((lab for key, lab in PMC_KERNELS if key in name.replace(" ", "")), None)
+                name = row.get("Kernel_Name", "").replace(" ", "")
+                label = next((lab for key, lab in PMC_KERNELS if key in name), None)
+                if label == "stiffness":
+                    # one entry per brick shape: k_hessian<double,BX,BY,BZ>
+                    dims = name.split("k_hessian<double,", 1)[1].split(">", 1)[0]
+                    label = "stiffness:" + dims.replace(",", "x")
                 if label is not None:
                     rows.append((int(row["Dispatch_Id"]), label, float(row["Counter_Value"])))
     out = {}
@@ -221,15 +231,19 @@ def pmc_summary(fetch_dir, write_dir, grid, tuning=None):
     kw = COPY_BYTES / (1024.0 * np.median(write["copy"]))
     shape = (grid, grid, grid)
     rows, table = [], {}
-    for label in ("stiffness", "residual", "fft_plane_fwd", "fft_pencil_green", "fft_plane_inv"):
+    labels = [hessian_label(k) for k in sorted(BRICKS)]
+    labels += ["residual", "fft_plane_fwd", "fft_pencil_green", "fft_plane_inv"]
+    for label in labels:
         if label not in fetch or label not in write:
             continue
+        base = label.split(":")[0]
         fb = float(np.median(fetch[label])) * 1024.0 * kf
         wb = float(np.median(write[label])) * 1024.0 * kw
-        alg = algorithmic_bytes(label, shape)
+        alg = algorithmic_bytes(base, shape)
+        keys = () if base == "stiffness" else SHAPE_KEYS[base]   # the brick is in the label
         table[label] = {"fetch_bytes": fb, "write_bytes": wb, "dispatches": len(fetch[label]),
-                        "algorithmic_bytes": alg, "sources": sources_digest(label),
-                        "launch": {k: tuning[k] for k in SHAPE_KEYS[label]} if tuning else None}
+                        "algorithmic_bytes": alg, "sources": sources_digest(base),
+                        "launch": {k: tuning[k] for k in keys} if tuning else None}
         rows.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (
             label, len(fetch[label]), fb / 1e6, wb / 1e6, (fb + wb) / 1e6,
             (fb + wb) / alg if alg else float("nan")))
@@ -255,12 +269,16 @@ def load_traffic(kernel, shape, tuning):
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    k = blob.get("kernels", {}).get(kernel)
+    if kernel == "stiffness":
+        label, keys = hessian_label(tuning["brick_shape"]), ()
+    else:
+        label, keys = kernel, SHAPE_KEYS.get(kernel, ())
+    k = blob.get("kernels", {}).get(label)
     if not k or tuple([blob.get("grid")] * 3) != tuple(shape):
         return None
     if k.get("sources") != sources_digest(kernel):
         return None
-    if k.get("launch") != {key: tuning[key] for key in SHAPE_KEYS.get(kernel, ())}:
+    if k.get("launch") != {key: tuning[key] for key in keys}:
         return None
     return k["fetch_bytes"] + k["write_bytes"]
 
@@ -268,11 +286,11 @@ def load_traffic(kernel, shape, tuning):
 def probe(n, tuning_out=None, tuning_in=None):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
 
-    One load step of the workload recipe at n^3, the autotuner (the launch
-    shapes the benchmark uses), then PROBE_REPS projected-Hessian applications
-    at that state and PROBE_REPS device-to-device copies of COPY_BYTES (the
-    copy kernel calibrates the counters: it reads and writes exactly
-    COPY_BYTES per launch)."""
+    One load step of the workload recipe at n^3, the autotuner (the FFT
+    launch shapes the benchmark uses), then, for every Hessian brick shape,
+    PROBE_REPS projected-Hessian applications at that state, and PROBE_REPS
+    device-to-device copies of COPY_BYTES (the copy kernel calibrates the
+    counters: it reads and writes exactly COPY_BYTES per launch)."""
     import torch
     from paper_2207_10657_amd import Solver
     from synthetic import workload
@@ -292,8 +310,10 @@ def probe(n, tuning_out=None, tuning_in=None):
             json.dump(tuned, fh)
     rng = np.random.default_rng(0)
     d = torch.tensor(rng.normal(size=(3,) + w.shape), device="cuda")
-    for _ in range(PROBE_REPS):
-        s.apply_projected_hessian(d)
+    for shape_index in sorted(BRICKS):      # every Hessian brick shape, FFT shapes as tuned
+        s.set_tuning(brick_shape=shape_index)
+        for _ in range(PROBE_REPS):
+            s.apply_projected_hessian(d)
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(PROBE_REPS):

@@ -216,6 +216,21 @@ hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* ctx, const float* dev_in, fl
 hfe_status hfe_solve_batch(hfe_ctx* const* ctxs, int n, const hfe_solver_params* params,
                            hfe_solve_report* reports);
 
+/* Effective stiffness of a cell (the six columns of C-bar, Voigt order xx,
+ * yy, zz, yz, xz, xy with engineering shears) from six contexts of the same
+ * grid, microstructure and materials, each in the state to linearise about
+ * (fresh, or restarted with hfe_set_state, e.g. u = 0, E = 0 and a damaged
+ * history: loads below the history unload, which gives the secant stiffness
+ * of the damaged cell). Context J gets the increment `strain` times the J-th
+ * unit strain (shears: E_ij = E_ji = strain / 2) and the six increments are
+ * solved as one batch (hfe_solve_batch); column J is the change of the
+ * homogenized stress divided by `strain`. 3D only. C (host, 36 doubles,
+ * row-major) receives C-bar; reports (host, 6, may be NULL) the solves. The
+ * contexts keep the solved increments. */
+hfe_status hfe_effective_stiffness(hfe_ctx* const* ctxs, double strain,
+                                   const hfe_solver_params* params, double C[36],
+                                   hfe_solve_report* reports);
+
 /* Launch shapes of the hot kernels, per context. FP64 fields serve the FP64
  * path, *32 fields the FP32 kernels of the HFE_MIXED CG. */
 typedef struct {

@@ -8,7 +8,9 @@ its Appendix A is not used) is
     d(kappa) = kf/kappa * (kappa - k0)/(kf - k0), clamped to [0, 1],
 
 with C isotropic (Lame constants from E, nu; plane strain in 2D, eps_zz = 0)
-and the history kappa_hist frozen during a load step. A point is loading iff
+and the history kappa_hist frozen during a load step. A phase may carry an
+eigenstrain eps_eig, added to the strain before the law is evaluated
+(Algorithm 2: eps_eval = eps + eps_eig), so eps above is sym(H) + eps_eig. A point is loading iff
 kappa_t > kappa_hist (strict); then d = d(kappa_t), else d = d(kappa_hist).
 
 The paper's Newton linearisation (eq. project_stress_linear) and energy
@@ -65,6 +67,21 @@ class MaterialField:
         self.damage = per_qp("kind", conv=lambda k: 1.0 if k == "damage" else 0.0) > 0.5
         self.k0 = np.where(self.damage, per_qp("kappa0"), 0.0)
         self.kf = np.where(self.damage, per_qp("kappaf"), 1.0)
+        self.phase = phase
+        self.eig_table = np.zeros((len(materials), self.dim, self.dim))
+        for p, m in enumerate(materials):
+            if m.get("eig") is not None:
+                self.set_eigenstrain(p, m["eig"])
+        self._update_eig()
+
+    def set_eigenstrain(self, p, eig):
+        """Eigenstrain of phase p (3x3, symmetric; the in-plane block in 2D)."""
+        e = np.asarray(eig, dtype=np.float64).reshape(3, 3)
+        self.eig_table[p] = 0.5 * (e + e.T)[:self.dim, :self.dim]
+        self._update_eig()
+
+    def _update_eig(self):
+        self.eig = np.repeat(self.eig_table[self.phase][..., None, :, :], self.nq, axis=-3)
 
     def initial_history(self):
         """kappa_hist := kappa0 on damage points (no damage yet), 0 elsewhere."""
@@ -84,8 +101,9 @@ def _c_contract(mat, eps):
 
 
 def evaluate(mat, H, kappa_hist):
-    """Stress and tangent data at the full-gradient field H (*grid, nq, d, d)."""
-    eps = sym(H)
+    """Stress and tangent data at the full-gradient field H (*grid, nq, d, d);
+    the law sees eps = sym(H) + eps_eig."""
+    eps = sym(H) + mat.eig
     s = _c_contract(mat, eps)
     ecs = np.sum(eps * s, axis=(-2, -1))
     kappa_t = np.sqrt(np.maximum(ecs, 0.0) / mat.E)

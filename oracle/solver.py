@@ -27,6 +27,12 @@ r_eq = ||G sigma|| / ||sigma||; r_NR = ||p|| / ||H|| as printed. Convergence
 needs an interior step and (r_eq <= eta_eq or r_NR <= eta_NR). The history
 (kappa_hist) is committed only when a load step converges.
 
+Eigenstrain (Algorithm 2, the eps_eval lines): a phase's eigenstrain is added
+to the strain before every evaluation of the law, the trial evaluation
+included; r_NR keeps the strain without it. A load by eigenstrain alone (zero
+first macroscopic increment) takes the radius scale from the largest phase
+eigenstrain.
+
 Pinned by (``tests/test_oracle_solver.py``, ``tests/test_oracle_cell.py``):
 dense SPD solves and exact boundary exits (Steihaug); the 1D damage-spring
 system of Sec. 3.1 against a brute-force energy scan; the homogeneous and
@@ -183,6 +189,12 @@ class CellSolver:
         self.r_eq = None
         self.n_qp = int(np.prod(self.grid)) * self.nq
 
+    def set_eigenstrain(self, phase, eig):
+        """Eigenstrain of a phase from now on (Algorithm 2 adds it to the
+        strain before every evaluation); the next apply_load_step evaluates
+        the state with it."""
+        self.mat.set_eigenstrain(phase, eig)
+
     # -- state evaluation -------------------------------------------------
     def _evaluate(self, H):
         return material.evaluate(self.mat, H, self.kappa_hist)
@@ -206,7 +218,14 @@ class CellSolver:
         d = self.dim
         self.H = self.H + dE[:d, :d]
         if self.R is None or self.Rmax is None:
-            R0, Rmax = default_radii(self.n_qp, dE[:d, :d])
+            # the load that sets the radius scale: the first macroscopic
+            # increment, or, for a load by eigenstrain alone, the largest
+            # phase eigenstrain
+            load = dE[:d, :d]
+            if not np.any(load):
+                norms = [np.linalg.norm(e) for e in self.mat.eig_table]
+                load = self.mat.eig_table[int(np.argmax(norms))]
+            R0, Rmax = default_radii(self.n_qp, load)
             self.R = R0 if self.R is None else self.R
             self.Rmax = Rmax if self.Rmax is None else self.Rmax
         self._set_state(self._evaluate(self.H))

@@ -5,4 +5,5 @@ in ``include/hfe.h``); ``hfe`` is its ctypes binding. Importing the package
 does not load the library; ``Solver(...)`` or ``hfe.load_library()`` does,
 and fails with ImportError when it has not been built.
 """
-from .hfe import Solver, HfeError, load_library, solve_batch, workspace_bytes  # noqa: F401
+from .hfe import (Solver, HfeError, effective_stiffness, load_library, solve_batch,  # noqa: F401
+                  workspace_bytes)

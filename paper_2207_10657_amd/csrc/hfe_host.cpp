@@ -1192,6 +1192,50 @@ hfe_status hfe_solve_batch(hfe_ctx* const* ctxs, int n, const hfe_solver_params*
   return HFE_OK;
 }
 
+hfe_status hfe_effective_stiffness(hfe_ctx* const* ctxs, double strain,
+                                   const hfe_solver_params* params, double C[36],
+                                   hfe_solve_report* reports) {
+  if (!ctxs || !C || !(strain > 0.0) || !std::isfinite(strain)) return HFE_EINVAL;
+  for (int i = 0; i < 6; ++i) {
+    if (!ctxs[i]) return HFE_EINVAL;
+    if (ctxs[i]->g.dim != 3 || ctxs[i]->g.nx != ctxs[0]->g.nx || ctxs[i]->g.ny != ctxs[0]->g.ny ||
+        ctxs[i]->g.nz != ctxs[0]->g.nz)
+      return fail(ctxs[i], HFE_EINVAL, "the six contexts need one 3D grid");
+  }
+  // Voigt order xx, yy, zz, yz, xz, xy; index pairs of the 3x3 tensor
+  static const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+  double before[6][9];
+  for (int J = 0; J < 6; ++J) {
+    hfe_ctx* c = ctxs[J];
+    double dE[9] = {0};
+    const double e = vi[J] == vj[J] ? strain : 0.5 * strain;
+    dE[3 * vi[J] + vj[J]] = e;
+    dE[3 * vj[J] + vi[J]] = e;
+    if (c->have_state) {
+      hfe_status st = hfe_homogenized_stress(c, before[J]);
+      if (st) return st;
+    } else {
+      for (int k = 0; k < 9; ++k) before[J][k] = 0.0;   // a fresh cell is stress free
+    }
+    hfe_status st = hfe_apply_load_step(c, dE);
+    if (st) return st;
+  }
+  hfe_solve_report rep[6];
+  hfe_status st = hfe_solve_batch(ctxs, 6, params, rep);
+  if (st) return st;
+  for (int J = 0; J < 6; ++J) {
+    double after[9];
+    st = hfe_homogenized_stress(ctxs[J], after);
+    if (st) return st;
+    for (int I = 0; I < 6; ++I) {
+      const int k = 3 * vi[I] + vj[I];
+      C[6 * I + J] = (after[k] - before[J][k]) / strain;
+    }
+    if (reports) reports[J] = rep[J];
+  }
+  return HFE_OK;
+}
+
 hfe_status hfe_homogenized_stress(const hfe_ctx* cc, double out[9]) {
   hfe_ctx* c = const_cast<hfe_ctx*>(cc);
   if (!c || !out) return HFE_EINVAL;

@@ -89,6 +89,9 @@ EXPORTS = {
     "hfe_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                                        ctypes.c_void_p]),
+    "hfe_effective_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double,
+                                               ctypes.POINTER(_Params), ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "hfe_apply_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_fft_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_fft_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -178,6 +181,25 @@ def solve_batch(solvers, params=None):
         msgs = "; ".join(lib.hfe_last_error(s.ctx).decode() for s in solvers)
         raise HfeError(st, msgs)
     return [_report(reps[i]) for i in range(n)]
+
+
+def effective_stiffness(solvers, strain=1e-4, params=None):
+    """The 6x6 effective stiffness (Voigt xx, yy, zz, yz, xz, xy, engineering
+    shears) about the current states of six solvers of one cell
+    (hfe_effective_stiffness); returns (C, reports)."""
+    lib = load_library()
+    if len(solvers) != 6:
+        raise ValueError("six solvers, one per unit load case")
+    arr = (ctypes.c_void_p * 6)(*[s.ctx.value for s in solvers])
+    cp = _params(params)
+    C = np.zeros(36)
+    reps = (_Report * 6)()
+    st = lib.hfe_effective_stiffness(arr, float(strain), ctypes.byref(cp),
+                                     C.ctypes.data_as(ctypes.c_void_p), reps)
+    if st != 0:
+        msgs = "; ".join(lib.hfe_last_error(s.ctx).decode() for s in solvers)
+        raise HfeError(st, msgs)
+    return C.reshape(6, 6), [_report(reps[i]) for i in range(6)]
 
 
 class Solver:

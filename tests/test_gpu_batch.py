@@ -104,3 +104,104 @@ def test_batch_of_six_load_cases_matches_single_solves():
         np.testing.assert_array_equal(sb.homogenized_stress(), s.homogenized_stress(), err_msg=str(n))
         np.testing.assert_array_equal(sb.get_state()["u"], s.get_state()["u"], err_msg=str(n))
         s.close()
+
+
+# ---- effective stiffness (six unit load cases as one batch) -------------------
+
+VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+TIGHT = {"eta_eq": 1e-12, "eta_nr": 1e-14, "eta_cg": 1e-10}
+
+
+def _unit_case(J, strain):
+    i, j = VOIGT[J]
+    dE = np.zeros((3, 3))
+    e = strain if i == j else 0.5 * strain
+    dE[i, j] = dE[j, i] = e
+    return dE
+
+
+def _oracle_stiffness(phase, materials, strain, kappa_hist=None):
+    from oracle.solver import CellSolver
+    C = np.zeros((6, 6))
+    for J in range(6):
+        o = CellSolver(phase, materials, "q1")
+        if kappa_hist is not None:
+            o.kappa_hist = kappa_hist.copy()
+        o.apply_load_step(_unit_case(J, strain))
+        assert o.solve_increment(TIGHT)["converged"]
+        S = o.homogenized_stress()
+        C[:, J] = [S[i, j] for i, j in VOIGT]
+    return C / strain
+
+
+def _gpu_stiffness(shape, phase, materials, strain, kappa_hist=None):
+    from paper_2207_10657_amd import Solver, effective_stiffness
+    sv = [Solver(shape, "q1", own_stream=True) for _ in range(6)]
+    for s in sv:
+        s.setup(phase, materials)
+        if kappa_hist is not None:
+            s.set_state(np.zeros((3,) + shape), kappa_hist, np.zeros((3, 3)), 0.0, 0.0)
+    C, reps = effective_stiffness(sv, strain, TIGHT)
+    assert all(r["converged"] for r in reps)
+    for s in sv:
+        s.close()
+    return C
+
+
+def test_effective_stiffness_of_a_laminate():
+    """Backus averages of a layered cell (layers normal to x), exact for the
+    voxel-aligned laminate."""
+    require_gpu()
+    announce("effective stiffness, laminate")
+    from synthetic import laminate_microstructure
+    shape = (8, 8, 16)
+    layers = np.array([0, 0, 1, 1, 1, 0, 1, 0] * 2, dtype=np.uint8)
+    phase = laminate_microstructure(shape, layers)
+    m1 = {"kind": "elastic", "E": 1.0, "nu": 0.3}
+    m2 = {"kind": "elastic", "E": 7.0, "nu": 0.2}
+    C = _gpu_stiffness(shape, phase, [m1, m2], 1e-4)
+    f = np.array([np.mean(layers == 0), np.mean(layers == 1)])
+    lam = np.array([m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"])) for m in (m1, m2)])
+    mu = np.array([m["E"] / (2 * (1 + m["nu"])) for m in (m1, m2)])
+    M = lam + 2 * mu
+    avg = lambda x: float(np.sum(f * x))
+    Cnn = 1.0 / avg(1.0 / M)
+    Cnt = avg(lam / M) * Cnn
+    Ctt = avg(M - lam ** 2 / M) + avg(lam / M) ** 2 * Cnn
+    Ctt2 = avg(lam - lam ** 2 / M) + avg(lam / M) ** 2 * Cnn
+    ref = np.zeros((6, 6))
+    ref[0, 0] = Cnn
+    ref[0, 1] = ref[1, 0] = ref[0, 2] = ref[2, 0] = Cnt
+    ref[1, 1] = ref[2, 2] = Ctt
+    ref[1, 2] = ref[2, 1] = Ctt2
+    ref[3, 3] = avg(mu)                    # yz: shear within the layers
+    ref[4, 4] = ref[5, 5] = 1.0 / avg(1.0 / mu)   # xz, xy: shear across the layers
+    err = np.abs(C - ref).max() / np.abs(ref).max()
+    print("[stiffness] laminate: max |C - Backus| / max|C| = %.2e" % err, flush=True)
+    assert err < 1e-9
+
+
+def test_effective_and_damaged_secant_stiffness_against_oracle():
+    """An inclusion cell (8^3): the initial stiffness, then the secant
+    stiffness of a damaged cell (a frozen history between kappa0 and kappaf:
+    small loads unload) against the oracle's six solves."""
+    require_gpu()
+    announce("effective stiffness vs oracle, 8^3")
+    w = workload("c1_3d16")
+    shape = (8, 8, 8)
+    phase = np.ascontiguousarray(w.phase[:8, :8, :8])
+    C0 = _gpu_stiffness(shape, phase, w.materials, 1e-5)
+    R0 = _oracle_stiffness(phase, w.materials, 1e-5)
+    e0 = np.abs(C0 - R0).max() / np.abs(R0).max()
+    sym = np.abs(C0 - C0.T).max() / np.abs(C0).max()
+    # a damaged history: kappa_hist between kappa0 and kappaf on the matrix points
+    rng = np.random.default_rng(11)
+    k0, kf = w.materials[0]["kappa0"], w.materials[0]["kappaf"]
+    kh = np.where((phase == 0)[..., None], k0 + (kf - k0) * rng.random(shape + (8,)), 0.0)
+    C1 = _gpu_stiffness(shape, phase, w.materials, 1e-6, kh)
+    R1 = _oracle_stiffness(phase, w.materials, 1e-6, kh)
+    e1 = np.abs(C1 - R1).max() / np.abs(R1).max()
+    print("[stiffness] 8^3 inclusion cell: initial vs oracle %.2e (asym %.1e); damaged secant vs "
+          "oracle %.2e; C11 %.4f -> %.4f" % (e0, sym, e1, C0[0, 0], C1[0, 0]), flush=True)
+    assert e0 < 1e-9 and e1 < 1e-9 and sym < 1e-8
+    assert C1[0, 0] < C0[0, 0]

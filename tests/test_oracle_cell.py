@@ -276,3 +276,112 @@ def test_rounding_sensitivity_of_the_method():
         if ok.any():
             drift = max(drift, float(np.max(np.abs(ta[:m][ok] - tb[:m][ok]) / np.abs(ta[:m][ok]))))
     assert drift > 1e-2, drift
+
+
+def _oracle_effective_stiffness(phase, materials, strain, params):
+    """Six unit load cases (Voigt xx, yy, zz, yz, xz, xy; engineering shears)."""
+    voigt = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+    C = np.zeros((6, 6))
+    for J, (i, j) in enumerate(voigt):
+        dE = np.zeros((3, 3))
+        dE[i, j] = dE[j, i] = strain if i == j else 0.5 * strain
+        o = CellSolver(phase, materials, "q1")
+        o.apply_load_step(dE)
+        assert o.solve_increment(params)["converged"]
+        S = o.homogenized_stress()
+        C[:, J] = [S[a, b] for a, b in voigt] 
+    return C / strain
+
+
+def test_oracle_effective_stiffness_laminate_backus_and_symmetry():
+    """The effective stiffness of a voxel laminate (normal x) equals the Backus
+    averages in all 36 entries; that of a random two-phase elastic cell is
+    symmetric positive definite and lies between the Reuss and Voigt bounds."""
+    from synthetic import laminate_microstructure
+    m1 = {"kind": "elastic", "E": 1.0, "nu": 0.3, "kappa0": 0.0, "kappaf": 0.0}
+    m2 = {"kind": "elastic", "E": 7.0, "nu": 0.2, "kappa0": 0.0, "kappaf": 0.0}
+    tight = {"eta_eq": 1e-12, "eta_nr": 1e-14, "eta_cg": 1e-10}
+    layers = np.array([0, 0, 1, 1, 1, 0, 1, 0], dtype=np.uint8)
+    shape = (4, 4, 8)
+    C = _oracle_effective_stiffness(laminate_microstructure(shape, layers), [m1, m2], 1e-4, tight)
+    f = np.array([np.mean(layers == 0), np.mean(layers == 1)])
+    lam = np.array([m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"])) for m in (m1, m2)])
+    mu = np.array([m["E"] / (2 * (1 + m["nu"])) for m in (m1, m2)])
+    M = lam + 2 * mu
+    avg = lambda x: float(np.sum(f * x))
+    Cnn = 1.0 / avg(1.0 / M)
+    ref = np.zeros((6, 6))
+    ref[0, 0] = Cnn
+    ref[0, 1] = ref[1, 0] = ref[0, 2] = ref[2, 0] = avg(lam / M) * Cnn
+    ref[1, 1] = ref[2, 2] = avg(M - lam ** 2 / M) + avg(lam / M) ** 2 * Cnn
+    ref[1, 2] = ref[2, 1] = avg(lam - lam ** 2 / M) + avg(lam / M) ** 2 * Cnn
+    ref[3, 3] = avg(mu)
+    ref[4, 4] = ref[5, 5] = 1.0 / avg(1.0 / mu)
+    assert np.abs(C - ref).max() < 1e-9 * np.abs(ref).max()
+    # random two-phase cell
+    rng = np.random.default_rng(5)
+    phase = (rng.random((4, 4, 4)) < 0.4).astype(np.uint8)
+    C = _oracle_effective_stiffness(phase, [m1, m2], 1e-4, tight)
+    assert np.abs(C - C.T).max() < 1e-10 * np.abs(C).max()
+    ev = np.linalg.eigvalsh(0.5 * (C + C.T))
+    assert ev.min() > 0
+    # Voigt / Reuss bounds on the bulk-like combination e.C.e for e = (1,1,1,0,0,0)
+    def iso(m):
+        l = m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"]))
+        u = m["E"] / (2 * (1 + m["nu"]))
+        return np.array([[l + 2 * u, l, l, 0, 0, 0], [l, l + 2 * u, l, 0, 0, 0],
+                         [l, l, l + 2 * u, 0, 0, 0], [0, 0, 0, u, 0, 0], [0, 0, 0, 0, u, 0],
+                         [0, 0, 0, 0, 0, u]])
+    fv = np.array([np.mean(phase == 0), np.mean(phase == 1)])
+    Cv = fv[0] * iso(m1) + fv[1] * iso(m2)
+    Cr = np.linalg.inv(fv[0] * np.linalg.inv(iso(m1)) + fv[1] * np.linalg.inv(iso(m2)))
+    e = np.array([1.0, 1, 1, 0, 0, 0])
+    assert e @ Cr @ e - 1e-12 <= e @ C @ e <= e @ Cv @ e + 1e-12
+
+
+# ---- eigenstrain (Algorithm 2: eps_eval = eps + eps_eig) -----------------------
+
+def test_oracle_eigenstrain_homogeneous_cell():
+    """Every point carries eps_eig and E = 0: no fluctuation, Sigma = C : eps_eig."""
+    m = {"kind": "elastic", "E": 3.0, "nu": 0.25, "kappa0": 0.0, "kappaf": 0.0}
+    eig = np.array([[1e-3, 2e-4, 0.0], [2e-4, -5e-4, 1e-4], [0.0, 1e-4, 3e-4]])
+    o = CellSolver(np.zeros((4, 4, 4), np.uint8), [m], "q1")
+    o.set_eigenstrain(0, eig)
+    r = o.apply_load_step(np.zeros((3, 3)))
+    assert r < 1e-14
+    lam, mu = 3.0 * 0.25 / (1.25 * 0.5), 3.0 / 2.5
+    ref = lam * np.trace(eig) * np.eye(3) + 2 * mu * eig
+    assert np.abs(o.homogenized_stress() - ref).max() < 1e-15
+
+
+def test_oracle_eigenstrain_laminate_closed_form():
+    """A laminate (normal x) whose phase 1 expands by theta I at E = 0: the
+    in-plane strains vanish in every layer, the normal strains average to
+    zero and carry one normal stress, sigma_xx = <b/M>/<1/M> with
+    b = (3 lam + 2 mu) theta, M = lam + 2 mu; sigma_yy = sigma_zz =
+    <lam eps_xx + b>."""
+    from synthetic import laminate_microstructure
+    m0 = {"kind": "elastic", "E": 1.0, "nu": 0.3, "kappa0": 0.0, "kappaf": 0.0}
+    m1 = {"kind": "elastic", "E": 7.0, "nu": 0.2, "kappa0": 0.0, "kappaf": 0.0}
+    theta = 2e-3
+    layers = np.array([0, 0, 1, 1, 1, 0, 1, 0], dtype=np.uint8)
+    phase = laminate_microstructure((4, 4, 8), layers)
+    o = CellSolver(phase, [m0, m1], "q1")
+    o.set_eigenstrain(1, theta * np.eye(3))
+    o.apply_load_step(np.zeros((3, 3)))
+    res = o.solve_increment({"eta_eq": 1e-12, "eta_nr": 1e-14, "eta_cg": 1e-10})
+    assert res["converged"]
+    assert all(abs(r - 1.0) < 1e-8 for r in res["rho"])        # a linear problem
+    f = np.array([np.mean(layers == 0), np.mean(layers == 1)])
+    lam = np.array([m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"])) for m in (m0, m1)])
+    mu = np.array([m["E"] / (2 * (1 + m["nu"])) for m in (m0, m1)])
+    M = lam + 2 * mu
+    b = (3 * lam + 2 * mu) * np.array([0.0, theta])
+    sxx = np.sum(f * b / M) / np.sum(f / M)
+    exx = (sxx - b) / M
+    syy = np.sum(f * (lam * exx + b))
+    S = o.homogenized_stress()
+    scale = abs(syy)
+    assert abs(S[0, 0] - sxx) < 1e-10 * scale
+    assert abs(S[1, 1] - syy) < 1e-10 * scale and abs(S[2, 2] - syy) < 1e-10 * scale
+    assert np.abs(S - np.diag(np.diag(S))).max() < 1e-10 * scale
