@@ -145,6 +145,16 @@ hfe_status hfe_set_microstructure(hfe_ctx* ctx, const uint8_t* phase, int n_phas
 /* Material of one phase (call once per phase before the first load step). */
 hfe_status hfe_set_material(hfe_ctx* ctx, int phase, const hfe_material* mat);
 
+/* Eigenstrain of a phase (host, 3x3 row-major; its symmetric part is used, in
+ * 2D only the in-plane block). Algorithm 2 adds it to the strain of every
+ * point of the phase before each evaluation of the law (the eps_eval lines),
+ * trial evaluations included. It may change between load steps (a growing
+ * eigenstrain, as for expanding inclusions): the next hfe_apply_load_step
+ * (with dE = 0 for a load by eigenstrain alone) evaluates the state with
+ * it. When the first increment is zero, the default trust radii take the
+ * scale of the largest phase eigenstrain instead of ||dE_1||. */
+hfe_status hfe_set_eigenstrain(hfe_ctx* ctx, int phase, const double eig[9]);
+
 /* Algorithm 2, start of a load increment: E <- E + dE (dE a host 3x3,
  * symmetric; in 2D only the in-plane block is used), keep the fluctuation of
  * the previous step as initial guess, evaluate sigma and B with the history

@@ -1010,6 +1010,7 @@ hfe_status hfe_set_microstructure(hfe_ctx* c, const uint8_t* phase, int n_phases
   destroy_graphs(c);
   c->n_phases = n_phases;
   for (int p = 0; p < hfe::kMaxPhases; ++p) c->mat_set[p] = false;
+  std::memset(c->mat.eig, 0, sizeof(c->mat.eig));
   c->have_micro = true;
   return reset_state(c);
 }
@@ -1036,6 +1037,24 @@ hfe_status hfe_set_material(hfe_ctx* c, int phase, const hfe_material* m) {
   return HFE_OK;
 }
 
+hfe_status hfe_set_eigenstrain(hfe_ctx* c, int phase, const double eig[9]) {
+  if (!c) return HFE_EINVAL;
+  if (!c->have_micro) return fail(c, HFE_ESTATE, "set the microstructure first");
+  if (!eig || phase < 0 || phase >= c->n_phases) return fail(c, HFE_EINVAL, "bad phase or eigenstrain");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(eig[k])) return fail(c, HFE_EINVAL, "non-finite eigenstrain");
+  const int D = c->g.dim;
+  // (xx, yy, zz, xy, xz, yz) of the symmetric part; 2D keeps the in-plane block
+  double v[6] = {eig[0], eig[4], eig[8], 0.5 * (eig[1] + eig[3]), 0.5 * (eig[2] + eig[6]),
+                 0.5 * (eig[5] + eig[7])};
+  if (D == 2) v[2] = v[4] = v[5] = 0.0;
+  hfe_status st = sync(c);
+  if (st) return st;
+  destroy_graphs(c);   // captured kernels hold the material table by value
+  for (int k = 0; k < 6; ++k) c->mat.eig[phase][k] = v[k];
+  return HFE_OK;
+}
+
 hfe_status hfe_apply_load_step(hfe_ctx* c, const double dE[9]) {
   if (!c) return HFE_EINVAL;
   if (!dE) return fail(c, HFE_EINVAL, "dE is NULL");
@@ -1053,6 +1072,15 @@ hfe_status hfe_apply_load_step(hfe_ctx* c, const double dE[9]) {
   if (!c->R_init) {
     double nrm = 0.0;
     for (int k = 0; k < 9; ++k) nrm += inc[k] * inc[k];
+    if (nrm == 0.0) {
+      // a load by eigenstrain alone: the scale of the largest phase eigenstrain
+      for (int p = 0; p < c->n_phases; ++p) {
+        const double* e = c->mat.eig[p];
+        const double n2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2] +
+                          2.0 * (e[3] * e[3] + e[4] * e[4] + e[5] * e[5]);
+        nrm = std::max(nrm, n2);
+      }
+    }
     const double s = std::sqrt((double)c->g.N * c->g.nq) * std::sqrt(nrm);
     c->R0_default = 10.0 * s;
     c->Rmax_default = 1000.0 * s;

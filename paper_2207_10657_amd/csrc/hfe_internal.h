@@ -20,6 +20,7 @@ constexpr int kMaxPartials = 16;   // doubles per block in a partial-sum row
 struct MatTable {
   double lam[kMaxPhases], mu[kMaxPhases], E[kMaxPhases];
   double k0[kMaxPhases], kf[kMaxPhases];
+  double eig[kMaxPhases][6];   // eigenstrain (xx, yy, zz, xy, xz, yz), added before the law
   int damage[kMaxPhases];
 };
 

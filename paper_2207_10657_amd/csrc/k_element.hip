@@ -114,6 +114,16 @@ __device__ __forceinline__ SymT<R> c_contract(const SymT<R>& e, R lam, R mu) {
   return s;
 }
 
+// The strain the law sees: sym(H) plus the phase's eigenstrain (Algorithm 2
+// adds it before every evaluation; in 2D only its in-plane part is set).
+template <int D, typename R>
+__device__ __forceinline__ SymT<R> eval_strain(const R (&H)[3][3], const MatTable& m, int ph) {
+  SymT<R> e = sym_of<D>(H);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) e.v[k] += (R)m.eig[ph][k];
+  return e;
+}
+
 // Norm^2 of the d x d block of a symmetric tensor (the plane-strain zz
 // component is not part of the unknowns' inner product in 2D).
 template <int D>
@@ -296,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
             for (int i = 0; i < 3; ++i)
 #pragma unroll
               for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
-            s = c_contract(sym_of<D>(H), lam, mu);
+            s = c_contract(eval_strain<D>(H, A.mat, ph), lam, mu);
           } else {
 #pragma unroll
             for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
@@ -317,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
-          const Sym eps = sym_of<D>(H);
+          const Sym eps = eval_strain<D>(H, A.mat, ph);
           const double kh = A.khist[q * g.N + ei];
           const PointLaw P = eval_law(eps, lam, mu, Ey, dmg, k0, kf, kh);
 #pragma unroll
@@ -349,12 +359,12 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
           const double kh = A.khist[q * g.N + ei];
-          const PointLaw P = eval_law(sym_of<D>(Ht), lam, mu, Ey, dmg, k0, kf, kh);
+          const PointLaw P = eval_law(eval_strain<D>(Ht, A.mat, ph), lam, mu, Ey, dmg, k0, kf, kh);
 #pragma unroll
           for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
           if (owner) {
             const double ao = A.a[q * g.N + ei], co = A.cp[q * g.N + ei];
-            const Sym so = c_contract(sym_of<D>(H), lam, mu);
+            const Sym so = c_contract(eval_strain<D>(H, A.mat, ph), lam, mu);
             const Sym ps = sym_of<D>(p);
             double sig_p = 0.0;  // sigma_old : p
             {
@@ -427,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) k_commit(ElemArgs A) {
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) H[i][j] += A.E[3 * i + j];
-    const Sym eps = sym_of<D>(H);
+    const Sym eps = eval_strain<D>(H, A.mat, ph);
     const Sym s = c_contract(eps, A.mat.lam[ph], A.mat.mu[ph]);
     const double kt = sqrt(fmax(sym_dot(eps, s), 0.0) / A.mat.E[ph]);
     const long long idx = q * g.N + n;
@@ -467,7 +477,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
       for (int i = 0; i < D; ++i)
         for (int j = 0; j < D; ++j) out_h[base + i * D + j] = H[i][j];
     if (out_s) {
-      const Sym eps = sym_of<D>(H);
+      const Sym eps = eval_strain<D>(H, A.mat, ph);
       const double kh = A.khist[q * g.N + n];
       const PointLaw P = eval_law(eps, A.mat.lam[ph], A.mat.mu[ph], A.mat.E[ph],
                                   A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh);
@@ -755,7 +765,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
           for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
         tile_grad(su, q, t0, sy, sz, H);
         const double kh = A.khist[q * g.N + eg];
-        const PointLaw P = eval_law(sym_of<3>(H), lam, mu, A.mat.E[ph], A.mat.damage[ph],
+        const PointLaw P = eval_law(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
                                     A.mat.k0[ph], A.mat.kf[ph], kh);
 #pragma unroll
         for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
@@ -875,14 +885,14 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
       const double kh = A.khist[q * g.N + eg];
-      const PointLaw P = eval_law(sym_of<3>(Ht), lam, mu, A.mat.E[ph], A.mat.damage[ph],
+      const PointLaw P = eval_law(eval_strain<3>(Ht, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
                                   A.mat.k0[ph], A.mat.kf[ph], kh);
       Sym tau;
 #pragma unroll
       for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
       const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
       const Sym ps = sym_of<3>(p);
-      const Sym so = c_contract(sym_of<3>(H), lam, mu);
+      const Sym so = c_contract(eval_strain<3>(H, A.mat, ph), lam, mu);
       const double s_p = sym_dot(so, ps);
       const double trp = ps.v[0] + ps.v[1] + ps.v[2];
       const double pCp = lam * trp * trp + 2.0 * mu * sym_dot(ps, ps);
@@ -1031,7 +1041,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
 #pragma unroll
           for (int j = 0; j < 3; ++j) H[i][j] = (R)A.E[3 * i + j];
         tile_grad<kTile>(su, q, t0, sy, sz, H);
-        s = c_contract(sym_of<3>(H), lam, mu);
+        s = c_contract(eval_strain<3>(H, A.mat, ph), lam, mu);
       }
       const SymT<R> tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
       if (owned) {

@@ -87,6 +87,7 @@ EXPORTS = {
     "hfe_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "hfe_set_eigenstrain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "hfe_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                                        ctypes.c_void_p]),
     "hfe_effective_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double,
@@ -277,6 +278,14 @@ class Solver:
         self.set_microstructure(phase, len(materials))
         for p, m in enumerate(materials):
             self.set_material(p, m)
+            if m.get("eig") is not None:
+                self.set_eigenstrain(p, m["eig"])
+
+    def set_eigenstrain(self, phase, eig):
+        """Eigenstrain of a phase (3x3), added to the strain before the law."""
+        a = np.ascontiguousarray(np.asarray(eig, dtype=np.float64).reshape(3, 3))
+        self._check(self.lib.hfe_set_eigenstrain(self.ctx, int(phase),
+                                                 a.ctypes.data_as(ctypes.c_void_p)))
 
     # -- Algorithm 2 -----------------------------------------------------
     def apply_load_step(self, dE):

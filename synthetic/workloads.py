@@ -38,6 +38,8 @@ class Workload:
     materials: list       # indexed by phase id
     load_path: np.ndarray  # (steps, 3, 3)
     info: dict = field(default_factory=dict)
+    eig_phase: int = -1          # phase whose eigenstrain grows along the path (or -1)
+    eig_path: np.ndarray = None  # (steps, 3, 3): that phase's eigenstrain at each step
 
     @property
     def nvox(self):
@@ -58,8 +60,34 @@ def workload(name, steps=None):
     ``c1_3dN``    (N in 8..128) the same recipe on an N^3 grid with radii
                   scaled by N/64 (small parity and large bandwidth cases),
                   seed 3 for N=128, else seed 1.
+    ``gel_3dN``   the c1_3dN cell with expanding sites: the inclusion voxels
+                  whose centres lie within half a radius (at least one voxel
+                  diagonal) of an inclusion centre form an elastic phase 2
+                  whose isotropic eigenstrain grows by 2.5e-4 per step, at zero
+                  macroscopic strain (20 steps).
     ``steps`` truncates the load path (the increment size is kept).
     """
+    if name.startswith("gel_3d"):
+        n = int(name[len("gel_3d"):])
+        base = workload("c1_3d%d" % n)
+        shape = np.array(base.shape[::-1], dtype=np.float64)          # (nx, ny, nz)
+        grid = np.stack(np.meshgrid(*[np.arange(k) + 0.5 for k in base.shape[::-1]],
+                                    indexing="ij"), axis=-1)           # voxel centres (x, y, z)
+        core = np.zeros(base.shape[::-1], dtype=bool)
+        for centre, r in base.info["inclusions"]:
+            d = grid - np.asarray(centre, dtype=np.float64)
+            d -= shape * np.round(d / shape)                          # minimum image
+            core |= np.sqrt(np.sum(d * d, axis=-1)) <= max(0.5 * r, 0.87)
+        core = core.transpose(2, 1, 0) & (base.phase == 1)            # back to (z, y, x)
+        phase = base.phase.copy()
+        phase[core] = 2
+        nsteps = 20 if steps is None else steps
+        eig = np.array([(k + 1) * 2.5e-4 * np.eye(3) for k in range(nsteps)])
+        gel = dict(INCLUSION_ELASTIC)
+        return Workload(name=name, dim=3, shape=base.shape, element="q1", phase=phase,
+                        materials=[dict(MATRIX_DAMAGE), dict(INCLUSION_ELASTIC), gel],
+                        load_path=np.zeros((nsteps, 3, 3)), info=dict(base.info, gel_voxels=int(core.sum())),
+                        eig_phase=2, eig_path=eig)
     if name == "c0_2d32":
         shape, (rmin, rmax), vf, seed = (32, 32), (3.0, 5.0), 0.3, 0
         total, nsteps, element = 5e-3, 20, "p1pair"
