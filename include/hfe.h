@@ -286,6 +286,49 @@ hfe_status hfe_kernel_stats(hfe_ctx* ctx, const char** names, int* counts, doubl
 /* Text of the last error on this context (never NULL). */
 const char* hfe_last_error(const hfe_ctx* ctx);
 
+/* ---- learned warm start (BF16 3D convolutions and their training) ----------
+ *
+ * A small convolutional network on the periodic voxel grid predicts the
+ * displacement increment of a load step from the cell's state; the solve
+ * then starts from it (the initial guess of Algorithm 2's load loop) and
+ * refines it to the same tolerance. These entry points are its building
+ * blocks. Fields are device arrays, channels-major [C][nz][ny][nx] (x
+ * fastest), n = {nx, ny, nz}; filter banks [cout][cin][27] with tap
+ * (dz+1)*9 + (dy+1)*3 + (dx+1); the grid is periodic. BF16 values are
+ * uint16_t (the upper half of an IEEE binary32, round to nearest even).
+ * Channel counts: 1, 2, 3, 4, 6, 8 or 16. `stream` is a hipStream_t (NULL:
+ * the default stream); the calls are asynchronous on it. HFE_EINVAL for bad
+ * arguments, HFE_EDEVICE if a launch fails. */
+
+/* out = conv(in; w) + bias (bias may be NULL), ReLU if relu != 0; FP32 out,
+ * and its BF16 copy in out_bf16 when not NULL. Products accumulate in FP32. */
+hfe_status hfe_nn_conv3d(const uint16_t* in, int cin, const uint16_t* w, const float* bias,
+                         int cout, const int n[3], int relu, float* out, uint16_t* out_bf16,
+                         void* stream);
+/* gin = the adjoint convolution of gout (masked by act > 0 when act, the
+ * layer's ReLU output, is not NULL): the gradient with respect to the input. */
+hfe_status hfe_nn_conv3d_backward_data(const float* gout, int cout, const float* act,
+                                       const uint16_t* w, int cin, const int n[3], float* gin,
+                                       void* stream);
+/* Weight and bias gradients (gb may be NULL) of the layer, with the same
+ * masking; sums over all voxels in FP64 in a fixed order. */
+hfe_status hfe_nn_conv3d_backward_weights(const float* gout, int cout, const float* act,
+                                          const uint16_t* in, int cin, const int n[3], float* gw,
+                                          float* gb, void* stream);
+/* Mean squared error over n values: grad = 2 (pred - target) / n, *loss
+ * (device) = mean (pred - target)^2; partials: device scratch of
+ * hfe_nn_mse_partials(n) doubles. */
+size_t hfe_nn_mse_partials(long long n);
+hfe_status hfe_nn_mse(const float* pred, const float* target, long long n, float* grad,
+                      double* partials, double* loss, void* stream);
+/* One Adam step (step = 1, 2, ...) on FP32 master weights w with moments m,
+ * v; writes the BF16 copy when w_bf16 is not NULL. */
+hfe_status hfe_nn_adam(float* w, float* m, float* v, const float* g, long long n, float lr,
+                       float beta1, float beta2, float eps, int step, uint16_t* w_bf16,
+                       void* stream);
+/* y = BF16(x). */
+hfe_status hfe_nn_to_bf16(const float* x, long long n, uint16_t* y, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

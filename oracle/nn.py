@@ -1,0 +1,73 @@
+"""Periodic 3x3x3 convolutions, their adjoints and Adam (oracle for the
+warm-start network kernels).
+
+TEST INFRASTRUCTURE ONLY: imported by tests and never by the library.
+
+Fields are (C, nz, ny, nx); a filter bank is (cout, cin, 27) with tap
+t = (dz+1)*9 + (dy+1)*3 + (dx+1), and out[co](v) = b[co] +
+sum_{ci,t} w[co, ci, t] in[ci](v + (dz, dy, dx)), indices periodic. FP64.
+
+Pinned by (``tests/test_oracle_nn.py``): explicit index loops on a tiny grid
+(the tap convention), the adjoint identity <conv x, y> = <x, conv^T y>, the
+weight gradient against finite differences of the (linear) map, and Adam's
+bias correction (a constant gradient gives m_hat = g at every step).
+"""
+import numpy as np
+
+TAPS = [(t // 9 - 1, (t // 3) % 3 - 1, t % 3 - 1) for t in range(27)]
+
+
+def _shift(x, off):
+    """y(v) = x(v + off), periodic, for x of shape (..., nz, ny, nx)."""
+    dz, dy, dx = off
+    return np.roll(x, shift=(-dz, -dy, -dx), axis=(-3, -2, -1))
+
+
+def conv3d(x, w, b=None):
+    cout = w.shape[0]
+    out = np.zeros((cout,) + x.shape[1:])
+    for t, off in enumerate(TAPS):
+        xs = _shift(x, off)
+        out += np.einsum("oc,c...->o...", w[:, :, t], xs)
+    if b is not None:
+        out += np.asarray(b)[:, None, None, None]
+    return out
+
+
+def conv3d_backward_data(g, w):
+    """The adjoint of conv3d (without bias) applied to g."""
+    cin = w.shape[1]
+    out = np.zeros((cin,) + g.shape[1:])
+    for t, (dz, dy, dx) in enumerate(TAPS):
+        gs = _shift(g, (-dz, -dy, -dx))
+        out += np.einsum("oc,o...->c...", w[:, :, t], gs)
+    return out
+
+
+def conv3d_backward_weights(g, x):
+    """d<g, conv3d(x; w)>/dw (cout, cin, 27) and d/db (cout,)."""
+    gw = np.zeros((g.shape[0], x.shape[0], 27))
+    for t, off in enumerate(TAPS):
+        xs = _shift(x, off)
+        gw[:, :, t] = np.einsum("ozyx,czyx->oc", g, xs)
+    return gw, g.sum(axis=(1, 2, 3))
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def adam(w, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba): returns (w, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def bf16_round(x):
+    """Round to BF16 (the upper 16 bits of binary32, ties to even), as float64."""
+    a = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) >> 16 << 16
+    return (a.astype(np.uint32)).view(np.float32).astype(np.float64)

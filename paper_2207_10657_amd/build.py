@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfe.so")
-SOURCES = ["k_element.hip", "k_fft.hip", "k_vec.hip", "hfe_host.cpp"]
+SOURCES = ["k_element.hip", "k_fft.hip", "k_vec.hip", "k_nn.hip", "hfe_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

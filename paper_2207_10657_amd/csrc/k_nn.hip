@@ -1,0 +1,335 @@
+// Kernels of the learned warm start: a small 3D convolutional network on the
+// periodic voxel grid that predicts the displacement increment of a load
+// step from the cell's state, with its training. Activations and weights are
+// stored in BF16; the convolutions accumulate their products in FP32, the
+// weight-gradient sums over all voxels in FP64; gradients and the Adam
+// moments are FP32 (master weights in FP32, a BF16 copy for the forward
+// passes).
+//
+// Layout: fields are channels-major [C][nz][ny][nx], x fastest; a 3x3x3
+// filter bank is [cout][cin][27] with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1);
+// the grid is periodic (the cell is), so every tap wraps.
+//
+// All reductions (weight gradients, the loss) add per-block partial sums in
+// a fixed order, so training runs give the same bits every time.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "hfe_internal.h"
+#include "hfe_reduce.h"
+
+namespace hfe {
+namespace {
+
+// BF16 = the upper 16 bits of an IEEE binary32 value; conversion rounds to
+// nearest, ties to even (NaN stays NaN).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int kNnBlock = 256;
+
+__device__ __forceinline__ int wrapi(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+// out[co][v] = b[co] + sum_{ci, t} w[co][ci][t] in[ci][v + off(t)]; optional
+// ReLU; FP32 result (and a BF16 copy when out16 is set). Weights of the
+// block in LDS as FP32.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(kNnBlock) k_conv_fwd(const uint16_t* __restrict__ in,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias,
+                                                      int nx, int ny, int nz, int relu,
+                                                      float* __restrict__ out,
+                                                      uint16_t* __restrict__ out16) {
+  constexpr int cin = CIN, cout = COUT;
+  __shared__ float sw[COUT * CIN * 27];   // [cout][cin][27]
+  constexpr int nw = cout * cin * 27;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) sw[i] = from_bf16(w[i]);
+  __syncthreads();
+  const long long N = (long long)nx * ny * nz;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+  float acc[COUT];
+#pragma unroll
+  for (int co = 0; co < cout; ++co) acc[co] = bias ? bias[co] : 0.f;
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const long long u = (long long)wrapi(x + dx, nx) +
+                        (long long)nx * (wrapi(y + dy, ny) + (long long)ny * wrapi(z + dz, nz));
+#pragma unroll
+    for (int ci = 0; ci < cin; ++ci) {
+      const float a = from_bf16(in[(long long)ci * N + u]);
+#pragma unroll
+      for (int co = 0; co < cout; ++co) acc[co] += sw[(co * cin + ci) * 27 + t] * a;
+    }
+  }
+#pragma unroll
+  for (int co = 0; co < cout; ++co) {
+    float r = acc[co];
+    if (relu) r = fmaxf(r, 0.f);
+    out[(long long)co * N + v] = r;
+    if (out16) out16[(long long)co * N + v] = to_bf16(r);
+  }
+}
+
+// gin[ci][v] = sum_{co, t} w[co][ci][t] g[co][v - off(t)] (the adjoint of the
+// convolution), g masked by (act > 0) when act is set (ReLU backward).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(kNnBlock) k_conv_bwd_data(const float* __restrict__ g,
+                                                           const float* __restrict__ act,
+                                                           const uint16_t* __restrict__ w,
+                                                           int nx, int ny, int nz,
+                                                           float* __restrict__ gin) {
+  constexpr int cin = CIN, cout = COUT;
+  __shared__ float sw[COUT * CIN * 27];
+  constexpr int nw = cout * cin * 27;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) sw[i] = from_bf16(w[i]);
+  __syncthreads();
+  const long long N = (long long)nx * ny * nz;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+  float acc[CIN];
+#pragma unroll
+  for (int ci = 0; ci < cin; ++ci) acc[ci] = 0.f;
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const long long u = (long long)wrapi(x - dx, nx) +
+                        (long long)nx * (wrapi(y - dy, ny) + (long long)ny * wrapi(z - dz, nz));
+#pragma unroll
+    for (int co = 0; co < cout; ++co) {
+      float gg = g[(long long)co * N + u];
+      if (act && !(act[(long long)co * N + u] > 0.f)) gg = 0.f;
+#pragma unroll
+      for (int ci = 0; ci < cin; ++ci) acc[ci] += sw[(co * cin + ci) * 27 + t] * gg;
+    }
+  }
+#pragma unroll
+  for (int ci = 0; ci < cin; ++ci) gin[(long long)ci * N + v] = acc[ci];
+}
+
+// One block per (co, ci): rows of partial sums over voxels for the 27 taps,
+// gw[co][ci][t] = sum_v gm[co][v] in[ci][v + off(t)], and (ci == 0) the bias
+// gradient sum_v gm[co][v]; gm = g masked by (act > 0) when act is set.
+__global__ void __launch_bounds__(kNnBlock) k_conv_bwd_w(const float* __restrict__ g, int cout,
+                                                        const float* __restrict__ act,
+                                                        const uint16_t* __restrict__ in, int cin,
+                                                        int nx, int ny, int nz,
+                                                        float* __restrict__ gw,
+                                                        float* __restrict__ gb) {
+  const int co = blockIdx.x / cin, ci = blockIdx.x % cin;
+  const long long N = (long long)nx * ny * nz;
+  double acc[28];
+#pragma unroll
+  for (int t = 0; t < 28; ++t) acc[t] = 0.0;
+  for (long long v = threadIdx.x; v < N; v += blockDim.x) {
+    float gg = g[(long long)co * N + v];
+    if (act && !(act[(long long)co * N + v] > 0.f)) gg = 0.f;
+    if (gg == 0.f) continue;
+    const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      const long long u = (long long)wrapi(x + dx, nx) +
+                          (long long)nx * (wrapi(y + dy, ny) + (long long)ny * wrapi(z + dz, nz));
+      acc[t] += (double)(gg * from_bf16(in[(long long)ci * N + u]));
+    }
+    acc[27] += (double)gg;
+  }
+  // fixed-order block reduction of the 28 sums
+  __shared__ double red[kNnBlock / 64][28];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 28; ++t) {
+    const double s = wave_sum(acc[t]);
+    if (lane == 0) red[wave][t] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    double s = 0.0;
+    for (int wv = 0; wv < kNnBlock / 64; ++wv) s += red[wv][threadIdx.x];
+    if (threadIdx.x < 27) gw[(co * cin + ci) * 27 + threadIdx.x] = (float)s;
+    else if (ci == 0 && gb) gb[co] = (float)s;
+  }
+}
+
+// grad = 2 (pred - target) / n, rows of partial sums of (pred - target)^2
+__global__ void __launch_bounds__(kNnBlock) k_mse(const float* __restrict__ pred,
+                                                 const float* __restrict__ target, long long n,
+                                                 float* __restrict__ grad, double* partials) {
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float d = pred[i] - target[i];
+    grad[i] = 2.f * d / (float)n;
+    acc[0] += (double)d * (double)d;
+  }
+  block_reduce_store<1>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kNnBlock) k_sum_rows(const double* __restrict__ partials, int nb,
+                                                      long long n, double* out) {
+  double t[1];
+  block_sum_rows<1>(partials, nb, t);
+  if (threadIdx.x == 0) *out = t[0] / (double)n;
+}
+
+// Adam on FP32 master weights; the BF16 copy for the forward passes.
+__global__ void __launch_bounds__(kNnBlock) k_adam(float* __restrict__ w, float* __restrict__ m,
+                                                  float* __restrict__ v,
+                                                  const float* __restrict__ g, long long n,
+                                                  float lr, float b1, float b2, float eps,
+                                                  float c1, float c2, uint16_t* __restrict__ w16) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (w16) w16[i] = to_bf16(wi);
+  }
+}
+
+__global__ void __launch_bounds__(kNnBlock) k_to_bf16(const float* __restrict__ x, long long n,
+                                                     uint16_t* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = to_bf16(x[i]);
+}
+
+// The channel counts the kernels are built for.
+#define HFE_NN_CHANNELS(X) X(1) X(2) X(3) X(4) X(6) X(8) X(16)
+
+template <int CIN>
+hipError_t conv_fwd_cin(int cout, const uint16_t* in, const uint16_t* w, const float* bias,
+                        const int n[3], int relu, float* out, uint16_t* out16, hipStream_t s) {
+  const long long N = (long long)n[0] * n[1] * n[2];
+  const dim3 grid((unsigned)((N + kNnBlock - 1) / kNnBlock));
+  switch (cout) {
+#define HFE_NN_FWD(C)                                                                          \
+    case C:                                                                                    \
+      hipLaunchKernelGGL((k_conv_fwd<CIN, C>), grid, dim3(kNnBlock), 0, s, in, w, bias, n[0], \
+                         n[1], n[2], relu, out, out16);                                        \
+      return hipGetLastError();
+    HFE_NN_CHANNELS(HFE_NN_FWD)
+#undef HFE_NN_FWD
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int CIN>
+hipError_t conv_bwd_data_cin(int cout, const float* g, const float* act, const uint16_t* w,
+                             const int n[3], float* gin, hipStream_t s) {
+  const long long N = (long long)n[0] * n[1] * n[2];
+  const dim3 grid((unsigned)((N + kNnBlock - 1) / kNnBlock));
+  switch (cout) {
+#define HFE_NN_BWD(C)                                                                          \
+    case C:                                                                                    \
+      hipLaunchKernelGGL((k_conv_bwd_data<CIN, C>), grid, dim3(kNnBlock), 0, s, g, act, w,    \
+                         n[0], n[1], n[2], gin);                                               \
+      return hipGetLastError();
+    HFE_NN_CHANNELS(HFE_NN_BWD)
+#undef HFE_NN_BWD
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int grid_1d(long long n) {
+  long long b = (n + kNnBlock - 1) / kNnBlock;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+bool dims_ok(const int n[3]) { return n && n[0] >= 1 && n[1] >= 1 && n[2] >= 1; }
+
+}  // namespace
+}  // namespace hfe
+
+using namespace hfe;
+
+extern "C" {
+
+static bool channels_ok(int c) {
+  return c == 1 || c == 2 || c == 3 || c == 4 || c == 6 || c == 8 || c == 16;
+}
+
+hfe_status hfe_nn_conv3d(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout,
+                         const int n[3], int relu, float* out, uint16_t* out_bf16, void* stream) {
+  if (!in || !w || !out || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
+    return HFE_EINVAL;
+  hipError_t e = hipErrorInvalidValue;
+  switch (cin) {
+#define HFE_NN_CIN(C)                                                                          \
+    case C:                                                                                    \
+      e = conv_fwd_cin<C>(cout, in, w, bias, n, relu, out, out_bf16, (hipStream_t)stream);    \
+      break;
+    HFE_NN_CHANNELS(HFE_NN_CIN)
+#undef HFE_NN_CIN
+  }
+  return e == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_conv3d_backward_data(const float* gout, int cout, const float* act,
+                                       const uint16_t* w, int cin, const int n[3], float* gin,
+                                       void* stream) {
+  if (!gout || !w || !gin || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
+    return HFE_EINVAL;
+  hipError_t e = hipErrorInvalidValue;
+  switch (cin) {
+#define HFE_NN_CIN(C)                                                                          \
+    case C:                                                                                    \
+      e = conv_bwd_data_cin<C>(cout, gout, act, w, n, gin, (hipStream_t)stream);              \
+      break;
+    HFE_NN_CHANNELS(HFE_NN_CIN)
+#undef HFE_NN_CIN
+  }
+  return e == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_conv3d_backward_weights(const float* gout, int cout, const float* act,
+                                          const uint16_t* in, int cin, const int n[3], float* gw,
+                                          float* gb, void* stream) {
+  if (!gout || !in || !gw || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
+    return HFE_EINVAL;
+  hipLaunchKernelGGL(k_conv_bwd_w, dim3(cout * cin), dim3(kNnBlock), 0, (hipStream_t)stream, gout,
+                     cout, act, in, cin, n[0], n[1], n[2], gw, gb);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+size_t hfe_nn_mse_partials(long long n) { return (size_t)grid_1d(n); }
+
+hfe_status hfe_nn_mse(const float* pred, const float* target, long long n, float* grad,
+                      double* partials, double* loss, void* stream) {
+  if (!pred || !target || !grad || !partials || !loss || n < 1) return HFE_EINVAL;
+  const int nb = grid_1d(n);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kNnBlock), 0, (hipStream_t)stream, pred, target, n, grad,
+                     partials);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kNnBlock), 0, (hipStream_t)stream, partials, nb, n,
+                     loss);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_adam(float* w, float* m, float* v, const float* g, long long n, float lr,
+                       float beta1, float beta2, float eps, int step, uint16_t* w_bf16,
+                       void* stream) {
+  if (!w || !m || !v || !g || n < 1 || step < 1) return HFE_EINVAL;
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_1d(n)), dim3(kNnBlock), 0, (hipStream_t)stream, w, m, v, g,
+                     n, lr, beta1, beta2, eps, c1, c2, w_bf16);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_to_bf16(const float* x, long long n, uint16_t* y, void* stream) {
+  if (!x || !y || n < 1) return HFE_EINVAL;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_1d(n)), dim3(kNnBlock), 0, (hipStream_t)stream, x, n, y);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+}  // extern "C"

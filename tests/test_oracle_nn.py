@@ -1,0 +1,67 @@
+"""Pins of the convolution oracle used to check the warm-start kernels."""
+import numpy as np
+
+from oracle import nn
+
+
+def test_tap_convention_against_index_loops():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 3, 4, 5))
+    w = rng.normal(size=(3, 2, 27))
+    b = rng.normal(size=3)
+    out = nn.conv3d(x, w, b)
+    nz, ny, nx = x.shape[1:]
+    ref = np.zeros_like(out)
+    for co in range(3):
+        for z in range(nz):
+            for y in range(ny):
+                for xx in range(nx):
+                    s = b[co]
+                    for ci in range(2):
+                        for dz in (-1, 0, 1):
+                            for dy in (-1, 0, 1):
+                                for dx in (-1, 0, 1):
+                                    t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+                                    s += w[co, ci, t] * x[ci, (z + dz) % nz, (y + dy) % ny,
+                                                          (xx + dx) % nx]
+                    ref[co, z, y, xx] = s
+    assert np.abs(out - ref).max() < 1e-12
+
+
+def test_adjoint_identity_and_weight_gradient():
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(3, 4, 5, 6))
+    y = rng.normal(size=(2, 4, 5, 6))
+    w = rng.normal(size=(2, 3, 27))
+    lhs = np.sum(nn.conv3d(x, w) * y)
+    rhs = np.sum(x * nn.conv3d_backward_data(y, w))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    gw, gb = nn.conv3d_backward_weights(y, x)
+    # the map w -> <y, conv(x; w)> is linear: the gradient entry is the value
+    # at the unit weight
+    for (co, ci, t) in [(0, 0, 0), (1, 2, 13), (0, 1, 26)]:
+        e = np.zeros_like(w)
+        e[co, ci, t] = 1.0
+        assert abs(np.sum(y * nn.conv3d(x, e)) - gw[co, ci, t]) < 1e-10
+    assert np.allclose(gb, y.sum(axis=(1, 2, 3)))
+
+
+def test_adam_bias_correction_with_a_constant_gradient():
+    w = np.array([1.0, -2.0])
+    g = np.array([0.5, -0.25])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for step in range(1, 6):
+        w_new, m, v = nn.adam(w, m, v, g, step, lr=0.1)
+        # m_hat = g and v_hat = g^2 exactly: the step is lr * sign(g) (up to eps)
+        assert np.allclose(w - w_new, 0.1 * np.sign(g), rtol=1e-6)
+        w = w_new
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -3.14159])
+    r = nn.bf16_round(x)
+    assert r[0] == 1.0 and r[1] == 1.0          # tie to even
+    assert r[2] == 1.0 + 2 ** -7
+    assert r[3] == 1.0 + 2 ** -6                # tie to even (up)
+    assert abs(r[4] + 3.140625) < 1e-12
