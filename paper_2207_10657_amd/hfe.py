@@ -88,6 +88,30 @@ EXPORTS = {
     "hfe_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_set_eigenstrain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    # learned warm start (paper_2207_10657_amd.warmstart)
+    "hfe_nn_conv3d": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "hfe_nn_conv3d_backward_data": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
+    "hfe_nn_conv3d_backward_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                                      ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                      ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_void_p]),
+    "hfe_nn_mse_partials": (ctypes.c_size_t, [ctypes.c_longlong]),
+    "hfe_nn_mse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+    "hfe_nn_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_longlong, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_nn_to_bf16": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
     "hfe_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                                        ctypes.c_void_p]),
     "hfe_effective_stiffness": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double,

@@ -1,0 +1,184 @@
+"""Learned warm start of a load increment.
+
+Algorithm 2 starts each load increment from the previous fluctuation. Here a
+small 3D convolutional network (periodic 3x3x3 convolutions, BF16
+activations and weights, FP32 accumulation; the kernels are the hfe_nn_*
+entry points of libhfe.so) predicts the increment of the fluctuation from the
+cell's state, and the solve starts from the prediction instead; the solver
+then refines it to the same tolerance, so the result does not depend on the
+guess beyond the solver's own tolerance (and, for the damage law, which of
+several equilibria is reached).
+
+Inputs per voxel (6 channels): the two phase indicators, the committed damage
+(mean over the points of the voxel) and the previous increment of the
+fluctuation, scaled by 1 / (||dE|| n) for a cell of n voxels per side. The
+network predicts a correction to that previous increment (the last layer
+starts at zero, so an untrained network repeats the previous increment: the
+linear-extrapolation guess). Only the target of converged increments is used
+for training.
+
+This module only arranges data and calls the kernels; every convolution, its
+gradients and the optimiser run in the HIP kernels.
+"""
+import ctypes
+
+import numpy as np
+
+from .hfe import HfeError, load_library
+
+CHANNELS = (6, 16, 16, 3)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class ConvNet:
+    """Layers conv(6->16)+ReLU, conv(16->16)+ReLU, conv(16->3) on a periodic grid."""
+
+    def __init__(self, channels=CHANNELS, seed=0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.channels = tuple(channels)
+        rng = np.random.default_rng(seed)
+        self.w, self.b, self.w16 = [], [], []
+        self.mw, self.vw, self.mb, self.vb = [], [], [], []
+        L = len(channels) - 1
+        for l in range(L):
+            cin, cout = channels[l], channels[l + 1]
+            std = np.sqrt(2.0 / (27 * cin))
+            w = rng.normal(scale=std, size=(cout, cin, 27)) if l < L - 1 else np.zeros((cout, cin, 27))
+            self.w.append(torch.tensor(w, dtype=torch.float32, device=self.device))
+            self.b.append(torch.zeros(cout, dtype=torch.float32, device=self.device))
+            self.w16.append(torch.empty(w.size, dtype=torch.int16, device=self.device))
+            for lst, ref in ((self.mw, self.w[-1]), (self.vw, self.w[-1]), (self.mb, self.b[-1]),
+                             (self.vb, self.b[-1])):
+                lst.append(torch.zeros_like(ref))
+            self._check(self.lib.hfe_nn_to_bf16(_ptr(self.w[-1]), self.w[-1].numel(),
+                                                _ptr(self.w16[-1]), self._stream()))
+        self.step = 0
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    @staticmethod
+    def _check(st):
+        if st != 0:
+            raise HfeError(st, "warm-start kernel call failed")
+
+    def to_bf16(self, x32):
+        y = self.torch.empty(x32.shape, dtype=self.torch.int16, device=self.device)
+        self._check(self.lib.hfe_nn_to_bf16(_ptr(x32), x32.numel(), _ptr(y), self._stream()))
+        return y
+
+    def forward(self, x16, shape):
+        """x16: BF16 input (cin, nz, ny, nx) as int16; returns the FP32 output
+        and the activations kept for the backward pass."""
+        torch = self.torch
+        n = (ctypes.c_int * 3)(shape[2], shape[1], shape[0])
+        acts = []
+        h16 = x16
+        L = len(self.w)
+        for l in range(L):
+            cin, cout = self.channels[l], self.channels[l + 1]
+            out = torch.empty((cout,) + tuple(shape), dtype=torch.float32, device=self.device)
+            out16 = torch.empty((cout,) + tuple(shape), dtype=torch.int16, device=self.device)
+            relu = 1 if l < L - 1 else 0
+            self._check(self.lib.hfe_nn_conv3d(_ptr(h16), cin, _ptr(self.w16[l]), _ptr(self.b[l]),
+                                               cout, n, relu, _ptr(out), _ptr(out16),
+                                               self._stream()))
+            acts.append((h16, out if relu else None))
+            h16 = out16
+        return out, acts
+
+    def train_step(self, x16, target, shape, lr=1e-3):
+        """One Adam step on the mean squared error; returns the loss (host)."""
+        torch = self.torch
+        pred, acts = self.forward(x16, shape)
+        n = (ctypes.c_int * 3)(shape[2], shape[1], shape[0])
+        N = pred.numel()
+        grad = torch.empty_like(pred)
+        partials = torch.empty(int(self.lib.hfe_nn_mse_partials(N)), dtype=torch.float64,
+                               device=self.device)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.hfe_nn_mse(_ptr(pred), _ptr(target), N, _ptr(grad), _ptr(partials),
+                                        _ptr(loss), self._stream()))
+        grads = []
+        for l in reversed(range(len(self.w))):
+            cin, cout = self.channels[l], self.channels[l + 1]
+            in16, act = acts[l]
+            act_p = _ptr(act) if act is not None else None
+            gw = torch.empty_like(self.w[l])
+            gb = torch.empty_like(self.b[l])
+            self._check(self.lib.hfe_nn_conv3d_backward_weights(
+                _ptr(grad), cout, act_p, _ptr(in16), cin, n, _ptr(gw), _ptr(gb), self._stream()))
+            grads.append((l, gw, gb))
+            if l > 0:
+                gin = torch.empty((cin,) + tuple(shape), dtype=torch.float32, device=self.device)
+                self._check(self.lib.hfe_nn_conv3d_backward_data(
+                    _ptr(grad), cout, act_p, _ptr(self.w16[l]), cin, n, _ptr(gin), self._stream()))
+                grad = gin
+        self.step += 1
+        for l, gw, gb in grads:
+            self._check(self.lib.hfe_nn_adam(_ptr(self.w[l]), _ptr(self.mw[l]), _ptr(self.vw[l]),
+                                             _ptr(gw), gw.numel(), lr, 0.9, 0.999, 1e-8, self.step,
+                                             _ptr(self.w16[l]), self._stream()))
+            self._check(self.lib.hfe_nn_adam(_ptr(self.b[l]), _ptr(self.mb[l]), _ptr(self.vb[l]),
+                                             _ptr(gb), gb.numel(), lr, 0.9, 0.999, 1e-8, self.step,
+                                             None, self._stream()))
+        return float(loss.item())
+
+    def predict(self, x16, shape):
+        out, _ = self.forward(x16, shape)
+        return out
+
+
+def features(phase, damage, du_prev, scale):
+    """The 6 input channels (numpy float32, (6, nz, ny, nx)).
+
+    phase (nz, ny, nx) with 0 = matrix, 1 = inclusion; damage (nz, ny, nx, nq)
+    committed damage; du_prev (3, nz, ny, nx) the previous increment of the
+    fluctuation; scale = ||dE|| n."""
+    f = np.empty((6,) + phase.shape, dtype=np.float32)
+    f[0] = phase == 0
+    f[1] = phase == 1
+    f[2] = damage.mean(axis=-1)
+    f[3:6] = du_prev / scale
+    return f
+
+
+class WarmStart:
+    """Training data from solves, training, and the warm-started solve."""
+
+    def __init__(self, net=None, seed=0):
+        self.net = net if net is not None else ConvNet(seed=seed)
+        self.samples = []      # (features, target, shape), target = du / scale - du_prev / scale
+
+    def _x16(self, f):
+        torch = self.net.torch
+        return self.net.to_bf16(torch.tensor(f, device=self.net.device))
+
+    def record(self, phase, damage, du_prev, du, scale):
+        f = features(phase, damage, du_prev, scale)
+        target = ((du - du_prev) / scale).astype(np.float32)
+        self.samples.append((f, target, phase.shape))
+
+    def train(self, epochs, lr=1e-3, seed=0):
+        torch = self.net.torch
+        rng = np.random.default_rng(seed)
+        data = [(self._x16(f), torch.tensor(t, device=self.net.device), sh)
+                for f, t, sh in self.samples]
+        losses = []
+        for _ in range(epochs):
+            for i in rng.permutation(len(data)):
+                x16, t, sh = data[i]
+                losses.append(self.net.train_step(x16, t, sh, lr))
+        return losses
+
+    def predict(self, phase, damage, du_prev, scale):
+        """Predicted increment of the fluctuation (3, nz, ny, nx), float64."""
+        f = features(phase, damage, du_prev, scale)
+        corr = self.net.predict(self._x16(f), phase.shape).double().cpu().numpy()
+        return du_prev + scale * corr

@@ -1,0 +1,216 @@
+"""GPU checks of the learned warm start: the BF16 convolution kernels against
+the FP64 oracle (on BF16-representable inputs, so only the FP32 accumulation
+differs: 1e-5 of the largest output allowed), the optimiser, training, and
+warm-started solves that reach the same results as plain ones."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import nn
+from synthetic import inclusion_microstructure, workload
+from tests.gpu_util import require_gpu, announce
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((5, 6, 7), 6, 16), ((4, 4, 4), 16, 16), ((8, 6, 4), 16, 3), ((3, 5, 2), 3, 8)]
+
+
+def _net_and_lib():
+    from paper_2207_10657_amd.warmstart import ConvNet
+    return ConvNet(seed=1)
+
+
+def _dev(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("shape,cin,cout", CASES)
+def test_conv_forward_and_adjoints_against_oracle(shape, cin, cout):
+    torch = require_gpu()
+    announce("nn conv", shape, cin, cout)
+    from paper_2207_10657_amd.warmstart import _ptr
+    net = _net_and_lib()
+    lib = net.lib
+    rng = np.random.default_rng(2)
+    x = nn.bf16_round(rng.normal(size=(cin,) + shape))
+    w = nn.bf16_round(rng.normal(scale=0.2, size=(cout, cin, 27)))
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    g = rng.normal(size=(cout,) + shape).astype(np.float32).astype(np.float64)
+    x16 = net.to_bf16(_dev(torch, x))
+    w16 = net.to_bf16(_dev(torch, w))
+    n = (ctypes.c_int * 3)(shape[2], shape[1], shape[0])
+    s = net._stream()
+    out = torch.empty((cout,) + shape, dtype=torch.float32, device="cuda")
+    out16 = torch.empty((cout,) + shape, dtype=torch.int16, device="cuda")
+    bt = _dev(torch, b)
+    for relu in (0, 1):
+        assert lib.hfe_nn_conv3d(_ptr(x16), cin, _ptr(w16), _ptr(bt), cout, n, relu, _ptr(out),
+                                 _ptr(out16), s) == 0
+        ref = nn.conv3d(x, w, b)
+        if relu:
+            ref = nn.relu(ref)
+        got = out.double().cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+        # the BF16 copy is the rounded FP32 output
+        back = net.to_bf16(out)
+        assert torch.equal(back, out16)
+    # adjoints, with the ReLU mask of the layer output (act = relu output)
+    act = out.double().cpu().numpy()
+    gt = _dev(torch, g)
+    gin = torch.empty((cin,) + shape, dtype=torch.float32, device="cuda")
+    assert lib.hfe_nn_conv3d_backward_data(_ptr(gt), cout, _ptr(out), _ptr(w16), cin, n, _ptr(gin),
+                                           s) == 0
+    gm = np.where(act > 0, g, 0.0)
+    ref = nn.conv3d_backward_data(gm, w)
+    assert np.abs(gin.double().cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+    gw = torch.empty((cout, cin, 27), dtype=torch.float32, device="cuda")
+    gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+    assert lib.hfe_nn_conv3d_backward_weights(_ptr(gt), cout, _ptr(out), _ptr(x16), cin, n,
+                                              _ptr(gw), _ptr(gb), s) == 0
+    rw, rb = nn.conv3d_backward_weights(gm, x)
+    assert np.abs(gw.double().cpu().numpy() - rw).max() <= 1e-6 * np.abs(rw).max()
+    assert np.abs(gb.double().cpu().numpy() - rb).max() <= 1e-6 * np.abs(rb).max()
+
+
+def test_mse_and_adam_against_oracle():
+    torch = require_gpu()
+    announce("nn mse adam")
+    from paper_2207_10657_amd.warmstart import _ptr
+    net = _net_and_lib()
+    lib = net.lib
+    s = net._stream()
+    rng = np.random.default_rng(3)
+    n = 1000
+    p = rng.normal(size=n).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    grad = torch.empty(n, dtype=torch.float32, device="cuda")
+    parts = torch.empty(int(lib.hfe_nn_mse_partials(n)), dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert lib.hfe_nn_mse(_ptr(_dev(torch, p)), _ptr(_dev(torch, t)), n, _ptr(grad), _ptr(parts),
+                          _ptr(loss), s) == 0
+    d = (p - t).astype(np.float64)          # the kernel differences in FP32, sums in FP64
+    assert abs(loss.item() - np.mean(d * d)) < 1e-12 * np.mean(d * d)
+    assert np.abs(grad.cpu().numpy() - 2 * d / n).max() < 1e-6 * np.abs(2 * d / n).max()
+    w = rng.normal(size=n).astype(np.float32)
+    wt, m, v = _dev(torch, w), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    w16 = torch.empty(n, dtype=torch.int16, device="cuda")
+    rw, rm, rv = w.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        assert lib.hfe_nn_adam(_ptr(wt), _ptr(m), _ptr(v), _ptr(_dev(torch, g)), n, 1e-2, 0.9,
+                               0.999, 1e-8, step, _ptr(w16), s) == 0
+        rw, rm, rv = nn.adam(rw, rm, rv, g.astype(np.float64), step, 1e-2)
+    assert np.abs(wt.double().cpu().numpy() - rw).max() < 1e-5
+    assert torch.equal(net.to_bf16(wt), w16)
+
+
+def test_training_fits_a_convolution():
+    """The network learns to reproduce a fixed periodic smoothing of its input
+    channels through its ReLU layers: the loss falls by 5x within 250 Adam
+    steps."""
+    torch = require_gpu()
+    announce("nn training")
+    from paper_2207_10657_amd.warmstart import ConvNet
+    net = ConvNet(seed=4)
+    rng = np.random.default_rng(5)
+    shape = (8, 8, 8)
+    wt = np.zeros((3, 6, 27))
+    for c in range(3):
+        wt[c, 3 + c, 13] = 0.5
+        wt[c, 3 + c, 12] = wt[c, 3 + c, 14] = 0.25
+    data = []
+    for _ in range(4):
+        x = nn.bf16_round(rng.normal(size=(6,) + shape))
+        data.append((net.to_bf16(_dev(torch, x)), _dev(torch, nn.conv3d(x, wt))))
+    losses = []
+    for it in range(250):
+        x16, y = data[it % 4]
+        losses.append(net.train_step(x16, y, shape, lr=3e-3))
+    print("[warmstart] fit loss %.3e -> %.3e" % (np.mean(losses[:4]), np.mean(losses[-4:])),
+          flush=True)
+    assert np.mean(losses[-4:]) < 0.2 * np.mean(losses[:4])
+
+
+def _cell(seed, n=16):
+    phase, _ = inclusion_microstructure((n, n, n), 4.0 * n / 64, 8.0 * n / 64, 0.25, seed)
+    return phase
+
+
+def _run(phase, materials, steps, dE, guess=None, ws=None):
+    """Solve `steps` increments; guess: None (previous fluctuation), "extrapolate"
+    or "learned". Returns per-step reports, stresses and largest damage, and
+    the training records (damage, previous increment, increment) of the
+    converged steps."""
+    from paper_2207_10657_amd import Solver
+    s = Solver(phase.shape, "q1")
+    s.setup(phase, materials)
+    scale = np.linalg.norm(dE) * phase.shape[0]
+    u_prev = np.zeros((3,) + phase.shape)
+    du_prev = None
+    reps, stress, dmax, rec = [], [], [], []
+    for k in range(steps):
+        s.apply_load_step(dE)
+        if guess is not None and du_prev is not None:
+            if guess == "extrapolate":
+                du = du_prev
+            else:
+                du = ws.predict(phase, s.damage(), du_prev, scale)
+            s.set_displacement(u_prev + du)
+        r = s.solve_increment()
+        u = s.get_state()["u"]
+        reps.append(r)
+        stress.append(s.homogenized_stress())
+        dmax.append(float(s.damage().max()))
+        if du_prev is not None and r["converged"]:
+            rec.append((s.damage(), du_prev, u - u_prev))
+        du_prev = u - u_prev
+        u_prev = u
+    s.close()
+    return reps, stress, dmax, rec
+
+
+def test_warm_started_solves_reach_the_same_results():
+    """Train on increments of three 16^3 cells of the workload recipe, then
+    solve a held-out cell with the plain, extrapolated and learned guesses
+    (four increments, to the onset of damage). Every step converges as the
+    plain one does. While the cell is undamaged the equilibrium is unique and
+    the homogenized stress agrees with the plain solve to the solver
+    tolerance (10x 1e-8 of the load stress scale); once damage grows, the
+    non-convex problem has several equilibria and a different guess may reach
+    another one (compared only in the log)."""
+    require_gpu()
+    announce("warm start end to end")
+    from paper_2207_10657_amd.warmstart import WarmStart
+    w = workload("c1_3d16")
+    dE = w.load_path[0]
+    scale = np.linalg.norm(dE) * 16
+    ws = WarmStart(seed=0)
+    for seed in (11, 12, 13):
+        phase = _cell(seed)
+        _, _, _, rec = _run(phase, w.materials, 4, dE)
+        for dmg, du_prev, du in rec:
+            ws.record(phase, dmg, du_prev, du, scale)
+    losses = ws.train(epochs=20, lr=1e-3)
+    phase = _cell(21)
+    out = {}
+    for guess in (None, "extrapolate", "learned"):
+        out[guess] = _run(phase, w.materials, 4, dE, guess, ws)
+        reps = out[guess][0]
+        print("[warmstart] %-11s Newton %s CG %s" % (guess, [r["newton_iters"] for r in reps],
+                                                   [r["cg_iters"] for r in reps]), flush=True)
+    print("[warmstart] training loss %.3e -> %.3e over %d samples" %
+          (np.mean(losses[:10]), np.mean(losses[-10:]), len(ws.samples)), flush=True)
+    reps0, S0, d0, _ = out[None]
+    lam = 10 * 0.3 / (1.3 * 0.4)
+    mu = 10 / 2.6
+    for guess in ("extrapolate", "learned"):
+        reps, S, d, _ = out[guess]
+        assert [r["converged"] for r in reps] == [r["converged"] for r in reps0]
+        for k in range(len(S)):
+            load = np.linalg.norm(lam * np.trace((k + 1) * dE) * np.eye(3) + 2 * mu * (k + 1) * dE)
+            dS = np.linalg.norm(S[k] - S0[k]) / load
+            print("[warmstart] %s step %d: |dSigma|/scale %.2e (max damage %.3f / %.3f)"
+                  % (guess, k, dS, d[k], d0[k]), flush=True)
+            if d0[k] == 0.0 and d[k] == 0.0:
+                assert dS < 1e-7, (guess, k, dS)
