@@ -98,6 +98,65 @@ def unit_load_cases(mag):
     return cases
 
 
+def warm_start_bench(n=16, train_seeds=(101, 102, 103, 104, 105, 106), test_seed=201, steps=4,
+                     epochs=20):
+    """Learned warm start on cells of the workload recipe at n^3: increments
+    of `train_seeds` cells train the network (hand-written BF16 kernels), then
+    a held-out cell is solved `steps` increments with the plain guess (the
+    previous fluctuation), the extrapolated previous increment, and the
+    network's prediction. Per guess: Newton and CG iterations, time."""
+    import torch
+    from paper_2207_10657_amd import Solver
+    from paper_2207_10657_amd.warmstart import WarmStart
+    from synthetic import inclusion_microstructure, workload
+    w = workload("c1_3d%d" % n)
+    dE = w.load_path[0]
+    scale = float(np.linalg.norm(dE)) * n
+
+    def cell(seed):
+        return inclusion_microstructure((n, n, n), 4.0 * n / 64, 8.0 * n / 64, 0.25, seed)[0]
+
+    def run(phase, guess=None, ws=None, record=None):
+        s = Solver(phase.shape, "q1")
+        s.setup(phase, w.materials)
+        u_prev = np.zeros((3,) + phase.shape)
+        du_prev = None
+        newton = cg = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.apply_load_step(dE)
+            if guess and du_prev is not None:
+                du = du_prev if guess == "extrapolate" else ws.predict(phase, s.damage(), du_prev, scale)
+                s.set_displacement(u_prev + du)
+            r = s.solve_increment()
+            newton += r["newton_iters"]
+            cg += r["cg_iters"]
+            u = s.get_state()["u"]
+            if record is not None and du_prev is not None and r["converged"]:
+                record.record(phase, s.damage(), du_prev, u - u_prev, scale)
+            du_prev, u_prev = u - u_prev, u
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        return {"newton_iters": newton, "cg_iters": cg, "ms_per_step": dt / steps * 1e3}
+
+    ws = WarmStart(seed=0)
+    t0 = time.perf_counter()
+    for seed in train_seeds:
+        run(cell(seed), record=ws)
+    t1 = time.perf_counter()
+    losses = ws.train(epochs)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    phase = cell(test_seed)
+    out = {g or "previous": run(phase, g, ws) for g in (None, "extrapolate", "learned")}
+    return {"grid": n, "train_cells": len(train_seeds), "samples": len(ws.samples),
+            "epochs": epochs, "data_s": t1 - t0, "train_s": t2 - t1,
+            "loss_first_last": [float(np.mean(losses[:10])), float(np.mean(losses[-10:]))],
+            "held_out_steps": steps, "guesses": out}
+
+
 def batch_bench(w, steps):
     """The six unit load cases of the cell, `steps` increments each after one
     untimed increment: solved one cell after the other, then as one batch
@@ -333,6 +392,8 @@ def main():
                     help="skip the mixed-precision run of the same steps")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the six-load-case batch run")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the learned warm-start run (16^3 cells)")
     ap.add_argument("--probe", action="store_true",
                     help="short run for hardware-counter passes: after one load step, a few "
                          "projected-Hessian applications and a calibration copy of known size")
@@ -493,6 +554,8 @@ def main():
     }
     if not args.no_batch:
         out["batch_six_load_cases"] = batch_bench(w, 2)
+    if not args.no_warm_start:
+        out["warm_start"] = warm_start_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)
     print(json.dumps(out), flush=True)

@@ -258,8 +258,9 @@ hfe_status hfe_get_tuning(const hfe_ctx* ctx, hfe_tuning* out);
  * pencil block pencil_cols * nz values at 15 per thread in 64 KiB of LDS. */
 hfe_status hfe_set_tuning(hfe_ctx* ctx, const hfe_tuning* in);
 /* Autotuner: times every valid plane / pencil shape on this grid's Green's
- * operator (FP64 and FP32) and, once a load step has been applied, every
- * brick shape on the Hessian at the current state; keeps the fastest and
+ * operator (FP64 and FP32) and, once a load step has been applied, the brick
+ * shapes on the Hessian at the current state (FP64: the 448-thread bricks 0
+ * and 3, which do not spill registers; FP32: all four); keeps the fastest and
  * returns them in `out` (may be NULL). Results do not depend on the shapes
  * (the arithmetic per value is the same), only the time does. */
 hfe_status hfe_autotune(hfe_ctx* ctx, hfe_tuning* out);

@@ -1553,9 +1553,13 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
       int bs = 0, bs32 = 0;
       for (int shape = 0; shape < 4; ++shape) {
         c->brick_shape = c->brick_shape32 = shape;
-        const double t = time_us([&]() { return stiffness(c, c->g0, c->Kd, false); });
+        // FP64: only the 448-thread bricks (0, 3); the 768-thread ones spill
+        // registers in FP64 and triple the memory traffic of the kernel
+        if (shape == 0 || shape == 3) {
+          const double t = time_us([&]() { return stiffness(c, c->g0, c->Kd, false); });
+          if (t < kMargin * best) { best = t; bs = shape; }
+        }
         const double t32 = time_us([&]() { return stiffness32(c, c->Kd32, c->tmp32, false); });
-        if (t < kMargin * best) { best = t; bs = shape; }
         if (t32 < kMargin * best32) { best32 = t32; bs32 = shape; }
       }
       c->brick_shape = bs;
