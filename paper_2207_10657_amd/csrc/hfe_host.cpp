@@ -607,7 +607,7 @@ hfe_status cg_iteration32(hfe_ctx* c) {
 // K d, [direction update of the previous iteration + curvature decision],
 // z/g update + forward FFT, Green z-pass, inverse FFT + y update + residual
 // sums, [residual decision], new direction. In 3D the bracketed decisions
-// are taken inside the neighbouring passes (4 launches per iteration).
+// are taken inside the neighbouring passes (5 launches per iteration).
 hfe_status cg_iteration(hfe_ctx* c) {
   const long long n = ndof(c);
   hfe::ElemArgs A = elem_args(c);
@@ -620,7 +620,7 @@ hfe_status cg_iteration(hfe_ctx* c) {
     HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
   }
   if (c->g.dim == 3) {
-    // 3D: four launches, the decisions fused into the forward plane pass
+    // 3D: five launches, the decisions fused into the forward plane pass
     // (direction + curvature) and into the direction update (residual)
     hfe::CgFuse<double> f = fuse_args<double>(c, nb, c->d, c->z, c->gv, c->y);
     {
