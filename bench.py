@@ -34,9 +34,11 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c1_3d64"
 
 
-def algorithmic_bytes(name, shape):
+def algorithmic_bytes(name, shape, n_soft=0.0):
     """Bytes per launch that each kernel must move at minimum (3D Q1, FP64, or
-    FP32 for the kernels of the mixed-precision CG, names ending in _f32)."""
+    FP32 for the kernels of the mixed-precision CG, names ending in _f32).
+    n_soft: softening points of the state; at each, the element kernels move
+    the six FP64 components of the rank-one softening factor w."""
     nz, ny, nx = shape
     N = nx * ny * nz
     f32 = name.endswith("_f32")
@@ -44,8 +46,8 @@ def algorithmic_bytes(name, shape):
     r = 4 if f32 else 8                        # bytes per real
     spec = 6.0 * r * (nx // 2 + 1) / nx         # 3 half-spectrum fields, B / voxel
     per_vox = {
-        # d, u (tangent direction s = C:eps), a and c' at 8 points, phase, K d
-        "stiffness": 3 * r + 3 * r + 16 * r + 1 + 3 * r,
+        # d, a at 8 points, phase, soft mask, K d
+        "stiffness": 3 * r + 8 * r + 1 + 1 + 3 * r,
         # 3 real fields in, 3 half spectra out (and back)
         "fft_plane_fwd": 3 * r + spec,
         "fft_pencil_green": 2 * spec,
@@ -53,14 +55,15 @@ def algorithmic_bytes(name, shape):
         # fused CG passes: + z, d, g in and z, g out / + y, g in and y out
         "fft_plane_fwd_cg": 3 * r + spec + 15 * r,
         "fft_plane_inv_cg": spec + 9 * r,
-        # u, kappa_hist, phase in; a, c' and D^T sigma out
-        "residual": 24 + 64 + 1 + 128 + 24,
-        # u, z, kappa_hist, old a/c', phase in; trial a/c', D^T sigma_t out
-        "trial": 24 + 24 + 64 + 128 + 1 + 128 + 24,
+        # u, kappa_hist, phase in; a, soft mask and D^T sigma out
+        "residual": 24 + 64 + 1 + 64 + 1 + 24,
+        # u, z, kappa_hist, a, phase, soft mask in; sums only
+        "trial": 24 + 24 + 64 + 64 + 1 + 1,
     }
     if base not in per_vox or (f32 and base in ("residual", "trial")):
         return None
-    return per_vox[base] * N
+    soft = 48.0 * n_soft if base in ("stiffness", "residual", "trial") else 0.0
+    return per_vox[base] * N + soft
 
 
 def cpu_baseline(w, n_matvec):
@@ -226,8 +229,9 @@ PMC_KERNELS = [("k_hessian<double,", "stiffness"), ("k_brick<0,", "residual"),
                ("k_plane<0,double>", "fft_plane_fwd"), ("k_pencil<0,double>", "fft_pencil_green"),
                ("k_plane<1,double>", "fft_plane_inv"), ("copyBuffer", "copy")]
 PROBE_REPS = 5
+PROBE_STEPS = 3
 # Hessian brick shapes (nodes per axis, x y z) by tuning index
-BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4)}
+BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4), 4: (8, 4, 4)}
 
 
 def hessian_label(shape_index):
@@ -283,6 +287,8 @@ def pmc_summary(fetch_dir, write_dir, grid, tuning=None):
     Both counters are in KiB per dispatch. The copy kernel moves COPY_BYTES in
     and COPY_BYTES out, which fixes one scale factor per counter."""
     fetch, write = read_pmc(fetch_dir), read_pmc(write_dir)
+    tuning = dict(tuning or {})
+    soft_points = float(tuning.pop("soft_points", 0.0))
     if "copy" not in fetch or "copy" not in write:
         raise SystemExit("the calibration copy is missing from the counter runs")
     # the calibration copies are the last copy dispatches of the probe
@@ -298,7 +304,7 @@ def pmc_summary(fetch_dir, write_dir, grid, tuning=None):
         base = label.split(":")[0]
         fb = float(np.median(fetch[label])) * 1024.0 * kf
         wb = float(np.median(write[label])) * 1024.0 * kw
-        alg = algorithmic_bytes(base, shape)
+        alg = algorithmic_bytes(base, shape, soft_points)
         keys = () if base == "stiffness" else SHAPE_KEYS[base]   # the brick is in the label
         table[label] = {"fetch_bytes": fb, "write_bytes": wb, "dispatches": len(fetch[label]),
                         "algorithmic_bytes": alg, "sources": sources_digest(base),
@@ -311,9 +317,12 @@ def pmc_summary(fetch_dir, write_dir, grid, tuning=None):
         "|---|---|---|---|---|---|"] + rows + [
         "",
         "Calibration (copy of %d bytes): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (COPY_BYTES, kf, kw),
+        "State: %d softening points (%.1f %% of the points); the element kernels' algorithmic "
+        "bytes include 48 B for each." % (soft_points, 100.0 * soft_points / (8.0 * grid ** 3)),
         "",
         "```json",
-        json.dumps({"grid": grid, "fetch_scale": kf, "write_scale": kw, "kernels": table}, indent=1),
+        json.dumps({"grid": grid, "fetch_scale": kf, "write_scale": kw, "soft_points": soft_points,
+                    "kernels": table}, indent=1),
         "```"]
     return "\n".join(lines)
 
@@ -345,8 +354,10 @@ def load_traffic(kernel, shape, tuning):
 def probe(n, tuning_out=None, tuning_in=None):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
 
-    One load step of the workload recipe at n^3, the autotuner (the FFT
-    launch shapes the benchmark uses), then, for every Hessian brick shape,
+    The first PROBE_STEPS load increments of the workload recipe at n^3,
+    solved (the state of the benchmark's first timed steps at 64^3), the
+    autotuner (the launch shapes the benchmark uses), then, for every Hessian
+    brick shape,
     PROBE_REPS projected-Hessian applications at that state, and PROBE_REPS
     device-to-device copies of COPY_BYTES (the copy kernel calibrates the
     counters: it reads and writes exactly COPY_BYTES per launch)."""
@@ -356,17 +367,22 @@ def probe(n, tuning_out=None, tuning_in=None):
     w = workload("c1_3d%d" % n)
     s = Solver(w.shape, w.element)
     s.setup(w.phase, w.materials)
-    s.apply_load_step(w.load_path[0] * 5)      # a damaged state (E_xx = 1e-3)
+    for k in range(PROBE_STEPS):
+        s.apply_load_step(w.load_path[k])
+        s.solve_increment()
     if tuning_in:
         with open(tuning_in) as fh:
-            s.set_tuning(**json.load(fh))
+            t = json.load(fh)
+        t.pop("soft_points", None)
+        s.set_tuning(**t)
         tuned = s.tuning()
     else:
         tuned = s.autotune()
-    print("probe launch shapes:", tuned, flush=True)
+    soft = s.soft_points()[0]
+    print("probe launch shapes:", tuned, "softening points:", soft, flush=True)
     if tuning_out:
         with open(tuning_out, "w") as fh:
-            json.dump(tuned, fh)
+            json.dump(dict(tuned, soft_points=soft), fh)
     rng = np.random.default_rng(0)
     d = torch.tensor(rng.normal(size=(3,) + w.shape), device="cuda")
     for shape_index in sorted(BRICKS):      # every Hessian brick shape, FFT shapes as tuned
@@ -479,6 +495,7 @@ def main():
     torch.cuda.synchronize()
     dt_prof = time.perf_counter() - t1
     stats = s.kernel_stats()
+    soft_mean = s.soft_points()[1]       # softening points, mean over the Hessian launches
     s.set_profiling(False)
     if replay[0] != matvecs:
         print("warning: event-timed replay differs from the timed run", replay, matvecs,
@@ -518,7 +535,7 @@ def main():
     kern = max(stats.items(), key=lambda kv: kv[1][1])
     kname, (kcount, kms) = kern
     avg_s = kms / max(kcount, 1) / 1e3
-    alg = algorithmic_bytes(kname, w.shape)
+    alg = algorithmic_bytes(kname, w.shape, soft_mean)
     roof = None
     if alg is not None and avg_s > 0:
         achieved = alg / avg_s / 1e9
@@ -526,6 +543,7 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": load_traffic(kname, w.shape, tuning),
                 "kernel": kname, "algorithmic_bytes": alg,
+                "softening_points_mean": soft_mean,
                 "avg_launch_us": avg_s * 1e6, "launches": kcount}
     value = w.nvox * matvecs / dt / 1e9
     out = {

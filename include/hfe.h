@@ -211,8 +211,9 @@ hfe_status hfe_apply_projected_hessian(hfe_ctx* ctx, const double* dev_in,
                                        double* dev_out, double dots[2]);
 
 /* The projected Hessian of hfe_apply_projected_hessian in the FP32 arithmetic
- * of the HFE_MIXED CG (3D only): the state (u, the tangent scalars) rounded to
- * FP32, FP32 Hessian and FFT, dots summed in FP64. `dev_in`, `dev_out` are
+ * of the HFE_MIXED CG (3D only): the tangent scalars 1-d rounded to FP32
+ * (the rank-one softening factors are read in FP64 and rounded on use), FP32
+ * Hessian and FFT, dots summed in FP64. `dev_in`, `dev_out` are
  * distinct device float arrays [dim][N]. HFE_EINVAL in 2D. */
 hfe_status hfe_apply_projected_hessian_f32(hfe_ctx* ctx, const float* dev_in, float* dev_out,
                                            double dots[2]);
@@ -247,7 +248,8 @@ typedef struct {
   int plane_threads;    /* threads of an x-y plane FFT block (64..1024, multiple of 64) */
   int pencil_cols;      /* z columns per pencil block (1..64)                       */
   int pencil_threads;   /* threads of a pencil block (64..256, multiple of 64)      */
-  int brick_shape;      /* Q1 Hessian brick: 0 = 8x8x4, 1 = 8x8x8, 2 = 16x8x4, 3 = 16x4x4 */
+  int brick_shape;      /* Q1 Hessian brick: 0 = 8x8x4, 1 = 8x8x8, 2 = 16x8x4, 3 = 16x4x4,
+                           4 = 8x4x4 */
   int plane_threads32, pencil_cols32, pencil_threads32, brick_shape32;
 } hfe_tuning;
 
@@ -259,8 +261,8 @@ hfe_status hfe_get_tuning(const hfe_ctx* ctx, hfe_tuning* out);
 hfe_status hfe_set_tuning(hfe_ctx* ctx, const hfe_tuning* in);
 /* Autotuner: times every valid plane / pencil shape on this grid's Green's
  * operator (FP64 and FP32) and, once a load step has been applied, the brick
- * shapes on the Hessian at the current state (FP64: the 448-thread bricks 0
- * and 3, which do not spill registers; FP32: all four); keeps the fastest and
+ * shapes on the Hessian at the current state (all five, FP64 and FP32);
+ * keeps the fastest and
  * returns them in `out` (may be NULL). Results do not depend on the shapes
  * (the arithmetic per value is the same), only the time does. */
 hfe_status hfe_autotune(hfe_ctx* ctx, hfe_tuning* out);
@@ -281,6 +283,14 @@ hfe_status hfe_fft_inverse(hfe_ctx* ctx, const double* dev_in_spec, double* dev_
  * context's stream. hfe_kernel_stats writes, for up to max kernels, the name
  * pointer, launch count and total milliseconds since the last reset. */
 hfe_status hfe_set_profiling(hfe_ctx* ctx, int on);
+
+/* Softening points of a Q1 state: points where the damage law of Appendix A
+ * is loading with 0 < d < 1, so that its consistent tangent carries the
+ * rank-one term c' (C:eps) (x) (C:eps) besides (1-d) C. *current gets the
+ * count of the evaluated state; *mean_per_hessian the mean of that count over
+ * the Hessian launches timed since the last hfe_set_profiling (0 if none).
+ * Either pointer may be null. Host pointers; 0 for P1 pairs. */
+hfe_status hfe_soft_points(hfe_ctx* ctx, double* current, double* mean_per_hessian);
 hfe_status hfe_kernel_stats(hfe_ctx* ctx, const char** names, int* counts, double* total_ms,
                             int max, int* n_kernels);
 

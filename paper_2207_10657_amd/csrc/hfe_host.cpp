@@ -38,12 +38,14 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kTraceCap = 1 << 16;    // CG trace entries kept per solve
 constexpr int kCgBatch = 8;           // CG iterations enqueued between host polls
+constexpr int kBrickShapes = 5;       // Q1 Hessian brick shapes (see launch_hessian_brick)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t u, z, d, g, y, Kd, w, g0, y0, tmp;          // nodal [dim][N]
   size_t a, cp, kh;                                   // per point [nq][N]
+  size_t sw;                                          // per point [nq][6][N] (Q1)
   size_t phase;                                       // N bytes
   size_t soft;                                        // N bytes: element softens
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
@@ -56,8 +58,8 @@ struct Layout {
   size_t tw;                                          // twiddles
   size_t stab;                                        // sin^2 tables
   // FP32 copies for the mixed-precision CG
-  size_t u32, z32, d32, g32, y32, Kd32, tmp32;        // nodal [dim][N] floats
-  size_t a32, cp32;                                   // per point [nq][N] floats
+  size_t z32, d32, g32, y32, Kd32, tmp32;             // nodal [dim][N] floats
+  size_t a32;                                         // per point [nq][N] floats
   size_t spec32;                                      // dim*nz*ny*(nx/2+1) float2
   size_t tw32, stab32;                                // tables
   size_t total;
@@ -113,6 +115,7 @@ Layout make_layout(const Grid& g) {
   L.Kd = take(nod); L.w = take(nod); L.g0 = take(nod); L.y0 = take(nod);
   L.tmp = take(nod);
   L.a = take(pts); L.cp = take(pts); L.kh = take(pts);
+  L.sw = take(g.element == HFE_Q1 ? 6 * pts : 0);
   L.phase = take((size_t)g.N);
   L.soft = take((size_t)g.N);
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
@@ -129,9 +132,9 @@ Layout make_layout(const Grid& g) {
   L.stab = take((size_t)L.n_stab * sizeof(double));
   const size_t nod32 = (size_t)g.dim * g.N * sizeof(float);
   const size_t pts32 = (size_t)g.nq * g.N * sizeof(float);
-  L.u32 = take(nod32); L.z32 = take(nod32); L.d32 = take(nod32); L.g32 = take(nod32);
+  L.z32 = take(nod32); L.d32 = take(nod32); L.g32 = take(nod32);
   L.y32 = take(nod32); L.Kd32 = take(nod32); L.tmp32 = take(nod32);
-  L.a32 = take(pts32); L.cp32 = take(pts32);
+  L.a32 = take(pts32);
   L.spec32 = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(float2));
   L.tw32 = take((size_t)L.n_tw * sizeof(float2));
   L.stab32 = take((size_t)L.n_stab * sizeof(float));
@@ -176,8 +179,12 @@ struct hfe_ctx {
   // device views
   double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *tmp;
   double *a, *cp, *kh;
+  double* sw;                // Q1: w = sqrt(c') s at the softening points
   uint8_t* phase;
-  uint8_t* soft;             // per element: c' != 0 at some point of the state
+  uint8_t* soft;             // per element: bit q set iff c' != 0 at point q (Q1)
+  double n_soft = 0.0;       // softening points of the state (Q1)
+  double prof_soft_sum = 0.0;  // profiling: n_soft summed over the Hessian launches
+  long long prof_soft_n = 0;
   double2* spec;
   double* partials;
   double* partials2;
@@ -188,10 +195,10 @@ struct hfe_ctx {
   double* trace;             // device CG trace
   hfe::FftTables tabs;
   // mixed precision: FP32 CG vectors, FP32 copies of the state, FP32 tables
-  float *u32, *z32, *d32, *g32, *y32, *Kd32, *tmp32, *a32, *cp32;
+  float *z32, *d32, *g32, *y32, *Kd32, *tmp32, *a32;
   float2* spec32;
   hfe::FftTablesT<float> tabs32;
-  bool state32_fresh = false;  // u32, a32, cp32 match u, a, cp
+  bool state32_fresh = false;  // a32 matches a
   double* hscal = nullptr;   // pinned, device-mapped: reduction totals land here
   double* dscal = nullptr;   // device alias of hscal
   hfe::CgState* hcg = nullptr;  // pinned host copy of the CG state
@@ -221,7 +228,7 @@ struct hfe_ctx {
   CgGraph graphs[2];
   int graph_precision = HFE_FP64;   // precision the captured graphs run
   bool use_graphs = true;
-  int brick_shape = 0;       // Q1 Hessian brick shape, FP64 (HFE_BRICK_SHAPE=0..3 overrides)
+  int brick_shape = 0;       // Q1 Hessian brick shape, FP64 (HFE_BRICK_SHAPE=0..4 overrides)
   int brick_shape32 = 0;     // and FP32
 };
 
@@ -267,6 +274,10 @@ struct Prof {
   Prof(hfe_ctx* ctx, const char* name) : c(ctx) {
     if (!c->profiling) return;
     id = kernel_id(c, name);
+    if (std::strncmp(name, "stiffness", 9) == 0) {
+      c->prof_soft_sum += c->n_soft;
+      ++c->prof_soft_n;
+    }
     s = take_event(c);
     if (s) hipEventRecord(s, c->stream);
   }
@@ -352,6 +363,8 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.f = nullptr;
   A.soft = c->soft;
   A.soft_out = nullptr;
+  A.sw = c->sw;
+  A.sw_out = nullptr;
   A.red = reducer(c);
   A.cg = nullptr;
   A.brick_shape = c->brick_shape;
@@ -361,7 +374,7 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
 long long ndof(const hfe_ctx* c) { return (long long)c->g.dim * c->g.N; }
 
 // Offsets of the reduction totals in hscal.
-enum { S_HES = 0, S_RES = 8, S_RR0 = 16, S_TRI = 24, S_DOT = 40, S_ESTAGE = 48, S_COUNT = 64 };
+enum { S_HES = 0, S_RES = 8, S_RR0 = 24, S_TRI = 32, S_DOT = 48, S_ESTAGE = 56, S_COUNT = 72 };
 
 // y = L^+ x (the passes are skipped once skip->done is set)
 hfe_status green(hfe_ctx* c, const double* x, double* y, const hfe::CgState* skip = nullptr) {
@@ -427,6 +440,7 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   A.a_out = c->a;
   A.cp_out = c->cp;
   A.soft_out = c->soft;
+  A.sw_out = c->sw;
   A.f = c->g0;
   int nb = 0;
   {
@@ -444,6 +458,7 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   const double* h = c->hscal;
   for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[S_RES + k];
   c->sig_norm2 = h[S_RES + hfe::RES_SS];
+  c->n_soft = h[S_RES + hfe::RES_NSOFT];
   c->rr0 = h[S_RR0];
   if (!std::isfinite(c->rr0) || !std::isfinite(c->sig_norm2))
     return fail(c, HFE_ENUMERIC, "non-finite stress or residual");
@@ -473,15 +488,14 @@ hfe_status direction(hfe_ctx* c) {
 
 // ---- mixed precision: the CG of Algorithm 1 on FP32 vectors ----------------
 
-// FP32 copies of the state (u, a, c') read by the FP32 Hessian.
+// FP32 copy of the tangent scalars a read by the FP32 Hessian (the softening
+// factors w are read in FP64).
 hfe_status refresh_state32(hfe_ctx* c) {
   if (c->state32_fresh) return HFE_OK;
   const long long np = (long long)c->g.nq * c->g.N;
   {
     Prof p(c, "convert");
-    HIPCHK(c, hfe::vec_to_f32(ndof(c), c->u, c->u32, c->stream));
     HIPCHK(c, hfe::vec_to_f32(np, c->a, c->a32, c->stream));
-    HIPCHK(c, hfe::vec_to_f32(np, c->cp, c->cp32, c->stream));
   }
   c->state32_fresh = true;
   return HFE_OK;
@@ -494,9 +508,8 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.E = c->Edev;
   H.phase = c->phase;
   H.soft = c->soft;
-  H.u = c->u32;
   H.a = c->a32;
-  H.cp = c->cp32;
+  H.sw = c->sw;
   H.v = v;
   H.f = out;
   H.red = reducer(c);
@@ -896,17 +909,18 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
   if (const char* bs = std::getenv("HFE_BRICK_SHAPE")) {
     const int v = std::atoi(bs);
-    if (v >= 0 && v <= 3) c->brick_shape = c->brick_shape32 = v;
+    if (v >= 0 && v < kBrickShapes) c->brick_shape = c->brick_shape32 = v;
   }
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
   c->Kd = D(L.Kd); c->w = D(L.w); c->g0 = D(L.g0); c->y0 = D(L.y0);
   c->tmp = D(L.tmp);
   c->a = D(L.a); c->cp = D(L.cp); c->kh = D(L.kh);
+  c->sw = c->g.element == HFE_Q1 ? D(L.sw) : nullptr;
   auto F = [&](size_t off) { return (float*)(c->ws + off); };
-  c->u32 = F(L.u32); c->z32 = F(L.z32); c->d32 = F(L.d32); c->g32 = F(L.g32);
+  c->z32 = F(L.z32); c->d32 = F(L.d32); c->g32 = F(L.g32);
   c->y32 = F(L.y32); c->Kd32 = F(L.Kd32); c->tmp32 = F(L.tmp32);
-  c->a32 = F(L.a32); c->cp32 = F(L.cp32);
+  c->a32 = F(L.a32);
   c->spec32 = (float2*)(c->ws + L.spec32);
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->soft = (uint8_t*)(c->ws + L.soft);
@@ -1448,8 +1462,9 @@ hfe_status hfe_set_tuning(hfe_ctx* c, const hfe_tuning* in) {
   if (!hfe::fft_launch_valid(c->g, in->plane_threads, in->pencil_cols, in->pencil_threads, 8) ||
       !hfe::fft_launch_valid(c->g, in->plane_threads32, in->pencil_cols32, in->pencil_threads32, 4))
     return fail(c, HFE_EINVAL, "an FFT launch shape does not fit this grid");
-  if (in->brick_shape < 0 || in->brick_shape > 3 || in->brick_shape32 < 0 || in->brick_shape32 > 3)
-    return fail(c, HFE_EINVAL, "brick_shape must be 0..3");
+  if (in->brick_shape < 0 || in->brick_shape >= kBrickShapes || in->brick_shape32 < 0 ||
+      in->brick_shape32 >= kBrickShapes)
+    return fail(c, HFE_EINVAL, "brick_shape must be 0..4");
   hfe_status st = sync(c);
   if (st) return st;
   destroy_graphs(c);
@@ -1551,11 +1566,9 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
     if (st == HFE_OK) {
       double best = INFINITY, best32 = INFINITY;
       int bs = 0, bs32 = 0;
-      for (int shape = 0; shape < 4; ++shape) {
+      for (int shape = 0; shape < kBrickShapes; ++shape) {
         c->brick_shape = c->brick_shape32 = shape;
-        // FP64: only the 448-thread bricks (0, 3); the 768-thread ones spill
-        // registers in FP64 and triple the memory traffic of the kernel
-        if (shape == 0 || shape == 3) {
+        {
           const double t = time_us([&]() { return stiffness(c, c->g0, c->Kd, false); });
           if (t < kMargin * best) { best = t; bs = shape; }
         }
@@ -1610,6 +1623,16 @@ hfe_status hfe_set_profiling(hfe_ctx* c, int on) {
     c->kcount[i] = 0;
     c->kms[i] = 0.0;
   }
+  c->prof_soft_sum = 0.0;
+  c->prof_soft_n = 0;
+  return HFE_OK;
+}
+
+hfe_status hfe_soft_points(hfe_ctx* c, double* current, double* mean_per_hessian) {
+  if (!c) return HFE_EINVAL;
+  if (current) *current = c->n_soft;
+  if (mean_per_hessian)
+    *mean_per_hessian = c->prof_soft_n ? c->prof_soft_sum / (double)c->prof_soft_n : 0.0;
   return HFE_OK;
 }
 

@@ -47,7 +47,11 @@ struct Reducer {
 // ---- element kernels (k_element.hip) -------------------------------------
 
 // Partial-sum layouts written by the element kernels (one row per block).
-enum { RES_S0 = 0 /* 6 stress sums xx,yy,zz,xy,xz,yz */, RES_SS = 6, RES_HH = 7, RES_NV = 8 };
+// RES_NSOFT: number of softening points (c' != 0) of the state, Q1 only.
+enum {
+  RES_S0 = 0 /* 6 stress sums xx,yy,zz,xy,xz,yz */, RES_SS = 6, RES_HH = 7, RES_NSOFT = 8,
+  RES_NV = 9
+};
 enum { TRI_SP = 0, TRI_PBP = 1, TRI_STP = 2, TRI_PP = 3, TRI_HH = 4, TRI_NV = 5 };
 enum { HES_DKD = 0, HES_DD = 1, HES_NV = 2 };
 
@@ -57,26 +61,33 @@ struct ElemArgs {
   const double* E;       // macroscopic strain, 3x3 row-major (device)
   const uint8_t* phase;
   const double* khist;   // [nq][N]
-  const double* a;       // [nq][N] current tangent scalars
-  const double* cp;
-  double* a_out;         // [nq][N] written by residual / trial
-  double* cp_out;
+  const double* a;       // [nq][N] current tangent scalars a = 1 - d
+  const double* cp;      // [nq][N] c' (P1 pairs; Q1 keeps w below instead)
+  double* a_out;         // [nq][N] written by the residual
+  double* cp_out;        // (P1 pairs)
   const double* u;       // [dim][N]
   const double* v;       // second nodal input: z (trial) or the direction (Hessian)
   double* f;             // nodal output [dim][N]
-  const uint8_t* soft;   // [N] element softens (c' != 0 at a point); read by the Hessian
-  uint8_t* soft_out;     // written by the residual (Q1)
+  // Q1: the softening term c' (s:e) s of the tangent as (w:e) w with
+  // w = sqrt(c') s, s = C : eps (c' >= 0). soft[e] has bit q set iff c' != 0
+  // at point q of element e; w [nq][6][N] (xx,yy,zz,xy,xz,yz) is written, and
+  // read, only at those points. Both come from the residual pass.
+  const uint8_t* soft;
+  uint8_t* soft_out;
+  const double* sw;
+  double* sw_out;
   Reducer red;
   CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
   int brick_shape;       // brick shape of the Q1 element passes (see launch_brick)
 };
 
-// Residual: f = D^T sigma(E + D u), writes a_out/cp_out, partial rows RES_*.
+// Residual: f = D^T sigma(E + D u), writes a_out and cp_out (P1 pairs) or
+// soft_out and sw_out (Q1), partial rows RES_*.
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Trial at u + v: sums over points only (rows TRI_*), no nodal or point output.
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
-// Hessian: f = D^T B D v at the state (u, a, cp), rows HES_* (no-op once
-// A.cg->done when A.cg is set).
+// Hessian: f = D^T B D v at the state (a and the softening term), rows HES_*
+// (no-op once A.cg->done when A.cg is set).
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Hessian operands in one precision (the FP32 copies of the state serve the
 // mixed-precision CG; Q1 only).
@@ -86,10 +97,9 @@ struct HessArgs {
   MatTable mat;
   const double* E;       // macroscopic strain (device, FP64)
   const uint8_t* phase;
-  const uint8_t* soft;   // [N] element softens at some point (from the residual pass)
-  const R* u;            // [dim][N] state displacement (s = C:eps at softening points)
+  const uint8_t* soft;   // [N] softening points of each element (bit q), as in ElemArgs
+  const double* sw;      // [nq][6][N] w = sqrt(c') s at the softening points (FP64)
   const R* a;            // [nq][N] tangent scalars of the state
-  const R* cp;
   const R* v;            // [dim][N] direction
   R* f;                  // [dim][N] K v
   Reducer red;           // rows HES_* (FP64)

@@ -38,6 +38,52 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* pa
   }
 }
 
+// Thread t's share of a fixed-order row sum: s[k] = the sum, in ascending r,
+// of rows[r * NV + k] over r = t, t + stride, ... < nb. The rows are loaded
+// in batches of 8 before they are added (in the same order), so a thread
+// waits for one memory latency per batch instead of one per row.
+template <int NV>
+__device__ __forceinline__ void strided_row_sums(const double* __restrict__ rows, int nb, int t,
+                                                 int stride, double (&s)[NV]) {
+  constexpr int kB = 8;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  for (int r0 = t; r0 < nb; r0 += kB * stride) {
+    double v[kB][NV];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int r = r0 + u * stride;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = r < nb ? rows[(size_t)r * NV + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (r0 + u * stride < nb) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += v[u][k];
+      }
+  }
+}
+
+// The same for a row length nv known at run time, one column k.
+__device__ __forceinline__ double strided_row_sum(const double* __restrict__ rows, int nb, int nv,
+                                                  int k, int t, int stride) {
+  constexpr int kB = 8;
+  double s = 0.0;
+  for (int r0 = t; r0 < nb; r0 += kB * stride) {
+    double v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int r = r0 + u * stride;
+      v[u] = r < nb ? rows[(size_t)r * nv + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (r0 + u * stride < nb) s += v[u];
+  }
+  return s;
+}
+
 // Fixed-order sum of nb rows of NV partials, done by the first 256 threads
 // of the block so that the order of the additions does not depend on the
 // block size (blockDim.x >= 256). The totals end in thread 0's tot. Every
@@ -48,12 +94,12 @@ __device__ __forceinline__ void block_sum_rows(const double* __restrict__ rows, 
   __shared__ double ws[4][NV];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < 256) {
+    double s[NV];
+    strided_row_sums<NV>(rows, nb, tid, 256, s);
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int r = tid; r < nb; r += 256) s += rows[(size_t)r * NV + k];
-      s = wave_sum(s);
-      if (lane == 0) ws[wave][k] = s;
+      const double sk = wave_sum(s[k]);
+      if (lane == 0) ws[wave][k] = sk;
     }
   }
   __syncthreads();

@@ -561,65 +561,63 @@ __device__ __forceinline__ void q1_grad_sf(const R (&v)[8], R (&G)[3][2][2]) {
   }
 }
 
-// Transpose of interp: a value r at Gauss point g adds (1-w) r to node 0 and
-// w r to node 1.
+// Transpose of interp for both Gauss points: values r0, r1 at points 0, 1
+// give the nodal sums n0 = kG1 r0 + kG0 r1 and n1 = kG0 r0 + kG1 r1 (the
+// weight of node 1 at point g is kG0 for g = 0 and kG1 for g = 1).
 template <typename R>
-__device__ __forceinline__ void interp_t(R r, int g, R& f0, R& f1) {
-  const R w1 = g ? R(kG1) : R(kG0);
-  f1 += w1 * r;
-  f0 += r - w1 * r;
+__device__ __forceinline__ void interp_t2(R r0, R r1, R& n0, R& n1) {
+  n0 = R(kG1) * r0 + R(kG0) * r1;
+  n1 = R(kG0) * r0 + R(kG1) * r1;
 }
 
 // T[j][m][n] (point values summed over the Gauss coordinate along j) -> f[a]
+// (assigned: the x part writes every node once, y and z add to it)
 template <typename R>
 __device__ __forceinline__ void q1_div_sf(const R (&T)[3][2][2], R (&f)[8]) {
-  // x: T[0][gy][gz] -> (ay, az) by transposed z then y interpolation -> +-1 along x
+  // x: T[0][gy][gz] -> z transposed -> y transposed -> -1 / +1 on ax = 0 / 1
   {
-    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gy][az]
+    R u[2][2], w[2][2];                      // u[gy][az], w[ay][az]
 #pragma unroll
-    for (int gy = 0; gy < 2; ++gy)
+    for (int gy = 0; gy < 2; ++gy) interp_t2(T[0][gy][0], T[0][gy][1], u[gy][0], u[gy][1]);
 #pragma unroll
-      for (int gz = 0; gz < 2; ++gz) interp_t(T[0][gy][gz], gz, u[gy][0], u[gy][1]);
+    for (int az = 0; az < 2; ++az) interp_t2(u[0][az], u[1][az], w[0][az], w[1][az]);
 #pragma unroll
-    for (int az = 0; az < 2; ++az) {
-      R w0 = R(0), w1 = R(0);                  // (ay = 0, 1)
+    for (int ay = 0; ay < 2; ++ay)
 #pragma unroll
-      for (int gy = 0; gy < 2; ++gy) interp_t(u[gy][az], gy, w0, w1);
-      f[1 + 4 * az] += w0; f[0 + 4 * az] -= w0;
-      f[3 + 4 * az] += w1; f[2 + 4 * az] -= w1;
-    }
+      for (int az = 0; az < 2; ++az) {
+        f[1 + 2 * ay + 4 * az] = w[ay][az];
+        f[0 + 2 * ay + 4 * az] = -w[ay][az];
+      }
   }
-  // y: T[1][gx][gz]
+  // y: T[1][gx][gz] -> z transposed -> x transposed -> -1 / +1 on ay = 0 / 1
   {
-    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gx][az]
+    R u[2][2], w[2][2];                      // u[gx][az], w[ax][az]
 #pragma unroll
-    for (int gx = 0; gx < 2; ++gx)
+    for (int gx = 0; gx < 2; ++gx) interp_t2(T[1][gx][0], T[1][gx][1], u[gx][0], u[gx][1]);
 #pragma unroll
-      for (int gz = 0; gz < 2; ++gz) interp_t(T[1][gx][gz], gz, u[gx][0], u[gx][1]);
+    for (int az = 0; az < 2; ++az) interp_t2(u[0][az], u[1][az], w[0][az], w[1][az]);
 #pragma unroll
-    for (int az = 0; az < 2; ++az) {
-      R w0 = R(0), w1 = R(0);                  // (ax = 0, 1)
+    for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-      for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][az], gx, w0, w1);
-      f[2 + 4 * az] += w0; f[0 + 4 * az] -= w0;
-      f[3 + 4 * az] += w1; f[1 + 4 * az] -= w1;
-    }
+      for (int az = 0; az < 2; ++az) {
+        f[ax + 2 + 4 * az] += w[ax][az];
+        f[ax + 0 + 4 * az] -= w[ax][az];
+      }
   }
-  // z: T[2][gx][gy]
+  // z: T[2][gx][gy] -> y transposed -> x transposed -> -1 / +1 on az = 0 / 1
   {
-    R u[2][2] = {{R(0), R(0)}, {R(0), R(0)}};   // u[gx][ay]
+    R u[2][2], w[2][2];                      // u[gx][ay], w[ax][ay]
 #pragma unroll
-    for (int gx = 0; gx < 2; ++gx)
+    for (int gx = 0; gx < 2; ++gx) interp_t2(T[2][gx][0], T[2][gx][1], u[gx][0], u[gx][1]);
 #pragma unroll
-      for (int gy = 0; gy < 2; ++gy) interp_t(T[2][gx][gy], gy, u[gx][0], u[gx][1]);
+    for (int ay = 0; ay < 2; ++ay) interp_t2(u[0][ay], u[1][ay], w[0][ay], w[1][ay]);
 #pragma unroll
-    for (int ay = 0; ay < 2; ++ay) {
-      R w0 = R(0), w1 = R(0);                  // (ax = 0, 1)
+    for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-      for (int gx = 0; gx < 2; ++gx) interp_t(u[gx][ay], gx, w0, w1);
-      f[4 + 2 * ay] += w0; f[0 + 2 * ay] -= w0;
-      f[5 + 2 * ay] += w1; f[1 + 2 * ay] -= w1;
-    }
+      for (int ay = 0; ay < 2; ++ay) {
+        f[ax + 2 * ay + 4] += w[ax][ay];
+        f[ax + 2 * ay + 0] -= w[ax][ay];
+      }
   }
 }
 
@@ -676,7 +674,7 @@ __device__ __forceinline__ void tile_grad(const R (*f)[TILE], int q, int t0, int
   }
 }
 
-template <int MODE, int NV, int BX, int BY, int BZ>
+template <int MODE, int NV, int BX, int BY, int BZ, bool FULL>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(ElemArgs A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
@@ -686,10 +684,12 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
-  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
+  const int bx = FULL ? BX : min(BX, g.nx - x0), by = FULL ? BY : min(BY, g.ny - y0),
+            bz = FULL ? BZ : min(BZ, g.nz - z0);            // FULL: whole bricks only
   const int tx = bx + 2, ty = by + 2, tz = bz + 2;          // staged node tile
   const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;    // element brick
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = BrickShape<BX, BY, BZ>::threads;
   const int ntile = tx * ty * tz;
   // local tile node l <-> global node (origin - 1 + l) mod n
   auto tile_node = [&](int i) {
@@ -753,26 +753,32 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Em[i][j] = A.E[3 * i + j];
-    bool soft = false;   // some point of this element softens (c' != 0)
+    unsigned soft = 0;   // bit q: c' != 0 at point q
 #pragma unroll 1
     for (int q = 0; q < 8; ++q) {
       Sym tau;
       {
+        const double kh = A.khist[q * g.N + eg];   // issued before the gradient
         double H[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
         tile_grad(su, q, t0, sy, sz, H);
-        const double kh = A.khist[q * g.N + eg];
         const PointLaw P = eval_law(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
                                     A.mat.k0[ph], A.mat.kf[ph], kh);
 #pragma unroll
         for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
         if (owned) {
           A.a_out[q * g.N + eg] = P.a;
-          A.cp_out[q * g.N + eg] = P.cp;
-          soft |= P.cp != 0.0;
+          if (P.cp != 0.0) {
+            // rank-one factor of the softening term (c' > 0 where loading)
+            soft |= 1u << q;
+            const double r = sqrt(P.cp);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A.sw_out[(q * 6 + k) * g.N + eg] = r * P.s.v[k];
+            red[RES_NSOFT] += 1.0;
+          }
           double hh = 0.0;
 #pragma unroll
           for (int i = 0; i < 3; ++i)
@@ -793,7 +799,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
           for (int i = 0; i < 3; ++i) f[i][a] += w * sym_at(tau, i, j);
         }
     }
-    if (owned) A.soft_out[eg] = soft ? 1 : 0;
+    if (owned) A.soft_out[eg] = (uint8_t)soft;
   }
   // assembly into the owned nodes, one local node per phase
 #pragma unroll
@@ -827,7 +833,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
 //   TRI_PP  |p|^2,  TRI_HH |H + p|^2
 // No nodal output, so no halo elements: one thread per owned element, the
 // nodes of u and v staged on the (BX+1)(BY+1)(BZ+1) tile.
-template <int BX, int BY, int BZ>
+template <int BX, int BY, int BZ, bool FULL>
 __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
   constexpr int kTile = (BX + 1) * (BY + 1) * (BZ + 1);
   const Grid& g = A.g;
@@ -837,9 +843,11 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
-  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
+  const int bx = FULL ? BX : min(BX, g.nx - x0), by = FULL ? BY : min(BY, g.ny - y0),
+            bz = FULL ? BZ : min(BZ, g.nz - z0);            // FULL: whole bricks only
   const int tx = bx + 1, ty = by + 1, tz = bz + 1;          // staged node tile
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = BX * BY * BZ;
   const int ntile = tx * ty * tz;
   for (int i = tid; i < ntile; i += nt) {
     const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
@@ -864,11 +872,24 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
   if (ex < bx && ey < by && ez < bz) {
     const long long eg = lin(g, x0 + ex, y0 + ey, z0 + ez);
     const int ph = A.phase[eg];
+    const unsigned soft = A.soft[eg];
     const double lam = A.mat.lam[ph], mu = A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     const int sy = tx, sz = tx * ty;
 #pragma unroll 1
     for (int q = 0; q < 8; ++q) {
+      // the point's state first, so that its loads overlap the gradients:
+      // kappa_hist, a and, at a softening point, w = sqrt(c') s
+      const bool sq = (soft >> q) & 1u;
+      const double kh = A.khist[q * g.N + eg];
+      const double ao = A.a[q * g.N + eg];
+      Sym w;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w.v[k] = 0.0;
+      if (sq) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w.v[k] = A.sw[(q * 6 + k) * g.N + eg];
+      }
       double H[3][3], p[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -884,13 +905,11 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
-      const double kh = A.khist[q * g.N + eg];
       const PointLaw P = eval_law(eval_strain<3>(Ht, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
                                   A.mat.k0[ph], A.mat.kf[ph], kh);
       Sym tau;
 #pragma unroll
       for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
-      const double ao = A.a[q * g.N + eg], co = A.cp[q * g.N + eg];
       const Sym ps = sym_of<3>(p);
       const Sym so = c_contract(eval_strain<3>(H, A.mat, ph), lam, mu);
       const double s_p = sym_dot(so, ps);
@@ -905,7 +924,13 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
           hh += Ht[i][j] * Ht[i][j];
         }
       red[TRI_SP] += ao * s_p;
-      red[TRI_PBP] += ao * pCp - co * s_p * s_p;
+      // c' (s:p)^2 = (w:p)^2
+      double soft_pp = 0.0;
+      if (sq) {
+        const double wp = sym_dot(w, ps);
+        soft_pp = wp * wp;
+      }
+      red[TRI_PBP] += ao * pCp - soft_pp;
       red[TRI_STP] += sym_dot(tau, ps);
       red[TRI_PP] += pp;
       red[TRI_HH] += hh;
@@ -914,38 +939,39 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
   block_reduce_store<TRI_NV>(red, A.red.partials);
 }
 
-// Hessian K v = D^T B D v at the state (u, a, c'), in FP64 (R = double) or,
-// for the mixed-precision CG, FP32 (R = float) with the reduction terms
-// {v.Kv, |D v|^2} accumulated in FP64. The same brick scheme as k_brick: the
-// direction is staged on the tile, the displacement only if some element of
-// the brick softens (c' != 0 at one of its points; a per-element flag written
-// by the residual pass). The gradient of v and the
-// divergence are sum-factorised; s = C : eps(u) is recomputed at softening
-// points only.
+// Hessian K v = D^T B D v at the state, in FP64 (R = double) or, for the
+// mixed-precision CG, FP32 (R = float) with the reduction terms {v.Kv, |D v|^2}
+// accumulated in FP64. The same brick scheme as k_brick, with the direction
+// staged on the tile. The gradient of v and the divergence are
+// sum-factorised. The tangent at a point is a C minus the rank-one softening
+// term, which the residual pass stored as w = sqrt(c') s at the points where
+// c' != 0 (bit q of the element's soft mask): B : e = a C : e - (w : e) w.
+// The state displacement is not read.
 // FP32: at most 128 VGPRs (4 waves per SIMD), which the FP32 kernel fits
 // without spills; FP64 keeps the compiler's choice.
 template <typename R> constexpr int hessian_waves_per_eu() { return sizeof(R) == 4 ? 4 : 1; }
 
-template <typename R, int BX, int BY, int BZ>
+template <typename R, int BX, int BY, int BZ, bool FULL>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
     k_hessian(HessArgs<R> A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
   if (A.cg && A.cg->done) return;
   __shared__ R sv[3][kTile];
-  __shared__ R su[3][kTile];
   __shared__ R acc[3][kOwn];
-  __shared__ int need_u_flag;
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
-  const int bx = min(BX, g.nx - x0), by = min(BY, g.ny - y0), bz = min(BZ, g.nz - z0);
+  // FULL: every brick is whole (the grid is a multiple of the brick), so the
+  // brick extents and all index arithmetic on them are compile-time constants
+  const int bx = FULL ? BX : min(BX, g.nx - x0), by = FULL ? BY : min(BY, g.ny - y0),
+            bz = FULL ? BZ : min(BZ, g.nz - z0);
   const int tx = bx + 2, ty = by + 2, tz = bz + 2;
   const int ex_n = bx + 1, ey_n = by + 1, ez_n = bz + 1;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = BrickShape<BX, BY, BZ>::threads;
   const int ntile = tx * ty * tz;
-  if (tid == 0) need_u_flag = 0;
   auto tile_node = [&](int i) {
     const int lx = i % tx, ly = (i / tx) % ty, lz = i / (tx * ty);
     return lin(g, wrap(x0 - 1 + lx, g.nx), wrap(y0 - 1 + ly, g.ny), wrap(z0 - 1 + lz, g.nz));
@@ -981,16 +1007,13 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
   long long eg = 0;
   int ph = 0;
+  unsigned soft = 0;
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
-    if (A.soft[eg]) need_u_flag = 1;
+    soft = A.soft[eg];
   }
   __syncthreads();
-  if (need_u_flag) {
-    stage(A.u, su);
-    __syncthreads();
-  }
   R f[3][8];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -1011,15 +1034,26 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
         v[a] = sv[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
       q1_grad_sf(v, G[c]);
     }
+    if (owned) {
+      // |D v|^2 over the points: each G value is the gradient entry of the
+      // two points that differ only in the Gauss coordinate along j
+      double s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) s2 += (double)G[c][j][m][k] * (double)G[c][j][m][k];
+      dd = 2.0 * s2;
+    }
+    const R* __restrict__ a_e = A.a + eg;
+    const double* __restrict__ w_e = A.sw + eg;
+    const long long N = g.N;
+    // T[c][j][m][n]: tau_cj summed over the Gauss coordinate along j; an
+    // entry is written at the first of its two points and added at the second
     R T[3][3][2][2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int k = 0; k < 2; ++k) T[c][j][m][k] = R(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
@@ -1030,31 +1064,32 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
         dH[c][1] = G[c][1][gx][gz];
         dH[c][2] = G[c][2][gx][gy];
       }
-      const R aq = A.a[q * g.N + eg], cq = A.cp[q * g.N + eg];
-      SymT<R> s;
+      // tau = a C : e - (w : e) w with e = sym(dH); h_ij = 2 e_ij
+      const R aq = a_e[q * N];
+      const R h01 = dH[0][1] + dH[1][0], h02 = dH[0][2] + dH[2][0], h12 = dH[1][2] + dH[2][1];
+      const R al = aq * lam, am = aq * mu;
+      const R ltr = al * (dH[0][0] + dH[1][1] + dH[2][2]), am2 = am + am;
+      R t00 = ltr + am2 * dH[0][0], t11 = ltr + am2 * dH[1][1], t22 = ltr + am2 * dH[2][2];
+      R t01 = am * h01, t02 = am * h02, t12 = am * h12;
+      if ((soft >> q) & 1u) {
+        R w[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) s.v[k] = R(0);
-      if (cq != R(0)) {
-        R H[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) H[i][j] = (R)A.E[3 * i + j];
-        tile_grad<kTile>(su, q, t0, sy, sz, H);
-        s = c_contract(eval_strain<3>(H, A.mat, ph), lam, mu);
+        for (int k = 0; k < 6; ++k) w[k] = (R)w_e[(q * 6 + k) * N];
+        const R we = w[0] * dH[0][0] + w[1] * dH[1][1] + w[2] * dH[2][2] + w[3] * h01 +
+                     w[4] * h02 + w[5] * h12;
+        t00 -= we * w[0];
+        t11 -= we * w[1];
+        t22 -= we * w[2];
+        t01 -= we * w[3];
+        t02 -= we * w[4];
+        t12 -= we * w[5];
       }
-      const SymT<R> tau = apply_tangent(sym_of<3>(dH), aq, cq, s, lam, mu);
-      if (owned) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) dd += (double)dH[i][j] * (double)dH[i][j];
-      }
+      const R tau[3][3] = {{t00, t01, t02}, {t01, t11, t12}, {t02, t12, t22}};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T[c][0][gy][gz] += sym_at(tau, c, 0);
-        T[c][1][gx][gz] += sym_at(tau, c, 1);
-        T[c][2][gx][gy] += sym_at(tau, c, 2);
+        if (gx == 0) T[c][0][gy][gz] = tau[c][0]; else T[c][0][gy][gz] += tau[c][0];
+        if (gy == 0) T[c][1][gx][gz] = tau[c][1]; else T[c][1][gx][gz] += tau[c][1];
+        if (gz == 0) T[c][2][gx][gy] = tau[c][2]; else T[c][2][gx][gy] += tau[c][2];
       }
     }
 #pragma unroll
@@ -1096,8 +1131,13 @@ template <int MODE, int NV, int BX, int BY, int BZ>
 hipError_t launch_brick_shape(const ElemArgs& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
-  hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ>), dim3(nb), dim3(BrickShape<BX, BY, BZ>::threads),
-                     0, s, A);
+  const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
+  if (full)
+    hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, true>), dim3(nb),
+                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, false>), dim3(nb),
+                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
   return hipGetLastError();
 }
 
@@ -1114,21 +1154,29 @@ template <typename R, int BX, int BY, int BZ>
 hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
-  hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ>), dim3(nb), dim3(BrickShape<BX, BY, BZ>::threads), 0,
-                     s, A);
+  const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
+  if (full)
+    hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true>), dim3(nb),
+                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false>), dim3(nb),
+                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
   return hipGetLastError();
 }
 
 // Hessian brick shapes: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768),
-// 2 = 16x8x4 (768), 3 = 16x4x4 (448).
+// 2 = 16x8x4 (768), 3 = 16x4x4 (448), 4 = 8x4x4 (256: two blocks share a CU
+// at the FP64 kernel's register count, so one block's loads overlap the
+// other's arithmetic, for 1.76 instead of 1.58 elements per owned node).
 template <typename R>
 hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
-  if (!A.v || !A.f || !A.u || !A.a || !A.cp || !A.phase || !A.soft || !A.E || !A.red.partials)
+  if (!A.v || !A.f || !A.a || !A.sw || !A.phase || !A.soft || !A.E || !A.red.partials)
     return hipErrorInvalidValue;
   switch (A.brick_shape) {
     case 1: return launch_hessian_shape<R, 8, 8, 8>(A, s, nblocks);
     case 2: return launch_hessian_shape<R, 16, 8, 4>(A, s, nblocks);
     case 3: return launch_hessian_shape<R, 16, 4, 4>(A, s, nblocks);
+    case 4: return launch_hessian_shape<R, 8, 4, 4>(A, s, nblocks);
     default: return launch_hessian_shape<R, 8, 8, 4>(A, s, nblocks);
   }
 }
@@ -1148,16 +1196,22 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
+  if (!A.u || !A.f || !A.a_out || !A.soft_out || !A.sw_out || !A.khist || !A.phase || !A.E ||
+      !A.red.partials)
+    return hipErrorInvalidValue;
   return launch_brick<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
 }
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
-  if (!A.u || !A.v || !A.a || !A.cp || !A.khist || !A.phase || !A.E || !A.red.partials)
+  if (!A.u || !A.v || !A.a || !A.soft || !A.sw || !A.khist || !A.phase || !A.E || !A.red.partials)
     return hipErrorInvalidValue;
   constexpr int BX = 8, BY = 8, BZ = 4;
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
-  hipLaunchKernelGGL((k_trial<BX, BY, BZ>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
+  if (A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0)
+    hipLaunchKernelGGL((k_trial<BX, BY, BZ, true>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_trial<BX, BY, BZ, false>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
   return hipGetLastError();
 }
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
@@ -1168,9 +1222,8 @@ hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   H.E = A.E;
   H.phase = A.phase;
   H.soft = A.soft;
-  H.u = A.u;
+  H.sw = A.sw;
   H.a = A.a;
-  H.cp = A.cp;
   H.v = A.v;
   H.f = A.f;
   H.red = A.red;

@@ -199,7 +199,7 @@ struct Passes<L, 1, NS, INV> {
 
 // In-place transform of nl lines of runtime length L (uniform over the block).
 template <bool INV, typename V>
-__device__ void lds_fft(int L, V* buf, int nl, int ls, int es, const V* tw) {
+__device__ __forceinline__ void lds_fft(int L, V* buf, int nl, int ls, int es, const V* tw) {
   switch (L) {
     case 2: Passes<2, 2, 1, INV>::run(buf, nl, ls, es, tw); break;
     case 3: Passes<3, 3, 1, INV>::run(buf, nl, ls, es, tw); break;
@@ -306,12 +306,52 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   const int z = blockIdx.x, c = blockIdx.y;
   const long long plane = (long long)c * g.N + (long long)z * nx * ny;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int npairs = M * ny;   // the plane's reals in pairs (x even, x odd)
+  // The fused CG passes read vectors of the plane that do not depend on the
+  // decisions or on the transform: their first kPre pairs per thread are
+  // loaded before the row sums (forward) or the spectrum (inverse), so that
+  // these memory latencies overlap.
+  constexpr int kPre = 4;
+  constexpr bool kFused = MODE == PLANE_FWD_CG || MODE == PLANE_INV_CG;
+  V pa[kFused ? kPre : 1], pb[kFused ? kPre : 1], pc[MODE == PLANE_FWD_CG ? kPre : 1],
+      pd[MODE == PLANE_FWD_CG ? kPre : 1];
+  // forward: pa = Kd, pb = z, pc = d, pd = g; inverse: pa = y, pb = g
+  auto load_round = [&](int base) {
+    if constexpr (MODE == PLANE_FWD_CG) {
+      const V* kd2 = reinterpret_cast<const V*>(in + plane);
+      const V* z2 = reinterpret_cast<const V*>(cf.z + plane);
+      const V* d2 = reinterpret_cast<const V*>(cf.d + plane);
+      const V* g2 = reinterpret_cast<const V*>(cf.g + plane);
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int i = base + u * nt + tid;
+        if (i < npairs) {
+          pa[u] = kd2[i];
+          pb[u] = z2[i];
+          pc[u] = d2[i];
+          pd[u] = g2[i];
+        }
+      }
+    } else if constexpr (MODE == PLANE_INV_CG) {
+      const V* y2 = reinterpret_cast<const V*>(cf.y + plane);
+      const V* g2 = reinterpret_cast<const V*>(cf.g + plane);
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int i = base + u * nt + tid;
+        if (i < npairs) {
+          pa[u] = y2[i];
+          pb[u] = g2[i];
+        }
+      }
+    }
+  };
   // CG state of this pass: the forward pass takes the direction and
   // curvature decisions itself (every block on its own copy, from the same
   // rows in the same order, so all copies agree); the inverse pass reads it
   __shared__ CgState sst;
   if constexpr (MODE == PLANE_FWD_CG) {
     if (!cf.st_in->done) {
+      load_round(0);
       double td[2], tc[2];
       block_sum_rows<2>(cf.rows_dir, cf.nb_dir, td);
       block_sum_rows<2>(cf.rows_hes, cf.nb_hes, tc);
@@ -330,13 +370,22 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
       // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
       if (sst.apply_tau && !cf.st_in->done) {
         const R tau = (R)sst.tau;
-        for (int i = tid; i < nx * ny; i += nt) cf.z[plane + i] += tau * cf.d[plane + i];
+        V* z2 = reinterpret_cast<V*>(cf.z + plane);
+        for (int base = 0; base < npairs; base += kPre * nt) {
+          if (base > 0) load_round(base);
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const int i = base + u * nt + tid;
+            if (i < npairs) z2[i] = mk<V>(pb[u].x + tau * pc[u].x, pb[u].y + tau * pc[u].y);
+          }
+        }
       }
       return;
     }
   }
   if constexpr (MODE == PLANE_INV_CG) {
     if (cf.st_in->done) return;
+    load_round(0);
   }
   if (skip && skip->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -358,22 +407,33 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   // start from the half spectrum
   constexpr bool kRealInput = MODE == PLANE_FWD || MODE == PLANE_FWD_CG || MODE == PLANE_GREEN2D;
   if (kRealInput) {
-    const V* src = reinterpret_cast<const V*>(in + plane);
-    staged_copy<V>(M * ny, [&](int i) { return src[i]; },
-                   [&](int i, V v) {
-                     const int y = i / M, m = i - y * M;
-                     lds[y * P + m] = v;
-                   });
-    __syncthreads();
-    if (MODE == PLANE_FWD_CG) {
+    if constexpr (MODE == PLANE_FWD_CG) {
       // z += alpha d, g += alpha Kd on this plane (Kd is the transform input)
       const R alpha = (R)sst.alpha;
-      const R* kd = in + plane;
-      for (int i = tid; i < nx * ny; i += nt) {
-        cf.z[plane + i] += alpha * cf.d[plane + i];
-        cf.g[plane + i] += alpha * kd[i];
+      V* z2 = reinterpret_cast<V*>(cf.z + plane);
+      V* g2 = reinterpret_cast<V*>(cf.g + plane);
+      for (int base = 0; base < npairs; base += kPre * nt) {
+        if (base > 0) load_round(base);
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+          const int i = base + u * nt + tid;
+          if (i < npairs) {
+            z2[i] = mk<V>(pb[u].x + alpha * pc[u].x, pb[u].y + alpha * pc[u].y);
+            g2[i] = mk<V>(pd[u].x + alpha * pa[u].x, pd[u].y + alpha * pa[u].y);
+            const int y = i / M, m = i - y * M;
+            lds[y * P + m] = pa[u];
+          }
+        }
       }
+    } else {
+      const V* src = reinterpret_cast<const V*>(in + plane);
+      staged_copy<V>(M * ny, [&](int i) { return src[i]; },
+                     [&](int i, V v) {
+                       const int y = i / M, m = i - y * M;
+                       lds[y * P + m] = v;
+                     });
     }
+    __syncthreads();
     lds_fft<false>(M, lds, ny, P, 1, twx);
     split_r2c(lds, M, ny, P, twp);
     lds_fft<false>(ny, lds, P, 1, P, twy);
@@ -401,17 +461,23 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
     // w never leaves LDS
     const R alpha = (R)cf.st_in->alpha;
     V* y2 = reinterpret_cast<V*>(cf.y + plane);
-    const V* g2 = reinterpret_cast<const V*>(cf.g + plane);
     double acc[2] = {0.0, 0.0};
-    for (int i = tid; i < M * ny; i += nt) {
-      const int yy = i / M, m = i - yy * M;
-      const V w = lds[yy * P + m];
-      const V yo = y2[i];
-      const V gi = g2[i];
-      const V yn = mk<V>(yo.x + alpha * w.x, yo.y + alpha * w.y);
-      y2[i] = yn;
-      acc[0] += (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
-      acc[1] += (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
+    for (int base = 0; base < npairs; base += kPre * nt) {
+      if (base > 0) load_round(base);
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int i = base + u * nt + tid;
+        if (i < npairs) {
+          const int yy = i / M, m = i - yy * M;
+          const V w = lds[yy * P + m];
+          const V yo = pa[u];
+          const V gi = pb[u];
+          const V yn = mk<V>(yo.x + alpha * w.x, yo.y + alpha * w.y);
+          y2[i] = yn;
+          acc[0] += (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
+          acc[1] += (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
+        }
+      }
     }
     block_reduce_store<2>(acc, cf.partials, (int)(blockIdx.y * gridDim.x + blockIdx.x));
     return;

@@ -95,6 +95,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restric
                                                  const CgState* st, const double* rows_res,
                                                  int nb_res, CgState* st_out, double* trace) {
   __shared__ CgState sst;
+  // the vectors do not depend on the decision: the first kPre elements of
+  // this thread are loaded before the row sums, so the latencies overlap
+  constexpr int kPre = 4;
+  const long long first = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  R py[kPre], pd[kPre], pz[kPre];
+  double pg[kPre];
+  auto load_round = [&](long long base) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const long long i = base + u * stride;
+      if (i < n) {
+        py[u] = y[i];
+        pd[u] = d[i];
+        pg[u] = g[i];
+        pz[u] = z[i];
+      }
+    }
+  };
+  if (!st->done) load_round(first);
   if (rows_res) {
     if (!st->done) {
       double t[2];
@@ -116,14 +136,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restric
   if (sst.done) return;
   const R beta = (R)sst.beta;
   double acc[2] = {0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    // beta = 0 starts a new direction without reading the old one
-    const R dn = beta == R(0) ? -y[i] : -y[i] + beta * d[i];
-    d[i] = dn;
-    const double gi = g[i];
-    acc[0] += gi * (double)dn;     // <r, d>
-    acc[1] += (double)z[i] * gi;   // z . g for <z, d>
+  for (long long base = first; base < n; base += kPre * stride) {
+    if (base != first) load_round(base);
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const long long i = base + u * stride;
+      if (i < n) {
+        // beta = 0 starts a new direction without using the old one
+        const R dn = beta == R(0) ? -py[u] : -py[u] + beta * pd[u];
+        d[i] = dn;
+        const double gi = pg[u];
+        acc[0] += gi * (double)dn;       // <r, d>
+        acc[1] += (double)pz[u] * gi;    // z . g for <z, d>
+      }
+    }
   }
   block_reduce_store<2>(acc, r.partials);
 }
@@ -168,8 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(Reducer r, int nblocks, int n
   __shared__ double wsum[kBlock / 64][kMaxPartials];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < nv; ++k) {
-    double s = 0.0;
-    for (int row = threadIdx.x; row < nblocks; row += blockDim.x) s += r.partials[(size_t)row * nv + k];
+    double s = strided_row_sum(r.partials, nblocks, nv, k, threadIdx.x, blockDim.x);
     s = wave_sum(s);
     if (lane == 0) wsum[wave][k] = s;
   }
@@ -196,11 +221,11 @@ __global__ void __launch_bounds__(kBlock) k_finish(Reducer r, int nblocks, int n
 __device__ __forceinline__ void sum_rows2(const double* __restrict__ rows, int nb, double (&tot)[2]) {
   __shared__ double wsum[kBlock / 64][2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double s[2];
+  strided_row_sums<2>(rows, nb, threadIdx.x, blockDim.x, s);
   for (int k = 0; k < 2; ++k) {
-    double s = 0.0;
-    for (int row = threadIdx.x; row < nb; row += blockDim.x) s += rows[(size_t)row * 2 + k];
-    s = wave_sum(s);
-    if (lane == 0) wsum[wave][k] = s;
+    const double sk = wave_sum(s[k]);
+    if (lane == 0) wsum[wave][k] = sk;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

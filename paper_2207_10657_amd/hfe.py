@@ -125,6 +125,8 @@ EXPORTS = {
                                         ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),
+    "hfe_soft_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
     "hfe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
@@ -496,3 +498,10 @@ class Solver:
         self._check(self.lib.hfe_kernel_stats(self.ctx, names, counts, ms, max_kernels,
                                               ctypes.byref(n)))
         return {names[i].decode(): (counts[i], ms[i]) for i in range(n.value)}
+
+    def soft_points(self):
+        """(softening points of the evaluated state, their mean over the Hessian
+        launches timed since the last set_profiling)."""
+        cur, mean = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.hfe_soft_points(self.ctx, ctypes.byref(cur), ctypes.byref(mean)))
+        return cur.value, mean.value

@@ -21,7 +21,7 @@ def _shapes(solver):
     out = []
     for pt in (256, 512, 1024):
         for pc, pth in ((4, 64), (4, 128), (8, 64), (8, 128), (8, 256), (16, 128), (16, 256), (32, 256)):
-            for bs in range(4):
+            for bs in range(5):
                 try:
                     solver.set_tuning(plane_threads=pt, pencil_cols=pc, pencil_threads=pth,
                                       plane_threads32=pt, pencil_cols32=pc, pencil_threads32=pth,
