@@ -261,9 +261,9 @@ def read_pmc(path):
                 name = row.get("Kernel_Name", "").replace(" ", "")
                 label = next((lab for key, lab in PMC_KERNELS if key in name), None)
                 if label == "stiffness":
-                    # one entry per brick shape: k_hessian<double,BX,BY,BZ>
-                    dims = name.split("k_hessian<double,", 1)[1].split(">", 1)[0]
-                    label = "stiffness:" + dims.replace(",", "x")
+                    # one entry per brick shape: k_hessian<double,BX,BY,BZ,FULL>
+                    dims = name.split("k_hessian<double,", 1)[1].split(">", 1)[0].split(",")[:3]
+                    label = "stiffness:" + "x".join(dims)
                 if label is not None:
                     rows.append((int(row["Dispatch_Id"]), label, float(row["Counter_Value"])))
     out = {}

@@ -729,9 +729,12 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
   const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
   long long eg = 0;
   int ph = 0;
+  double kh[8];        // the history of the element's points, loaded with the tile
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) kh[q] = A.khist[q * g.N + eg];
   }
   stage(A.u, su);
   __syncthreads();
@@ -753,52 +756,64 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Em[i][j] = A.E[3 * i + j];
+    // sum-factorised gradient of u at the 8 points (as in the Hessian)
+    double G[3][3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        v[a] = su[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
+      q1_grad_sf(v, G[c]);
+    }
     unsigned soft = 0;   // bit q: c' != 0 at point q
-#pragma unroll 1
+    // T[c][j][m][n]: sigma_cj summed over the Gauss coordinate along j
+    double T[3][3][2][2];
+#pragma unroll
     for (int q = 0; q < 8; ++q) {
+      const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
+      double H[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        H[c][0] = Em[c][0] + G[c][0][gy][gz];
+        H[c][1] = Em[c][1] + G[c][1][gx][gz];
+        H[c][2] = Em[c][2] + G[c][2][gx][gy];
+      }
+      const PointLaw P = eval_law(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph],
+                                  A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh[q]);
       Sym tau;
-      {
-        const double kh = A.khist[q * g.N + eg];   // issued before the gradient
-        double H[3][3];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
+      if (owned) {
+        A.a_out[q * g.N + eg] = P.a;
+        if (P.cp != 0.0) {
+          // rank-one factor of the softening term (c' > 0 where loading)
+          soft |= 1u << q;
+          const double r = sqrt(P.cp);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) A.sw_out[(q * 6 + k) * g.N + eg] = r * P.s.v[k];
+          red[RES_NSOFT] += 1.0;
+        }
+        double hh = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) H[i][j] = Em[i][j];
-        tile_grad(su, q, t0, sy, sz, H);
-        const PointLaw P = eval_law(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
-                                    A.mat.k0[ph], A.mat.kf[ph], kh);
+          for (int j = 0; j < 3; ++j) hh += H[i][j] * H[i][j];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
-        if (owned) {
-          A.a_out[q * g.N + eg] = P.a;
-          if (P.cp != 0.0) {
-            // rank-one factor of the softening term (c' > 0 where loading)
-            soft |= 1u << q;
-            const double r = sqrt(P.cp);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) A.sw_out[(q * 6 + k) * g.N + eg] = r * P.s.v[k];
-            red[RES_NSOFT] += 1.0;
-          }
-          double hh = 0.0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) hh += H[i][j] * H[i][j];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
-          red[RES_SS] += sym_dot(tau, tau);
-          red[RES_HH] += hh;
-        }
+        for (int k = 0; k < 6; ++k) red[RES_S0 + k] += tau.v[k];
+        red[RES_SS] += sym_dot(tau, tau);
+        red[RES_HH] += hh;
       }
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double w = kQ1B.v[q][a][j];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) f[i][a] += w * sym_at(tau, i, j);
-        }
+      for (int c = 0; c < 3; ++c) {
+        const double t0c = sym_at(tau, c, 0), t1c = sym_at(tau, c, 1), t2c = sym_at(tau, c, 2);
+        if (gx == 0) T[c][0][gy][gz] = t0c; else T[c][0][gy][gz] += t0c;
+        if (gy == 0) T[c][1][gx][gz] = t1c; else T[c][1][gx][gz] += t1c;
+        if (gz == 0) T[c][2][gx][gy] = t2c; else T[c][2][gx][gy] += t2c;
+      }
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
     if (owned) A.soft_out[eg] = (uint8_t)soft;
   }
   // assembly into the owned nodes, one local node per phase
@@ -997,21 +1012,27 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
       }
     }
   };
-  stage(A.v, sv);
-  for (int i = tid; i < bx * by * bz; i += nt) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c][i] = R(0);
-  }
+  // this thread's element and its state (phase, softening mask, a at the 8
+  // points), loaded before the tile so that all these loads are in flight
+  // together
   const int ne = ex_n * ey_n * ez_n;
   const bool active = tid < ne;
   const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
   long long eg = 0;
   int ph = 0;
   unsigned soft = 0;
+  R aq[8];
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
     ph = A.phase[eg];
     soft = A.soft[eg];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) aq[q] = A.a[q * g.N + eg];
+  }
+  stage(A.v, sv);
+  for (int i = tid; i < bx * by * bz; i += nt) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c][i] = R(0);
   }
   __syncthreads();
   R f[3][8];
@@ -1048,7 +1069,6 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
             for (int k = 0; k < 2; ++k) s2 += (double)G[c][j][m][k] * (double)G[c][j][m][k];
       dd = 2.0 * s2;
     }
-    const R* __restrict__ a_e = A.a + eg;
     const double* __restrict__ w_e = A.sw + eg;
     const long long N = g.N;
     // T[c][j][m][n]: tau_cj summed over the Gauss coordinate along j; an
@@ -1065,9 +1085,8 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
         dH[c][2] = G[c][2][gx][gy];
       }
       // tau = a C : e - (w : e) w with e = sym(dH); h_ij = 2 e_ij
-      const R aq = a_e[q * N];
       const R h01 = dH[0][1] + dH[1][0], h02 = dH[0][2] + dH[2][0], h12 = dH[1][2] + dH[2][1];
-      const R al = aq * lam, am = aq * mu;
+      const R al = aq[q] * lam, am = aq[q] * mu;
       const R ltr = al * (dH[0][0] + dH[1][1] + dH[2][2]), am2 = am + am;
       R t00 = ltr + am2 * dH[0][0], t11 = ltr + am2 * dH[1][1], t22 = ltr + am2 * dH[2][2];
       R t01 = am * h01, t02 = am * h02, t12 = am * h12;
