@@ -229,6 +229,7 @@ PMC_KERNELS = [("k_hessian<double,", "stiffness"), ("k_brick<0,", "residual"),
                ("k_plane<0,double>", "fft_plane_fwd"), ("k_pencil<0,double>", "fft_pencil_green"),
                ("k_plane<1,double>", "fft_plane_inv"), ("copyBuffer", "copy")]
 PROBE_REPS = 5
+LBFGS_STEPS = 2
 PROBE_STEPS = 3
 # Hessian brick shapes (nodes per axis, x y z) by tuning index
 BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4), 4: (8, 4, 4)}
@@ -408,6 +409,8 @@ def main():
                     help="skip the mixed-precision run of the same steps")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the six-load-case batch run")
+    ap.add_argument("--no-lbfgs", action="store_true",
+                    help="skip the L-BFGS run of the first timed load steps")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the learned warm-start run (16^3 cells)")
     ap.add_argument("--probe", action="store_true",
@@ -531,6 +534,27 @@ def main():
                  "note": "same load steps from the same checkpoint; the reference is the FP64 "
                          "GPU solve above (the FP64 path is checked against the oracle)"}
 
+    # the paper's quasi-Newton remark: the first LBFGS_STEPS timed increments
+    # from the same checkpoint by L-BFGS on the approximate energy increment
+    lbfgs = None
+    if not args.no_lbfgs:
+        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        per = []
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for n in range(W, W + min(LBFGS_STEPS, K)):
+            s.apply_load_step(w.load_path[n])
+            r = s.solve_increment_lbfgs()
+            per.append({k: r[k] for k in ("iters", "trials", "pairs_skipped", "resets", "r_eq",
+                                          "converged", "time_ms")})
+        torch.cuda.synchronize()
+        dtl = time.perf_counter() - t3
+        lbfgs = {"steps": len(per), "ms_per_step": dtl / max(len(per), 1) * 1e3,
+                 "per_step": per,
+                 "newton_ms_per_step": dt / K * 1e3,
+                 "note": "m = 5, Armijo on the approximate energy increment; same checkpoint "
+                         "as the timed Newton steps"}
+
     # dominant kernel: largest total time in the timed region
     kern = max(stats.items(), key=lambda kv: kv[1][1])
     kname, (kcount, kms) = kern
@@ -569,6 +593,7 @@ def main():
                          "same checkpoint (kernel-by-kernel launches, %.1f ms/step)" % (dt_prof / K * 1e3),
         "kernels_ms": {k: {"launches": c, "total_ms": m} for k, (c, m) in stats.items() if c},
         "mixed_precision": mixed,
+        "lbfgs": lbfgs,
     }
     if not args.no_batch:
         out["batch_six_load_cases"] = batch_bench(w, 2)

@@ -169,6 +169,46 @@ hfe_status hfe_apply_load_step(hfe_ctx* ctx, const double dE[9]);
 hfe_status hfe_solve_increment(hfe_ctx* ctx, const hfe_solver_params* params,
                                hfe_solve_report* out);
 
+/* Quasi-Newton alternative to hfe_solve_increment for the same increment:
+ * L-BFGS on the approximate incremental energy. Sec. 2.2 notes that the
+ * first-order energy increment of eq. incr_energy_func makes quasi-Newton
+ * solvers usable; the method below is this library's reading of that remark:
+ *   direction p = -H_k g (g = G sigma) by the two-loop recursion over the
+ *   last m pairs (s, y), H_0 = gamma I, gamma = s.y / y.y of the newest pair,
+ *   before any pair 1 / max over phases of (lambda + 2 mu); a direction with
+ *   sigma:p >= 0 is replaced by -gamma g and the pairs dropped;
+ *   step: alpha = 1, halved up to max_backtracks times, until
+ *   DeltaW_bar(alpha p) = (sigma + sigma(u + alpha p)) : alpha p / 2
+ *   <= c1 alpha sigma:p (history frozen);
+ *   a pair is kept iff s.y > 1e-12 |s| |y|;
+ *   convergence and commit of the history as Algorithm 2 (r_eq <= eta_eq, or
+ *   r_NR <= eta_nr after an accepted step).
+ * Inner products are those of strain space (s.y = du . dg0 with g0 = D^T sigma).
+ * FP64. `workspace`: device buffer of hfe_lbfgs_workspace_bytes(grid, m)
+ * bytes (borrowed; it holds the pairs and work vectors). HFE_EINVAL for
+ * m < 1 or m > HFE_LBFGS_MAX_M or a small workspace; `params` may be NULL
+ * (defaults below), `out` may be NULL. */
+#define HFE_LBFGS_MAX_M 32
+typedef struct {
+  double eta_eq;       /* 1e-8 */
+  double eta_nr;       /* 1e-8 */
+  int max_iters;       /* 500 quasi-Newton iterations */
+  int m;               /* 5 pairs */
+  double c1;           /* 1e-4 */
+  int max_backtracks;  /* 30 */
+} hfe_lbfgs_params;
+typedef struct {
+  int status;          /* HFE_CONVERGED or HFE_NOT_CONVERGED                      */
+  int iters;           /* quasi-Newton iterations (directions formed)            */
+  int trials;          /* energy evaluations of the line search                  */
+  int pairs_skipped;   /* pairs failing the curvature test                       */
+  int resets;          /* non-descent directions replaced by -gamma g            */
+  double r_eq, r_nr, time_ms;
+} hfe_lbfgs_report;
+size_t hfe_lbfgs_workspace_bytes(const hfe_grid* grid, int m);
+hfe_status hfe_solve_increment_lbfgs(hfe_ctx* ctx, const hfe_lbfgs_params* params,
+                                     void* workspace, size_t ws_bytes, hfe_lbfgs_report* out);
+
 /* Mean stress over all quadrature points (3x3; in 2D includes sigma_zz of
  * plane strain) at the last evaluated state. */
 hfe_status hfe_homogenized_stress(const hfe_ctx* ctx, double out[9]);
@@ -307,7 +347,7 @@ const char* hfe_last_error(const hfe_ctx* ctx);
  * fastest), n = {nx, ny, nz}; filter banks [cout][cin][27] with tap
  * (dz+1)*9 + (dy+1)*3 + (dx+1); the grid is periodic. BF16 values are
  * uint16_t (the upper half of an IEEE binary32, round to nearest even).
- * Channel counts: 1, 2, 3, 4, 6, 8 or 16. `stream` is a hipStream_t (NULL:
+ * Channel counts: 1, 2, 3, 4, 6, 8, 16 or 32. `stream` is a hipStream_t (NULL:
  * the default stream); the calls are asynchronous on it. HFE_EINVAL for bad
  * arguments, HFE_EDEVICE if a launch fails. */
 
@@ -339,6 +379,21 @@ hfe_status hfe_nn_adam(float* w, float* m, float* v, const float* g, long long n
                        void* stream);
 /* y = BF16(x). */
 hfe_status hfe_nn_to_bf16(const float* x, long long n, uint16_t* y, void* stream);
+/* Levels of the encoder-decoder. hfe_nn_pool2: the mean over 2x2x2 blocks of
+ * c FP32 channels on the fine grid n (all even) into FP32 out and / or its
+ * BF16 copy (either may be NULL, not both); hfe_nn_pool2_backward ADDS its
+ * adjoint (gout / 8 to each child) to the fine gin. hfe_nn_upsample2: nearest
+ * doubling of every axis of the coarse grid m into out / out_bf16;
+ * hfe_nn_upsample2_backward writes its adjoint (the sum over the 8 children)
+ * to the coarse gin. Device pointers, layout [c][z][y][x]. */
+hfe_status hfe_nn_pool2(const float* in, int c, const int n[3], float* out, uint16_t* out_bf16,
+                        void* stream);
+hfe_status hfe_nn_pool2_backward(const float* gout, int c, const int n[3], float* gin,
+                                 void* stream);
+hfe_status hfe_nn_upsample2(const float* in, int c, const int m[3], float* out,
+                            uint16_t* out_bf16, void* stream);
+hfe_status hfe_nn_upsample2_backward(const float* gout, int c, const int m[3], float* gin,
+                                     void* stream);
 
 #ifdef __cplusplus
 }

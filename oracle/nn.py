@@ -8,9 +8,11 @@ t = (dz+1)*9 + (dy+1)*3 + (dx+1), and out[co](v) = b[co] +
 sum_{ci,t} w[co, ci, t] in[ci](v + (dz, dy, dx)), indices periodic. FP64.
 
 Pinned by (``tests/test_oracle_nn.py``): explicit index loops on a tiny grid
-(the tap convention), the adjoint identity <conv x, y> = <x, conv^T y>, the
-weight gradient against finite differences of the (linear) map, and Adam's
-bias correction (a constant gradient gives m_hat = g at every step).
+(the tap convention, the 2x2x2 pooling and the nearest upsampling), the
+adjoint identities <A x, y> = <x, A^T y> of the convolution, pooling and
+upsampling, the weight gradient against the (linear) map at unit weights,
+and Adam's bias correction (a constant gradient gives m_hat = g at every
+step).
 """
 import numpy as np
 
@@ -71,3 +73,25 @@ def bf16_round(x):
     a = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
     a = (a + 0x7FFF + ((a >> 16) & 1)) >> 16 << 16
     return (a.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def pool2(x):
+    """Mean over 2x2x2 blocks (C, nz, ny, nx) -> (C, nz/2, ny/2, nx/2)."""
+    C, nz, ny, nx = x.shape
+    return x.reshape(C, nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4, 6))
+
+
+def pool2_backward(g):
+    """The adjoint of pool2: every child of a block gets g / 8."""
+    return np.repeat(np.repeat(np.repeat(g, 2, axis=1), 2, axis=2), 2, axis=3) / 8.0
+
+
+def upsample2(x):
+    """Nearest-neighbour doubling of every axis (C, nz, ny, nx) -> (C, 2nz, 2ny, 2nx)."""
+    return np.repeat(np.repeat(np.repeat(x, 2, axis=1), 2, axis=2), 2, axis=3)
+
+
+def upsample2_backward(g):
+    """The adjoint of upsample2: the sum over the 8 children of a block."""
+    C, nz, ny, nx = g.shape
+    return g.reshape(C, nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(2, 4, 6))

@@ -1214,6 +1214,176 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
   return HFE_OK;
 }
 
+size_t hfe_lbfgs_workspace_bytes(const hfe_grid* grid, int m) {
+  std::string why;
+  if (!grid_ok(grid, &why) || m < 1 || m > HFE_LBFGS_MAX_M) return 0;
+  const Grid g = make_grid(grid);
+  const size_t vec = align_up((size_t)g.dim * g.N * sizeof(double));
+  return (3 * ((size_t)m + 1) + 4) * vec;
+}
+
+// L-BFGS on the approximate energy increment (the quasi-Newton use of eq.
+// incr_energy_func that Sec. 2.2 proposes); the steps are those documented
+// with hfe_solve_increment_lbfgs. The strain-space vectors are held in
+// displacement coordinates: a strain D x is stored as x, and since
+// L = D^T D, (D x):(D y) = x . L y. The gradient G sigma is D y0 with
+// L y0 = g0 = D^T sigma; a pair keeps s (du), y (dy0) and L y (dg0), and the
+// first loop keeps q both as qd and as L qd, so that every inner product is a
+// plain dot of two stored vectors and no operator is applied.
+hfe_status hfe_solve_increment_lbfgs(hfe_ctx* c, const hfe_lbfgs_params* prm, void* workspace,
+                                     size_t ws_bytes, hfe_lbfgs_report* out) {
+  if (!c) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "apply a load step first");
+  const auto t0 = std::chrono::steady_clock::now();
+  hfe_lbfgs_params p;
+  p.eta_eq = 1e-8; p.eta_nr = 1e-8; p.max_iters = 500; p.m = 5; p.c1 = 1e-4;
+  p.max_backtracks = 30;
+  if (prm) p = *prm;
+  if (p.m < 1 || p.m > HFE_LBFGS_MAX_M || p.max_iters < 0 || p.max_backtracks < 0 ||
+      !(p.c1 > 0.0 && p.c1 < 1.0))
+    return fail(c, HFE_EINVAL, "bad L-BFGS parameters");
+  const long long n = ndof(c);
+  const size_t vec = align_up((size_t)n * sizeof(double));
+  if (!workspace || ws_bytes < (3 * ((size_t)p.m + 1) + 4) * vec || ((uintptr_t)workspace & 255))
+    return fail(c, HFE_EINVAL, "L-BFGS workspace too small or misaligned");
+  char* w = (char*)workspace;
+  auto V = [&](size_t k) { return (double*)(w + k * vec); };
+  const int m = p.m;
+  // m + 1 pair slots (a new pair is formed before the oldest one is dropped):
+  // slot k holds su (du), sy (dy0), sg (dg0); then qd, qf, rd, v
+  const int ns = m + 1;
+  double* qd = V(3 * ns);
+  double* qf = V(3 * ns + 1);
+  double* rd = V(3 * ns + 2);
+  double* v = V(3 * ns + 3);
+  std::vector<int> order;            // slots of the kept pairs, oldest first
+  std::vector<double> rho(ns, 0.0), yy(ns, 0.0);
+  double lpm = 0.0;                  // max over phases of lambda + 2 mu
+  for (int ph = 0; ph < c->n_phases; ++ph) lpm = std::max(lpm, c->mat.lam[ph] + 2.0 * c->mat.mu[ph]);
+  const double gamma0 = 1.0 / lpm;
+  // host value of x . y
+  auto dotv = [&](const double* x, const double* y, double* res) -> hfe_status {
+    hfe_status st = dot(c, x, y, c->dscal + S_DOT);
+    if (st) return st;
+    st = sync(c);
+    if (st) return st;
+    *res = c->hscal[S_DOT];
+    return HFE_OK;
+  };
+  hfe_lbfgs_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  rep.status = HFE_NOT_CONVERGED;
+  hfe_status st = HFE_OK;
+  bool converged = c->r_eq <= p.eta_eq;
+  for (int it = 0; it < p.max_iters && !converged; ++it) {
+    rep.iters = it + 1;
+    // two-loop recursion: rd = H_k (G sigma), displacement coordinates
+    double gamma = gamma0;
+    if (!order.empty()) gamma = 1.0 / (rho[order.back()] * yy[order.back()]);
+    HIPCHK(c, hipMemcpyAsync(qd, c->y0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(qf, c->g0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    std::vector<double> alpha(ns, 0.0);
+    for (int k = (int)order.size() - 1; k >= 0; --k) {
+      const int j = order[k];
+      double sq;
+      st = dotv(V(3 * j), qf, &sq);
+      if (st) return st;
+      alpha[j] = rho[j] * sq;
+      HIPCHK(c, hfe::vec_axpy(n, -alpha[j], V(3 * j + 1), qd, c->stream));
+      HIPCHK(c, hfe::vec_axpy(n, -alpha[j], V(3 * j + 2), qf, c->stream));
+    }
+    HIPCHK(c, hfe::vec_lincomb(n, gamma, qd, 0.0, qd, rd, c->stream));
+    for (size_t k = 0; k < order.size(); ++k) {
+      const int j = order[k];
+      double yr;
+      st = dotv(V(3 * j + 2), rd, &yr);
+      if (st) return st;
+      const double b = rho[j] * yr;
+      HIPCHK(c, hfe::vec_axpy(n, alpha[j] - b, V(3 * j), rd, c->stream));
+    }
+    // p = -rd; sigma:p = g0 . p
+    double sp;
+    st = dotv(c->g0, rd, &sp);
+    if (st) return st;
+    sp = -sp;
+    if (!(sp < 0.0)) {
+      order.clear();
+      rep.resets++;
+      HIPCHK(c, hfe::vec_lincomb(n, gamma0, c->y0, 0.0, c->y0, rd, c->stream));
+      st = dotv(c->g0, rd, &sp);
+      if (st) return st;
+      sp = -sp;
+    }
+    // backtracking on the approximate energy increment
+    double a = 1.0;
+    bool found = false;
+    double h[hfe::TRI_NV];
+    for (int bt = 0; bt <= p.max_backtracks; ++bt) {
+      HIPCHK(c, hfe::vec_lincomb(n, -a, rd, 0.0, rd, v, c->stream));
+      hfe::ElemArgs A = elem_args(c);
+      A.v = v;
+      int nb = 0;
+      {
+        Prof pr(c, "trial");
+        HIPCHK(c, hfe::launch_trial(A, c->stream, &nb));
+      }
+      st = finish(c, hfe::FIN_OUT, nb, hfe::TRI_NV, c->dscal + S_TRI);
+      if (st) return st;
+      st = sync(c);
+      if (st) return st;
+      rep.trials++;
+      for (int k = 0; k < hfe::TRI_NV; ++k) h[k] = c->hscal[S_TRI + k];
+      const double dW = 0.5 * (h[hfe::TRI_SP] + h[hfe::TRI_STP]);
+      if (dW <= p.c1 * a * sp) {
+        found = true;
+        break;
+      }
+      a *= 0.5;
+    }
+    if (!found) break;
+    // accept u + v; a free slot gets s = v and the old y0, g0
+    int j = 0;
+    while (std::find(order.begin(), order.end(), j) != order.end()) ++j;
+    HIPCHK(c, hipMemcpyAsync(V(3 * j), v, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(V(3 * j + 1), c->y0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(V(3 * j + 2), c->g0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hfe::vec_axpy(n, 1.0, v, c->u, c->stream));
+    st = evaluate_residual(c);
+    if (st) return st;
+    HIPCHK(c, hfe::vec_lincomb(n, 1.0, c->y0, -1.0, V(3 * j + 1), V(3 * j + 1), c->stream));
+    HIPCHK(c, hfe::vec_lincomb(n, 1.0, c->g0, -1.0, V(3 * j + 2), V(3 * j + 2), c->stream));
+    double sy, yyj;
+    st = dotv(V(3 * j), V(3 * j + 2), &sy);
+    if (st) return st;
+    st = dotv(V(3 * j + 1), V(3 * j + 2), &yyj);
+    if (st) return st;
+    const double ss = h[hfe::TRI_PP];        // |D v|^2 over the points
+    if (sy > 1e-12 * std::sqrt(ss * yyj)) {
+      rho[j] = 1.0 / sy;
+      yy[j] = yyj;
+      order.push_back(j);
+      if ((int)order.size() > m) order.erase(order.begin());
+    } else {
+      rep.pairs_skipped++;
+    }
+    const double hh = h[hfe::TRI_HH];
+    const double r_nr = hh > 0.0 ? std::sqrt(ss) / std::sqrt(hh) : 0.0;
+    rep.r_nr = r_nr;
+    if (c->r_eq <= p.eta_eq || r_nr <= p.eta_nr) converged = true;
+  }
+  if (converged) {
+    st = commit(c);
+    if (st) return st;
+    rep.status = HFE_CONVERGED;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->profiling) prof_drain(c);
+  rep.r_eq = c->r_eq;
+  rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = rep;
+  return HFE_OK;
+}
+
 hfe_status hfe_solve_batch(hfe_ctx* const* ctxs, int n, const hfe_solver_params* params,
                            hfe_solve_report* reports) {
   if (!ctxs || !reports || n < 1) return HFE_EINVAL;

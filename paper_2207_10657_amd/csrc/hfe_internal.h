@@ -215,6 +215,9 @@ hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipSt
 hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
                        hipStream_t s);
 // rows of x . y
+// out = alpha x + beta y (out may alias x or y; with beta = 0 pass y = x)
+hipError_t vec_lincomb(long long n, double alpha, const double* x, double beta, const double* y,
+                       double* out, hipStream_t s);
 hipError_t vec_dot(long long n, const double* x, const double* y, const Reducer& r,
                    hipStream_t s, int* nblocks);
 // CG, after the curvature decision: z += alpha d ; g += alpha Kd, or, when the

@@ -198,6 +198,87 @@ __global__ void __launch_bounds__(kNnBlock) k_adam(float* __restrict__ w, float*
   }
 }
 
+// 2x2x2 mean pooling of c channels on a fine grid (nx, ny, nz even): one
+// thread per coarse voxel and channel; the 8 children are added in a fixed
+// order in FP32 and divided by 8 (exact).
+__global__ void __launch_bounds__(kNnBlock) k_pool2(const float* __restrict__ in, int c, int nx,
+                                                   int ny, int nz, float* __restrict__ out,
+                                                   uint16_t* __restrict__ out16) {
+  const int mx = nx / 2, my = ny / 2, mz = nz / 2;
+  const long long M = (long long)mx * my * mz, N = (long long)nx * ny * nz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M * c;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i / M);
+    const long long r = i - (long long)ch * M;
+    const int x = (int)(r % mx), y = (int)((r / mx) % my), z = (int)(r / ((long long)mx * my));
+    const float* src = in + (long long)ch * N;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int fx = 2 * x + (k & 1), fy = 2 * y + ((k >> 1) & 1), fz = 2 * z + ((k >> 2) & 1);
+      s += src[fx + (long long)nx * (fy + (long long)ny * fz)];
+    }
+    s *= 0.125f;
+    if (out) out[i] = s;
+    if (out16) out16[i] = to_bf16(s);
+  }
+}
+
+// gin (fine) += the adjoint of k_pool2 applied to g (coarse): g / 8 to each
+// of the 8 children.
+__global__ void __launch_bounds__(kNnBlock) k_pool2_bwd(const float* __restrict__ g, int c, int nx,
+                                                       int ny, int nz, float* __restrict__ gin) {
+  const long long N = (long long)nx * ny * nz;
+  const int mx = nx / 2, my = ny / 2;
+  const long long M = (long long)mx * my * (nz / 2);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N * c;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i / N);
+    const long long r = i - (long long)ch * N;
+    const int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / ((long long)nx * ny));
+    gin[i] += 0.125f * g[(long long)ch * M + x / 2 + (long long)mx * (y / 2 + (long long)my * (z / 2))];
+  }
+}
+
+// Nearest doubling of every axis: coarse (mx, my, mz) -> fine, c channels.
+__global__ void __launch_bounds__(kNnBlock) k_upsample2(const float* __restrict__ in, int c, int mx,
+                                                       int my, int mz, float* __restrict__ out,
+                                                       uint16_t* __restrict__ out16) {
+  const int nx = 2 * mx, ny = 2 * my;
+  const long long N = (long long)nx * ny * (2 * mz), M = (long long)mx * my * mz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N * c;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i / N);
+    const long long r = i - (long long)ch * N;
+    const int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / ((long long)nx * ny));
+    const float v = in[(long long)ch * M + x / 2 + (long long)mx * (y / 2 + (long long)my * (z / 2))];
+    if (out) out[i] = v;
+    if (out16) out16[i] = to_bf16(v);
+  }
+}
+
+// The adjoint of k_upsample2: gin (coarse) = sum over the 8 children of g.
+__global__ void __launch_bounds__(kNnBlock) k_upsample2_bwd(const float* __restrict__ g, int c,
+                                                           int mx, int my, int mz,
+                                                           float* __restrict__ gin) {
+  const int nx = 2 * mx, ny = 2 * my;
+  const long long N = (long long)nx * ny * (2 * mz), M = (long long)mx * my * mz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < M * c;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i / M);
+    const long long r = i - (long long)ch * M;
+    const int x = (int)(r % mx), y = (int)((r / mx) % my), z = (int)(r / ((long long)mx * my));
+    const float* src = g + (long long)ch * N;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int fx = 2 * x + (k & 1), fy = 2 * y + ((k >> 1) & 1), fz = 2 * z + ((k >> 2) & 1);
+      s += src[fx + (long long)nx * (fy + (long long)ny * fz)];
+    }
+    gin[i] = s;
+  }
+}
+
 __global__ void __launch_bounds__(kNnBlock) k_to_bf16(const float* __restrict__ x, long long n,
                                                      uint16_t* __restrict__ y) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -205,8 +286,9 @@ __global__ void __launch_bounds__(kNnBlock) k_to_bf16(const float* __restrict__ 
     y[i] = to_bf16(x[i]);
 }
 
-// The channel counts the kernels are built for.
-#define HFE_NN_CHANNELS(X) X(1) X(2) X(3) X(4) X(6) X(8) X(16)
+// The channel counts the kernels are built for (32: the decoder's input, the
+// skip connection and the upsampled coarse level side by side).
+#define HFE_NN_CHANNELS(X) X(1) X(2) X(3) X(4) X(6) X(8) X(16) X(32)
 
 template <int CIN>
 hipError_t conv_fwd_cin(int cout, const uint16_t* in, const uint16_t* w, const float* bias,
@@ -257,7 +339,7 @@ using namespace hfe;
 extern "C" {
 
 static bool channels_ok(int c) {
-  return c == 1 || c == 2 || c == 3 || c == 4 || c == 6 || c == 8 || c == 16;
+  return c == 1 || c == 2 || c == 3 || c == 4 || c == 6 || c == 8 || c == 16 || c == 32;
 }
 
 hfe_status hfe_nn_conv3d(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout,
@@ -323,6 +405,46 @@ hfe_status hfe_nn_adam(float* w, float* m, float* v, const float* g, long long n
   const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(grid_1d(n)), dim3(kNnBlock), 0, (hipStream_t)stream, w, m, v, g,
                      n, lr, beta1, beta2, eps, c1, c2, w_bf16);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+static bool even_dims(const int n[3]) {
+  return dims_ok(n) && n[0] % 2 == 0 && n[1] % 2 == 0 && n[2] % 2 == 0;
+}
+
+hfe_status hfe_nn_pool2(const float* in, int c, const int n[3], float* out, uint16_t* out_bf16,
+                        void* stream) {
+  if (!in || c < 1 || !even_dims(n) || (!out && !out_bf16)) return HFE_EINVAL;
+  const long long M = (long long)c * (n[0] / 2) * (n[1] / 2) * (n[2] / 2);
+  hipLaunchKernelGGL(k_pool2, dim3(grid_1d(M)), dim3(kNnBlock), 0, (hipStream_t)stream, in, c,
+                     n[0], n[1], n[2], out, out_bf16);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_pool2_backward(const float* gout, int c, const int n[3], float* gin,
+                                 void* stream) {
+  if (!gout || !gin || c < 1 || !even_dims(n)) return HFE_EINVAL;
+  const long long N = (long long)c * n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_pool2_bwd, dim3(grid_1d(N)), dim3(kNnBlock), 0, (hipStream_t)stream, gout,
+                     c, n[0], n[1], n[2], gin);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_upsample2(const float* in, int c, const int m[3], float* out,
+                            uint16_t* out_bf16, void* stream) {
+  if (!in || c < 1 || !dims_ok(m) || (!out && !out_bf16)) return HFE_EINVAL;
+  const long long N = 8LL * c * m[0] * m[1] * m[2];
+  hipLaunchKernelGGL(k_upsample2, dim3(grid_1d(N)), dim3(kNnBlock), 0, (hipStream_t)stream, in, c,
+                     m[0], m[1], m[2], out, out_bf16);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
+
+hfe_status hfe_nn_upsample2_backward(const float* gout, int c, const int m[3], float* gin,
+                                     void* stream) {
+  if (!gout || !gin || c < 1 || !dims_ok(m)) return HFE_EINVAL;
+  const long long M = (long long)c * m[0] * m[1] * m[2];
+  hipLaunchKernelGGL(k_upsample2_bwd, dim3(grid_1d(M)), dim3(kNnBlock), 0, (hipStream_t)stream,
+                     gout, c, m[0], m[1], m[2], gin);
   return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
 }
 

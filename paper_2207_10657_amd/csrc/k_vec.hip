@@ -8,6 +8,8 @@
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
 
+#include <type_traits>
+
 namespace hfe {
 namespace {
 
@@ -34,6 +36,14 @@ __global__ void __launch_bounds__(kBlock) k_axpy_to(long long n, const double* _
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     out[i] = x[i] + alpha * y[i];
+}
+
+// out = alpha x + beta y, elementwise; out may alias x or y (no restrict)
+__global__ void __launch_bounds__(kBlock) k_lincomb(long long n, double alpha, const double* x,
+                                                    double beta, const double* y, double* out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = alpha * x[i] + beta * y[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot(long long n, const double* __restrict__ x,
@@ -193,10 +203,28 @@ __global__ void __launch_bounds__(kBlock) k_finish(Reducer r, int nblocks, int n
   }
   __shared__ double wsum[kBlock / 64][kMaxPartials];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < nv; ++k) {
-    double s = strided_row_sum(r.partials, nblocks, nv, k, threadIdx.x, blockDim.x);
-    s = wave_sum(s);
-    if (lane == 0) wsum[wave][k] = s;
+  // the row widths in use get all their columns loaded together
+  auto cols = [&](auto nvc) {
+    constexpr int NV = decltype(nvc)::value;
+    double sk[NV];
+    strided_row_sums<NV>(r.partials, nblocks, threadIdx.x, blockDim.x, sk);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double t = wave_sum(sk[k]);
+      if (lane == 0) wsum[wave][k] = t;
+    }
+  };
+  switch (nv) {
+    case 1: cols(std::integral_constant<int, 1>()); break;
+    case 2: cols(std::integral_constant<int, 2>()); break;
+    case TRI_NV: cols(std::integral_constant<int, TRI_NV>()); break;
+    case RES_NV: cols(std::integral_constant<int, RES_NV>()); break;
+    default:
+      for (int k = 0; k < nv; ++k) {
+        double t = strided_row_sum(r.partials, nblocks, nv, k, threadIdx.x, blockDim.x);
+        t = wave_sum(t);
+        if (lane == 0) wsum[wave][k] = t;
+      }
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -268,6 +296,12 @@ hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipSt
 hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_to, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, alpha, y, out);
+  return hipGetLastError();
+}
+
+hipError_t vec_lincomb(long long n, double alpha, const double* x, double beta, const double* y,
+                       double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, alpha, x, beta, y, out);
   return hipGetLastError();
 }
 

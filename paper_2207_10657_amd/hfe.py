@@ -52,6 +52,22 @@ class _Report(ctypes.Structure):
                 ("time_ms", ctypes.c_double)]
 
 
+class _LbfgsParams(ctypes.Structure):
+    _fields_ = [("eta_eq", ctypes.c_double), ("eta_nr", ctypes.c_double),
+                ("max_iters", ctypes.c_int), ("m", ctypes.c_int), ("c1", ctypes.c_double),
+                ("max_backtracks", ctypes.c_int)]
+
+
+class _LbfgsReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("trials", ctypes.c_int),
+                ("pairs_skipped", ctypes.c_int), ("resets", ctypes.c_int),
+                ("r_eq", ctypes.c_double), ("r_nr", ctypes.c_double), ("time_ms", ctypes.c_double)]
+
+
+LBFGS_DEFAULTS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "max_iters": 500, "m": 5, "c1": 1e-4,
+                  "max_backtracks": 30}
+
+
 class _Record(ctypes.Structure):
     _fields_ = [("flag", ctypes.c_int), ("cg_iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("accepted", ctypes.c_int), ("dm", ctypes.c_double), ("dW", ctypes.c_double),
@@ -127,6 +143,20 @@ EXPORTS = {
                                         ctypes.POINTER(ctypes.c_int)]),
     "hfe_soft_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
+    "hfe_nn_pool2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_nn_pool2_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "hfe_nn_upsample2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_nn_upsample2_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
+    "hfe_lbfgs_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_Grid), ctypes.c_int]),
+    "hfe_solve_increment_lbfgs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_LbfgsParams),
+                                                 ctypes.c_void_p, ctypes.c_size_t,
+                                                 ctypes.POINTER(_LbfgsReport)]),
     "hfe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
@@ -323,6 +353,31 @@ class Solver:
         rep = _Report()
         self._check(self.lib.hfe_solve_increment(self.ctx, ctypes.byref(cp), ctypes.byref(rep)))
         return _report(rep)
+
+    def solve_increment_lbfgs(self, params=None):
+        """The increment by L-BFGS on the approximate energy increment
+        (hfe_solve_increment_lbfgs); params: keys of LBFGS_DEFAULTS. The pair
+        storage is a device buffer of this solver, kept between calls."""
+        p = dict(LBFGS_DEFAULTS)
+        if params:
+            p.update({k: v for k, v in params.items() if v is not None})
+        cp = _LbfgsParams(**p)
+        g = _grid(self.shape, self.element)
+        nbytes = int(self.lib.hfe_lbfgs_workspace_bytes(ctypes.byref(g), int(p["m"])))
+        if nbytes == 0:
+            raise HfeError(-1, "bad L-BFGS memory size m = %s" % p["m"])
+        ws = getattr(self, "_lbfgs_ws", None)
+        if ws is None or ws.numel() < nbytes:
+            ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            if self.own_stream:
+                ws.record_stream(self.stream)
+            self._lbfgs_ws = ws
+        rep = _LbfgsReport()
+        self._check(self.lib.hfe_solve_increment_lbfgs(
+            self.ctx, ctypes.byref(cp), ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.byref(rep)))
+        out = {name: getattr(rep, name) for name, _ in _LbfgsReport._fields_}
+        out["converged"] = out["status"] == 0
+        return out
 
     def newton_log(self, max_records=10000):
         recs = (_Record * max_records)()

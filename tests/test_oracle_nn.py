@@ -65,3 +65,30 @@ def test_bf16_rounding():
     assert r[2] == 1.0 + 2 ** -7
     assert r[3] == 1.0 + 2 ** -6                # tie to even (up)
     assert abs(r[4] + 3.140625) < 1e-12
+
+
+def test_pool_and_upsample_against_index_loops_and_adjoints():
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(2, 4, 6, 2))
+    p = nn.pool2(x)
+    assert p.shape == (2, 2, 3, 1)
+    for c in range(2):
+        for z in range(2):
+            for y in range(3):
+                s = 0.0
+                for dz in range(2):
+                    for dy in range(2):
+                        for dx in range(2):
+                            s += x[c, 2 * z + dz, 2 * y + dy, dx]
+                assert abs(p[c, z, y, 0] - s / 8) < 1e-14
+    u = nn.upsample2(p)
+    assert u.shape == x.shape
+    for c in range(2):
+        for z in range(4):
+            for y in range(6):
+                for xx in range(2):
+                    assert u[c, z, y, xx] == p[c, z // 2, y // 2, xx // 2]
+    g = rng.normal(size=p.shape)
+    assert abs(np.sum(nn.pool2(x) * g) - np.sum(x * nn.pool2_backward(g))) < 1e-12
+    h = rng.normal(size=x.shape)
+    assert abs(np.sum(nn.upsample2(p) * h) - np.sum(p * nn.upsample2_backward(h))) < 1e-12
