@@ -101,10 +101,11 @@ def unit_load_cases(mag):
     return cases
 
 
-def warm_start_bench(n=16, train_seeds=(101, 102, 103, 104, 105, 106), test_seed=201, steps=4,
+def warm_start_bench(n=16, train_seeds=tuple(range(101, 149)), test_seed=201, steps=6,
                      epochs=20):
     """Learned warm start on cells of the workload recipe at n^3: increments
-    of `train_seeds` cells train the network (hand-written BF16 kernels), then
+    of `train_seeds` cells train the encoder-decoder (hand-written BF16
+    kernels), then
     a held-out cell is solved `steps` increments with the plain guess (the
     previous fluctuation), the extrapolated previous increment, and the
     network's prediction. Per guess: Newton and CG iterations, time."""

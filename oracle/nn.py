@@ -95,3 +95,60 @@ def upsample2_backward(g):
     """The adjoint of upsample2: the sum over the 8 children of a block."""
     C, nz, ny, nx = g.shape
     return g.reshape(C, nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(2, 4, 6))
+
+
+def unet_forward(x, params, levels, bf16=False):
+    """The encoder-decoder of the warm start (levels resolutions, 2x2x2 mean
+    pooling, nearest upsampling, the decoder's input = [encoder features,
+    upsampled coarse features]); params = {"enc": [(w, b)] * levels,
+    "dec": [(w, b)] * (levels - 1) (finest first), "out": (w, b)}. With bf16,
+    every convolution input is rounded to BF16 first (as the kernels store
+    activations). Returns the output and the intermediate values the backward
+    pass needs."""
+    rnd = bf16_round if bf16 else (lambda a: a)
+    st = {"enc": [], "in": [], "dec": [None] * (levels - 1), "cat": [None] * (levels - 1)}
+    h = x
+    for l in range(levels):
+        if l > 0:
+            h = pool2(st["enc"][l - 1])
+        w, b = params["enc"][l]
+        hin = rnd(h)
+        st["in"].append(hin)
+        st["enc"].append(relu(conv3d(hin, w, b)))
+    prev = st["enc"][levels - 1]
+    for l in range(levels - 2, -1, -1):
+        cat = np.concatenate([rnd(st["enc"][l]), rnd(upsample2(prev))], axis=0)
+        st["cat"][l] = cat
+        w, b = params["dec"][l]
+        st["dec"][l] = relu(conv3d(cat, w, b))
+        prev = st["dec"][l]
+    w, b = params["out"]
+    st["out_in"] = rnd(st["dec"][0])
+    return conv3d(st["out_in"], w, b), st
+
+
+def unet_backward(gy, params, st, levels):
+    """Gradients of <gy, y> with respect to every (w, b), for the values `st`
+    of unet_forward (the BF16 roundings of the forward pass are treated as
+    identities). Returns a dict shaped like params."""
+    C = params["enc"][0][0].shape[0]
+    grads = {"enc": [None] * levels, "dec": [None] * (levels - 1)}
+    w, _ = params["out"]
+    grads["out"] = conv3d_backward_weights(gy, st["out_in"])
+    g = conv3d_backward_data(gy, w)
+    g_enc = [None] * levels
+    for l in range(levels - 1):
+        gm = np.where(st["dec"][l] > 0, g, 0.0)
+        w, _ = params["dec"][l]
+        grads["dec"][l] = conv3d_backward_weights(gm, st["cat"][l])
+        gcat = conv3d_backward_data(gm, w)
+        g_enc[l] = gcat[:C]
+        g = upsample2_backward(gcat[C:])
+    for l in range(levels - 1, -1, -1):
+        gm = np.where(st["enc"][l] > 0, g, 0.0)
+        w, _ = params["enc"][l]
+        grads["enc"][l] = conv3d_backward_weights(gm, st["in"][l])
+        if l == 0:
+            break
+        g = g_enc[l - 1] + pool2_backward(conv3d_backward_data(gm, w))
+    return grads

@@ -135,6 +135,183 @@ class ConvNet:
         return out
 
 
+class _Conv:
+    """One 3x3x3 layer: FP32 master weights and bias, Adam moments, BF16 copy."""
+
+    def __init__(self, net, cin, cout, rng, zero=False):
+        torch = net.torch
+        self.cin, self.cout = cin, cout
+        std = np.sqrt(2.0 / (27 * cin))
+        w = np.zeros((cout, cin, 27)) if zero else rng.normal(scale=std, size=(cout, cin, 27))
+        self.w = torch.tensor(w, dtype=torch.float32, device=net.device)
+        self.b = torch.zeros(cout, dtype=torch.float32, device=net.device)
+        self.w16 = torch.empty(w.size, dtype=torch.int16, device=net.device)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+        net._check(net.lib.hfe_nn_to_bf16(_ptr(self.w), self.w.numel(), _ptr(self.w16),
+                                          net._stream()))
+
+
+class UNet:
+    """Encoder-decoder on the periodic grid (row f3): `levels` resolutions,
+    each halving the grid by 2x2x2 mean pooling; 16 channels at every level;
+    the decoder upsamples (nearest) and convolves the upsampled coarse
+    features side by side with the encoder's features of the same level (32
+    channels in). conv(6->16)+ReLU at the finest level, conv(16->16)+ReLU
+    after every pooling, conv(32->16)+ReLU at every decoder level,
+    conv(16->3) out (zero-initialised, so an untrained network predicts no
+    correction). BF16 activations and weights, FP32 accumulation; every
+    operation runs in the hfe_nn_* kernels."""
+
+    C = 16
+
+    def __init__(self, levels=3, seed=0, device="cuda:0", in_channels=6, out_channels=3):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.levels = levels
+        rng = np.random.default_rng(seed)
+        C = self.C
+        self.enc = [_Conv(self, in_channels, C, rng)] + \
+            [_Conv(self, C, C, rng) for _ in range(levels - 1)]
+        self.dec = [_Conv(self, 2 * C, C, rng) for _ in range(levels - 1)]   # dec[l]: level l
+        self.out = _Conv(self, C, out_channels, rng, zero=True)
+        self.step = 0
+
+    _stream = ConvNet._stream
+    _check = staticmethod(ConvNet._check)
+    to_bf16 = ConvNet.to_bf16
+
+    def _dims(self, shape, l):
+        nz, ny, nx = (int(v) >> l for v in shape)
+        return (ctypes.c_int * 3)(nx, ny, nz), (nz, ny, nx)
+
+    def _conv(self, layer, in16, n, relu, out, out16):
+        self._check(self.lib.hfe_nn_conv3d(_ptr(in16), layer.cin, _ptr(layer.w16), _ptr(layer.b),
+                                           layer.cout, n, 1 if relu else 0, _ptr(out),
+                                           _ptr(out16) if out16 is not None else None,
+                                           self._stream()))
+
+    def forward(self, x16, shape):
+        """x16: BF16 input (6, nz, ny, nx), every axis divisible by 2^(levels-1)."""
+        torch, C, L = self.torch, self.C, self.levels
+        f32 = dict(dtype=torch.float32, device=self.device)
+        i16 = dict(dtype=torch.int16, device=self.device)
+        st = {"enc": [], "cat": [], "pool16": [], "dec": []}
+        # encoder
+        inp = x16
+        for l in range(L):
+            n, dims = self._dims(shape, l)
+            e = torch.empty((C,) + dims, **f32)
+            cat = torch.empty((2 * C,) + dims, **i16) if l < L - 1 else None
+            if l > 0:
+                nf, _ = self._dims(shape, l - 1)
+                p16 = torch.empty((C,) + dims, **i16)
+                self._check(self.lib.hfe_nn_pool2(_ptr(st["enc"][l - 1]), C, nf, None, _ptr(p16),
+                                                  self._stream()))
+                st["pool16"].append(p16)
+                inp = p16
+            # the encoder's BF16 copy is the first half of the decoder input
+            self._conv(self.enc[l], inp, n, True, e, cat[:C] if cat is not None else None)
+            st["enc"].append(e)
+            st["cat"].append(cat)
+        # decoder, coarse to fine
+        prev = st["enc"][L - 1]
+        dec = [None] * (L - 1)
+        for l in range(L - 2, -1, -1):
+            n, dims = self._dims(shape, l)
+            m, _ = self._dims(shape, l + 1)
+            cat = st["cat"][l]
+            self._check(self.lib.hfe_nn_upsample2(_ptr(prev), C, m, None, _ptr(cat[C:]),
+                                                  self._stream()))
+            d = torch.empty((C,) + dims, **f32)
+            d16 = torch.empty((C,) + dims, **i16) if l == 0 else None
+            self._conv(self.dec[l], cat, n, True, d, d16)
+            dec[l] = (d, d16)
+            prev = d
+        st["dec"] = dec
+        n, dims = self._dims(shape, 0)
+        y = torch.empty((self.out.cout,) + dims, **f32)
+        self._conv(self.out, dec[0][1], n, False, y, None)
+        return y, st
+
+    def _grads(self, layer, g, act, in16, n):
+        gw = self.torch.empty_like(layer.w)
+        gb = self.torch.empty_like(layer.b)
+        self._check(self.lib.hfe_nn_conv3d_backward_weights(
+            _ptr(g), layer.cout, _ptr(act) if act is not None else None, _ptr(in16), layer.cin, n,
+            _ptr(gw), _ptr(gb), self._stream()))
+        return gw, gb
+
+    def _gin(self, layer, g, act, n, dims):
+        gin = self.torch.empty((layer.cin,) + dims, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hfe_nn_conv3d_backward_data(
+            _ptr(g), layer.cout, _ptr(act) if act is not None else None, _ptr(layer.w16),
+            layer.cin, n, _ptr(gin), self._stream()))
+        return gin
+
+    def backward(self, gy, x16, st, shape):
+        """Weight and bias gradients [(layer, gw, gb)] for dL/dy = gy."""
+        torch, C, L = self.torch, self.C, self.levels
+        out = []
+        n0, d0 = self._dims(shape, 0)
+        dec0, dec0_16 = st["dec"][0]
+        out.append((self.out,) + self._grads(self.out, gy, None, dec0_16, n0))
+        g = self._gin(self.out, gy, None, n0, d0)          # d loss / d dec_0
+        g_enc_part = [None] * L
+        for l in range(L - 1):
+            n, dims = self._dims(shape, l)
+            m, mdims = self._dims(shape, l + 1)
+            d = st["dec"][l][0]
+            out.append((self.dec[l],) + self._grads(self.dec[l], g, d, st["cat"][l], n))
+            gcat = self._gin(self.dec[l], g, d, n, dims)    # (2C, level l)
+            g_enc_part[l] = gcat[:C]
+            gc = torch.empty((C,) + mdims, dtype=torch.float32, device=self.device)
+            self._check(self.lib.hfe_nn_upsample2_backward(_ptr(gcat[C:].contiguous()), C, m,
+                                                           _ptr(gc), self._stream()))
+            g = gc                                          # d loss / d (dec_{l+1} or enc_{L-1})
+        # encoder, coarse to fine: g is d loss / d enc_{L-1}
+        for l in range(L - 1, -1, -1):
+            n, dims = self._dims(shape, l)
+            e = st["enc"][l]
+            inp = x16 if l == 0 else st["pool16"][l - 1]
+            out.append((self.enc[l],) + self._grads(self.enc[l], g, e, inp, n))
+            if l == 0:
+                break
+            gp = self._gin(self.enc[l], g, e, n, dims)      # d loss / d pooled input
+            nf, _ = self._dims(shape, l - 1)
+            ge = g_enc_part[l - 1].contiguous()
+            self._check(self.lib.hfe_nn_pool2_backward(_ptr(gp), C, nf, _ptr(ge), self._stream()))
+            g = ge
+        return out
+
+    def train_step(self, x16, target, shape, lr=1e-3):
+        torch = self.torch
+        y, st = self.forward(x16, shape)
+        N = y.numel()
+        gy = torch.empty_like(y)
+        partials = torch.empty(int(self.lib.hfe_nn_mse_partials(N)), dtype=torch.float64,
+                               device=self.device)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.hfe_nn_mse(_ptr(y), _ptr(target), N, _ptr(gy), _ptr(partials),
+                                        _ptr(loss), self._stream()))
+        grads = self.backward(gy, x16, st, shape)
+        self.step += 1
+        for layer, gw, gb in grads:
+            self._check(self.lib.hfe_nn_adam(_ptr(layer.w), _ptr(layer.mw), _ptr(layer.vw),
+                                             _ptr(gw), gw.numel(), lr, 0.9, 0.999, 1e-8, self.step,
+                                             _ptr(layer.w16), self._stream()))
+            self._check(self.lib.hfe_nn_adam(_ptr(layer.b), _ptr(layer.mb), _ptr(layer.vb),
+                                             _ptr(gb), gb.numel(), lr, 0.9, 0.999, 1e-8, self.step,
+                                             None, self._stream()))
+        return float(loss.item())
+
+    def predict(self, x16, shape):
+        y, _ = self.forward(x16, shape)
+        return y
+
+
 def features(phase, damage, du_prev, scale):
     """The 6 input channels (numpy float32, (6, nz, ny, nx)).
 
@@ -153,7 +330,7 @@ class WarmStart:
     """Training data from solves, training, and the warm-started solve."""
 
     def __init__(self, net=None, seed=0):
-        self.net = net if net is not None else ConvNet(seed=seed)
+        self.net = net if net is not None else UNet(seed=seed)
         self.samples = []      # (features, target, shape), target = du / scale - du_prev / scale
 
     def _x16(self, f):

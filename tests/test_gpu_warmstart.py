@@ -214,3 +214,117 @@ def test_warm_started_solves_reach_the_same_results():
                   % (guess, k, dS, d[k], d0[k]), flush=True)
             if d0[k] == 0.0 and d[k] == 0.0:
                 assert dS < 1e-7, (guess, k, dS)
+
+
+def _bf16_to_f64(t16):
+    a = t16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    return a.view(np.float32).astype(np.float64)
+
+
+def test_pool_and_upsample_kernels_against_oracle():
+    torch = require_gpu()
+    announce("nn pool upsample")
+    from paper_2207_10657_amd.warmstart import _ptr
+    net = _net_and_lib()
+    lib, s = net.lib, net._stream()
+    rng = np.random.default_rng(8)
+    c, fine = 5, (6, 8, 4)
+    x = rng.normal(size=(c,) + fine).astype(np.float32).astype(np.float64)
+    n = (ctypes.c_int * 3)(fine[2], fine[1], fine[0])
+    m = (ctypes.c_int * 3)(fine[2] // 2, fine[1] // 2, fine[0] // 2)
+    coarse = (c,) + tuple(v // 2 for v in fine)
+    out = torch.empty(coarse, dtype=torch.float32, device="cuda")
+    out16 = torch.empty(coarse, dtype=torch.int16, device="cuda")
+    assert lib.hfe_nn_pool2(_ptr(_dev(torch, x)), c, n, _ptr(out), _ptr(out16), s) == 0
+    ref = nn.pool2(x)
+    assert np.abs(out.double().cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert torch.equal(net.to_bf16(out), out16)
+    # pool backward adds g / 8 to every child
+    g = rng.normal(size=coarse)
+    base = rng.normal(size=(c,) + fine)
+    gin = _dev(torch, base)
+    assert lib.hfe_nn_pool2_backward(_ptr(_dev(torch, g)), c, n, _ptr(gin), s) == 0
+    ref = base + nn.pool2_backward(g)
+    assert np.abs(gin.double().cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
+    # upsample and its adjoint
+    up = torch.empty((c,) + fine, dtype=torch.float32, device="cuda")
+    up16 = torch.empty((c,) + fine, dtype=torch.int16, device="cuda")
+    xc = rng.normal(size=coarse).astype(np.float32).astype(np.float64)
+    assert lib.hfe_nn_upsample2(_ptr(_dev(torch, xc)), c, m, _ptr(up), _ptr(up16), s) == 0
+    assert np.array_equal(up.double().cpu().numpy(), nn.upsample2(xc))
+    assert torch.equal(net.to_bf16(up), up16)
+    gf = rng.normal(size=(c,) + fine)
+    gc = torch.empty(coarse, dtype=torch.float32, device="cuda")
+    assert lib.hfe_nn_upsample2_backward(_ptr(_dev(torch, gf)), c, m, _ptr(gc), s) == 0
+    ref = nn.upsample2_backward(gf)
+    assert np.abs(gc.double().cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_unet_forward_and_gradients_against_oracle():
+    """The encoder-decoder (3 levels) on an 8^3 cell: output and every layer's
+    weight and bias gradients against the oracle's FP64 composition with the
+    same BF16 weights and the same BF16 rounding of every convolution input.
+    The kernels accumulate in FP32, so a BF16 rounding of an activation can
+    land one unit apart (2^-8) at a few voxels: 1e-3 of the norm allowed."""
+    torch = require_gpu()
+    announce("nn unet parity")
+    from paper_2207_10657_amd.warmstart import UNet, _ptr
+    net = UNet(levels=3, seed=2)
+    rng = np.random.default_rng(9)
+    # a non-zero output layer (its initial weights are zero)
+    w = rng.normal(scale=0.1, size=tuple(net.out.w.shape))
+    net.out.w.copy_(torch.tensor(w, dtype=torch.float32))
+    net._check(net.lib.hfe_nn_to_bf16(_ptr(net.out.w), net.out.w.numel(), _ptr(net.out.w16),
+                                      net._stream()))
+    for layer in net.enc + net.dec + [net.out]:
+        layer.b.copy_(torch.tensor(rng.normal(scale=0.05, size=layer.cout), dtype=torch.float32))
+    shape = (8, 8, 8)
+    x = nn.bf16_round(rng.normal(size=(6,) + shape))
+    x16 = net.to_bf16(_dev(torch, x))
+    y, st = net.forward(x16, shape)
+    gy = rng.normal(size=tuple(y.shape)).astype(np.float32).astype(np.float64)
+    grads = net.backward(_dev(torch, gy), x16, st, shape)
+    torch.cuda.synchronize()
+
+    def pw(layer):
+        return _bf16_to_f64(layer.w16).reshape(layer.w.shape), layer.b.double().cpu().numpy()
+    p = {"enc": [pw(l) for l in net.enc], "dec": [pw(l) for l in net.dec], "out": pw(net.out)}
+    yr, sr = nn.unet_forward(x, p, 3, bf16=True)
+    gr = nn.unet_backward(gy, p, sr, 3)
+    yg = y.double().cpu().numpy()
+    assert np.linalg.norm(yg - yr) <= 1e-3 * np.linalg.norm(yr)
+    ref = {id(net.out): gr["out"]}
+    for l, layer in enumerate(net.enc):
+        ref[id(layer)] = gr["enc"][l]
+    for l, layer in enumerate(net.dec):
+        ref[id(layer)] = gr["dec"][l]
+    assert len(grads) == len(ref)
+    for layer, gw, gb in grads:
+        rw, rb = ref[id(layer)]
+        gwn = gw.double().cpu().numpy()
+        gbn = gb.double().cpu().numpy()
+        assert np.linalg.norm(gwn - rw) <= 1e-3 * np.linalg.norm(rw), (layer.cin, layer.cout)
+        assert np.linalg.norm(gbn - rb) <= 1e-3 * np.linalg.norm(rb) + 1e-12
+
+
+def test_unet_training_fits_a_smoothing():
+    """The encoder-decoder learns a fixed periodic smoothing of its input
+    channels: the loss falls by 5x within 300 Adam steps."""
+    torch = require_gpu()
+    announce("nn unet training")
+    from paper_2207_10657_amd.warmstart import UNet
+    net = UNet(levels=3, seed=4)
+    rng = np.random.default_rng(5)
+    shape = (8, 8, 8)
+    wt = np.zeros((3, 6, 27))
+    for c in range(3):
+        wt[c, 3 + c, 13] = 0.5
+        wt[c, 3 + c, 12] = wt[c, 3 + c, 14] = 0.25
+    data = []
+    for _ in range(4):
+        x = nn.bf16_round(rng.normal(size=(6,) + shape))
+        data.append((net.to_bf16(_dev(torch, x)), _dev(torch, nn.conv3d(x, wt))))
+    losses = [net.train_step(*data[it % 4], shape, lr=3e-3) for it in range(300)]
+    print("[warmstart] unet fit loss %.3e -> %.3e" % (np.mean(losses[:4]), np.mean(losses[-4:])),
+          flush=True)
+    assert np.mean(losses[-4:]) < 0.2 * np.mean(losses[:4])

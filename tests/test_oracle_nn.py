@@ -92,3 +92,50 @@ def test_pool_and_upsample_against_index_loops_and_adjoints():
     assert abs(np.sum(nn.pool2(x) * g) - np.sum(x * nn.pool2_backward(g))) < 1e-12
     h = rng.normal(size=x.shape)
     assert abs(np.sum(nn.upsample2(p) * h) - np.sum(p * nn.upsample2_backward(h))) < 1e-12
+
+
+def _unet_params(rng, levels, cin=3, C=4, cout=2):
+    p = {"enc": [], "dec": []}
+    for l in range(levels):
+        p["enc"].append((rng.normal(scale=0.3, size=(C, cin if l == 0 else C, 27)),
+                         rng.normal(scale=0.1, size=C)))
+    for l in range(levels - 1):
+        p["dec"].append((rng.normal(scale=0.3, size=(C, 2 * C, 27)), rng.normal(scale=0.1, size=C)))
+    p["out"] = (rng.normal(scale=0.3, size=(cout, C, 27)), rng.normal(scale=0.1, size=cout))
+    return p
+
+
+def test_unet_backward_against_finite_differences():
+    """The encoder-decoder is piecewise linear in each weight (ReLU), so a
+    central difference with a small step reproduces the gradient of <gy, y>
+    away from the kinks."""
+    rng = np.random.default_rng(4)
+    levels = 3
+    p = _unet_params(rng, levels)
+    x = rng.normal(size=(3, 8, 8, 4))
+    y, st = nn.unet_forward(x, p, levels)
+    gy = rng.normal(size=y.shape)
+    g = nn.unet_backward(gy, p, st, levels)
+    h = 1e-6
+    for part, idx in [("enc", 0), ("enc", 1), ("enc", 2), ("dec", 0), ("dec", 1), ("out", None)]:
+        w, b = p[part] if idx is None else p[part][idx]
+        gw, gb = g[part] if idx is None else g[part][idx]
+        for k in range(3):
+            pos = tuple(rng.integers(0, s) for s in w.shape)
+            w0 = w[pos]
+            w[pos] = w0 + h
+            yp, _ = nn.unet_forward(x, p, levels)
+            w[pos] = w0 - h
+            ym, _ = nn.unet_forward(x, p, levels)
+            w[pos] = w0
+            fd = np.sum(gy * (yp - ym)) / (2 * h)
+            assert abs(fd - gw[pos]) < 1e-6 * max(1.0, abs(fd)), (part, idx, pos, fd, gw[pos])
+        j = int(rng.integers(0, b.shape[0]))
+        b0 = b[j]
+        b[j] = b0 + h
+        yp, _ = nn.unet_forward(x, p, levels)
+        b[j] = b0 - h
+        ym, _ = nn.unet_forward(x, p, levels)
+        b[j] = b0
+        fd = np.sum(gy * (yp - ym)) / (2 * h)
+        assert abs(fd - gb[j]) < 1e-6 * max(1.0, abs(fd)), (part, idx, "bias", fd, gb[j])
