@@ -37,7 +37,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kTraceCap = 1 << 16;    // CG trace entries kept per solve
-constexpr int kCgBatch = 8;           // CG iterations enqueued between host polls
+constexpr int kCgBatch = 8;           // the longest batch of CG iterations between host polls
+constexpr int kCgSlots = 4;           // captured batches of 1, 2, 4, 8 iterations
 constexpr int kBrickShapes = 5;       // Q1 Hessian brick shapes (see launch_hessian_brick)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -223,9 +224,10 @@ struct hfe_ctx {
   std::vector<ProfEvent> pending;
   std::vector<hipEvent_t> pool;
   std::vector<ProfEvent>* prof_sink = nullptr;   // events recorded while capturing
-  // CG iteration graphs: a short batch for the start of a solve, a long one after
+  // CG iteration graphs of 1, 2, 4 and 8 iterations (slot s holds 2^s)
   hipStream_t cap_stream = nullptr;
-  CgGraph graphs[2];
+  CgGraph graphs[kCgSlots];
+  int cg_predict = 2;        // CG iterations of the previous solve (first batch size)
   int graph_precision = HFE_FP64;   // precision the captured graphs run
   bool use_graphs = true;
   int brick_shape = 0;       // Q1 Hessian brick shape, FP64 (HFE_BRICK_SHAPE=0..4 overrides)
@@ -776,23 +778,36 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
     if (st) return st;
   }
   int restarts = 0;
-  int slot = 0;
+  int batch = 0;        // batches of this (re)start
+  int enq = 0;          // iterations enqueued since the (re)start
   for (;;) {
-    // a profiled solve polls after every iteration, so no launch of a batch
-    // runs after the stop (such launches return at entry and would bias the
-    // per-kernel averages)
-    const int k = c->profiling ? 1 : slot == 0 ? 2 : kCgBatch;
-    hfe_status st = cg_batch(c, slot, k);
+    // Iterations enqueued after the stop return at entry but still cost
+    // their launches, and every host poll costs a round trip. The first
+    // batch is the previous solve's iteration count (trust-region solves of
+    // one load step are alike), later ones grow 2, 4, 8, 8, ...; a batch of
+    // k iterations is replayed from the captured graphs of 8, 4, 2 and 1.
+    // A profiled solve polls after every iteration, so no launch of a batch
+    // runs after the stop (such launches would bias the per-kernel averages).
+    int k = 1;
+    if (!c->profiling) {
+      k = batch == 0 ? std::min(std::max(c->cg_predict - enq, 1), kCgBatch)
+                     : std::min(2 << std::min(batch - 1, 2), kCgBatch);
+    }
+    hfe_status st = HFE_OK;
+    for (int sl = kCgSlots - 1, rem = k; sl >= 0 && st == HFE_OK; --sl)
+      while (rem >= (1 << sl) && st == HFE_OK) {
+        st = cg_batch(c, sl, 1 << sl);
+        rem -= 1 << sl;
+      }
     if (st) return st;
+    ++batch;
+    enq += k;
     HIPCHK(c, hipMemcpyAsync(c->hcg, c->cg, sizeof(hfe::CgState), hipMemcpyDeviceToHost, c->stream));
     st = sync(c);
     if (st) return st;
 
     const hfe::CgState h = *c->hcg;
-    if (!h.done) {
-      slot = 1;
-      continue;
-    }
+    if (!h.done) continue;
     if (h.flag == hfe::CG_NUMERIC) return fail(c, HFE_ENUMERIC, "non-finite curvature in CG");
     if (h.restart) {
       // Powell's test: recompute the true residual at the new iterate and
@@ -820,11 +835,13 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
         st = direction(c);
       }
       if (st) return st;
-      slot = 0;
+      batch = 0;
+      enq = h.iters;
       continue;
     }
     info->iters = h.iters;
     info->restarts = restarts;
+    c->cg_predict = std::max(h.iters, 1);
     info->matvecs = h.iters + restarts;
     *flag = h.flag;
     // the step of a mixed-precision solve continues in FP64
