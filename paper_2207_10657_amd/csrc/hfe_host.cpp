@@ -744,9 +744,11 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
   const long long n = ndof(c);
   const size_t bytes = (size_t)n * sizeof(double);
   const bool mixed = prec == HFE_MIXED;
-  HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
   *flag = HFE_CG_INTERIOR;
-  if (c->rr0 == 0.0) return HFE_OK;
+  if (c->rr0 == 0.0) {
+    HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
+    return HFE_OK;
+  }
   if (c->graph_precision != prec) {
     // captured iterations run one precision's kernels and buffers
     destroy_graphs(c);
@@ -755,12 +757,10 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
   if (mixed) {
     hfe_status st0 = refresh_state32(c);
     if (st0) return st0;
+    HIPCHK(c, hipMemsetAsync(c->z, 0, bytes, c->stream));
     HIPCHK(c, hipMemsetAsync(c->z32, 0, (size_t)n * sizeof(float), c->stream));
     HIPCHK(c, hfe::vec_to_f32(n, c->g0, c->g32, c->stream));
     HIPCHK(c, hfe::vec_to_f32(n, c->y0, c->y32, c->stream));
-  } else {
-    HIPCHK(c, hipMemcpyAsync(c->gv, c->g0, bytes, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->y, c->y0, bytes, hipMemcpyDeviceToDevice, c->stream));
   }
   hfe::CgState init;
   std::memset(&init, 0, sizeof(init));
@@ -772,10 +772,16 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
   init.trace_cap = kTraceCap;
   *c->hcg = init;
   HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
-  // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0
-  {
-    hfe_status st = mixed ? direction32(c) : direction(c);
+  // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0; in FP64 one kernel also
+  // sets z = 0, g = g0 and y = y0
+  if (mixed) {
+    hfe_status st = direction32(c);
     if (st) return st;
+  } else {
+    hfe::Reducer r;
+    r.partials = c->partials2;
+    Prof p(c, "cg_vec");
+    HIPCHK(c, hfe::cg_start(n, c->g0, c->y0, c->z, c->gv, c->y, c->d, r, c->stream, &c->nb_dir));
   }
   int restarts = 0;
   int batch = 0;        // batches of this (re)start

@@ -232,6 +232,11 @@ hipError_t cg_step_y(long long n, const double* w, double* y, const double* g, c
 // y_old.g} of the inverse plane pass and takes the residual decision on its
 // own copy of st (block 0 stores it in st_out and writes the trace);
 // otherwise it reads beta from st.
+// Start of a CG solve (FP64): z = 0, g = g0, y = y0, d0 = -y0, with the rows
+// {g.d, z.g = 0} of the first direction decision (the sums of cg_step_d at
+// beta = 0, in the same order).
+hipError_t cg_start(long long n, const double* g0, const double* y0, double* z, double* g,
+                    double* y, double* d, const Reducer& r, hipStream_t s, int* nblocks);
 template <typename R>
 hipError_t cg_step_d(long long n, const R* y, R* d, const R* g, const R* z, const Reducer& r,
                      const CgState* st, hipStream_t s, int* nblocks,

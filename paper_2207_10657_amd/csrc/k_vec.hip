@@ -164,6 +164,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restric
   block_reduce_store<2>(acc, r.partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_cg_start(long long n, const double* __restrict__ g0,
+                                                     const double* __restrict__ y0,
+                                                     double* __restrict__ z, double* __restrict__ g,
+                                                     double* __restrict__ y, double* __restrict__ d,
+                                                     Reducer r) {
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double gi = g0[i], yi = y0[i];
+    const double dn = -yi;
+    z[i] = 0.0;
+    g[i] = gi;
+    y[i] = yi;
+    d[i] = dn;
+    acc[0] += gi * dn;
+    acc[1] += 0.0 * gi;   // z . g with z = 0, as in k_cg_d
+  }
+  block_reduce_store<2>(acc, r.partials);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_dot_t(long long n, const R* __restrict__ x,
                                                   const R* __restrict__ y, Reducer r) {
@@ -296,6 +316,13 @@ hipError_t vec_axpy(long long n, double alpha, const double* y, double* x, hipSt
 hipError_t vec_axpy_to(long long n, const double* x, double alpha, const double* y, double* out,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_to, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, alpha, y, out);
+  return hipGetLastError();
+}
+
+hipError_t cg_start(long long n, const double* g0, const double* y0, double* z, double* g,
+                    double* y, double* d, const Reducer& r, hipStream_t s, int* nblocks) {
+  *nblocks = vec_blocks(n);
+  hipLaunchKernelGGL(k_cg_start, dim3(*nblocks), dim3(kBlock), 0, s, n, g0, y0, z, g, y, d, r);
   return hipGetLastError();
 }
 

@@ -131,7 +131,8 @@ def test_full_size_projected_hessian_64cubed():
     s.apply_load_step(E)
     s.set_displacement(u)
     d = rng.normal(size=(3,) + w.shape)
-    out, dots = s.apply_projected_hessian(torch.tensor(d, device="cuda"))
+    dt = torch.tensor(d, device="cuda")
+    out, dots = s.apply_projected_hessian(dt)
     out = out.cpu().numpy()
     mf = material.MaterialField(w.phase, w.materials, 8)
     H = fe.gradient(u, "q1") + E
@@ -139,3 +140,9 @@ def test_full_size_projected_hessian_64cubed():
     Dd = fe.gradient(d, "q1")
     ref = Projector(w.shape, "q1")(material.apply_tangent(mf, st, Dd))
     assert rel_err(fe.gradient(out, "q1"), ref) < 1e-12
+    # the launch shapes the benchmark times (its autotuner at this state):
+    # the same bits, since a shape changes which block computes a value, not
+    # the order of its arithmetic
+    s.autotune()
+    out2, dots2 = s.apply_projected_hessian(dt)
+    assert np.array_equal(out2.cpu().numpy(), out)
