@@ -6,9 +6,9 @@ oracle and the HIP path can draw identical inputs from it without sharing
 any of the method's code.
 """
 from .microstructure import inclusion_microstructure, laminate_microstructure
-from .workloads import (MATRIX_DAMAGE, INCLUSION_ELASTIC, Workload, workload,
+from .workloads import (MATRIX_DAMAGE, MATRIX_TENSILE, INCLUSION_ELASTIC, Workload, workload,
                         uniaxial_load_path)
 
 __all__ = ["inclusion_microstructure", "laminate_microstructure",
-           "MATRIX_DAMAGE", "INCLUSION_ELASTIC", "Workload", "workload",
+           "MATRIX_DAMAGE", "MATRIX_TENSILE", "INCLUSION_ELASTIC", "Workload", "workload",
            "uniaxial_load_path"]

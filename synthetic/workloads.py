@@ -14,6 +14,9 @@ from .microstructure import inclusion_microstructure
 # material records: plain dicts so both sides can read them without sharing code
 MATRIX_DAMAGE = {"kind": "damage", "E": 1.0, "nu": 0.3, "kappa0": 1e-3, "kappaf": 5e-3}
 INCLUSION_ELASTIC = {"kind": "elastic", "E": 10.0, "nu": 0.3, "kappa0": 0.0, "kappaf": 0.0}
+# the tensile-masking law (the paper's Appendix A) with the matrix's threshold
+# and softening: relative softening slope alpha = kappa0 / (kappaf - kappa0) = 0.25
+MATRIX_TENSILE = {"kind": "tensile", "E": 1.0, "nu": 0.3, "kappa0": 1e-3, "kappaf": 5e-3}
 
 
 def uniaxial_load_path(dim, total, steps):
