@@ -57,7 +57,7 @@ typedef enum {
 enum { HFE_CONVERGED = 0, HFE_NOT_CONVERGED = 1 };
 
 enum { HFE_P1_PAIR = 1, HFE_Q1 = 2 };
-enum { HFE_ELASTIC = 0, HFE_DAMAGE_ENERGY_NORM = 1 };
+enum { HFE_ELASTIC = 0, HFE_DAMAGE_ENERGY_NORM = 1, HFE_DAMAGE_TENSILE = 2 };
 enum { HFE_MAX_PHASES = 8 };
 /* Arithmetic of the CG inside hfe_solve_increment (hfe_solver_params.precision). */
 enum { HFE_FP64 = 0, HFE_MIXED = 1 };
@@ -84,7 +84,7 @@ typedef struct {
  * (one spectral plane fits in LDS); nz = 1 exactly when dim = 2. */
 
 typedef struct {
-  int kind;        /* HFE_ELASTIC or HFE_DAMAGE_ENERGY_NORM */
+  int kind;        /* HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM or HFE_DAMAGE_TENSILE */
   double E, nu;    /* Young's modulus > 0, Poisson ratio in (-1, 1/2)          */
   double kappa0;   /* damage threshold of the equivalent strain (damage only) */
   double kappaf;   /* equivalent strain at full damage, > kappa0             */
@@ -93,7 +93,16 @@ typedef struct {
  * loading iff kappa_t > kappa_hist, d = clamp(kf/k (k - k0)/(kf - k0), 0, 1)
  * with k = kappa_t when loading else kappa_hist, sigma = (1 - d) C : eps.
  * Consistent tangent B = (1-d) C - c' (C:eps) (x) (C:eps),
- * c' = d'(kappa_t)/(E kappa_t) while loading with 0 < d < 1, else 0. */
+ * c' = d'(kappa_t)/(E kappa_t) while loading with 0 < d < 1, else 0.
+ * HFE_DAMAGE_TENSILE, the tensile-masking law of Appendix A (eqs.
+ * strain_measure, stress_contributions_maksing_matrices, Mask_matrices_t,
+ * our_model_damage_variable): the same d(kappa) and sigma, with
+ * kappa_t = |eps_t|, eps_t = sum_i max(e_i, 0) q_i (x) q_i over the
+ * eigenpairs of eps; the appendix's relative softening slope alpha is
+ * kappaf = kappa0 (1 + alpha) / alpha. Tangent B = (1-d) C - c' (C:eps) (x) eps_t,
+ * c' = d'(kappa_t)/kappa_t, which is not symmetric: the CG of Algorithm 1
+ * runs on it unchanged (3D Q1: the state keeps a second factor per softening
+ * point). */
 
 typedef struct {
   double eta_eq;   /* equilibrium tolerance on ||G sigma|| / ||sigma||        */

@@ -47,6 +47,7 @@ struct Layout {
   size_t u, z, d, g, y, Kd, w, g0, y0, tmp;          // nodal [dim][N]
   size_t a, cp, kh;                                   // per point [nq][N]
   size_t sw;                                          // per point [nq][6][N] (Q1)
+  size_t sn;                                          // per point [nq][6][N] (Q1)
   size_t phase;                                       // N bytes
   size_t soft;                                        // N bytes: element softens
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
@@ -117,6 +118,7 @@ Layout make_layout(const Grid& g) {
   L.tmp = take(nod);
   L.a = take(pts); L.cp = take(pts); L.kh = take(pts);
   L.sw = take(g.element == HFE_Q1 ? 6 * pts : 0);
+  L.sn = take(g.element == HFE_Q1 ? 6 * pts : 0);
   L.phase = take((size_t)g.N);
   L.soft = take((size_t)g.N);
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
@@ -181,6 +183,8 @@ struct hfe_ctx {
   double *u, *z, *d, *gv, *y, *Kd, *w, *g0, *y0, *tmp;
   double *a, *cp, *kh;
   double* sw;                // Q1: w = sqrt(c') s at the softening points
+  double* sn;                // Q1, tensile-masking phases present: w_n = sqrt(c') n
+  bool tens = false;         // some phase follows the tensile-masking law
   uint8_t* phase;
   uint8_t* soft;             // per element: bit q set iff c' != 0 at point q (Q1)
   double n_soft = 0.0;       // softening points of the state (Q1)
@@ -367,6 +371,9 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.soft_out = nullptr;
   A.sw = c->sw;
   A.sw_out = nullptr;
+  A.tens = c->tens;
+  A.sn = c->sn;
+  A.sn_out = nullptr;
   A.red = reducer(c);
   A.cg = nullptr;
   A.brick_shape = c->brick_shape;
@@ -443,6 +450,7 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   A.cp_out = c->cp;
   A.soft_out = c->soft;
   A.sw_out = c->sw;
+  A.sn_out = c->sn;
   A.f = c->g0;
   int nb = 0;
   {
@@ -512,6 +520,8 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.soft = c->soft;
   H.a = c->a32;
   H.sw = c->sw;
+  H.tens = c->tens;
+  H.sn = c->sn;
   H.v = v;
   H.f = out;
   H.red = reducer(c);
@@ -940,6 +950,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tmp = D(L.tmp);
   c->a = D(L.a); c->cp = D(L.cp); c->kh = D(L.kh);
   c->sw = c->g.element == HFE_Q1 ? D(L.sw) : nullptr;
+  c->sn = c->g.element == HFE_Q1 ? D(L.sn) : nullptr;
   auto F = [&](size_t off) { return (float*)(c->ws + off); };
   c->z32 = F(L.z32); c->d32 = F(L.d32); c->g32 = F(L.g32);
   c->y32 = F(L.y32); c->Kd32 = F(L.Kd32); c->tmp32 = F(L.tmp32);
@@ -1058,17 +1069,21 @@ hfe_status hfe_set_material(hfe_ctx* c, int phase, const hfe_material* m) {
   if (c->have_state) return fail(c, HFE_ESTATE, "materials are fixed once loading started");
   if (!m || phase < 0 || phase >= c->n_phases) return fail(c, HFE_EINVAL, "bad phase or material");
   if (!(m->E > 0.0) || !(m->nu > -1.0 && m->nu < 0.5)) return fail(c, HFE_EINVAL, "E > 0 and -1 < nu < 1/2 required");
-  if (m->kind != HFE_ELASTIC && m->kind != HFE_DAMAGE_ENERGY_NORM) return fail(c, HFE_EINVAL, "unknown material kind");
-  if (m->kind == HFE_DAMAGE_ENERGY_NORM && !(m->kappa0 > 0.0 && m->kappaf > m->kappa0))
+  if (m->kind != HFE_ELASTIC && m->kind != HFE_DAMAGE_ENERGY_NORM && m->kind != HFE_DAMAGE_TENSILE)
+    return fail(c, HFE_EINVAL, "unknown material kind");
+  if (m->kind != HFE_ELASTIC && !(m->kappa0 > 0.0 && m->kappaf > m->kappa0))
     return fail(c, HFE_EINVAL, "damage needs 0 < kappa0 < kappaf");
   const double E = m->E, nu = m->nu;
   c->mat.lam[phase] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   c->mat.mu[phase] = E / (2.0 * (1.0 + nu));
   c->mat.E[phase] = E;
-  c->mat.damage[phase] = m->kind == HFE_DAMAGE_ENERGY_NORM;
+  c->mat.damage[phase] = m->kind;   // the law: 0 elastic, else the damage kind
   c->mat.k0[phase] = c->mat.damage[phase] ? m->kappa0 : 0.0;
   c->mat.kf[phase] = c->mat.damage[phase] ? m->kappaf : 1.0;
   c->mat_set[phase] = true;
+  c->tens = false;
+  for (int p = 0; p < c->n_phases; ++p)
+    c->tens = c->tens || (c->mat_set[p] && c->mat.damage[p] == HFE_DAMAGE_TENSILE);
   destroy_graphs(c);
   c->history_ready = false;  // kappa0 may have changed: re-initialise before the first step
   return HFE_OK;

@@ -76,6 +76,13 @@ struct ElemArgs {
   uint8_t* soft_out;
   const double* sw;
   double* sw_out;
+  // tens != 0: some phase follows the tensile-masking law, whose tangent
+  // a C - c' (n:e) s is not symmetric (n = eps_t): the residual pass also
+  // writes w_n = sqrt(c') n [nq][6][N] at the softening points (n = s at
+  // energy-norm points), read by the trial and Hessian passes.
+  int tens;
+  const double* sn;
+  double* sn_out;
   Reducer red;
   CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
   int brick_shape;       // brick shape of the Q1 element passes (see launch_brick)
@@ -99,6 +106,8 @@ struct HessArgs {
   const uint8_t* phase;
   const uint8_t* soft;   // [N] softening points of each element (bit q), as in ElemArgs
   const double* sw;      // [nq][6][N] w = sqrt(c') s at the softening points (FP64)
+  int tens;              // as in ElemArgs: sn holds w_n = sqrt(c') n (FP64)
+  const double* sn;
   const R* a;            // [nq][N] tangent scalars of the state
   const R* v;            // [dim][N] direction
   R* f;                  // [dim][N] K v

@@ -114,6 +114,64 @@ __device__ __forceinline__ SymT<R> c_contract(const SymT<R>& e, R lam, R mu) {
   return s;
 }
 
+// One Jacobi rotation in the (p, q) plane that zeroes A[p][q] of the symmetric
+// 3x3 A, accumulated into the eigenvector columns of V (Rutishauser's form:
+// t = tan of the angle, the smaller root, tau = s / (1 + c)).
+template <int P, int Q>
+__host__ __device__ __forceinline__ void jacobi_rotate(double (&A)[3][3], double (&V)[3][3]) {
+  constexpr int Rr = 3 - P - Q;
+  const double apq = A[P][Q];
+  if (apq == 0.0) return;
+  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * apq);
+  const double at = fabs(theta);
+  double t = at > 1e150 ? 0.5 / at : 1.0 / (at + sqrt(at * at + 1.0));
+  if (theta < 0.0) t = -t;
+  const double c = 1.0 / sqrt(t * t + 1.0), s = t * c, tau = s / (1.0 + c);
+  A[P][P] -= t * apq;
+  A[Q][Q] += t * apq;
+  A[P][Q] = A[Q][P] = 0.0;
+  const double g = A[Rr][P], h = A[Rr][Q];
+  A[Rr][P] = A[P][Rr] = g - s * (h + g * tau);
+  A[Rr][Q] = A[Q][Rr] = h + s * (g - h * tau);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double vg = V[r][P], vh = V[r][Q];
+    V[r][P] = vg - s * (vh + vg * tau);
+    V[r][Q] = vh + s * (vg - vh * tau);
+  }
+}
+
+// Tensile part eps_t = sum_i max(e_i, 0) q_i (x) q_i of a symmetric strain
+// over its eigenpairs (e_i, q_i): the masked strain M eps M of Appendix A.
+// Cyclic Jacobi sweeps until the off-diagonal part is below 1e-17 of the
+// diagonal (quadratic convergence: a few sweeps); no division by an
+// eigenvalue gap, so equal principal strains need no special case. In 2D
+// the zz, xz and yz entries are zero and one rotation is exact.
+__host__ __device__ inline Sym tensile_part(const Sym& e) {
+  double A[3][3] = {{e.v[0], e.v[3], e.v[4]}, {e.v[3], e.v[1], e.v[5]}, {e.v[4], e.v[5], e.v[2]}};
+  double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (!(off > 1e-34 * dia)) break;
+    jacobi_rotate<0, 1>(A, V);
+    jacobi_rotate<0, 2>(A, V);
+    jacobi_rotate<1, 2>(A, V);
+  }
+  const double l0 = fmax(A[0][0], 0.0), l1 = fmax(A[1][1], 0.0), l2 = fmax(A[2][2], 0.0);
+  auto ent = [&](int a, int b) {
+    return l0 * V[a][0] * V[b][0] + l1 * V[a][1] * V[b][1] + l2 * V[a][2] * V[b][2];
+  };
+  Sym t;
+  t.v[0] = ent(0, 0);
+  t.v[1] = ent(1, 1);
+  t.v[2] = ent(2, 2);
+  t.v[3] = ent(0, 1);
+  t.v[4] = ent(0, 2);
+  t.v[5] = ent(1, 2);
+  return t;
+}
+
 // The strain the law sees: sym(H) plus the phase's eigenstrain (Algorithm 2
 // adds it before every evaluation; in 2D only its in-plane part is set).
 template <int D, typename R>
@@ -134,27 +192,42 @@ __device__ __forceinline__ double sym_norm2(const Sym& s) {
 
 struct PointLaw {
   Sym s;        // C : eps
+  Sym n;        // direction of the equivalent strain's derivative (TENS builds)
   double a;     // 1 - d
   double cp;    // c' of the rank-one softening term
   double kt;    // equivalent strain kappa_t
 };
 
-// Damage law at one point with the history kappa_hist frozen.
+// Damage law at one point with the history kappa_hist frozen. law is the
+// phase's kind: HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM (kappa_t the energy norm
+// sqrt(eps:C:eps/E), d kappa_t/d eps = s/(E kappa_t)) or, in TENS builds,
+// HFE_DAMAGE_TENSILE (Appendix A: kappa_t = |eps_t| of the tensile part,
+// d kappa_t/d eps = eps_t/kappa_t). Both share the bilinear d(kappa); the
+// tangent is a C - c' (n : deps) s with n = s or eps_t.
+template <bool TENS = false>
 __device__ __forceinline__ PointLaw eval_law(const Sym& eps, double lam, double mu, double E,
-                                             int damage, double k0, double kf, double kh) {
+                                             int law, double k0, double kf, double kh) {
   PointLaw P;
   P.s = c_contract(eps, lam, mu);
-  const double ecs = sym_dot(eps, P.s);
-  P.kt = sqrt(fmax(ecs, 0.0) / E);
+  double scale = E;
+  if (TENS && law == HFE_DAMAGE_TENSILE) {
+    P.n = tensile_part(eps);
+    P.kt = sqrt(sym_dot(P.n, P.n));
+    scale = 1.0;
+  } else {
+    const double ecs = sym_dot(eps, P.s);
+    P.kt = sqrt(fmax(ecs, 0.0) / E);
+    if (TENS) P.n = P.s;
+  }
   double d = 0.0, cp = 0.0;
-  if (damage) {
+  if (law) {
     const bool loading = P.kt > kh;
     const double ke = loading ? P.kt : kh;
     d = kf / ke * (ke - k0) / (kf - k0);
     d = fmin(fmax(d, 0.0), 1.0);
     if (loading && d > 0.0 && d < 1.0) {
       const double dprime = kf * k0 / ((kf - k0) * (P.kt * P.kt));
-      cp = dprime / (E * P.kt);
+      cp = dprime / (scale * P.kt);
     }
   }
   P.a = 1.0 - d;
@@ -162,17 +235,28 @@ __device__ __forceinline__ PointLaw eval_law(const Sym& eps, double lam, double 
   return P;
 }
 
-// Tangent applied to a perturbation: a C:deps - c' (s:deps) s.
+// Equivalent strain kappa_t of either damage law (for the history commit).
+__device__ inline double equiv_strain(const Sym& eps, double lam, double mu, double E, int law) {
+  if (law == HFE_DAMAGE_TENSILE) {
+    const Sym t = tensile_part(eps);
+    return sqrt(sym_dot(t, t));
+  }
+  const Sym s = c_contract(eps, lam, mu);
+  return sqrt(fmax(sym_dot(eps, s), 0.0) / E);
+}
+
+// Tangent applied to a perturbation: a C:deps - c' (n:deps) s (n = s for
+// the energy-norm law).
 template <typename R>
 __device__ __forceinline__ SymT<R> apply_tangent(const SymT<R>& de, R a, R cp, const SymT<R>& s,
-                                                 R lam, R mu) {
+                                                 const SymT<R>& n, R lam, R mu) {
   SymT<R> t = c_contract(de, lam, mu);
 #pragma unroll
   for (int k = 0; k < 6; ++k) t.v[k] *= a;
   if (cp != R(0)) {
-    const R sde = sym_dot(s, de);
+    const R nde = sym_dot(n, de);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) t.v[k] -= cp * sde * s.v[k];
+    for (int k = 0; k < 6; ++k) t.v[k] -= cp * nde * s.v[k];
   }
   return t;
 }
@@ -298,7 +382,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
           double dH[3][3];
           grad_at<EL>(q, vn, dH);
           const double aq = A.a[q * g.N + ei], cq = A.cp[q * g.N + ei];
-          Sym s;
+          Sym s, nv;
           if (cq != 0.0) {
             double H[3][3];
             grad_at<EL>(q, un, H);
@@ -306,12 +390,14 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
             for (int i = 0; i < 3; ++i)
 #pragma unroll
               for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
-            s = c_contract(eval_strain<D>(H, A.mat, ph), lam, mu);
+            const Sym eps = eval_strain<D>(H, A.mat, ph);
+            s = c_contract(eps, lam, mu);
+            nv = dmg == HFE_DAMAGE_TENSILE ? tensile_part(eps) : s;
           } else {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) s.v[k] = 0.0;
+            for (int k = 0; k < 6; ++k) s.v[k] = nv.v[k] = 0.0;
           }
-          tau = apply_tangent(sym_of<D>(dH), aq, cq, s, lam, mu);
+          tau = apply_tangent(sym_of<D>(dH), aq, cq, s, nv, lam, mu);
           if (owner) {
             double dd = 0.0;
 #pragma unroll
@@ -329,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
             for (int j = 0; j < 3; ++j) H[i][j] += Em[i][j];
           const Sym eps = eval_strain<D>(H, A.mat, ph);
           const double kh = A.khist[q * g.N + ei];
-          const PointLaw P = eval_law(eps, lam, mu, Ey, dmg, k0, kf, kh);
+          const PointLaw P = eval_law<true>(eps, lam, mu, Ey, dmg, k0, kf, kh);
 #pragma unroll
           for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
           if (owner) {
@@ -359,12 +445,15 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
           const double kh = A.khist[q * g.N + ei];
-          const PointLaw P = eval_law(eval_strain<D>(Ht, A.mat, ph), lam, mu, Ey, dmg, k0, kf, kh);
+          const PointLaw P = eval_law<true>(eval_strain<D>(Ht, A.mat, ph), lam, mu, Ey, dmg, k0, kf,
+                                            kh);
 #pragma unroll
           for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
           if (owner) {
             const double ao = A.a[q * g.N + ei], co = A.cp[q * g.N + ei];
-            const Sym so = c_contract(eval_strain<D>(H, A.mat, ph), lam, mu);
+            const Sym eo = eval_strain<D>(H, A.mat, ph);
+            const Sym so = c_contract(eo, lam, mu);
+            const Sym no = (co != 0.0 && dmg == HFE_DAMAGE_TENSILE) ? tensile_part(eo) : so;
             const Sym ps = sym_of<D>(p);
             double sig_p = 0.0;  // sigma_old : p
             {
@@ -373,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(ElemArgs A) {
               for (int k = 0; k < 6; ++k) sig.v[k] = ao * so.v[k];
               sig_p = sym_dot(sig, ps);
             }
-            const Sym Bp = apply_tangent(ps, ao, co, so, lam, mu);
+            const Sym Bp = apply_tangent(ps, ao, co, so, no, lam, mu);
             acc[TRI_SP] += sig_p;
             acc[TRI_PBP] += sym_dot(Bp, ps);
             acc[TRI_STP] += sym_dot(tau, ps);
@@ -437,9 +526,8 @@ __global__ void __launch_bounds__(kBlock) k_commit(ElemArgs A) {
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) H[i][j] += A.E[3 * i + j];
-    const Sym eps = eval_strain<D>(H, A.mat, ph);
-    const Sym s = c_contract(eps, A.mat.lam[ph], A.mat.mu[ph]);
-    const double kt = sqrt(fmax(sym_dot(eps, s), 0.0) / A.mat.E[ph]);
+    const double kt = equiv_strain(eval_strain<D>(H, A.mat, ph), A.mat.lam[ph], A.mat.mu[ph],
+                                   A.mat.E[ph], A.mat.damage[ph]);
     const long long idx = q * g.N + n;
     kh[idx] = fmax(kh[idx], kt);
   }
@@ -479,8 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(ElemArgs A, double* out_h, do
     if (out_s) {
       const Sym eps = eval_strain<D>(H, A.mat, ph);
       const double kh = A.khist[q * g.N + n];
-      const PointLaw P = eval_law(eps, A.mat.lam[ph], A.mat.mu[ph], A.mat.E[ph],
-                                  A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh);
+      const PointLaw P = eval_law<true>(eps, A.mat.lam[ph], A.mat.mu[ph], A.mat.E[ph],
+                                        A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh);
       for (int i = 0; i < D; ++i)
         for (int j = 0; j < D; ++j) out_s[base + i * D + j] = P.a * sym_at(P.s, i, j);
     }
@@ -674,12 +762,16 @@ __device__ __forceinline__ void tile_grad(const R (*f)[TILE], int q, int t0, int
   }
 }
 
-template <int MODE, int NV, int BX, int BY, int BZ, bool FULL>
+template <int MODE, int NV, int BX, int BY, int BZ, bool FULL, bool TENS>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(ElemArgs A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
-  __shared__ double su[3][kTile];   // u
-  __shared__ double acc[3][kOwn];
+  // one LDS area: the staged u tile su[3][kTile], then the element forces
+  // F[8][3][kElems] (corner, component, element)
+  constexpr int kElems = BrickShape<BX, BY, BZ>::elems;
+  constexpr int kLds = 3 * kTile > 24 * kElems ? 3 * kTile : 24 * kElems;
+  __shared__ double lds[kLds];
+  double (*su)[kTile] = reinterpret_cast<double (*)[kTile]>(lds);
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
@@ -719,10 +811,6 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
       }
     }
   };
-  for (int i = tid; i < bx * by * bz; i += nt) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c][i] = 0.0;
-  }
   // this thread's element
   const int ne = ex_n * ey_n * ez_n;
   const bool active = tid < ne;
@@ -779,8 +867,8 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
         H[c][1] = Em[c][1] + G[c][1][gx][gz];
         H[c][2] = Em[c][2] + G[c][2][gx][gy];
       }
-      const PointLaw P = eval_law(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph],
-                                  A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh[q]);
+      const PointLaw P = eval_law<TENS>(eval_strain<3>(H, A.mat, ph), lam, mu, A.mat.E[ph],
+                                        A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh[q]);
       Sym tau;
 #pragma unroll
       for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
@@ -792,6 +880,11 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
           const double r = sqrt(P.cp);
 #pragma unroll
           for (int k = 0; k < 6; ++k) A.sw_out[(q * 6 + k) * g.N + eg] = r * P.s.v[k];
+          if (TENS) {
+            // the second factor sqrt(c') n of a tangent that is not symmetric
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A.sn_out[(q * 6 + k) * g.N + eg] = r * P.n.v[k];
+          }
           red[RES_NSOFT] += 1.0;
         }
         double hh = 0.0;
@@ -816,25 +909,32 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
     if (owned) A.soft_out[eg] = (uint8_t)soft;
   }
-  // assembly into the owned nodes, one local node per phase
+  // Assembly: every owned node adds the forces of its 8 elements in the
+  // fixed order of the corner a; the element forces go through the tile's
+  // LDS once every element has read the tile.
+  static_assert(kOwn <= nt, "one owned node per thread");
+  __syncthreads();
+  if (active) {
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    __syncthreads();
-    if (active) {
-      const int lx = ex + (a & 1) - 1, ly = ey + ((a >> 1) & 1) - 1, lz = ez + ((a >> 2) & 1) - 1;
-      if (lx >= 0 && lx < bx && ly >= 0 && ly < by && lz >= 0 && lz < bz) {
-        const int o = lx + bx * (ly + by * lz);
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c][o] += f[c][a];
-      }
-    }
+      for (int c = 0; c < 3; ++c) lds[(a * 3 + c) * kElems + tid] = f[c][a];
   }
   __syncthreads();
-  for (int i = tid; i < bx * by * bz; i += nt) {
-    const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
+  if (tid < bx * by * bz) {
+    const int lx = tid % bx, ly = (tid / bx) % by, lz = tid / (bx * by);
     const long long n = lin(g, x0 + lx, y0 + ly, z0 + lz);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) A.f[c * g.N + n] = acc[c][i];
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int e = (lx + 1 - (a & 1)) + ex_n * ((ly + 1 - ((a >> 1) & 1)) +
+                                                   ey_n * (lz + 1 - ((a >> 2) & 1)));
+        v += lds[(a * 3 + c) * kElems + e];
+      }
+      A.f[c * g.N + n] = v;
+    }
   }
   block_reduce_store<NV>(red, A.red.partials);
 }
@@ -843,12 +943,13 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
 // point of the elements the brick owns, with H = E + D u, p = D v and the
 // history frozen,
 //   TRI_SP  sigma(H) : p = a (s:p),      s = C : eps(H)
-//   TRI_PBP p : B(H) : p = a (p:C:p) - c' (s:p)^2
+//   TRI_PBP p : B(H) : p = a (p:C:p) - c' (n:p)(s:p), n = s for the energy
+//           norm (w:p)^2 with w = sqrt(c') s; TENS: (w:p)(w_n:p), w_n = sqrt(c') n
 //   TRI_STP sigma(H + p) : p
 //   TRI_PP  |p|^2,  TRI_HH |H + p|^2
 // No nodal output, so no halo elements: one thread per owned element, the
 // nodes of u and v staged on the (BX+1)(BY+1)(BZ+1) tile.
-template <int BX, int BY, int BZ, bool FULL>
+template <int BX, int BY, int BZ, bool FULL, bool TENS>
 __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
   constexpr int kTile = (BX + 1) * (BY + 1) * (BZ + 1);
   const Grid& g = A.g;
@@ -898,12 +999,16 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
       const bool sq = (soft >> q) & 1u;
       const double kh = A.khist[q * g.N + eg];
       const double ao = A.a[q * g.N + eg];
-      Sym w;
+      Sym w, wn;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) w.v[k] = 0.0;
+      for (int k = 0; k < 6; ++k) w.v[k] = wn.v[k] = 0.0;
       if (sq) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) w.v[k] = A.sw[(q * 6 + k) * g.N + eg];
+        if (TENS) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wn.v[k] = A.sn[(q * 6 + k) * g.N + eg];
+        }
       }
       double H[3][3], p[3][3];
 #pragma unroll
@@ -920,8 +1025,8 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) Ht[i][j] = H[i][j] + p[i][j];
-      const PointLaw P = eval_law(eval_strain<3>(Ht, A.mat, ph), lam, mu, A.mat.E[ph], A.mat.damage[ph],
-                                  A.mat.k0[ph], A.mat.kf[ph], kh);
+      const PointLaw P = eval_law<TENS>(eval_strain<3>(Ht, A.mat, ph), lam, mu, A.mat.E[ph],
+                                        A.mat.damage[ph], A.mat.k0[ph], A.mat.kf[ph], kh);
       Sym tau;
 #pragma unroll
       for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
@@ -939,11 +1044,11 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
           hh += Ht[i][j] * Ht[i][j];
         }
       red[TRI_SP] += ao * s_p;
-      // c' (s:p)^2 = (w:p)^2
+      // c' (n:p)(s:p) = (w_n:p)(w:p)
       double soft_pp = 0.0;
       if (sq) {
         const double wp = sym_dot(w, ps);
-        soft_pp = wp * wp;
+        soft_pp = TENS ? sym_dot(wn, ps) * wp : wp * wp;
       }
       red[TRI_PBP] += ao * pCp - soft_pp;
       red[TRI_STP] += sym_dot(tau, ps);
@@ -961,19 +1066,25 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 // sum-factorised. The tangent at a point is a C minus the rank-one softening
 // term, which the residual pass stored as w = sqrt(c') s at the points where
 // c' != 0 (bit q of the element's soft mask): B : e = a C : e - (w : e) w.
-// The state displacement is not read.
+// NS (a tensile-masking phase is present): the tangent is not symmetric and
+// the residual pass also stored w_n = sqrt(c') n, so B : e = a C : e -
+// (w_n : e) w. The state displacement is not read.
 // FP32: at most 128 VGPRs (4 waves per SIMD), which the FP32 kernel fits
 // without spills; FP64 keeps the compiler's choice.
 template <typename R> constexpr int hessian_waves_per_eu() { return sizeof(R) == 4 ? 4 : 1; }
 
-template <typename R, int BX, int BY, int BZ, bool FULL>
+template <typename R, int BX, int BY, int BZ, bool FULL, bool NS>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
     k_hessian(HessArgs<R> A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
   const Grid& g = A.g;
   if (A.cg && A.cg->done) return;
-  __shared__ R sv[3][kTile];
-  __shared__ R acc[3][kOwn];
+  // One LDS area serves first as the staged direction tile sv[3][kTile], then
+  // as the element forces F[8][3][kElems] (corner, component, element).
+  constexpr int kElems = BrickShape<BX, BY, BZ>::elems;
+  constexpr int kLds = 3 * kTile > 24 * kElems ? 3 * kTile : 24 * kElems;
+  __shared__ R lds[kLds];
+  R (*sv)[kTile] = reinterpret_cast<R (*)[kTile]>(lds);
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
   const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
@@ -1030,10 +1141,6 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
     for (int q = 0; q < 8; ++q) aq[q] = A.a[q * g.N + eg];
   }
   stage(A.v, sv);
-  for (int i = tid; i < bx * by * bz; i += nt) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c][i] = R(0);
-  }
   __syncthreads();
   R f[3][8];
 #pragma unroll
@@ -1070,6 +1177,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
       dd = 2.0 * s2;
     }
     const double* __restrict__ w_e = A.sw + eg;
+    const double* __restrict__ n_e = NS ? A.sn + eg : nullptr;
     const long long N = g.N;
     // T[c][j][m][n]: tau_cj summed over the Gauss coordinate along j; an
     // entry is written at the first of its two points and added at the second
@@ -1091,11 +1199,18 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
       R t00 = ltr + am2 * dH[0][0], t11 = ltr + am2 * dH[1][1], t22 = ltr + am2 * dH[2][2];
       R t01 = am * h01, t02 = am * h02, t12 = am * h12;
       if ((soft >> q) & 1u) {
-        R w[6];
+        R w[6], wn[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) w[k] = (R)w_e[(q * 6 + k) * N];
-        const R we = w[0] * dH[0][0] + w[1] * dH[1][1] + w[2] * dH[2][2] + w[3] * h01 +
-                     w[4] * h02 + w[5] * h12;
+        if (NS) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wn[k] = (R)n_e[(q * 6 + k) * N];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wn[k] = w[k];
+        }
+        const R we = wn[0] * dH[0][0] + wn[1] * dH[1][1] + wn[2] * dH[2][2] + wn[3] * h01 +
+                     wn[4] * h02 + wn[5] * h12;
         t00 -= we * w[0];
         t11 -= we * w[1];
         t22 -= we * w[2];
@@ -1114,30 +1229,44 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
 #pragma unroll
     for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
   }
-  // assembly into the owned nodes, one local node per phase
+  // Assembly. Every owned node adds the forces of its 8 elements in the fixed
+  // order of the corner a (the same order whatever the brick shape). The
+  // direction at the owned node is read from the tile first (for v.Kv), then
+  // the tile's LDS is reused for the element forces.
+  static_assert(kOwn <= nt, "one owned node per thread");
+  const int nown = bx * by * bz;
+  R vn[3] = {R(0), R(0), R(0)};
+  int lx = 0, ly = 0, lz = 0;
+  if (tid < nown) {
+    lx = tid % bx;
+    ly = (tid / bx) % by;
+    lz = tid / (bx * by);
+    const int ti = (lx + 1) + tx * ((ly + 1) + ty * (lz + 1));
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    __syncthreads();
-    if (active) {
-      const int lx = ex + (a & 1) - 1, ly = ey + ((a >> 1) & 1) - 1, lz = ez + ((a >> 2) & 1) - 1;
-      if (lx >= 0 && lx < bx && ly >= 0 && ly < by && lz >= 0 && lz < bz) {
-        const int o = lx + bx * (ly + by * lz);
+    for (int c = 0; c < 3; ++c) vn[c] = sv[c][ti];
+  }
+  __syncthreads();
+  if (active) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c][o] += f[c][a];
-      }
-    }
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lds[(a * 3 + c) * kElems + tid] = f[c][a];
   }
   __syncthreads();
   double dkd = 0.0;
-  for (int i = tid; i < bx * by * bz; i += nt) {
-    const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
+  if (tid < nown) {
     const long long n = lin(g, x0 + lx, y0 + ly, z0 + lz);
-    const int ti = (lx + 1) + tx * ((ly + 1) + ty * (lz + 1));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const R v = acc[c][i];
+      R v = R(0);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int e = (lx + 1 - (a & 1)) + ex_n * ((ly + 1 - ((a >> 1) & 1)) +
+                                                   ey_n * (lz + 1 - ((a >> 2) & 1)));
+        v += lds[(a * 3 + c) * kElems + e];
+      }
       A.f[c * g.N + n] = v;
-      dkd += (double)v * (double)sv[c][ti];
+      dkd += (double)v * (double)vn[c];
     }
   }
   double red[HES_NV];
@@ -1151,12 +1280,14 @@ hipError_t launch_brick_shape(const ElemArgs& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
   const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
-  if (full)
-    hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, true>), dim3(nb),
-                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
-  else
-    hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, false>), dim3(nb),
-                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
+  const dim3 grid(nb), block(BrickShape<BX, BY, BZ>::threads);
+  if (A.tens) {
+    if (full) hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, true, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, false, true>), grid, block, 0, s, A);
+  } else {
+    if (full) hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, true, false>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_brick<MODE, NV, BX, BY, BZ, false, false>), grid, block, 0, s, A);
+  }
   return hipGetLastError();
 }
 
@@ -1174,12 +1305,14 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
   const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
-  if (full)
-    hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true>), dim3(nb),
-                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
-  else
-    hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false>), dim3(nb),
-                       dim3(BrickShape<BX, BY, BZ>::threads), 0, s, A);
+  const dim3 grid(nb), block(BrickShape<BX, BY, BZ>::threads);
+  if (A.tens) {
+    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true>), grid, block, 0, s, A);
+  } else {
+    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false>), grid, block, 0, s, A);
+  }
   return hipGetLastError();
 }
 
@@ -1189,7 +1322,8 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
 // other's arithmetic, for 1.76 instead of 1.58 elements per owned node).
 template <typename R>
 hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
-  if (!A.v || !A.f || !A.a || !A.sw || !A.phase || !A.soft || !A.E || !A.red.partials)
+  if (!A.v || !A.f || !A.a || !A.sw || !A.phase || !A.soft || !A.E || !A.red.partials ||
+      (A.tens && !A.sn))
     return hipErrorInvalidValue;
   switch (A.brick_shape) {
     case 1: return launch_hessian_shape<R, 8, 8, 8>(A, s, nblocks);
@@ -1216,21 +1350,27 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
   if (!A.u || !A.f || !A.a_out || !A.soft_out || !A.sw_out || !A.khist || !A.phase || !A.E ||
-      !A.red.partials)
+      !A.red.partials || (A.tens && !A.sn_out))
     return hipErrorInvalidValue;
   return launch_brick<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
 }
 hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_TRIAL, TRI_NV>(A, s, nblocks);
-  if (!A.u || !A.v || !A.a || !A.soft || !A.sw || !A.khist || !A.phase || !A.E || !A.red.partials)
+  if (!A.u || !A.v || !A.a || !A.soft || !A.sw || !A.khist || !A.phase || !A.E ||
+      !A.red.partials || (A.tens && !A.sn))
     return hipErrorInvalidValue;
   constexpr int BX = 8, BY = 8, BZ = 4;
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
   *nblocks = nb;
-  if (A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0)
-    hipLaunchKernelGGL((k_trial<BX, BY, BZ, true>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
-  else
-    hipLaunchKernelGGL((k_trial<BX, BY, BZ, false>), dim3(nb), dim3(BX * BY * BZ), 0, s, A);
+  const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
+  const dim3 grid(nb), block(BX * BY * BZ);
+  if (A.tens) {
+    if (full) hipLaunchKernelGGL((k_trial<BX, BY, BZ, true, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_trial<BX, BY, BZ, false, true>), grid, block, 0, s, A);
+  } else {
+    if (full) hipLaunchKernelGGL((k_trial<BX, BY, BZ, true, false>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_trial<BX, BY, BZ, false, false>), grid, block, 0, s, A);
+  }
   return hipGetLastError();
 }
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
@@ -1242,6 +1382,8 @@ hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   H.phase = A.phase;
   H.soft = A.soft;
   H.sw = A.sw;
+  H.sn = A.sn;
+  H.tens = A.tens;
   H.a = A.a;
   H.v = A.v;
   H.f = A.f;

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfe.so")
 
 HFE_P1_PAIR, HFE_Q1 = 1, 2
-HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM = 0, 1
+HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM, HFE_DAMAGE_TENSILE = 0, 1, 2
 FIELD_U, FIELD_GRAD, FIELD_STRESS, FIELD_DAMAGE, FIELD_KAPPA = range(5)
 CG_INTERIOR, CG_BOUNDARY, CG_NEGCURV, CG_MAXITER = 1, 2, 3, 4
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE"}
@@ -324,7 +324,11 @@ class Solver:
 
     def set_material(self, phase, mat):
         m = _Material()
-        m.kind = HFE_DAMAGE_ENERGY_NORM if mat["kind"] == "damage" else HFE_ELASTIC
+        kinds = {"elastic": HFE_ELASTIC, "damage": HFE_DAMAGE_ENERGY_NORM,
+                 "tensile": HFE_DAMAGE_TENSILE}
+        if mat["kind"] not in kinds:
+            raise ValueError("unknown material kind %r" % (mat["kind"],))
+        m.kind = kinds[mat["kind"]]
         m.E, m.nu = float(mat["E"]), float(mat["nu"])
         m.kappa0 = float(mat.get("kappa0", 0.0))
         m.kappaf = float(mat.get("kappaf", 0.0))

@@ -17,6 +17,14 @@ INCLUSION_ELASTIC = {"kind": "elastic", "E": 10.0, "nu": 0.3, "kappa0": 0.0, "ka
 # the tensile-masking law (the paper's Appendix A) with the matrix's threshold
 # and softening: relative softening slope alpha = kappa0 / (kappaf - kappa0) = 0.25
 MATRIX_TENSILE = {"kind": "tensile", "E": 1.0, "nu": 0.3, "kappa0": 1e-3, "kappaf": 5e-3}
+# the ASR example's phases (the paper's table of material properties, moduli
+# divided by the cement paste's 12 GPa): paste and aggregates damage in
+# tension with kappa0 = f_t / E; the softening end kappaf = 10 kappa0 stands in
+# for the paper's fracture-energy regularisation, which needs its mesh size
+ASR_PASTE = {"kind": "tensile", "E": 1.0, "nu": 0.3, "kappa0": 2.5e-4, "kappaf": 2.5e-3}
+ASR_AGGREGATE = {"kind": "tensile", "E": 59.0 / 12.0, "nu": 0.3, "kappa0": 10.0 / 59e3,
+                 "kappaf": 100.0 / 59e3}
+ASR_GEL = {"kind": "elastic", "E": 11.0 / 12.0, "nu": 0.18, "kappa0": 0.0, "kappaf": 0.0}
 
 
 def uniaxial_load_path(dim, total, steps):
@@ -68,8 +76,18 @@ def workload(name, steps=None):
                   diagonal) of an inclusion centre form an elastic phase 2
                   whose isotropic eigenstrain grows by 2.5e-4 per step, at zero
                   macroscopic strain (20 steps).
+    ``asr_3dN``   the gel_3dN geometry with the ASR example's phases: cement
+                  paste and aggregates under the tensile-masking law, gel
+                  sites expanding by 1e-4 per step (20 steps).
     ``steps`` truncates the load path (the increment size is kept).
     """
+    if name.startswith("asr_3d"):
+        base = workload("gel_3d" + name[len("asr_3d"):], steps)
+        nsteps = len(base.eig_path)
+        eig = np.array([(k + 1) * 1e-4 * np.eye(3) for k in range(nsteps)])
+        return Workload(name=name, dim=3, shape=base.shape, element="q1", phase=base.phase,
+                        materials=[dict(ASR_PASTE), dict(ASR_AGGREGATE), dict(ASR_GEL)],
+                        load_path=base.load_path, info=base.info, eig_phase=2, eig_path=eig)
     if name.startswith("gel_3d"):
         n = int(name[len("gel_3d"):])
         base = workload("c1_3d%d" % n)

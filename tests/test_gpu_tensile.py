@@ -1,0 +1,247 @@
+"""GPU parity of the tensile-masking damage law (Appendix A) against the
+oracle: the law at the points (stress, softening points), the stiffness action
+and the projected Hessian with its non-symmetric tangent (FP64, and FP32 for
+the mixed-precision CG), and whole load increments of 2D and 3D inclusion
+cells started from the oracle's state (FP64 and mixed-precision CG, and the
+L-BFGS increment)."""
+import numpy as np
+import pytest
+
+from oracle import fe, material
+from oracle import quasi_newton as qn
+from oracle.projection import Projector
+from oracle.solver import CellSolver
+from synthetic import inclusion_microstructure, MATRIX_TENSILE, INCLUSION_ELASTIC
+from tests.gpu_util import require_gpu, announce, rel_err
+
+pytestmark = pytest.mark.gpu
+
+MATS = [dict(MATRIX_TENSILE), dict(INCLUSION_ELASTIC)]
+
+
+def _state(shape, seed, scale):
+    """Phase map, macroscopic strain with principal values of both signs and
+    a displacement that puts part of the matrix into softening."""
+    rng = np.random.default_rng(seed)
+    phase = (rng.random(shape) < 0.3).astype(np.uint8)
+    E = np.zeros((3, 3))
+    E[0, 0] = 1.5e-3
+    E[1, 1] = -6e-4
+    E[0, 1] = E[1, 0] = 5e-4
+    if len(shape) == 3:
+        E[2, 2] = 2e-4
+        E[1, 2] = E[2, 1] = -3e-4
+    u = scale * rng.normal(size=(len(shape),) + shape)
+    return phase, E, u
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (16, 12, 8), (24, 16, 16), (32, 32), (6, 8)])
+def test_tensile_law_stiffness_and_projected_hessian(shape):
+    torch = require_gpu()
+    announce("tensile operators", shape)
+    from paper_2207_10657_amd import Solver
+    el = "q1" if len(shape) == 3 else "p1pair"
+    dim = len(shape)
+    phase, E, u = _state(shape, 5, 4e-4)
+    s = Solver(shape, el)
+    s.setup(phase, MATS)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    mf = material.MaterialField(phase, MATS, 8 if el == "q1" else 2)
+    H = fe.gradient(u, el) + E[:dim, :dim]
+    st = material.evaluate(mf, H, mf.initial_history())
+    assert np.mean(st["cprime"] > 0) > 0.05
+    # points whose tensile part differs from the strain (a principal strain
+    # below zero): the masking is exercised
+    assert np.mean(np.any(np.linalg.eigvalsh(st["eps"]) < 0, axis=-1)[st["cprime"] > 0]) > 0.3
+    if el == "q1":
+        assert s.soft_points()[0] == np.count_nonzero(st["cprime"])
+    assert rel_err(s.field(2), st["sigma"]) < 1e-12
+    rng = np.random.default_rng(6)
+    d = rng.normal(size=(dim,) + shape)
+    dt = torch.tensor(d, device="cuda")
+    Kd = s.apply_stiffness(dt).cpu().numpy()
+    ref = fe.divergence(material.apply_tangent(mf, st, fe.gradient(d, el)), el)
+    assert rel_err(Kd, ref) < 1e-12
+    # the operator is not symmetric: <w, K d> != <d, K w>
+    w = rng.normal(size=(dim,) + shape)
+    Kw = s.apply_stiffness(torch.tensor(w, device="cuda")).cpu().numpy()
+    a, b = np.sum(w * Kd), np.sum(d * Kw)
+    assert abs(a - b) > 1e-6 * abs(a)
+    out, dots = s.apply_projected_hessian(dt)
+    Dd = fe.gradient(d, el)
+    BDd = material.apply_tangent(mf, st, Dd)
+    assert rel_err(fe.gradient(out.cpu().numpy(), el), Projector(shape, el)(BDd)) < 1e-12
+    assert abs(dots[0] - np.sum(Dd * BDd)) < 1e-12 * abs(dots[0])
+    if el == "q1":
+        # FP32 Hessian of the mixed-precision CG, on the FP32-rounded direction
+        o32, d32 = s.apply_projected_hessian_f32(torch.tensor(d, dtype=torch.float32,
+                                                              device="cuda"))
+        dr = d.astype(np.float32).astype(np.float64)
+        B32 = material.apply_tangent(mf, st, fe.gradient(dr, el))
+        err = rel_err(fe.gradient(o32.double().cpu().numpy(), el), Projector(shape, el)(B32))
+        print("[tensile] f32 projected Hessian %s: rel %.2e" % (shape, err), flush=True)
+        assert err < 3e-6
+
+
+def _cells(shape):
+    if len(shape) == 3:
+        phase, _ = inclusion_microstructure(shape, 1.0, 2.0, 0.25, 3)
+    else:
+        phase, _ = inclusion_microstructure(shape, 1.5, 3.0, 0.25, 3)
+    from paper_2207_10657_amd import Solver
+    el = "q1" if len(shape) == 3 else "p1pair"
+    g = Solver(shape, el)
+    g.setup(phase, MATS)
+    o = CellSolver(phase, [dict(m) for m in MATS], el)
+    return g, o
+
+
+@pytest.mark.parametrize("shape,steps,precision", [((16, 16), 4, "fp64"), ((8, 8, 8), 3, "fp64"),
+                                                   ((8, 8, 8), 2, "mixed")])
+def test_tensile_increments_against_oracle(shape, steps, precision):
+    """Uniaxial E_xx increments of 4e-4 into the softening regime, each
+    started on the GPU from the oracle's state. With a non-symmetric tangent
+    the CG trajectories of the two sides separate by rounding within an
+    increment, so the Newton paths may differ; both must converge, and the
+    converged results agree to 10x the stopping tolerance (stress 1e-8 of the
+    load scale, damage and gradient 1e-7)."""
+    require_gpu()
+    g, o = _cells(shape)
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 4e-4
+    prm = {"eta_eq": 1e-8, "eta_nr": 1e-12}
+    lam, mu = material.lame(10.0, 0.3)
+    for n in range(steps):
+        announce("tensile", shape, precision, "step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        g.apply_load_step(dE)
+        o.apply_load_step(dE)
+        rg = g.solve_increment(dict(prm, precision=precision))
+        ro = o.solve_increment(prm)
+        scale = np.linalg.norm(lam * np.trace(o.E) * np.eye(3) + 2 * mu * o.E)
+        dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
+        dd = float(np.abs(g.damage() - o.damage()).max())
+        dH = rel_err(g.gradient(), o.H)
+        print("[tensile] %s %s step %d: Newton %d/%d, CG %d/%d, |dSigma|/scale %.2e, damage %.2e, "
+              "grad %.2e, max damage %.3f" % (shape, precision, n, rg["newton_iters"],
+                                              ro["newton_iters"], rg["cg_iters"], ro["cg_iters"],
+                                              dS, dd, dH, float(o.damage().max())), flush=True)
+        assert rg["converged"] and ro["converged"], n
+        assert dS < 1e-8 and dd < 1e-7 and dH < 1e-7, (n, dS, dd, dH)
+    assert o.damage().max() > 0.0
+
+
+def test_tensile_lbfgs_increment_against_oracle():
+    """The L-BFGS increment (first-order energy increment in the line search)
+    on the 3D cell with the tensile law: first two increments, the second
+    from the oracle's state; results at 10x the tolerance."""
+    require_gpu()
+    g, o = _cells((8, 8, 8))
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 4e-4
+    prm = {"eta_eq": 1e-8, "eta_nr": 1e-12}
+    for n in range(2):
+        announce("tensile lbfgs step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        g.apply_load_step(dE)
+        o.apply_load_step(dE)
+        rg = g.solve_increment_lbfgs(prm)
+        ro = qn.solve_increment_lbfgs(o, prm)
+        dS = rel_err(g.homogenized_stress(), o.homogenized_stress())
+        dd = float(np.abs(g.damage() - o.damage()).max())
+        print("[tensile] lbfgs step %d: iters %d/%d, dSigma %.2e, damage %.2e"
+              % (n, rg["iters"], ro["iters"], dS, dd), flush=True)
+        assert rg["converged"] and ro["converged"]
+        assert dS < 1e-7 and dd < 1e-6
+
+
+def test_asr_expanding_sites_16_against_oracle():
+    """The ASR example's setting on a 16^3 cell: cement paste and aggregates
+    under the tensile-masking law, elastic gel sites inside the aggregates
+    expanding by 1e-4 per increment at zero macroscopic strain. Each
+    increment starts from the oracle's state; both converge and the results
+    agree to 10x the stopping tolerance (the cracks open from increment 5)."""
+    require_gpu()
+    from paper_2207_10657_amd import Solver
+    from synthetic import workload
+    w = workload("asr_3d16", steps=8)
+    g = Solver(w.shape, "q1")
+    g.setup(w.phase, w.materials)
+    o = CellSolver(w.phase, [dict(m) for m in w.materials], "q1")
+    lam, mu = material.lame(w.materials[1]["E"], w.materials[1]["nu"])
+    for n, dE in enumerate(w.load_path):
+        announce("asr_3d16 step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        eig = w.eig_path[n]
+        g.set_eigenstrain(w.eig_phase, eig)
+        o.set_eigenstrain(w.eig_phase, eig)
+        g.apply_load_step(dE)
+        o.apply_load_step(dE)
+        rg = g.solve_increment()
+        ro = o.solve_increment()
+        scale = np.linalg.norm(lam * np.trace(eig) * np.eye(3) + 2 * mu * eig)
+        dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
+        dd = float(np.abs(g.damage() - o.damage()).max())
+        dH = rel_err(g.gradient(), o.H)
+        print("[tensile] asr step %d: Newton %d/%d, CG %d/%d, |dSigma|/scale %.2e, damage %.2e, "
+              "grad %.2e, max damage %.3f" % (n, rg["newton_iters"], ro["newton_iters"],
+                                              rg["cg_iters"], ro["cg_iters"], dS, dd, dH,
+                                              float(o.damage().max())), flush=True)
+        assert rg["converged"] and ro["converged"], n
+        assert dS < 1e-8 and dd < 1e-7 and dH < 1e-7, (n, dS, dd, dH)
+    assert o.damage().max() > 0.0
+
+
+def test_tensile_full_size_projected_hessian_every_brick_64cubed():
+    """The 64^3 cell with the tensile-masking matrix at a softening state: one
+    projected-Hessian application against the oracle, then the same bits from
+    every Hessian brick shape (FP64), and the FP32 Hessian of each shape
+    within its rounding bound."""
+    torch = require_gpu()
+    announce("tensile projected hessian 64^3")
+    from paper_2207_10657_amd import Solver
+    from synthetic import workload
+    w = workload("c1_3d64")
+    mats = [dict(MATRIX_TENSILE)] + [dict(m) for m in w.materials[1:]]
+    rng = np.random.default_rng(7)
+    u = 4e-4 * rng.normal(size=(3,) + w.shape)
+    E = np.zeros((3, 3))
+    E[0, 0] = 1.5e-3
+    E[1, 1] = -4e-4
+    s = Solver(w.shape, "q1")
+    s.setup(w.phase, mats)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    d = rng.normal(size=(3,) + w.shape)
+    dt = torch.tensor(d, device="cuda")
+    s.set_tuning(brick_shape=0)
+    out, _ = s.apply_projected_hessian(dt)
+    out = out.cpu().numpy()
+    mf = material.MaterialField(w.phase, mats, 8)
+    st = material.evaluate(mf, fe.gradient(u, "q1") + E, mf.initial_history())
+    assert np.mean(st["cprime"] > 0) > 0.05
+    Dd = fe.gradient(d, "q1")
+    ref = Projector(w.shape, "q1")(material.apply_tangent(mf, st, Dd))
+    assert rel_err(fe.gradient(out, "q1"), ref) < 1e-12
+    d32 = torch.tensor(d, dtype=torch.float32, device="cuda")
+    for shape in range(1, 5):
+        s.set_tuning(brick_shape=shape)
+        o2, _ = s.apply_projected_hessian(dt)
+        assert np.array_equal(o2.cpu().numpy(), out), shape
+    ref32 = None
+    for shape in range(5):
+        s.set_tuning(brick_shape32=shape)
+        o32, _ = s.apply_projected_hessian_f32(d32)
+        if ref32 is None:
+            dr = d.astype(np.float32).astype(np.float64)
+            ref32 = Projector(w.shape, "q1")(material.apply_tangent(mf, st, fe.gradient(dr, "q1")))
+        err = rel_err(fe.gradient(o32.double().cpu().numpy(), "q1"), ref32)
+        print("[tensile] 64^3 f32 brick shape %d: rel %.2e" % (shape, err), flush=True)
+        assert err < 3e-6, (shape, err)
