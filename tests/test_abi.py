@@ -56,3 +56,13 @@ def test_create_rejects_bad_arguments_without_gpu():
     # too small a workspace
     assert lib.hfe_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == -2
     assert lib.hfe_last_error(None) == b"null context"
+
+
+def test_binding_constants_match_the_header():
+    """The binding's material kinds are the header's (parsed from
+    include/hfe.h)."""
+    hfe, _ = _lib()
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "hfe.h")).read()
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(HFE_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    for name in ("HFE_ELASTIC", "HFE_DAMAGE_ENERGY_NORM", "HFE_DAMAGE_TENSILE"):
+        assert getattr(hfe, name) == consts[name], name
