@@ -304,6 +304,45 @@ def tensile_bench(W=6, K=4, grid=64):
                     "Newton limit (50) end unconverged, as the oracle does on such increments"}
 
 
+def hessian_scaling(grids=(64, 128), launches=50):
+    """The FP64 Hessian (K d, the dominant kernel) alone at a softening state
+    on the cells of the workload recipe at each grid: event-timed per-launch
+    duration at the autotuned brick, and its algorithmic bandwidth against the
+    HBM peak. The 64^3 cell fills the chip poorly (512 blocks of one brick);
+    a larger cell shows the kernel with more blocks per CU."""
+    import torch
+    from paper_2207_10657_amd import Solver
+    from synthetic import workload
+    out = {}
+    for n in grids:
+        w = workload("c1_3d%d" % n)
+        s = Solver(w.shape, w.element)
+        s.setup(w.phase, w.materials)
+        E = np.zeros((3, 3))
+        E[0, 0] = 2e-3
+        s.apply_load_step(E)
+        rng = np.random.default_rng(5)
+        s.set_displacement(4e-4 * rng.normal(size=(3,) + w.shape))
+        tuning = s.autotune()
+        d = torch.tensor(rng.normal(size=(3,) + w.shape), device="cuda")
+        for _ in range(5):
+            s.apply_stiffness(d)
+        s.set_profiling(True)
+        for _ in range(launches):
+            s.apply_stiffness(d)
+        torch.cuda.synchronize()
+        c, ms = s.kernel_stats()["stiffness"]
+        s.set_profiling(False)
+        soft = s.soft_points()[0]
+        alg = algorithmic_bytes("stiffness", w.shape, soft)
+        us = ms / c * 1e3
+        out["%d^3" % n] = {"us_per_launch": us, "algorithmic_bytes": alg, "softening_points": soft,
+                           "achieved_GBs": alg / us / 1e3, "frac": alg / us / 1e3 / HBM_PEAK_GBS,
+                           "brick_shape": tuning["brick_shape"]}
+        s.close()
+    return out
+
+
 def hessian_label(shape_index):
     return "stiffness:%dx%dx%d" % BRICKS[shape_index]
 
@@ -686,6 +725,7 @@ def main():
         out["batch_six_load_cases"] = batch_bench(w, 2)
     if not args.no_tensile:
         out["tensile_law"] = tensile_bench()
+    out["hessian_scaling"] = hessian_scaling()
     if not args.no_warm_start:
         out["warm_start"] = warm_start_bench()
     if not args.no_cpu_baseline:
