@@ -519,6 +519,8 @@ def main():
                     help="skip the six-load-case batch run")
     ap.add_argument("--no-lbfgs", action="store_true",
                     help="skip the L-BFGS run of the first timed load steps")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip the Hessian-alone line at 64^3 and 128^3")
     ap.add_argument("--no-tensile", action="store_true",
                     help="skip the tensile-masking law (Appendix A) line")
     ap.add_argument("--no-warm-start", action="store_true",
@@ -725,7 +727,8 @@ def main():
         out["batch_six_load_cases"] = batch_bench(w, 2)
     if not args.no_tensile:
         out["tensile_law"] = tensile_bench()
-    out["hessian_scaling"] = hessian_scaling()
+    if not args.no_scaling:
+        out["hessian_scaling"] = hessian_scaling()
     if not args.no_warm_start:
         out["warm_start"] = warm_start_bench()
     if not args.no_cpu_baseline:
