@@ -220,6 +220,58 @@ def batch_bench(w, steps):
             "same_results_as_sequential": bool(same and mv_seq == mv_bat),
             "autotuned_launch": tuned}
 
+def uneven_batch_bench(sizes=(32, 48, 64, 96), per_size=2, steps=1):
+    """Many cells of uneven sizes (the recipe's seeds 11, 12, ... at each size,
+    `per_size` cells per size), each under the six unit load cases: one
+    increment of 2e-4 solved one context after the other, then as one batch
+    (one context per cell and case, each on its own stream), from the same
+    states. Launch shapes stay at the library's defaults."""
+    import torch
+    from paper_2207_10657_amd import Solver, solve_batch
+    from synthetic import inclusion_microstructure, MATRIX_DAMAGE, INCLUSION_ELASTIC
+    mats = [dict(MATRIX_DAMAGE), dict(INCLUSION_ELASTIC)]
+    cases = unit_load_cases(2e-4)
+    jobs = []
+    seed = 11
+    for n in sizes:
+        for _ in range(per_size):
+            phase = inclusion_microstructure((n, n, n), 4.0 * n / 64, 8.0 * n / 64, 0.25, seed)[0]
+            seed += 1
+            for dE in cases:
+                s = Solver(phase.shape, "q1", own_stream=True)
+                s.setup(phase, mats)
+                jobs.append((s, dE, phase.size))
+    cks = [s.get_state() for s, _, _ in jobs]
+
+    def run(batched):
+        vm = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for s, dE, _ in jobs:
+                s.apply_load_step(dE)
+            solvers = [s for s, _, _ in jobs]
+            reps = solve_batch(solvers) if batched else [s.solve_increment() for s in solvers]
+            vm += sum(r["matvecs"] * nv for r, (_, _, nv) in zip(reps, jobs))
+        torch.cuda.synchronize()
+        return vm, time.perf_counter() - t0, reps
+
+    vm_seq, dt_seq, reps = run(False)
+    out_seq = [s.homogenized_stress() for s, _, _ in jobs]
+    for (s, _, _), ck in zip(jobs, cks):
+        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+    vm_bat, dt_bat, _ = run(True)
+    same = all(np.array_equal(a, s.homogenized_stress()) for a, (s, _, _) in zip(out_seq, jobs))
+    for s, _, _ in jobs:
+        s.close()
+    return {"cells": len(sizes) * per_size, "sizes": list(sizes), "solves": len(jobs),
+            "converged": sum(int(r["converged"]) for r in reps),
+            "sequential": {"value": vm_seq / dt_seq / 1e9, "ms": dt_seq * 1e3},
+            "batched": {"value": vm_bat / dt_bat / 1e9, "ms": dt_bat * 1e3},
+            "unit": "Gvoxel-matvec/s", "speedup": dt_seq / dt_bat,
+            "same_results_as_sequential": bool(same)}
+
+
 # Counter summary written by `--pmc-summary`; read back for roofline.traffic.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_64cubed.md")
 CSRC = os.path.join(ROOT, "paper_2207_10657_amd", "csrc")
@@ -725,6 +777,7 @@ def main():
     }
     if not args.no_batch:
         out["batch_six_load_cases"] = batch_bench(w, 2)
+        out["batch_uneven_cells"] = uneven_batch_bench()
     if not args.no_tensile:
         out["tensile_law"] = tensile_bench()
     if not args.no_scaling:

@@ -106,6 +106,37 @@ def test_batch_of_six_load_cases_matches_single_solves():
         s.close()
 
 
+def test_batch_of_uneven_cells_matches_single_solves():
+    """Cells of uneven sizes (8^3, 12^3, 16^3, 24^3 of the workload recipe, an
+    uneven brick fit at 12^3 and 24^3), each under its own unit load case,
+    solved as one batch and one by one: the same bits."""
+    require_gpu()
+    announce("batch of uneven cells")
+    from paper_2207_10657_amd import Solver, solve_batch
+    cases = _load_cases(2e-4)
+    cells = []
+    for k, n in enumerate((8, 12, 16, 24)):
+        w = workload("c1_3d%d" % n)
+        cells.append((w, cases[k]))
+    batch = [Solver(w.shape, "q1", own_stream=True) for w, _ in cells]
+    for s, (w, _) in zip(batch, cells):
+        s.setup(w.phase, w.materials)
+    for step in range(2):
+        for s, (_, dE) in zip(batch, cells):
+            s.apply_load_step(dE)
+        reps = solve_batch(batch)
+        announce("uneven batch step", step, [(r["newton_iters"], r["cg_iters"]) for r in reps])
+    for n, (sb, (w, dE)) in enumerate(zip(batch, cells)):
+        s = Solver(w.shape, "q1")
+        s.setup(w.phase, w.materials)
+        for step in range(2):
+            s.apply_load_step(dE)
+            s.solve_increment()
+        np.testing.assert_array_equal(sb.homogenized_stress(), s.homogenized_stress(), err_msg=str(n))
+        np.testing.assert_array_equal(sb.get_state()["u"], s.get_state()["u"], err_msg=str(n))
+        s.close()
+
+
 # ---- effective stiffness (six unit load cases as one batch) -------------------
 
 VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
