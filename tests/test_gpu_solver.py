@@ -206,6 +206,15 @@ def test_lockstep_3d_workload_16():
     _lockstep("c1_3d16", 10)
 
 
+def test_lockstep_3d_workload_16_solved_to_tolerance():
+    """The same cell with the benchmark's Newton limit (2000): the first four
+    steps each solved to the 1e-8 residual, through the damage onset that the
+    default limit of 50 cuts short (59 Newton iterations in step 2)."""
+    require_gpu()
+    compared, ties = _lockstep("c1_3d16", 4, {"i_nr_max": 2000})
+    assert compared + len(ties) == 4
+
+
 def test_checkpoint_restart_is_exact():
     """Solve 4 steps; save after 2, restore into a fresh context, redo steps
     3-4: identical bits."""
