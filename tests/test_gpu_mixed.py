@@ -70,6 +70,46 @@ def test_f32_projected_hessian(shape):
     assert err < F32_OP_TOL and e0 < F32_OP_TOL and e1 < F32_OP_TOL
 
 
+def test_projected_hessian_128cubed_fp64_and_fp32():
+    """The 128^3 cell of the mixed-precision case (the recipe's seed-3 cell):
+    one projected-Hessian application at a damaged state, FP64 against the
+    oracle at 1e-12 and FP32 within the operator bound (the oracle on the
+    FP32-rounded direction)."""
+    torch = require_gpu()
+    announce("projected hessian 128^3, FP64 and FP32")
+    from paper_2207_10657_amd import Solver
+    w = workload("c1_3d128")
+    rng = np.random.default_rng(9)
+    u = 4e-4 * rng.normal(size=(3,) + w.shape)
+    E = np.zeros((3, 3))
+    E[0, 0] = 2e-3
+    s = Solver(w.shape, "q1")
+    s.setup(w.phase, w.materials)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    d = rng.normal(size=(3,) + w.shape)
+    out, dots = s.apply_projected_hessian(torch.tensor(d, device="cuda"))
+    out = out.cpu().numpy()
+    o32, _ = s.apply_projected_hessian_f32(torch.tensor(d, dtype=torch.float32, device="cuda"))
+    o32 = o32.double().cpu().numpy()
+    s.close()
+    mf = material.MaterialField(w.phase, w.materials, 8)
+    st = material.evaluate(mf, fe.gradient(u, "q1") + E, mf.initial_history())
+    assert np.mean(st["cprime"] > 0) > 0.05
+    del u
+    P = Projector(w.shape, "q1")
+    Dd = fe.gradient(d, "q1")
+    BDd = material.apply_tangent(mf, st, Dd)
+    err64 = rel_err(fe.gradient(out, "q1"), P(BDd))
+    assert abs(dots[1] - np.sum(Dd * Dd)) < 1e-12 * dots[1]
+    del Dd, BDd
+    dr = d.astype(np.float32).astype(np.float64)
+    err32 = rel_err(fe.gradient(o32, "q1"), P(material.apply_tangent(mf, st, fe.gradient(dr, "q1"))))
+    print("[mixed] 128^3 projected Hessian: FP64 rel %.2e, FP32 rel %.2e" % (err64, err32), flush=True)
+    assert err64 < 1e-12
+    assert err32 < F32_OP_TOL
+
+
 def test_mixed_laminate_closed_form():
     require_gpu()
     announce("mixed laminate")
