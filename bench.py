@@ -298,6 +298,12 @@ PROBE_STEPS = 3
 BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4), 4: (8, 4, 4)}
 
 
+def progress(what):
+    """One line on stderr per finished section (stdout carries only the JSON
+    line)."""
+    print("[bench] %s" % what, file=sys.stderr, flush=True)
+
+
 def tensile_bench(W=6, K=4, grid=64):
     """The paper's own damage law (Appendix A, tensile masking) in the setting
     of its ASR example on the 64^3 cell: cement paste and aggregates under that
@@ -644,6 +650,7 @@ def main():
             sigmas.append(s.homogenized_stress())
         return matvecs, newton, cg, converged
 
+    progress("setup and autotuning done")
     # timed region: CG iterations replayed from captured HIP graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -679,6 +686,7 @@ def main():
     # the same steps with the mixed-precision CG (FP32 Hessian, FFT and CG
     # vectors; FP64 residual, trial and energy ratio) from the same state
     mixed = None
+    progress("timed steps, 50-iteration comparison and event-timed replay done")
     if not args.no_mixed:
         s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
         torch.cuda.synchronize()
@@ -709,6 +717,8 @@ def main():
     # the paper's quasi-Newton remark: the first LBFGS_STEPS timed increments
     # from the same checkpoint by L-BFGS on the approximate energy increment
     lbfgs = None
+    if mixed is not None:
+        progress("mixed precision done")
     if not args.no_lbfgs:
         s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
         per = []
@@ -778,12 +788,16 @@ def main():
     if not args.no_batch:
         out["batch_six_load_cases"] = batch_bench(w, 2)
         out["batch_uneven_cells"] = uneven_batch_bench()
+        progress("batches done")
     if not args.no_tensile:
         out["tensile_law"] = tensile_bench()
+        progress("tensile-masking law done")
     if not args.no_scaling:
         out["hessian_scaling"] = hessian_scaling()
+        progress("Hessian scaling done")
     if not args.no_warm_start:
         out["warm_start"] = warm_start_bench()
+        progress("warm start done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)
     print(json.dumps(out), flush=True)
