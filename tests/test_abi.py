@@ -66,3 +66,22 @@ def test_binding_constants_match_the_header():
     consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(HFE_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
     for name in ("HFE_ELASTIC", "HFE_DAMAGE_ENERGY_NORM", "HFE_DAMAGE_TENSILE"):
         assert getattr(hfe, name) == consts[name], name
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hfe.h compiles as strict C99 with every warning enabled (no
+    C++ or HIP types in the boundary)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "hfe.h"\nint main(void) {\n  hfe_material m;\n'
+                   '  m.kind = HFE_DAMAGE_TENSILE;\n  return m.kind == HFE_DAMAGE_TENSILE ? 0 : 1;\n}\n')
+    out = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc,
+                          str(src), "-o", str(tmp_path / "use_header")],
+                         capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert subprocess.run([str(tmp_path / "use_header")]).returncode == 0
