@@ -151,7 +151,11 @@ hfe_status hfe_destroy(hfe_ctx* ctx);
  * HFE_MAX_PHASES. Resets the state (u = 0, E = 0, history = kappa0). */
 hfe_status hfe_set_microstructure(hfe_ctx* ctx, const uint8_t* phase, int n_phases);
 
-/* Material of one phase (call once per phase before the first load step). */
+/* Material of one phase (Sec. 3, Appendix A; call once per phase before the
+ * first load step). The struct is copied. Errors: HFE_EINVAL for a null
+ * material, a phase outside [0, n_phases), an unknown kind, E <= 0, nu outside
+ * (-1, 1/2), or a damage kind without 0 < kappa0 < kappaf; HFE_ESTATE before
+ * the microstructure is set or once loading has started. */
 hfe_status hfe_set_material(hfe_ctx* ctx, int phase, const hfe_material* mat);
 
 /* Eigenstrain of a phase (host, 3x3 row-major; its symmetric part is used, in
