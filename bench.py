@@ -31,7 +31,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "c1_3d64"
 # The metric is the time per load step at a 1e-8 residual, so every timed
 # increment runs until it converges. The library's default of 50 Newton
 # iterations (the parity tests' setting) stops the damage-onset increments of
@@ -587,7 +586,8 @@ def main():
                     help="short run for hardware-counter passes: after one load step, a few "
                          "projected-Hessian applications and a calibration copy of known size")
     ap.add_argument("--grid", type=int, default=64,
-                    help="cell size of the --probe run (the 64^3 workload recipe at N^3)")
+                    help="cell size N of the workload recipe at N^3 (the main line and --probe; "
+                         "the default 64 is the benchmark configuration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc runs of --probe "
                          "(FETCH_SIZE, then WRITE_SIZE; csv output)")
@@ -618,7 +618,7 @@ def main():
     if args.probe:
         probe(args.grid, args.probe_tuning, args.probe_set_tuning)
         return
-    w = workload(WORKLOAD)
+    w = workload("c1_3d%d" % args.grid)
     W, K = args.warmup, args.steps
     if W + K > len(w.load_path):
         K = len(w.load_path) - W
@@ -765,8 +765,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D 64^3 Q1 inclusion cell (vf 0.25, seed 1), damage matrix, "
-                               "uniaxial 30 x 2e-4 load path, FP64 TR+Steihaug tol 1e-8",
+        "config": {"workload": "3D %d^3 Q1 inclusion cell (vf 0.25, seed %d), damage matrix, "
+                               "uniaxial 30 x 2e-4 load path, FP64 TR+Steihaug tol 1e-8"
+                               % (args.grid, 3 if args.grid == 128 else 1),
                    "load_steps_timed": [W, W + K - 1], "i_nr_max": NEWTON_CAP,
                    "matvecs": matvecs,
                    "newton_iters": newton, "cg_iters": cg, "converged_steps": converged,
