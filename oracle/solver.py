@@ -13,9 +13,18 @@ Powell and Dai, eq. 1): z is the iterate, r = A z + g the model gradient
     of the two roots the one with the smaller model value (ties: tau > 0);
   * boundary (||z + alpha d|| >= R): return z + tau d with the root tau >= 0;
   * convergence: ||r_{j+1}|| <= eta_cg ||r_0||;
-  * reset: if |r_{j+1}.r_j| > 0.2 r_{j+1}.r_{j+1}, recompute the residual
-    r_{j+1} = A z_{j+1} + g and take beta = 0 (a steepest-descent restart);
-  * after j_max steps the last iterate is returned (an interior step).
+  * reset: if |r_{j+1}.r_j| > c r_{j+1}.r_{j+1} (Powell's constant c = 0.2
+    in the paper, a knob here), recompute the residual r_{j+1} = A z_{j+1} + g
+    and take beta = 0 (a steepest-descent restart). Any c < 0 restarts after
+    every step, which turns the method into steepest descent with exact line
+    search; c = inf never restarts (plain CG);
+  * after j_max steps the last iterate is returned (an interior step);
+  * optional stall exit (not in the paper; ``stall`` > 0 iterations): the
+    residual norm is followed against a reference that starts at ||r_0||
+    and is replaced by every residual at or below half of it; once ``stall``
+    iterations pass without such a replacement the current iterate is
+    returned as an interior step (flag STALL). Tested after convergence and
+    before the reset.
 
 Trust region (Algorithm 2; eq. modeling_trust, eq. incr_energy_func, eq.
 rho_bar): Delta m = sigma:p + p:B:p/2 and DeltaW = (sigma + sigma_trial):p/2
@@ -46,9 +55,9 @@ import numpy as np
 from . import fe, material
 from .projection import Projector
 
-INTERIOR, BOUNDARY, NEGCURV, MAXITER = 1, 2, 3, 4
+INTERIOR, BOUNDARY, NEGCURV, MAXITER, STALL = 1, 2, 3, 4, 5
 FLAG_NAMES = {INTERIOR: "interior", BOUNDARY: "boundary", NEGCURV: "negcurv",
-              MAXITER: "maxiter"}
+              MAXITER: "maxiter", STALL: "stall"}
 
 
 def inner(X, Y):
@@ -67,8 +76,11 @@ def _roots(zz, zd, dd, R):
     return min(t1, t2), max(t1, t2)
 
 
-def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
-    """Truncated CG on min g.p + p.Ap/2, ||p|| <= R. Returns (p, flag, info)."""
+def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None, restart=0.2, stall=0):
+    """Truncated CG on min g.p + p.Ap/2, ||p|| <= R. Returns (p, flag, info).
+
+    ``restart`` is the constant of Powell's reset test (eq. 1); ``stall`` the
+    window of the optional stall exit (0: off)."""
     info = {"iters": 0, "restarts": 0, "matvecs": 0}
     z = np.zeros_like(g)
     r = g.copy()
@@ -77,6 +89,7 @@ def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
     if rr0 == 0.0:
         return z, INTERIOR, info
     d = -r
+    rr_ref, j_ref = rr0, 0
     for j in range(j_max):
         Ad = apply_A(d)
         info["matvecs"] += 1
@@ -106,7 +119,11 @@ def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
             log.append(("cg", j, kappa, math.sqrt(rr_new / rr0)))
         if math.sqrt(rr_new) <= eta_cg * math.sqrt(rr0):
             return z_new, INTERIOR, info
-        if abs(dot(r_new, r)) > 0.2 * rr_new:
+        if rr_new <= 0.25 * rr_ref:
+            rr_ref, j_ref = rr_new, j + 1
+        elif stall > 0 and j + 1 - j_ref >= stall:
+            return z_new, STALL, info
+        if abs(dot(r_new, r)) > restart * rr_new:
             r_new = apply_A(z_new) + g
             info["matvecs"] += 1
             rr_new = dot(r_new, r_new)
@@ -120,7 +137,7 @@ def steihaug(apply_A, g, R, eta_cg, j_max, dot=inner, log=None):
 
 
 DEFAULTS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "eta_cg": 1e-6, "eta_up": 0.15,
-            "i_nr_max": 50, "j_cg_max": 2000}
+            "i_nr_max": 50, "j_cg_max": 2000, "restart": 0.2, "cg_stall": 0}
 
 
 def default_radii(n_qp, dE):
@@ -236,8 +253,9 @@ class CellSolver:
         if params:
             p.update({k: v for k, v in params.items() if v is not None})
         rep = {"newton_iters": 0, "rejected": 0, "cg_iters": 0, "restarts": 0,
-               "boundary_exits": 0, "negcurv_exits": 0, "matvecs": 0,
+               "boundary_exits": 0, "negcurv_exits": 0, "matvecs": 0, "stall_exits": 0,
                "converged": False, "rho": [], "flags": [], "cg_per_newton": [],
+               "restarts_per_newton": [],
                "r_nr": None}
         if self.r_eq <= p["eta_eq"]:
             rep["converged"] = True
@@ -247,16 +265,20 @@ class CellSolver:
         for it in range(p["i_nr_max"]):
             rep["newton_iters"] = it + 1
             step, flag, info = steihaug(self.apply_hessian, self.g, self.R,
-                                        p["eta_cg"], p["j_cg_max"], log=log)
+                                        p["eta_cg"], p["j_cg_max"], log=log,
+                                        restart=p["restart"], stall=p["cg_stall"])
             rep["cg_iters"] += info["iters"]
             rep["restarts"] += info["restarts"]
             rep["matvecs"] += info["matvecs"]
             rep["cg_per_newton"].append(info["iters"])
+            rep["restarts_per_newton"].append(info["restarts"])
             rep["flags"].append(flag)
             if flag == BOUNDARY:
                 rep["boundary_exits"] += 1
             elif flag == NEGCURV:
                 rep["negcurv_exits"] += 1
+            elif flag == STALL:
+                rep["stall_exits"] += 1
             sp = inner(self.sigma, step)
             pBp = inner(step, material.apply_tangent(self.mat, self.state, step))
             st_t = self._evaluate(self.H + step)

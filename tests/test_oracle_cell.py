@@ -252,8 +252,8 @@ def test_rounding_sensitivity_of_the_method():
     orig = S.steihaug
 
     def run(dot):
-        def st(apply_A, g, R, eta, jmax, dot_=None, log=None):
-            return orig(apply_A, g, R, eta, jmax, dot=dot, log=log)
+        def st(apply_A, g, R, eta, jmax, dot_=None, log=None, **kw):
+            return orig(apply_A, g, R, eta, jmax, dot=dot, log=log, **kw)
         S.steihaug = st
         try:
             o = CellSolver(w.phase, w.materials, w.element)

@@ -64,6 +64,79 @@ def test_steihaug_negative_curvature_exit():
     assert g @ p + 0.5 * p @ A @ p < 0.0
 
 
+def test_steihaug_restart_after_every_step_is_steepest_descent():
+    """Powell's reset (eq. 1) with a negative constant fires after every step
+    (the measure |r_{j+1}.r_j| / r_{j+1}.r_{j+1} is never negative): the
+    residual is recomputed as A z + g and the direction restarts along it
+    (beta = 0). The iterates are then those of steepest descent with exact
+    line search, written out here from its textbook definition:
+        r_j = A z_j + g,  z_{j+1} = z_j - (r_j.r_j / r_j.A r_j) r_j."""
+    rng = np.random.default_rng(4)
+    n, k = 24, 17
+    A = _spd(n, rng, cond=30.0)
+    g = rng.normal(size=n)
+    p, flag, info = solver.steihaug(lambda v: A @ v, g, 1e9, 1e-14, k, restart=-1.0)
+    z = np.zeros(n)
+    for _ in range(k):
+        r = A @ z + g
+        z = z - (r @ r) / (r @ (A @ r)) * r
+    assert flag == solver.MAXITER
+    assert info["restarts"] == k and info["matvecs"] == 2 * k
+    assert np.linalg.norm(p - z) <= 1e-12 * np.linalg.norm(z)
+    # and it is not CG: plain CG (no reset) is much further along after k steps
+    q, _, info_cg = solver.steihaug(lambda v: A @ v, g, 1e9, 1e-14, k, restart=np.inf)
+    x = np.linalg.solve(A, -g)
+    assert info_cg["restarts"] == 0
+    assert np.linalg.norm(q - x) < 1e-2 * np.linalg.norm(p - x)
+
+
+def test_steihaug_restart_keeps_the_model_decreasing_and_stops_on_the_sphere():
+    """With resets at every step the trust-region exits still land on
+    ||p|| = R, and a reset iterate keeps Algorithm 1's residual equal to the
+    true model gradient A z + g (checked through the returned interior step:
+    its model gradient norm meets the stopping test)."""
+    rng = np.random.default_rng(5)
+    n = 16
+    A = _spd(n, rng, cond=8.0)
+    g = rng.normal(size=n)
+    x = np.linalg.solve(A, -g)
+    R = 0.97 * np.linalg.norm(x)
+    p, flag, info = solver.steihaug(lambda v: A @ v, g, R, 1e-10, 400, restart=-1.0)
+    assert flag == solver.BOUNDARY and info["restarts"] >= 1
+    assert abs(np.linalg.norm(p) - R) <= 1e-12 * R
+    assert g @ p + 0.5 * p @ A @ p < 0.0
+    p, flag, info = solver.steihaug(lambda v: A @ v, g, 1e9, 1e-8, 4000, restart=-1.0)
+    assert flag == solver.INTERIOR and info["restarts"] >= 1
+    assert np.linalg.norm(A @ p + g) <= 1.0001e-8 * np.linalg.norm(g)
+
+
+def test_steihaug_stall_exit():
+    """The optional stall exit (not in the paper) on a singular SPD system
+    whose right-hand side has a component in the null space: the model
+    gradient A z + g cannot fall below that component, so the CG stalls. The
+    exit returns the CG iterate of the iteration at which it fires (the same
+    iterate plain CG reaches after as many iterations). On a well-conditioned
+    system it never fires."""
+    rng = np.random.default_rng(6)
+    n = 20
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.geomspace(1.0, 40.0, n)
+    ev[0] = 0.0
+    A = Q @ np.diag(ev) @ Q.T
+    g = Q @ np.concatenate([[1e-3], rng.normal(size=n - 1)])
+    p, flag, info = solver.steihaug(lambda v: A @ v, g, np.inf, 1e-12, 500, stall=6)
+    assert flag == solver.STALL
+    assert 6 <= info["iters"] < 500
+    q, flag_q, info_q = solver.steihaug(lambda v: A @ v, g, np.inf, 1e-12, info["iters"])
+    assert flag_q == solver.MAXITER and info_q["iters"] == info["iters"]
+    np.testing.assert_array_equal(p, q)
+    # a well-conditioned SPD system halves its residual well within the window
+    B = _spd(20, rng, cond=10.0)
+    p, flag, info = solver.steihaug(lambda v: B @ v, g, 1e9, 1e-12, 500, stall=6)
+    assert flag == solver.INTERIOR
+    np.testing.assert_allclose(p, np.linalg.solve(B, -g), rtol=1e-9, atol=1e-12)
+
+
 def test_steihaug_zero_gradient_returns_zero():
     p, flag, info = solver.steihaug(lambda v: v, np.zeros(5), 1.0, 1e-6, 10)
     assert flag == solver.INTERIOR and np.all(p == 0) and info["iters"] == 0
