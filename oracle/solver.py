@@ -36,6 +36,17 @@ r_eq = ||G sigma|| / ||sigma||; r_NR = ||p|| / ||H|| as printed. Convergence
 needs an interior step and (r_eq <= eta_eq or r_NR <= eta_NR). The history
 (kappa_hist) is committed only when a load step converges.
 
+Mean-stress control (Sec. 3.3 imposes a zero mean stress with a modified
+projector from cited work; this is the reading used here): chosen components
+of the macroscopic strain are unknowns whose mean stress must vanish. The
+projector becomes G_M = G + M, where M maps a field to its mean in the free
+components (for a free shear pair (i, j) the mean of (X_ij + X_ji)/2 in both
+entries), an orthogonal projector onto uniform fields that G annihilates, so
+G_M is again an orthogonal projector. The model gradient is G_M sigma, the
+projected Hessian G_M B, and the steps p = D du + uniform free part; an
+accepted step moves E by the mean of p. At convergence G sigma = 0 and the
+mean stress vanishes in the free components.
+
 Eigenstrain (Algorithm 2, the eps_eval lines): a phase's eigenstrain is added
 to the strain before every evaluation of the law, the trial evaluation
 included; r_NR keeps the strain without it. A load by eigenstrain alone (zero
@@ -205,6 +216,29 @@ class CellSolver:
         self.g = None
         self.r_eq = None
         self.n_qp = int(np.prod(self.grid)) * self.nq
+        self.free = np.zeros((self.dim, self.dim), dtype=bool)
+
+    def set_mean_stress_control(self, free):
+        """Free macroscopic strain components (a symmetric boolean 3x3, the
+        d x d block used) whose mean stress is held at zero from the next load
+        step on; all False restores full strain control."""
+        f = np.asarray(free, dtype=bool).reshape(3, 3)[: self.dim, : self.dim]
+        self.free = f | f.T
+
+    def _mean_free(self, X):
+        """M X: the uniform field of X's mean in the free components (a free
+        shear pair gets the mean of (X_ij + X_ji) / 2 in both entries)."""
+        m = X.mean(axis=tuple(range(self.dim + 1)))
+        m = 0.5 * (m + m.T)
+        out = np.zeros_like(X)
+        out[...] = np.where(self.free, m, 0.0)
+        return out
+
+    def project(self, X):
+        """G_M X = G X + M X (G alone without stress control)."""
+        if not self.free.any():
+            return self.G(X)
+        return self.G(X) + self._mean_free(X)
 
     def set_eigenstrain(self, phase, eig):
         """Eigenstrain of a phase from now on (Algorithm 2 adds it to the
@@ -219,13 +253,14 @@ class CellSolver:
     def _set_state(self, st):
         self.state = st
         self.sigma = st["sigma"]
-        self.g = self.G(self.sigma)
+        self.g = self.project(self.sigma)
         ns = math.sqrt(inner(self.sigma, self.sigma))
         self.r_eq = math.sqrt(inner(self.g, self.g)) / ns if ns > 0.0 else 0.0
 
     def apply_hessian(self, X):
-        """Projected Hessian G : B : X (eq. project_stress_linear)."""
-        return self.G(material.apply_tangent(self.mat, self.state, X))
+        """Projected Hessian G : B : X (eq. project_stress_linear); G_M : B : X
+        under mean-stress control."""
+        return self.project(material.apply_tangent(self.mat, self.state, X))
 
     # -- Algorithm 2 --------------------------------------------------------
     def apply_load_step(self, dE):
@@ -291,6 +326,10 @@ class CellSolver:
             self.R = tr_update(rho, self.R, self.Rmax, on_boundary)
             if rho > p["eta_up"]:
                 self.H = self.H + step
+                if self.free.any():
+                    # the uniform part of the step moves the free macroscopic strain
+                    dEf = self._mean_free(step).reshape(-1, self.dim, self.dim)[0]
+                    self.E[: self.dim, : self.dim] += dEf
                 r_nr = math.sqrt(inner(step, step)) / math.sqrt(inner(self.H, self.H))
                 self._set_state(st_t)
                 rep["r_nr"] = r_nr
