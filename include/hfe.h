@@ -68,11 +68,15 @@ enum {
   HFE_FIELD_GRAD = 1,    /* full gradient H = E + D u at points, [N][nq][dim][dim] */
   HFE_FIELD_STRESS = 2,  /* stress at points, [N][nq][dim][dim]                  */
   HFE_FIELD_DAMAGE = 3,  /* committed damage d(kappa_hist), [N][nq]              */
-  HFE_FIELD_KAPPA = 4    /* committed history kappa_hist, [N][nq]                */
+  HFE_FIELD_KAPPA = 4,   /* committed history kappa_hist, [N][nq]                */
+  HFE_FIELD_SOFTENING = 5 /* 1 where the tangent of the evaluated state carries the
+                           * softening term (loading with 0 < d < 1), else 0, [N][nq] */
 };
 
-/* Exit flags of the truncated CG (Algorithm 1), as logged per Newton step. */
-enum { HFE_CG_INTERIOR = 1, HFE_CG_BOUNDARY = 2, HFE_CG_NEGCURV = 3, HFE_CG_MAXITER = 4 };
+/* Exit flags of the truncated CG (Algorithm 1), as logged per Newton step.
+ * HFE_CG_STALL: the optional stall exit (hfe_solver_params.cg_stall). */
+enum { HFE_CG_INTERIOR = 1, HFE_CG_BOUNDARY = 2, HFE_CG_NEGCURV = 3, HFE_CG_MAXITER = 4,
+       HFE_CG_STALL = 5 };
 
 typedef struct {
   int dim;       /* 2 or 3 */
@@ -120,12 +124,30 @@ typedef struct {
                     * the energy terms of the ratio rho_bar, the history and
                     * the state stay FP64, so each Newton step starts from an
                     * FP64 residual and the tolerances keep their meaning.   */
+  double restart;  /* constant c of the reset test of Algorithm 1 (eq. 1):
+                    * after a CG step, if |<r_{j+1}, r_j>| > c <r_{j+1}, r_{j+1}>
+                    * the residual is recomputed as A z_{j+1} + g and the
+                    * next direction is -r_{j+1} (beta = 0). The paper's value
+                    * is 0.2 (the default). Any c < 0 restarts after every
+                    * step (steepest descent with exact line search); +inf
+                    * never restarts. HFE_EINVAL if NaN. */
+  int cg_stall;    /* stall exit of the CG, an addition to Algorithm 1 (0, the
+                    * default, switches it off): the CG returns its current
+                    * iterate as an interior step (flag HFE_CG_STALL) once
+                    * cg_stall iterations have passed without the residual
+                    * norm falling to half of its last reference value (the
+                    * reference starts at ||r_0|| and is replaced by every
+                    * residual at or below half of it). At damaged states the
+                    * residual of Algorithm 1 can plateau far above eta_cg
+                    * for thousands of iterations (in FP64 and FP32 alike);
+                    * this ends such solves. HFE_EINVAL if negative. */
 } hfe_solver_params;
 
 typedef struct {
   int status;          /* HFE_CONVERGED or HFE_NOT_CONVERGED                       */
   int newton_iters, rejected, cg_iters, restarts, boundary_exits, negcurv_exits;
   int matvecs;         /* projected-Hessian applications (CG + restarts)          */
+  int stall_exits;     /* Newton steps whose CG ended at the stall exit           */
   double r_eq, r_nr, R, rho_last;
   double time_ms;      /* wall time of the call                                    */
 } hfe_solve_report;
@@ -171,14 +193,18 @@ hfe_status hfe_set_eigenstrain(hfe_ctx* ctx, int phase, const double eig[9]);
 /* Algorithm 2, start of a load increment: E <- E + dE (dE a host 3x3,
  * symmetric; in 2D only the in-plane block is used), keep the fluctuation of
  * the previous step as initial guess, evaluate sigma and B with the history
- * frozen, the right-hand side -G sigma and its relative norm. */
+ * frozen, the right-hand side -G sigma and its relative norm. Errors:
+ * HFE_EINVAL for a NULL or non-finite dE; HFE_ESTATE before the
+ * microstructure and every material are set; HFE_ENUMERIC if the stress or
+ * the residual at the new E is not finite (E and the evaluated state are
+ * then those before the call). */
 hfe_status hfe_apply_load_step(hfe_ctx* ctx, const double dE[9]);
 
 /* Algorithm 2 (Newton / trust-region loop with Algorithm 1 inside) for the
  * current increment. Commits the damage history iff it converges. `params`
  * may be NULL (defaults: eta_eq = eta_nr = 1e-8, eta_cg = 1e-6, eta_up = 0.15,
- * i_nr_max = 50, j_cg_max = 2000, radii from the first increment). `out`
- * may be NULL. */
+ * i_nr_max = 50, j_cg_max = 2000, radii from the first increment, restart
+ * = 0.2, cg_stall = 0). `out` may be NULL. */
 hfe_status hfe_solve_increment(hfe_ctx* ctx, const hfe_solver_params* params,
                                hfe_solve_report* out);
 
@@ -252,7 +278,8 @@ hfe_status hfe_set_state(hfe_ctx* ctx, const double* u, const double* kappa_hist
 hfe_status hfe_get_cg_trace(const hfe_ctx* ctx, double* out, int max, int* count);
 
 /* Replace the nodal fluctuation u (host, [dim][N]) and re-evaluate the state
- * at the current E without committing (operator tests and restarts). */
+ * at the current E without committing (operator tests and restarts).
+ * HFE_EINVAL (nothing changed) if an entry is not finite. */
 hfe_status hfe_set_displacement(hfe_ctx* ctx, const double* host_u);
 
 /* Projected Hessian in displacement coordinates at the current state
@@ -301,8 +328,12 @@ typedef struct {
   int plane_threads;    /* threads of an x-y plane FFT block (64..1024, multiple of 64) */
   int pencil_cols;      /* z columns per pencil block (1..64)                       */
   int pencil_threads;   /* threads of a pencil block (64..256, multiple of 64)      */
-  int brick_shape;      /* Q1 Hessian brick: 0 = 8x8x4, 1 = 8x8x8, 2 = 16x8x4, 3 = 16x4x4,
-                           4 = 8x4x4 */
+  int brick_shape;      /* Q1 Hessian launch shape. Bricks of nodes (any grid): 0 = 8x8x4,
+                           1 = 8x8x8, 2 = 16x8x4, 3 = 16x4x4, 4 = 8x4x4. Columns of
+                           CX x CY nodes marching over BZ node layers (nx a multiple
+                           of CX, ny of CY): 5 = 16x16x16, 6 = 16x16x8, 7 = 16x8x16,
+                           8 = 16x8x8, 9 = 8x8x8, 10 = 8x8x16, 11 = 16x8x32,
+                           12 = 16x16x32. Every shape gives the same K d bits. */
   int plane_threads32, pencil_cols32, pencil_threads32, brick_shape32;
 } hfe_tuning;
 
@@ -310,7 +341,8 @@ typedef struct {
 hfe_status hfe_get_tuning(const hfe_ctx* ctx, hfe_tuning* out);
 /* Set launch shapes; HFE_EINVAL (context unchanged) if one does not fit the
  * grid: a plane block must stage (nx/2+1) ny values at 15 per thread, a
- * pencil block pencil_cols * nz values at 15 per thread in 64 KiB of LDS. */
+ * pencil block pencil_cols * nz values at 15 per thread in 64 KiB of LDS, a
+ * Hessian column must divide nx and ny. */
 hfe_status hfe_set_tuning(hfe_ctx* ctx, const hfe_tuning* in);
 /* Autotuner: times every valid plane / pencil shape on this grid's Green's
  * operator (FP64 and FP32) and, once a load step has been applied, the brick

@@ -11,7 +11,7 @@
 namespace hfe {
 
 enum { CG_RUN = 0, CG_INTERIOR = 1, CG_BOUNDARY = 2, CG_NEGCURV = 3, CG_MAXITER = 4,
-       CG_NUMERIC = 5 };
+       CG_STALL = 5, CG_NUMERIC = 6 };
 
 struct CgState {
   // scalars of the recurrences (strain-space inner products)
@@ -20,6 +20,10 @@ struct CgState {
   double dd, kap, rd;       // ||d||^2, <d, G B d>, <r, d>
   double alpha, beta, tau;
   double R, eta_cg;
+  double restart_c;         // constant of Powell's reset test (eq. 1)
+  double rr_ref;            // stall exit: reference residual (squared)
+  int j_ref;                // and the iteration that set it
+  int stall;                // stall window in iterations (0: off)
   int iters;                // Hessian applications of this solve (CG iterations)
   int jmax;
   int done;                 // 1: stop; the remaining kernels of the batch are no-ops
@@ -102,7 +106,16 @@ __device__ __forceinline__ void cg_decide_residual(CgState* s, double* trace, do
     s->done = 1;
     return;
   }
-  if (fabs(pw) > 0.2 * rr_new) {
+  // stall exit: the residual norm has not halved within `stall` iterations
+  if (rr_new <= 0.25 * s->rr_ref) {
+    s->rr_ref = rr_new;
+    s->j_ref = s->iters;
+  } else if (s->stall > 0 && s->iters - s->j_ref >= s->stall) {
+    s->flag = CG_STALL;
+    s->done = 1;
+    return;
+  }
+  if (fabs(pw) > s->restart_c * rr_new) {
     s->restart = 1;
     s->done = 1;
     return;

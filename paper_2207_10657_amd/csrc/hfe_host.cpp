@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -39,7 +40,6 @@ constexpr size_t kAlign = 256;
 constexpr int kTraceCap = 1 << 16;    // CG trace entries kept per solve
 constexpr int kCgBatch = 8;           // the longest batch of CG iterations between host polls
 constexpr int kCgSlots = 4;           // captured batches of 1, 2, 4, 8 iterations
-constexpr int kBrickShapes = 5;       // Q1 Hessian brick shapes (see launch_hessian_brick)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -50,6 +50,7 @@ struct Layout {
   size_t sn;                                          // per point [nq][6][N] (Q1)
   size_t phase;                                       // N bytes
   size_t soft;                                        // N bytes: element softens
+  size_t emask;                                       // N uint16: Hessian mask word
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
   size_t partials2;                                   // second row buffer (direction sums)
@@ -121,6 +122,7 @@ Layout make_layout(const Grid& g) {
   L.sn = take(g.element == HFE_Q1 ? 6 * pts : 0);
   L.phase = take((size_t)g.N);
   L.soft = take((size_t)g.N);
+  L.emask = take((size_t)g.N * sizeof(uint16_t));
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
@@ -187,6 +189,7 @@ struct hfe_ctx {
   bool tens = false;         // some phase follows the tensile-masking law
   uint8_t* phase;
   uint8_t* soft;             // per element: bit q set iff c' != 0 at point q (Q1)
+  uint16_t* emask;           // per element: soft mask, phase, intact bit (Q1 Hessian)
   double n_soft = 0.0;       // softening points of the state (Q1)
   double prof_soft_sum = 0.0;  // profiling: n_soft summed over the Hessian launches
   long long prof_soft_n = 0;
@@ -369,6 +372,8 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.f = nullptr;
   A.soft = c->soft;
   A.soft_out = nullptr;
+  A.emask = c->emask;
+  A.emask_out = nullptr;
   A.sw = c->sw;
   A.sw_out = nullptr;
   A.tens = c->tens;
@@ -449,6 +454,7 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   A.a_out = c->a;
   A.cp_out = c->cp;
   A.soft_out = c->soft;
+  A.emask_out = c->emask;
   A.sw_out = c->sw;
   A.sn_out = c->sn;
   A.f = c->g0;
@@ -516,8 +522,7 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.g = c->g;
   H.mat = c->mat;
   H.E = c->Edev;
-  H.phase = c->phase;
-  H.soft = c->soft;
+  H.emask = c->emask;
   H.a = c->a32;
   H.sw = c->sw;
   H.tens = c->tens;
@@ -692,6 +697,11 @@ hfe_status cg_iteration(hfe_ctx* c) {
   return direction(c);
 }
 
+// Graph capture and instantiation are serialised across the process: the
+// contexts of a batch solve on separate host threads, and each captures its
+// CG graphs the first time it needs them. Replays stay concurrent.
+std::mutex g_capture_mutex;
+
 // Enqueue `k` CG iterations: a replay of a captured graph (captured on a
 // private stream, launched on the context's stream), or plain launches.
 hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
@@ -718,6 +728,7 @@ hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
     G.ev.clear();
   }
   if (!G.exec) {
+    std::lock_guard<std::mutex> lock(g_capture_mutex);
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const hipStream_t saved = c->stream;
     c->stream = c->cap_stream;
@@ -749,8 +760,8 @@ hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
 }
 
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
-hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, int* flag,
-                    CgInfo* info) {
+hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, double restart_c,
+                    int stall, int* flag, CgInfo* info) {
   const long long n = ndof(c);
   const size_t bytes = (size_t)n * sizeof(double);
   const bool mixed = prec == HFE_MIXED;
@@ -777,6 +788,10 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, in
   init.rr = init.rr0 = init.rr_new = c->rr0;
   init.R = R;
   init.eta_cg = eta_cg;
+  init.restart_c = restart_c;
+  init.rr_ref = c->rr0;
+  init.j_ref = 0;
+  init.stall = stall;
   init.jmax = j_max;
   init.flag = hfe::CG_RUN;
   init.trace_cap = kTraceCap;
@@ -942,7 +957,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->use_graphs = std::getenv("HFE_NO_GRAPHS") == nullptr;
   if (const char* bs = std::getenv("HFE_BRICK_SHAPE")) {
     const int v = std::atoi(bs);
-    if (v >= 0 && v < kBrickShapes) c->brick_shape = c->brick_shape32 = v;
+    if (hfe::hessian_shape_valid(g, v)) c->brick_shape = c->brick_shape32 = v;
   }
   auto D = [&](size_t off) { return (double*)(c->ws + off); };
   c->u = D(L.u); c->z = D(L.z); c->d = D(L.d); c->gv = D(L.g); c->y = D(L.y);
@@ -958,6 +973,7 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->spec32 = (float2*)(c->ws + L.spec32);
   c->phase = (uint8_t*)(c->ws + L.phase);
   c->soft = (uint8_t*)(c->ws + L.soft);
+  c->emask = (uint16_t*)(c->ws + L.emask);
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
   c->partials2 = D(L.partials2);
@@ -1005,8 +1021,10 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->tabs32.plane_threads = c->tabs.plane_threads;
   c->tabs32.pencil_cols = c->tabs.pencil_cols;
   c->tabs32.pencil_threads = c->tabs.pencil_threads;
-  hipError_t e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double),
-                               hipHostMallocMapped | hipHostMallocCoherent);
+  hipError_t e = hfe::fft_prepare(g);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dscal, c->hscal, 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hcg, sizeof(hfe::CgState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
@@ -1137,9 +1155,17 @@ hfe_status hfe_apply_load_step(hfe_ctx* c, const double dE[9]) {
     c->R0_default = 10.0 * s;
     c->Rmax_default = 1000.0 * s;
   }
+  const bool had_state = c->have_state;
   st = evaluate_state(c);
   if (st) {
+    // back to the previous increment: E and, if there was one, the evaluated
+    // state (stress, tangent, residual) at it
+    const std::string why = c->err;
     for (int k = 0; k < 9; ++k) c->E[k] = Eold[k];
+    c->have_state = false;
+    if (had_state && evaluate_state(c) != HFE_OK)
+      return fail(c, st, why + "; the previous state could not be re-evaluated");
+    c->err = why;
     return st;
   }
   c->log.clear();
@@ -1153,7 +1179,10 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
   hfe_solver_params p;
   p.eta_eq = 1e-8; p.eta_nr = 1e-8; p.eta_cg = 1e-6; p.eta_up = 0.15;
   p.R0 = 0.0; p.Rmax = 0.0; p.i_nr_max = 50; p.j_cg_max = 2000; p.precision = HFE_FP64;
+  p.restart = 0.2; p.cg_stall = 0;
   if (prm) p = *prm;
+  if (std::isnan(p.restart)) return fail(c, HFE_EINVAL, "restart constant is NaN");
+  if (p.cg_stall < 0) return fail(c, HFE_EINVAL, "cg_stall must be >= 0");
   if (p.precision != HFE_FP64 && p.precision != HFE_MIXED)
     return fail(c, HFE_EINVAL, "precision must be HFE_FP64 or HFE_MIXED");
   if (p.precision == HFE_MIXED && c->g.dim != 3)
@@ -1180,13 +1209,15 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       rep.newton_iters = it + 1;
       int flag = 0;
       CgInfo info;
-      st = steihaug(c, c->R, p.eta_cg, p.j_cg_max, p.precision, &flag, &info);
+      st = steihaug(c, c->R, p.eta_cg, p.j_cg_max, p.precision, p.restart, p.cg_stall, &flag,
+                    &info);
       if (st) return st;
       rep.cg_iters += info.iters;
       rep.restarts += info.restarts;
       rep.matvecs += info.matvecs;
       if (flag == HFE_CG_BOUNDARY) rep.boundary_exits++;
       if (flag == HFE_CG_NEGCURV) rep.negcurv_exits++;
+      if (flag == HFE_CG_STALL) rep.stall_exits++;
       // trial evaluation at u + z (Algorithm 2: model change, trial stress, FAIEF)
       hfe::ElemArgs A = elem_args(c);
       A.v = c->z;
@@ -1509,10 +1540,31 @@ hfe_status hfe_get_field(const hfe_ctx* cc, int which, double* host_out, size_t 
   switch (which) {
     case HFE_FIELD_U: need = (size_t)g.dim * g.N; break;
     case HFE_FIELD_GRAD: case HFE_FIELD_STRESS: need = (size_t)g.N * g.nq * g.dim * g.dim; break;
-    case HFE_FIELD_DAMAGE: case HFE_FIELD_KAPPA: need = (size_t)g.N * g.nq; break;
+    case HFE_FIELD_DAMAGE: case HFE_FIELD_KAPPA: case HFE_FIELD_SOFTENING:
+      need = (size_t)g.N * g.nq;
+      break;
     default: return fail(c, HFE_EINVAL, "unknown field");
   }
   if (n < need) return fail(c, HFE_EINVAL, "output buffer too small");
+  if (which == HFE_FIELD_SOFTENING) {
+    if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+    if (g.element == HFE_Q1) {
+      // the element masks: bit q set iff c' != 0 at point q
+      std::vector<uint8_t> m((size_t)g.N);
+      HIPCHK(c, hipMemcpyAsync(m.data(), c->soft, (size_t)g.N, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (long long e = 0; e < g.N; ++e)
+        for (int q = 0; q < g.nq; ++q) host_out[e * g.nq + q] = (m[e] >> q) & 1 ? 1.0 : 0.0;
+    } else {
+      std::vector<double> cp((size_t)g.nq * g.N);
+      HIPCHK(c, hipMemcpyAsync(cp.data(), c->cp, cp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (long long e = 0; e < g.N; ++e)
+        for (int q = 0; q < g.nq; ++q) host_out[e * g.nq + q] = cp[(size_t)q * g.N + e] != 0.0 ? 1.0 : 0.0;
+    }
+    return HFE_OK;
+  }
   if (which == HFE_FIELD_U) {
     HIPCHK(c, hipMemcpyAsync(host_out, c->u, need * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1610,6 +1662,8 @@ hfe_status hfe_set_state(hfe_ctx* c, const double* u, const double* kappa_hist, 
 hfe_status hfe_set_displacement(hfe_ctx* c, const double* host_u) {
   if (!c || !host_u) return HFE_EINVAL;
   if (!materials_ready(c)) return fail(c, HFE_ESTATE, "microstructure and every material must be set");
+  for (long long i = 0; i < ndof(c); ++i)
+    if (!std::isfinite(host_u[i])) return fail(c, HFE_EINVAL, "non-finite displacement");
   hfe_status st = ensure_history(c);
   if (st) return st;
   HIPCHK(c, hipMemcpyAsync(c->u, host_u, (size_t)ndof(c) * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1670,9 +1724,11 @@ hfe_status hfe_set_tuning(hfe_ctx* c, const hfe_tuning* in) {
   if (!hfe::fft_launch_valid(c->g, in->plane_threads, in->pencil_cols, in->pencil_threads, 8) ||
       !hfe::fft_launch_valid(c->g, in->plane_threads32, in->pencil_cols32, in->pencil_threads32, 4))
     return fail(c, HFE_EINVAL, "an FFT launch shape does not fit this grid");
-  if (in->brick_shape < 0 || in->brick_shape >= kBrickShapes || in->brick_shape32 < 0 ||
-      in->brick_shape32 >= kBrickShapes)
-    return fail(c, HFE_EINVAL, "brick_shape must be 0..4");
+  if ((c->g.dim == 3 && (!hfe::hessian_shape_valid(c->g, in->brick_shape) ||
+                         !hfe::hessian_shape_valid(c->g, in->brick_shape32))) ||
+      (c->g.dim == 2 && (in->brick_shape < 0 || in->brick_shape >= hfe::kHessianShapes ||
+                         in->brick_shape32 < 0 || in->brick_shape32 >= hfe::kHessianShapes)))
+    return fail(c, HFE_EINVAL, "brick_shape is not a Hessian shape of this grid");
   hfe_status st = sync(c);
   if (st) return st;
   destroy_graphs(c);
@@ -1774,7 +1830,8 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
     if (st == HFE_OK) {
       double best = INFINITY, best32 = INFINITY;
       int bs = 0, bs32 = 0;
-      for (int shape = 0; shape < kBrickShapes; ++shape) {
+      for (int shape = 0; shape < hfe::kHessianShapes; ++shape) {
+        if (!hfe::hessian_shape_valid(c->g, shape)) continue;
         c->brick_shape = c->brick_shape32 = shape;
         {
           const double t = time_us([&]() { return stiffness(c, c->g0, c->Kd, false); });

@@ -74,6 +74,10 @@ struct ElemArgs {
   // read, only at those points. Both come from the residual pass.
   const uint8_t* soft;
   uint8_t* soft_out;
+  // Q1: the Hessian's per-element mask word (bits 0-7 the soft mask, 8-10 the
+  // phase, 15 a = 1 at all 8 points), written by the residual pass
+  const uint16_t* emask;
+  uint16_t* emask_out;
   const double* sw;
   double* sw_out;
   // tens != 0: some phase follows the tensile-masking law, whose tangent
@@ -103,8 +107,7 @@ struct HessArgs {
   Grid g;
   MatTable mat;
   const double* E;       // macroscopic strain (device, FP64)
-  const uint8_t* phase;
-  const uint8_t* soft;   // [N] softening points of each element (bit q), as in ElemArgs
+  const uint16_t* emask; // [N] mask word of each element (soft mask, phase, intact), as in ElemArgs
   const double* sw;      // [nq][6][N] w = sqrt(c') s at the softening points (FP64)
   int tens;              // as in ElemArgs: sn holds w_n = sqrt(c') n (FP64)
   const double* sn;
@@ -115,6 +118,11 @@ struct HessArgs {
   CgState* cg;           // skipped once cg->done when set
   int brick_shape;
 };
+// Hessian launch shapes: bricks 0..kBrickOnly-1, marching columns up to
+// kHessianShapes-1 (valid where the grid's nx, ny are multiples of the column).
+constexpr int kBrickOnly = 5;
+constexpr int kHessianShapes = 13;
+bool hessian_shape_valid(const Grid& g, int shape);
 // FP32 Hessian f = D^T B D v (rows HES_* in FP64), 3D Q1 only.
 hipError_t launch_hessian_f32(const HessArgs<float>& A, hipStream_t s, int* nblocks);
 // Commit: khist <- max(khist, kappa_t(E + D u)) on damage points (khist is
@@ -156,6 +164,9 @@ bool fft_launch_valid(const Grid& g, int plane_threads, int pencil_cols, int pen
                       size_t real_bytes);
 void fft_default_launch(const Grid& g, int* plane_threads, int* pencil_cols, int* pencil_threads);
 template <typename R> size_t fft_plane_lds_bytes(const Grid& g);
+// Raise the dynamic-LDS limit of the plane kernels a grid needs above 64 KiB
+// (once per device; call on the context's device before any capture).
+hipError_t fft_prepare(const Grid& g);
 // The plane passes of this grid fit one block (LDS and staged values).
 template <typename R> bool fft_plane_fits(const Grid& g);
 // Pipeline entry points, R = double or float. `in`/`out` are [dim][N] reals,

@@ -709,6 +709,12 @@ __device__ __forceinline__ void q1_div_sf(const R (&T)[3][2][2], R (&f)[8]) {
   }
 }
 
+// Element mask word written by the residual pass for the Hessian: bits 0-7
+// the softening points (as the soft mask), bits 8-10 the phase, bit 15 set
+// when a = 1 at all 8 points (an intact element: its tangent is C and its
+// a values are not read).
+constexpr unsigned kIntact = 0x8000u;
+
 // ---- brick kernels (Q1) ---------------------------------------------------
 //
 // One block per brick of BX x BY x BZ nodes. The block computes the
@@ -855,6 +861,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
       q1_grad_sf(v, G[c]);
     }
     unsigned soft = 0;   // bit q: c' != 0 at point q
+    bool intact = true;  // a = 1 at every point
     // T[c][j][m][n]: sigma_cj summed over the Gauss coordinate along j
     double T[3][3][2][2];
 #pragma unroll
@@ -874,6 +881,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
       for (int k = 0; k < 6; ++k) tau.v[k] = P.a * P.s.v[k];
       if (owned) {
         A.a_out[q * g.N + eg] = P.a;
+        intact = intact && P.a == 1.0;
         if (P.cp != 0.0) {
           // rank-one factor of the softening term (c' > 0 where loading)
           soft |= 1u << q;
@@ -907,7 +915,10 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads)) k_brick(Ele
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
-    if (owned) A.soft_out[eg] = (uint8_t)soft;
+    if (owned) {
+      A.soft_out[eg] = (uint8_t)soft;
+      A.emask_out[eg] = (uint16_t)(soft | ((unsigned)ph << 8) | (intact ? kIntact : 0u));
+    }
   }
   // Assembly: every owned node adds the forces of its 8 elements in the
   // fixed order of the corner a; the element forces go through the tile's
@@ -1073,6 +1084,116 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 // without spills; FP64 keeps the compiler's choice.
 template <typename R> constexpr int hessian_waves_per_eu() { return sizeof(R) == 4 ? 4 : 1; }
 
+// Forces of one element under the Hessian: the sum-factorised gradient of
+// the staged direction, the tangent at the 8 points (a C : e minus the
+// rank-one softening term at the points of the element's mask), and the
+// sum-factorised divergence into f[c][corner]. tile(c, i) reads component c
+// of staged node i; corner a = ax + 2 ay + 4 az sits at t0 + ax + ay sy + az sz.
+// dd receives sum |D v|^2 over the element's points if `owned` (else 0).
+template <typename R, bool NS, typename Tile>
+__device__ __forceinline__ void hess_element(const Tile& tile, int t0, int sy, int sz, R lam, R mu,
+                                             const R (&aq)[8], unsigned soft,
+                                             const double* __restrict__ w_e,
+                                             const double* __restrict__ n_e, long long N,
+                                             R (&f)[3][8], double& dd, bool owned) {
+  R G[3][3][2][2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      v[a] = tile(c, t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz);
+    q1_grad_sf(v, G[c]);
+  }
+  dd = 0.0;
+  if (owned) {
+    // |D v|^2 over the points: each G value is the gradient entry of the two
+    // points that differ only in the Gauss coordinate along j
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) s2 += (double)G[c][j][m][k] * (double)G[c][j][m][k];
+    dd = 2.0 * s2;
+  }
+  // T[c][j][m][n]: tau_cj summed over the Gauss coordinate along j; an entry
+  // is written at the first of its two points and added at the second
+  R T[3][3][2][2];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
+    R dH[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dH[c][0] = G[c][0][gy][gz];
+      dH[c][1] = G[c][1][gx][gz];
+      dH[c][2] = G[c][2][gx][gy];
+    }
+    // tau = a C : e - (w : e) w with e = sym(dH); h_ij = 2 e_ij
+    const R h01 = dH[0][1] + dH[1][0], h02 = dH[0][2] + dH[2][0], h12 = dH[1][2] + dH[2][1];
+    const R al = aq[q] * lam, am = aq[q] * mu;
+    const R ltr = al * (dH[0][0] + dH[1][1] + dH[2][2]), am2 = am + am;
+    R t00 = ltr + am2 * dH[0][0], t11 = ltr + am2 * dH[1][1], t22 = ltr + am2 * dH[2][2];
+    R t01 = am * h01, t02 = am * h02, t12 = am * h12;
+    if ((soft >> q) & 1u) {
+      R w[6], wn[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = (R)w_e[(q * 6 + k) * N];
+      if (NS) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wn[k] = (R)n_e[(q * 6 + k) * N];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wn[k] = w[k];
+      }
+      const R we = wn[0] * dH[0][0] + wn[1] * dH[1][1] + wn[2] * dH[2][2] + wn[3] * h01 +
+                   wn[4] * h02 + wn[5] * h12;
+      t00 -= we * w[0];
+      t11 -= we * w[1];
+      t22 -= we * w[2];
+      t01 -= we * w[3];
+      t02 -= we * w[4];
+      t12 -= we * w[5];
+    }
+    const R tau[3][3] = {{t00, t01, t02}, {t01, t11, t12}, {t02, t12, t22}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (gx == 0) T[c][0][gy][gz] = tau[c][0]; else T[c][0][gy][gz] += tau[c][0];
+      if (gy == 0) T[c][1][gx][gz] = tau[c][1]; else T[c][1][gx][gz] += tau[c][1];
+      if (gz == 0) T[c][2][gx][gy] = tau[c][2]; else T[c][2][gx][gy] += tau[c][2];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
+}
+
+// The element state the Hessian reads: phase and softening mask from the
+// mask word, a at the 8 points (1 without a load at intact elements).
+template <typename R>
+__device__ __forceinline__ void hess_state(const HessArgs<R>& A, long long eg, int& ph,
+                                           unsigned& soft, R (&aq)[8]) {
+  const unsigned m = A.emask[eg];
+  ph = (m >> 8) & 7u;
+  soft = m & 0xffu;
+  if (m & kIntact) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) aq[q] = R(1);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) aq[q] = A.a[q * A.g.N + eg];
+  }
+}
+
+// The node sum of the assembly has one fixed order in every Hessian kernel:
+// the four corners with az = 0 (the element layer of the node), then the
+// four with az = 1 (the layer below), each group summed in corner order
+// ((f0 + f1) + f2) + f3, then the two group sums added. It is what lets the
+// column kernel carry the az = 1 sums from one layer to the next.
+
 template <typename R, int BX, int BY, int BZ, bool FULL, bool NS>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
     k_hessian(HessArgs<R> A) {
@@ -1123,9 +1244,8 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
       }
     }
   };
-  // this thread's element and its state (phase, softening mask, a at the 8
-  // points), loaded before the tile so that all these loads are in flight
-  // together
+  // this thread's element and its state, loaded before the tile so that all
+  // these loads are in flight together
   const int ne = ex_n * ey_n * ez_n;
   const bool active = tid < ne;
   const int ex = tid % ex_n, ey = (tid / ex_n) % ey_n, ez = tid / (ex_n * ey_n);
@@ -1135,10 +1255,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   R aq[8];
   if (active) {
     eg = lin(g, wrap(x0 - 1 + ex, g.nx), wrap(y0 - 1 + ey, g.ny), wrap(z0 - 1 + ez, g.nz));
-    ph = A.phase[eg];
-    soft = A.soft[eg];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) aq[q] = A.a[q * g.N + eg];
+    hess_state(A, eg, ph, soft, aq);
   }
   stage(A.v, sv);
   __syncthreads();
@@ -1151,86 +1268,12 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   if (active) {
     const R lam = (R)A.mat.lam[ph], mu = (R)A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
-    const int sy = tx, sz = tx * ty;
-    const bool owned = ex >= 1 && ey >= 1 && ez >= 1;
-    R G[3][3][2][2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      R v[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        v[a] = sv[c][t0 + (a & 1) + ((a >> 1) & 1) * sy + ((a >> 2) & 1) * sz];
-      q1_grad_sf(v, G[c]);
-    }
-    if (owned) {
-      // |D v|^2 over the points: each G value is the gradient entry of the
-      // two points that differ only in the Gauss coordinate along j
-      double s2 = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-          for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) s2 += (double)G[c][j][m][k] * (double)G[c][j][m][k];
-      dd = 2.0 * s2;
-    }
-    const double* __restrict__ w_e = A.sw + eg;
-    const double* __restrict__ n_e = NS ? A.sn + eg : nullptr;
-    const long long N = g.N;
-    // T[c][j][m][n]: tau_cj summed over the Gauss coordinate along j; an
-    // entry is written at the first of its two points and added at the second
-    R T[3][3][2][2];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int gx = q & 1, gy = (q >> 1) & 1, gz = (q >> 2) & 1;
-      R dH[3][3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        dH[c][0] = G[c][0][gy][gz];
-        dH[c][1] = G[c][1][gx][gz];
-        dH[c][2] = G[c][2][gx][gy];
-      }
-      // tau = a C : e - (w : e) w with e = sym(dH); h_ij = 2 e_ij
-      const R h01 = dH[0][1] + dH[1][0], h02 = dH[0][2] + dH[2][0], h12 = dH[1][2] + dH[2][1];
-      const R al = aq[q] * lam, am = aq[q] * mu;
-      const R ltr = al * (dH[0][0] + dH[1][1] + dH[2][2]), am2 = am + am;
-      R t00 = ltr + am2 * dH[0][0], t11 = ltr + am2 * dH[1][1], t22 = ltr + am2 * dH[2][2];
-      R t01 = am * h01, t02 = am * h02, t12 = am * h12;
-      if ((soft >> q) & 1u) {
-        R w[6], wn[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) w[k] = (R)w_e[(q * 6 + k) * N];
-        if (NS) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) wn[k] = (R)n_e[(q * 6 + k) * N];
-        } else {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) wn[k] = w[k];
-        }
-        const R we = wn[0] * dH[0][0] + wn[1] * dH[1][1] + wn[2] * dH[2][2] + wn[3] * h01 +
-                     wn[4] * h02 + wn[5] * h12;
-        t00 -= we * w[0];
-        t11 -= we * w[1];
-        t22 -= we * w[2];
-        t01 -= we * w[3];
-        t02 -= we * w[4];
-        t12 -= we * w[5];
-      }
-      const R tau[3][3] = {{t00, t01, t02}, {t01, t11, t12}, {t02, t12, t22}};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (gx == 0) T[c][0][gy][gz] = tau[c][0]; else T[c][0][gy][gz] += tau[c][0];
-        if (gy == 0) T[c][1][gx][gz] = tau[c][1]; else T[c][1][gx][gz] += tau[c][1];
-        if (gz == 0) T[c][2][gx][gy] = tau[c][2]; else T[c][2][gx][gy] += tau[c][2];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
+    auto tile = [&](int c, int i) { return sv[c][i]; };
+    hess_element<R, NS>(tile, t0, tx, tx * ty, lam, mu, aq, soft, A.sw + eg,
+                        NS ? A.sn + eg : nullptr, g.N, f, dd, ex >= 1 && ey >= 1 && ez >= 1);
   }
-  // Assembly. Every owned node adds the forces of its 8 elements in the fixed
-  // order of the corner a (the same order whatever the brick shape). The
+  // Assembly. Every owned node adds the forces of its 8 elements in the
+  // fixed order of corner_sum (the same for every Hessian kernel). The
   // direction at the owned node is read from the tile first (for v.Kv), then
   // the tile's LDS is reused for the element forces.
   static_assert(kOwn <= nt, "one owned node per thread");
@@ -1258,16 +1301,181 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
     const long long n = lin(g, x0 + lx, y0 + ly, z0 + lz);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      R v = R(0);
+      // corner order of corner_sum: ((f0 + f1) + f2) + f3, the same for
+      // f4..f7, then the two sums added
+      R lo = R(0), hi = R(0);
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         const int e = (lx + 1 - (a & 1)) + ex_n * ((ly + 1 - ((a >> 1) & 1)) +
                                                    ey_n * (lz + 1 - ((a >> 2) & 1)));
-        v += lds[(a * 3 + c) * kElems + e];
+        const R x = lds[(a * 3 + c) * kElems + e];
+        if (a == 0) lo = x; else if (a < 4) lo += x; else if (a == 4) hi = x; else hi += x;
       }
+      const R v = lo + hi;
       A.f[c * g.N + n] = v;
       dkd += (double)v * (double)vn[c];
     }
+  }
+  double red[HES_NV];
+  red[HES_DKD] = dkd;
+  red[HES_DD] = dd;
+  block_reduce_store<HES_NV>(red, A.red.partials);
+}
+
+// ---- column-marching Hessian (Q1) -----------------------------------------
+//
+// One block per column of CX x CY owned nodes and `bz` node layers. The
+// block walks the element layers of its column upwards, one per step: the
+// (CX+1)(CY+1) elements of a layer (one per thread; a halo of one element
+// on the low x and y sides is recomputed by the neighbouring column, one
+// halo element layer below the column), their forces through LDS to the
+// nodes. A node layer takes the az = 0 corners of the element layer it is
+// the bottom of and the az = 1 corners of the layer below: the latter are
+// summed one step earlier and carried in registers, so no element is
+// computed twice along z. The direction is staged as a ring of two node
+// layers; the next node layer and the next element layer's mask word are
+// loaded while the current layer is computed. The node sums follow the
+// fixed corner order, so the result has the bits of the brick kernels.
+template <int CX, int CY> struct ColumnShape {
+  static constexpr int tx = CX + 2, ty = CY + 2;
+  static constexpr int layer = tx * ty;                     // staged nodes per layer
+  static constexpr int ex = CX + 1, ey = CY + 1;
+  static constexpr int elems = ex * ey;                     // elements per layer
+  static constexpr int threads = (elems + 63) / 64 * 64;
+  static constexpr int own = CX * CY;
+  static constexpr int pre = (layer + threads - 1) / threads;
+};
+
+template <typename R, int CX, int CY, bool NS>
+__global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_per_eu<R>())
+    k_hessian_col(HessArgs<R> A, int bz) {
+  using S = ColumnShape<CX, CY>;
+  const Grid& g = A.g;
+  if (A.cg && A.cg->done) return;
+  __shared__ R sv[3][2][S::layer];       // direction: component, ring slot, node
+  __shared__ R F[24][S::elems];          // element forces: corner * 3 + component, element
+  const int ncx = g.nx / CX, ncy = g.ny / CY;
+  const int blk = xcd_brick(blockIdx.x, gridDim.x);
+  const int cxi = blk % ncx, cyi = (blk / ncx) % ncy, czi = blk / (ncx * ncy);
+  const int x0 = cxi * CX, y0 = cyi * CY, z0 = czi * bz;
+  const int nzl = min(bz, g.nz - z0);    // owned node layers
+  const int tid = threadIdx.x;
+  const long long N = g.N, nxy = (long long)g.nx * g.ny;
+  // staged node positions of this thread within a layer (xy offsets)
+  long long sxy[S::pre];
+#pragma unroll
+  for (int it = 0; it < S::pre; ++it) {
+    const int i = tid + it * S::threads;
+    const int lx = i % S::tx, ly = i / S::tx;
+    sxy[it] = i < S::layer ? wrap(x0 - 1 + lx, g.nx) + (long long)g.nx * wrap(y0 - 1 + ly, g.ny)
+                           : 0;
+  }
+  // local node layer k is the global layer z0 - 1 + k; it sits in ring slot k & 1
+  auto load_layer = [&](int k, R (&r)[S::pre][3]) {
+    const long long zoff = (long long)wrap(z0 - 1 + k, g.nz) * nxy;
+#pragma unroll
+    for (int it = 0; it < S::pre; ++it)
+      if (tid + it * S::threads < S::layer) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[it][c] = A.v[c * N + zoff + sxy[it]];
+      }
+  };
+  auto store_layer = [&](int k, const R (&r)[S::pre][3]) {
+#pragma unroll
+    for (int it = 0; it < S::pre; ++it) {
+      const int i = tid + it * S::threads;
+      if (i < S::layer) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[c][k & 1][i] = r[it][c];
+      }
+    }
+  };
+  // this thread's element within a layer, and its owned node
+  const bool active = tid < S::elems;
+  const int ex = tid % S::ex, ey = tid / S::ex;
+  const long long exy = wrap(x0 - 1 + ex, g.nx) + (long long)g.nx * wrap(y0 - 1 + ey, g.ny);
+  const bool node = tid < S::own;
+  const int lx = tid % CX, ly = tid / CX;
+  const long long oxy = (x0 + lx) + (long long)g.nx * (y0 + ly);
+  const int ti = (lx + 1) + S::tx * (ly + 1);             // owned node in a staged layer
+  // element layer k (local) is the global layer z0 - 1 + k; its mask word
+  auto elem_of = [&](int k) { return (long long)wrap(z0 - 1 + k, g.nz) * nxy + exy; };
+  unsigned m_next = 0;
+  {
+    R r[S::pre][3];
+    load_layer(0, r);
+    store_layer(0, r);
+    load_layer(1, r);
+    store_layer(1, r);
+    if (active) m_next = A.emask[elem_of(0)];
+  }
+  __syncthreads();
+  R top[3] = {R(0), R(0), R(0)};        // az = 1 sums of the layer below, for node layer k
+  double dkd = 0.0, dd = 0.0;
+  for (int k = 0; k <= nzl; ++k) {
+    // element layer k: nodes k (bottom) and k + 1 (top); this step's loads
+    // ahead of the arithmetic: node layer k + 2 and the next mask word
+    R rn[S::pre][3];
+    const bool more = k + 2 <= nzl + 1;
+    if (more) load_layer(k + 2, rn);
+    const unsigned m = m_next;
+    if (active && k < nzl) m_next = A.emask[elem_of(k + 1)];
+    R f[3][8];
+    if (active) {
+      const long long eg = elem_of(k);
+      const int ph = (m >> 8) & 7u;
+      const unsigned soft = m & 0xffu;
+      R aq[8];
+      if (m & kIntact) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) aq[q] = R(1);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) aq[q] = A.a[q * N + eg];
+      }
+      const R lam = (R)A.mat.lam[ph], mu = (R)A.mat.mu[ph];
+      const int t0 = (k & 1) * S::layer + ex + S::tx * ey;
+      const int sz = (k & 1) ? -S::layer : S::layer;       // to the other ring slot
+      auto tile = [&](int c, int i) { return (&sv[c][0][0])[i]; };
+      double de = 0.0;
+      hess_element<R, NS>(tile, t0, S::tx, sz, lam, mu, aq, soft, A.sw + eg,
+                          NS ? A.sn + eg : nullptr, N, f, de, k >= 1 && ex >= 1 && ey >= 1);
+      dd += de;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[a * 3 + c][tid] = f[c][a];
+    }
+    // the direction at this thread's node of layer k (read before the ring
+    // slot is refilled below)
+    R vn[3] = {R(0), R(0), R(0)};
+    if (node && k >= 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vn[c] = sv[c][k & 1][ti];
+    }
+    __syncthreads();
+    if (node) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R lo = R(0), hi = R(0);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int e = (lx + 1 - (a & 1)) + S::ex * (ly + 1 - ((a >> 1) & 1));
+          const R x = F[a * 3 + c][e];
+          if (a == 0) lo = x; else if (a < 4) lo += x; else if (a == 4) hi = x; else hi += x;
+        }
+        if (k >= 1) {
+          // node layer k: the bottom corners (az = 0) of element layer k,
+          // then the top sums carried from element layer k - 1
+          const R v = lo + top[c];
+          A.f[c * N + (long long)(z0 + k - 1) * nxy + oxy] = v;
+          dkd += (double)v * (double)vn[c];
+        }
+        top[c] = hi;
+      }
+    }
+    if (more) store_layer(k + 2, rn);    // slot k & 1: node layer k is done
+    __syncthreads();
   }
   double red[HES_NV];
   red[HES_DKD] = dkd;
@@ -1316,15 +1524,43 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
   return hipGetLastError();
 }
 
-// Hessian brick shapes: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768),
+// Column shapes of the marching Hessian (shape ids kBrickOnly..): owned
+// nodes per layer CX x CY and node layers per block.
+struct ColShape { int cx, cy, bz; };
+constexpr ColShape kColShapes[kHessianShapes - kBrickOnly] = {
+    {16, 16, 16}, {16, 16, 8}, {16, 8, 16}, {16, 8, 8}, {8, 8, 8}, {8, 8, 16}, {16, 8, 32},
+    {16, 16, 32}};
+
+template <typename R, int CX, int CY>
+hipError_t launch_hessian_col(const HessArgs<R>& A, int bz, hipStream_t s, int* nblocks) {
+  const Grid& g = A.g;
+  if (g.nx % CX != 0 || g.ny % CY != 0 || bz < 1) return hipErrorInvalidValue;
+  const int nb = (g.nx / CX) * (g.ny / CY) * ((g.nz + bz - 1) / bz);
+  *nblocks = nb;
+  const dim3 grid(nb), block(ColumnShape<CX, CY>::threads);
+  if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true>), grid, block, 0, s, A, bz);
+  else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false>), grid, block, 0, s, A, bz);
+  return hipGetLastError();
+}
+
+// Hessian shapes. Bricks: 0 = 8x8x4 (448 threads), 1 = 8x8x8 (768),
 // 2 = 16x8x4 (768), 3 = 16x4x4 (448), 4 = 8x4x4 (256: two blocks share a CU
 // at the FP64 kernel's register count, so one block's loads overlap the
 // other's arithmetic, for 1.76 instead of 1.58 elements per owned node).
+// Columns (kBrickOnly and up): kColShapes, where nx and ny are multiples of
+// the column.
 template <typename R>
 hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
-  if (!A.v || !A.f || !A.a || !A.sw || !A.phase || !A.soft || !A.E || !A.red.partials ||
+  if (!A.v || !A.f || !A.a || !A.sw || !A.emask || !A.E || !A.red.partials ||
       (A.tens && !A.sn))
     return hipErrorInvalidValue;
+  if (A.brick_shape >= kBrickOnly) {
+    if (A.brick_shape >= kHessianShapes) return hipErrorInvalidValue;
+    const ColShape c = kColShapes[A.brick_shape - kBrickOnly];
+    if (c.cx == 16 && c.cy == 16) return launch_hessian_col<R, 16, 16>(A, c.bz, s, nblocks);
+    if (c.cx == 16 && c.cy == 8) return launch_hessian_col<R, 16, 8>(A, c.bz, s, nblocks);
+    return launch_hessian_col<R, 8, 8>(A, c.bz, s, nblocks);
+  }
   switch (A.brick_shape) {
     case 1: return launch_hessian_shape<R, 8, 8, 8>(A, s, nblocks);
     case 2: return launch_hessian_shape<R, 16, 8, 4>(A, s, nblocks);
@@ -1349,8 +1585,8 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
-  if (!A.u || !A.f || !A.a_out || !A.soft_out || !A.sw_out || !A.khist || !A.phase || !A.E ||
-      !A.red.partials || (A.tens && !A.sn_out))
+  if (!A.u || !A.f || !A.a_out || !A.soft_out || !A.emask_out || !A.sw_out || !A.khist ||
+      !A.phase || !A.E || !A.red.partials || (A.tens && !A.sn_out))
     return hipErrorInvalidValue;
   return launch_brick<MODE_RESIDUAL, RES_NV>(A, s, nblocks);
 }
@@ -1373,14 +1609,19 @@ hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks) {
   }
   return hipGetLastError();
 }
+bool hessian_shape_valid(const Grid& g, int shape) {
+  if (shape < 0 || shape >= kHessianShapes) return false;
+  if (shape < kBrickOnly) return true;
+  const ColShape c = kColShapes[shape - kBrickOnly];
+  return g.element == HFE_Q1 && g.nx % c.cx == 0 && g.ny % c.cy == 0;
+}
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_HESSIAN, HES_NV>(A, s, nblocks);
   HessArgs<double> H;
   H.g = A.g;
   H.mat = A.mat;
   H.E = A.E;
-  H.phase = A.phase;
-  H.soft = A.soft;
+  H.emask = A.emask;
   H.sw = A.sw;
   H.sn = A.sn;
   H.tens = A.tens;

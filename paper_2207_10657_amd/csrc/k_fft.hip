@@ -23,6 +23,8 @@
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
 
+#include <mutex>
+
 namespace hfe {
 namespace {
 
@@ -575,6 +577,36 @@ void fft_default_launch(const Grid& g, int* plane_threads, int* pencil_cols, int
 
 namespace {
 
+constexpr int kLdsPerCu = 160 * 1024;   // gfx950: LDS of one workgroup at most
+constexpr int kMaxDevices = 64;
+
+// Raise the dynamic-LDS limit of a plane kernel to what the 160 KiB of a
+// workgroup leave beside its static LDS, once per device (the attribute is
+// per function and device), not on every launch: launches happen from
+// several host threads at once (batches of contexts) and inside graph
+// captures.
+template <int MODE, typename R>
+hipError_t plane_lds_limit() {
+  static std::mutex mu;
+  static bool set[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (set[dev]) return hipSuccess;
+  hipFuncAttributes fa;
+  e = hipFuncGetAttributes(&fa, (const void*)k_plane<MODE, R>);
+  if (e == hipSuccess && fa.sharedSizeBytes >= (size_t)kLdsPerCu) e = hipErrorInvalidValue;
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_plane<MODE, R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsPerCu - (int)fa.sharedSizeBytes);
+  if (e == hipSuccess) set[dev] = true;
+  else (void)hipGetLastError();   // the failure is returned, not left for later calls
+  return e;
+}
+
 template <int MODE, typename R>
 hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* out, C2<R>* spec,
                         R scale, hipStream_t s, const CgState* skip = nullptr,
@@ -594,8 +626,7 @@ hipError_t launch_plane(const Grid& g, const FftTablesT<R>& t, const R* in, R* o
     return hipErrorInvalidValue;
   const size_t lds = fft_plane_lds_bytes<R>(g);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_plane<MODE, R>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = plane_lds_limit<MODE, R>();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_plane<MODE, R>), dim3(g.nz, g.dim), dim3(t.plane_threads), lds, s, g, t,
@@ -640,6 +671,25 @@ template <typename R>
 bool fft_plane_fits(const Grid& g) {
   // LDS of one CU, and at most 15 staged values per thread of a 1024-thread block
   return fft_plane_lds_bytes<R>(g) <= 160 * 1024 && (long long)(g.nx / 2 + 1) * g.ny <= 15 * 1024;
+}
+
+namespace {
+template <typename R>
+hipError_t plane_limits_all(const Grid& g) {
+  if (fft_plane_lds_bytes<R>(g) <= 65536) return hipSuccess;
+  hipError_t e = plane_lds_limit<PLANE_FWD, R>();
+  if (e == hipSuccess) e = plane_lds_limit<PLANE_INV, R>();
+  if (e == hipSuccess) e = plane_lds_limit<PLANE_GREEN2D, R>();
+  if (e == hipSuccess) e = plane_lds_limit<PLANE_FWD_CG, R>();
+  if (e == hipSuccess) e = plane_lds_limit<PLANE_INV_CG, R>();
+  return e;
+}
+}  // namespace
+
+hipError_t fft_prepare(const Grid& g) {
+  hipError_t e = plane_limits_all<double>(g);
+  if (e == hipSuccess) e = plane_limits_all<float>(g);
+  return e;
 }
 
 template <typename R>

@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libhfe.so")
 
 HFE_P1_PAIR, HFE_Q1 = 1, 2
 HFE_ELASTIC, HFE_DAMAGE_ENERGY_NORM, HFE_DAMAGE_TENSILE = 0, 1, 2
-FIELD_U, FIELD_GRAD, FIELD_STRESS, FIELD_DAMAGE, FIELD_KAPPA = range(5)
-CG_INTERIOR, CG_BOUNDARY, CG_NEGCURV, CG_MAXITER = 1, 2, 3, 4
+FIELD_U, FIELD_GRAD, FIELD_STRESS, FIELD_DAMAGE, FIELD_KAPPA, FIELD_SOFTENING = range(6)
+CG_INTERIOR, CG_BOUNDARY, CG_NEGCURV, CG_MAXITER, CG_STALL = 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "ESTATE"}
 
 
@@ -33,7 +33,8 @@ class _Params(ctypes.Structure):
                 ("eta_cg", ctypes.c_double), ("eta_up", ctypes.c_double),
                 ("R0", ctypes.c_double), ("Rmax", ctypes.c_double),
                 ("i_nr_max", ctypes.c_int), ("j_cg_max", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("restart", ctypes.c_double),
+                ("cg_stall", ctypes.c_int)]
 
 
 class _Tuning(ctypes.Structure):
@@ -47,6 +48,7 @@ class _Report(ctypes.Structure):
                 ("rejected", ctypes.c_int), ("cg_iters", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("boundary_exits", ctypes.c_int),
                 ("negcurv_exits", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("stall_exits", ctypes.c_int),
                 ("r_eq", ctypes.c_double), ("r_nr", ctypes.c_double),
                 ("R", ctypes.c_double), ("rho_last", ctypes.c_double),
                 ("time_ms", ctypes.c_double)]
@@ -206,7 +208,8 @@ def workspace_bytes(shape, element):
 # CG arithmetic (hfe_solver_params.precision)
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DEFAULT_PARAMS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "eta_cg": 1e-6, "eta_up": 0.15,
-                  "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000, "precision": 0}
+                  "R0": 0.0, "Rmax": 0.0, "i_nr_max": 50, "j_cg_max": 2000, "precision": 0,
+                  "restart": 0.2, "cg_stall": 0}
 
 
 def _params(params):
@@ -427,7 +430,8 @@ class Solver:
                   FIELD_GRAD: self.shape + (nq, d, d),
                   FIELD_STRESS: self.shape + (nq, d, d),
                   FIELD_DAMAGE: self.shape + (nq,),
-                  FIELD_KAPPA: self.shape + (nq,)}
+                  FIELD_KAPPA: self.shape + (nq,),
+                  FIELD_SOFTENING: self.shape + (nq,)}
         out = np.zeros(shapes[which])
         self._check(self.lib.hfe_get_field(self.ctx, which, out.ctypes.data_as(ctypes.c_void_p),
                                            out.size))

@@ -22,10 +22,26 @@ def announce(*parts):
     sys.stdout.flush()
 
 
+def _as_arrays(a, b):
+    """Both as float64, or both as complex128 if either is complex (so that
+    imaginary parts are compared too)."""
+    a, b = np.asarray(a), np.asarray(b)
+    dt = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    return a.astype(dt), b.astype(dt)
+
+
 def rel_err(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+    """Relative L2 error ||a - b|| / ||b|| (real or complex)."""
+    a, b = _as_arrays(a, b)
     nb = np.linalg.norm(b.ravel())
     if nb == 0.0:
         return float(np.linalg.norm(a.ravel()))
     return float(np.linalg.norm((a - b).ravel()) / nb)
+
+
+def max_err(a, b):
+    """Element-wise max |a - b| / max |b| (real or complex)."""
+    a, b = _as_arrays(a, b)
+    mb = float(np.max(np.abs(b))) if b.size else 0.0
+    md = float(np.max(np.abs(a - b))) if a.size else 0.0
+    return md if mb == 0.0 else md / mb

@@ -85,3 +85,36 @@ def test_header_is_plain_c(tmp_path):
                          capture_output=True, text=True)
     assert out.returncode == 0, out.stderr
     assert subprocess.run([str(tmp_path / "use_header")]).returncode == 0
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the header's size and field
+    offsets (compiled with the system C compiler)."""
+    import shutil
+    import subprocess
+    hfe, _ = _lib()
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    pairs = [("hfe_solver_params", hfe._Params), ("hfe_solve_report", hfe._Report),
+             ("hfe_newton_record", hfe._Record), ("hfe_material", hfe._Material),
+             ("hfe_grid", hfe._Grid), ("hfe_tuning", hfe._Tuning),
+             ("hfe_lbfgs_params", hfe._LbfgsParams), ("hfe_lbfgs_report", hfe._LbfgsReport)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hfe.h"', 'int main(void) {']
+    expect = []
+    for cname, ct in pairs:
+        lines.append('  printf("%%zu\\n", sizeof(%s));' % cname)
+        expect.append(ctypes.sizeof(ct))
+        for f, _ in ct._fields_:
+            lines.append('  printf("%%zu\\n", offsetof(%s, %s));' % (cname, f))
+            expect.append(getattr(ct, f).offset)
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    out = subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)],
+                         capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == expect

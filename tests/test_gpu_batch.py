@@ -21,7 +21,7 @@ def _shapes(solver):
     out = []
     for pt in (256, 512, 1024):
         for pc, pth in ((4, 64), (4, 128), (8, 64), (8, 128), (8, 256), (16, 128), (16, 256), (32, 256)):
-            for bs in range(5):
+            for bs in range(13):
                 try:
                     solver.set_tuning(plane_threads=pt, pencil_cols=pc, pencil_threads=pth,
                                       plane_threads32=pt, pencil_cols32=pc, pencil_threads32=pth,
@@ -32,8 +32,11 @@ def _shapes(solver):
     return out
 
 
-@pytest.mark.parametrize("shape", [(16, 12, 8), (32, 32, 32)])
+@pytest.mark.parametrize("shape", [(16, 12, 8), (32, 32, 32), (24, 16, 16)])
 def test_every_launch_shape_gives_the_same_bits(shape):
+    """(16, 12, 8): bricks only (no column divides ny = 12); (32, 32, 32):
+    bricks and every marching column; (24, 16, 16): columns whose last block
+    marches fewer layers (24 is not a multiple of 16 or 32)."""
     torch = require_gpu()
     announce("launch shapes", shape)
     from paper_2207_10657_amd import Solver

@@ -177,3 +177,38 @@ def test_mixed_workload_steps_against_oracle(name, steps, tol):
             assert dS < tol and dd < tol, (n, dS, dd)
             compared += 1
     assert compared >= steps // 2
+
+
+def test_mixed_with_a_reset_after_every_cg_step():
+    """Mixed precision with Powell's reset forced after every CG step
+    (restart constant -1, eq. 1): the FP32 CG recomputes its residual
+    (FP32 Hessian of the iterate plus the FP64 residual, rounded), restarts
+    along it and resumes; from the oracle's state, both sides solve two
+    increments of the 16^3 cell with j_CG,max = 40 and must converge to the
+    same stress and damage within the mixed-precision bound (1e-6 of the load
+    stress scale)."""
+    require_gpu()
+    from paper_2207_10657_amd import Solver
+    w = workload("c1_3d16", steps=2)
+    g = Solver(w.shape, "q1")
+    g.setup(w.phase, w.materials)
+    o = CellSolver(w.phase, w.materials, "q1")
+    prm = {"restart": -1.0, "j_cg_max": 40}
+    for n, dE in enumerate(w.load_path):
+        announce("mixed, reset after every CG step, step", n)
+        if n > 0:
+            ck = o.checkpoint()
+            g.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
+        g.apply_load_step(dE)
+        o.apply_load_step(dE)
+        rg = g.solve_increment(dict(prm, precision="mixed"))
+        ro = o.solve_increment(prm)
+        scale = _load_scale(w, o.E)
+        dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
+        dd = float(np.abs(g.damage() - o.damage()).max())
+        print("[mixed] reset every step, step %d: Newton %d/%d, restarts %d/%d, |dSigma|/scale "
+              "%.2e, damage %.2e" % (n, rg["newton_iters"], ro["newton_iters"], rg["restarts"],
+                                     ro["restarts"], dS, dd), flush=True)
+        assert rg["converged"] and ro["converged"]
+        assert rg["restarts"] >= rg["cg_iters"] - rg["newton_iters"] > 0
+        assert dS < 1e-6 and dd < 1e-6, (n, dS, dd)

@@ -13,7 +13,7 @@ import pytest
 from oracle import fe, material
 from oracle.projection import Projector
 from synthetic import workload, MATRIX_DAMAGE, INCLUSION_ELASTIC
-from tests.gpu_util import require_gpu, announce, rel_err
+from tests.gpu_util import require_gpu, announce, rel_err, max_err
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +40,13 @@ def test_fft_forward_inverse(shape):
     if len(shape) == 2:
         ref = ref[:, None]
     assert rel_err(specc, ref) < 1e-14
+    # element by element, real and imaginary parts (a conjugated or
+    # sign-flipped transform fails here)
+    assert max_err(specc, ref) < 1e-13
+    assert max_err(specc.imag, ref.imag) < 1e-13
     back = s.fft_inverse(torch.tensor(spec, device="cuda")).cpu().numpy()
     assert rel_err(back, f * np.prod(shape)) < 1e-14
+    assert max_err(back, f * np.prod(shape)) < 1e-13
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D + SHAPES_2D + [(64, 64, 64)])
@@ -57,6 +62,7 @@ def test_green_operator(shape):
     axes = tuple(range(1, len(shape) + 1))
     ref = np.fft.ifftn(np.fft.fftn(f, axes=axes) * P.invS[None], axes=axes).real
     assert rel_err(out, ref) < 1e-13
+    assert max_err(out, ref) < 1e-12
 
 
 def _state(shape, seed, scale):
@@ -96,6 +102,8 @@ def test_stiffness_residual_fields_and_projected_hessian(shape):
     # point fields
     assert rel_err(s.field(1), H) < 1e-14
     assert rel_err(s.field(2), st["sigma"]) < 1e-13
+    assert max_err(s.field(1), H) < 1e-13
+    assert max_err(s.field(2), st["sigma"]) < 1e-12
     np.testing.assert_array_equal(s.field(4), mf.initial_history())
     # stiffness K d = D^T B D d
     rng = np.random.default_rng(4)
@@ -104,6 +112,7 @@ def test_stiffness_residual_fields_and_projected_hessian(shape):
     Kd = s.apply_stiffness(dt).cpu().numpy()
     ref = fe.divergence(material.apply_tangent(mf, st, fe.gradient(d, el)), el)
     assert rel_err(Kd, ref) < 1e-13
+    assert max_err(Kd, ref) < 1e-12
     # projected Hessian: D out = G B D d
     out, dots = s.apply_projected_hessian(dt)
     out = out.cpu().numpy()
@@ -111,6 +120,7 @@ def test_stiffness_residual_fields_and_projected_hessian(shape):
     Dd = fe.gradient(d, el)
     GBDd = P(material.apply_tangent(mf, st, Dd))
     assert rel_err(fe.gradient(out, el), GBDd) < 1e-12
+    assert max_err(fe.gradient(out, el), GBDd) < 1e-12
     assert abs(dots[0] - np.sum(Dd * material.apply_tangent(mf, st, Dd))) < 1e-12 * abs(dots[0])
     assert abs(dots[1] - np.sum(Dd * Dd)) < 1e-12 * dots[1]
 
@@ -140,6 +150,7 @@ def test_full_size_projected_hessian_64cubed():
     Dd = fe.gradient(d, "q1")
     ref = Projector(w.shape, "q1")(material.apply_tangent(mf, st, Dd))
     assert rel_err(fe.gradient(out, "q1"), ref) < 1e-12
+    assert max_err(fe.gradient(out, "q1"), ref) < 1e-12
     # the launch shapes the benchmark times (its autotuner at this state):
     # the same bits, since a shape changes which block computes a value, not
     # the order of its arithmetic
