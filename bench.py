@@ -728,9 +728,11 @@ def main():
             converged += int(rep["converged"])
             detail.append(record(rep))
             sigmas.append(s.homogenized_stress())
+            if keep_states:
+                progress("replay step %d: Newton %d, CG %d" % (n, rep["newton_iters"], rep["cg_iters"]))
         return matvecs, newton, cg, converged
 
-    def from_states(params):
+    def from_states(params, label):
         """Each timed load step once more, each from the FP64 state before it
         (restarts are bit-exact): per step its time and result, and the
         homogenized stress against the FP64 step from the same state."""
@@ -746,6 +748,9 @@ def main():
             per.append(record(rep))
             S = s.homogenized_stress()
             errs.append(float(np.linalg.norm(S - sig64[j]) / max(np.linalg.norm(sig64[j]), 1e-300)))
+            progress("%s step %d: Newton %d, CG %d, %.2f s, stress error %.1e"
+                     % (label, W + j, rep["newton_iters"], rep["cg_iters"],
+                        time.perf_counter() - ts, errs[-1]))
         unconverged = sum(1 for p in per if not p["converged"])
         return {"value": w.nvox * mv / secs / 1e9, "unit": "Gvoxel-matvec/s",
                 "ms_per_step": secs / len(states) * 1e3,
@@ -801,7 +806,7 @@ def main():
     mixed = stall = None
     progress("timed steps, 50-iteration comparison and event-timed replay done")
     if not args.no_mixed:
-        mixed = from_states(dict(SOLVE, precision="mixed"))
+        mixed = from_states(dict(SOLVE, precision="mixed"), "mixed")
         s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
         s.set_profiling(True)
         for j, st in enumerate(states[:2]):
@@ -818,8 +823,9 @@ def main():
                          "checked against the oracle); bound %.0e" % MIXED_SIGMA_BOUND)
         mixed["within_bound"] = bool(mixed["sigma_rel_err_max"] <= MIXED_SIGMA_BOUND)
         stall = {"window": STALL_WINDOW,
-                 "fp64": from_states(dict(SOLVE, cg_stall=STALL_WINDOW)),
-                 "mixed": from_states(dict(SOLVE, precision="mixed", cg_stall=STALL_WINDOW)),
+                 "fp64": from_states(dict(SOLVE, cg_stall=STALL_WINDOW), "fp64 stall"),
+                 "mixed": from_states(dict(SOLVE, precision="mixed", cg_stall=STALL_WINDOW),
+                                      "mixed stall"),
                  "note": "the CG returns its iterate once its residual has not halved in "
                          "`window` iterations (an exit this library adds to Algorithm 1; off "
                          "by default); each step from the FP64 state before it"}

@@ -152,10 +152,13 @@ typedef struct {
   double time_ms;      /* wall time of the call                                    */
 } hfe_solve_report;
 
-/* Per-Newton-step record (lockstep logs against the oracle). */
+/* Per-Newton-step record (lockstep logs against the oracle). p_norm is the
+ * step's strain-space norm ||p|| summed directly over the points by the trial
+ * pass (the CG tracks it by recurrences; on a boundary or negative-curvature
+ * exit it equals R_before). */
 typedef struct {
   int flag, cg_iters, restarts, accepted;
-  double dm, dW, rho, R_before;
+  double dm, dW, rho, R_before, p_norm;
 } hfe_newton_record;
 
 /* Bytes of device workspace needed for a grid; 0 if the grid is unsupported. */
@@ -189,6 +192,22 @@ hfe_status hfe_set_material(hfe_ctx* ctx, int phase, const hfe_material* mat);
  * it. When the first increment is zero, the default trust radii take the
  * scale of the largest phase eigenstrain instead of ||dE_1||. */
 hfe_status hfe_set_eigenstrain(hfe_ctx* ctx, int phase, const double eig[9]);
+
+/* Mean-stress control (Sec. 3.3 holds its cell's mean stress at zero, free
+ * expansion, through a modified projector). Bit v of free_mask (Voigt order
+ * v = 0..5: xx, yy, zz, yz, xz, xy) makes that macroscopic strain component
+ * an unknown whose mean stress must vanish; the others stay prescribed.
+ * The projector becomes G + M, M the projection onto uniform fields in the
+ * free components (a free shear pair (i, j) as (e_i e_j + e_j e_i) / sqrt 2),
+ * an orthogonal projector that G annihilates: Algorithm 1 runs on fields
+ * D u + sum_m e_m B_m, the trust-region ratio is unchanged, and an accepted
+ * step moves E by its uniform part. The residual r_eq measures
+ * ||(G + M) sigma|| / ||sigma||. 0 restores strain control. Takes effect at
+ * the next solve (hfe_get_state returns E with the solved components).
+ * 3D and FP64 only: HFE_EINVAL for a mask outside 0..63, a non-zero mask on a
+ * 2D grid, and later for HFE_MIXED solves or the L-BFGS increment while a
+ * component is free. */
+hfe_status hfe_set_mean_stress_control(hfe_ctx* ctx, int free_mask);
 
 /* Algorithm 2, start of a load increment: E <- E + dE (dE a host 3x3,
  * symmetric; in 2D only the in-plane block is used), keep the fluctuation of

@@ -348,6 +348,16 @@ class CellSolver:
         return {"u": self.displacement(), "kappa_hist": self.kappa_hist.copy(),
                 "E": self.E.copy(), "R": self.R, "Rmax": self.Rmax}
 
+    def restore(self, ck):
+        """Resume from a checkpoint: H = E + D u, the history and the radii;
+        the next apply_load_step evaluates the state."""
+        E = np.asarray(ck["E"], dtype=np.float64).reshape(3, 3)
+        self.E = E.copy()
+        self.H = fe.gradient(np.asarray(ck["u"], dtype=np.float64), self.element) \
+            + E[: self.dim, : self.dim]
+        self.kappa_hist = np.asarray(ck["kappa_hist"], dtype=np.float64).copy()
+        self.R, self.Rmax = float(ck["R"]), float(ck["Rmax"])
+
     def _commit(self):
         self.kappa_hist = material.committed_history(self.mat, self.state, self.kappa_hist)
 

@@ -13,6 +13,15 @@ namespace hfe {
 enum { CG_RUN = 0, CG_INTERIOR = 1, CG_BOUNDARY = 2, CG_NEGCURV = 3, CG_MAXITER = 4,
        CG_STALL = 5, CG_NUMERIC = 6 };
 
+// Mean-stress control adds up to kMaxFree uniform unknowns to the CG vectors:
+// free macroscopic strain components m with unit tensors B_m (e_i (x) e_i, or
+// (e_i (x) e_j + e_j (x) e_i) / sqrt 2 for a shear pair), orthonormal under
+// the point sum. Their coordinates ("tails") live in this state: a vector is
+// (nodal part, tail), its strain-space field D x + sum_m x_m B_m, the inner
+// products gain x.y-type tail terms (the cross terms vanish: the point sum
+// of D x is zero), and the preconditioned tail is y_m = g_m / N_qp.
+constexpr int kMaxFree = 6;
+
 struct CgState {
   // scalars of the recurrences (strain-space inner products)
   double rr, rr0, rr_new;   // <r,r>, <r0,r0>, <r_{j+1},r_{j+1}>
@@ -24,6 +33,14 @@ struct CgState {
   double rr_ref;            // stall exit: reference residual (squared)
   int j_ref;                // and the iteration that set it
   int stall;                // stall window in iterations (0: off)
+  // mean-stress control: tails of the iterate, direction, gradient,
+  // preconditioned gradient and K d, and the direction's uniform part
+  // sum_m d_m B_m (row-major 3x3) read by the Hessian
+  int ne;                   // free components (0: strain control, tails unused)
+  int comp[kMaxFree];       // Voigt index (xx, yy, zz, yz, xz, xy) of each
+  double nqp;               // points of the grid (the tails' metric)
+  double ze[kMaxFree], de[kMaxFree], ge[kMaxFree], ye[kMaxFree], kde[kMaxFree];
+  double dU[9];
   int iters;                // Hessian applications of this solve (CG iterations)
   int jmax;
   int done;                 // 1: stop; the remaining kernels of the batch are no-ops
@@ -46,6 +63,28 @@ __device__ __forceinline__ void cg_roots(double zz, double zd, double dd, double
   *tp = fmax(t1, t2);
 }
 
+// sum_m x_m B_m as a row-major 3x3 (Voigt comp: xx, yy, zz, yz, xz, xy)
+__host__ __device__ inline void tail_tensor(const CgState* s, const double* x, double* U) {
+  for (int k = 0; k < 9; ++k) U[k] = 0.0;
+  const double r = 0.70710678118654752440;   // 1 / sqrt 2
+  for (int m = 0; m < s->ne; ++m) {
+    const int v = s->comp[m];
+    if (v < 3) {
+      U[4 * v] += x[m];
+    } else {
+      const int i = v == 3 ? 1 : 0, j = v == 5 ? 1 : 2;
+      U[3 * i + j] += r * x[m];
+      U[3 * j + i] += r * x[m];
+    }
+  }
+}
+
+// The pairing sum_q tau : B_m from the point sums of a symmetric tensor in
+// Voigt order (xx, yy, zz, yz, xz, xy).
+__host__ __device__ inline double tail_pair(int v, const double* voigt) {
+  return v < 3 ? voigt[v] : 1.41421356237309504880 * voigt[v];
+}
+
 __device__ __forceinline__ void cg_trace(CgState* s, double* trace, double kap, double ratio) {
   if (trace && s->ntrace < s->trace_cap) {
     trace[2 * s->ntrace] = kap;
@@ -55,9 +94,17 @@ __device__ __forceinline__ void cg_trace(CgState* s, double* trace, double kap, 
 }
 
 // After the Hessian application: curvature test, step length, boundary test.
+// kvoigt (mean-stress control): the point sums of B : D d in Voigt order.
 __device__ __forceinline__ void cg_decide_curvature(CgState* s, double* trace, double kap,
-                                                    double dd) {
+                                                    double dd, const double* kvoigt = nullptr) {
   if (s->done) return;
+  if (s->ne > 0 && kvoigt) {
+    for (int m = 0; m < s->ne; ++m) {
+      s->kde[m] = tail_pair(s->comp[m], kvoigt);
+      kap += s->de[m] * s->kde[m];
+      dd += s->nqp * s->de[m] * s->de[m];
+    }
+  }
   s->kap = kap;
   s->dd = dd;
   s->iters += 1;
@@ -74,6 +121,7 @@ __device__ __forceinline__ void cg_decide_curvature(CgState* s, double* trace, d
     const double mp = tp * s->rd + 0.5 * tp * tp * kap;
     s->tau = mm < mp ? tm : tp;
     s->apply_tau = 1;
+    for (int m = 0; m < s->ne; ++m) s->ze[m] += s->tau * s->de[m];
     s->flag = CG_NEGCURV;
     s->done = 1;
     cg_trace(s, trace, kap, NAN);
@@ -86,6 +134,7 @@ __device__ __forceinline__ void cg_decide_curvature(CgState* s, double* trace, d
     cg_roots(s->zz, s->zd, dd, s->R, &tm, &tp);
     s->tau = tp;
     s->apply_tau = 1;
+    for (int m = 0; m < s->ne; ++m) s->ze[m] += s->tau * s->de[m];
     s->flag = CG_BOUNDARY;
     s->done = 1;
     cg_trace(s, trace, kap, NAN);
@@ -93,12 +142,23 @@ __device__ __forceinline__ void cg_decide_curvature(CgState* s, double* trace, d
   }
   s->alpha = alpha;
   s->zz_new = zz_new;
+  for (int m = 0; m < s->ne; ++m) {
+    s->ze[m] += alpha * s->de[m];
+    s->ge[m] += alpha * s->kde[m];
+  }
 }
 
 // After the residual update: convergence, restart test, beta.
 __device__ __forceinline__ void cg_decide_residual(CgState* s, double* trace, double rr_new,
                                                    double pw) {
   if (s->done) return;
+  // tails: <r_{j+1}, r_{j+1}> gains |g_e|^2 / N_qp, the Powell numerator
+  // y_e(old) . g_e(new); then y_e = g_e / N_qp
+  for (int m = 0; m < s->ne; ++m) {
+    pw += s->ye[m] * s->ge[m];
+    s->ye[m] = s->ge[m] / s->nqp;
+    rr_new += s->ge[m] * s->ye[m];
+  }
   cg_trace(s, trace, s->kap, sqrt(fmax(rr_new, 0.0) / s->rr0));
   s->rr_new = rr_new;
   if (sqrt(fmax(rr_new, 0.0)) <= s->eta_cg * sqrt(s->rr0)) {
@@ -123,9 +183,22 @@ __device__ __forceinline__ void cg_decide_residual(CgState* s, double* trace, do
   s->beta = rr_new / s->rr;
 }
 
+// The tail of the next direction, d_e = -y_e + beta d_e (beta as decided,
+// 0 after a restart), and its uniform tensor for the next Hessian; taken
+// where the nodal direction update is.
+__device__ __forceinline__ void cg_tail_direction(CgState* s) {
+  if (s->done || s->ne == 0) return;
+  for (int m = 0; m < s->ne; ++m) s->de[m] = -s->ye[m] + s->beta * s->de[m];
+  tail_tensor(s, s->de, s->dU);
+}
+
 // After the direction update: <z,d>, ||z||^2 and <r,r> for the next iteration.
 __device__ __forceinline__ void cg_decide_direction(CgState* s, double gd, double zg) {
   if (s->done) return;
+  for (int m = 0; m < s->ne; ++m) {
+    gd += s->ge[m] * s->de[m];
+    zg += s->ze[m] * s->ge[m];
+  }
   s->zd = -zg + s->beta * (s->zd + s->alpha * s->dd);
   s->zz = s->zz_new;
   s->rr = s->rr_new;

@@ -54,6 +54,8 @@ struct Layout {
   size_t spec;                                        // dim*nz*ny*(nx/2+1) double2
   size_t partials;                                    // rows * 16 doubles
   size_t partials2;                                   // second row buffer (direction sums)
+  size_t partials3;                                   // rows of 6 (mean-stress tail sums)
+  size_t Udev, Pudev;                                 // 3x3 uniform parts (mean-stress control)
   size_t cgstate;                                     // device CgState
   size_t cgmid;                                       // its copy between the fused passes
   size_t trace;                                       // CG trace, 2 doubles per entry
@@ -127,6 +129,9 @@ Layout make_layout(const Grid& g) {
   L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
   L.partials2 = take((size_t)L.partial_rows * 2 * sizeof(double));
+  L.partials3 = take((size_t)L.partial_rows * 6 * sizeof(double));
+  L.Udev = take(9 * sizeof(double));
+  L.Pudev = take(9 * sizeof(double));
   L.cgstate = take(sizeof(hfe::CgState));
   L.cgmid = take(sizeof(hfe::CgState));
   L.trace = take((size_t)2 * kTraceCap * sizeof(double));
@@ -196,6 +201,9 @@ struct hfe_ctx {
   double2* spec;
   double* partials;
   double* partials2;
+  double* partials3;         // the Hessian's tail rows (mean-stress control)
+  double* Udev;              // uniform part of an operator input (mean-stress control)
+  double* Pudev;             // uniform part of the trial step (mean-stress control)
   int nb_dir = 0;            // rows of the pending direction sums in partials2
   hfe::CgState* cg;          // device CG state (after each iteration)
   hfe::CgState* cg_mid;      // the state after the forward plane pass's decisions (3D)
@@ -219,6 +227,12 @@ struct hfe_ctx {
   bool R_init = false;
   double R = 0, Rmax = 0, R0_default = 0, Rmax_default = 0;
   double r_eq = 0, sig_norm2 = 0, rr0 = 0;
+  double rr0_nodal = 0;      // y0 . g0 (rr0 adds the tails of mean-stress control)
+  // mean-stress control: free macroscopic strain components (Voigt index)
+  int ne = 0;
+  int comp[hfe::kMaxFree] = {};
+  double g0e[hfe::kMaxFree] = {};   // tails of the residual: sum_q sigma : B_m
+  double ze[hfe::kMaxFree] = {};    // tail of the last CG step
   double sigma_sum[6] = {0};
   std::vector<hfe_newton_record> log;
   std::vector<double> cg_trace;
@@ -382,13 +396,17 @@ hfe::ElemArgs elem_args(hfe_ctx* c) {
   A.red = reducer(c);
   A.cg = nullptr;
   A.brick_shape = c->brick_shape;
+  A.U = nullptr;
+  A.red_tail.partials = c->partials3;
+  A.Pu = nullptr;
   return A;
 }
 
 long long ndof(const hfe_ctx* c) { return (long long)c->g.dim * c->g.N; }
 
 // Offsets of the reduction totals in hscal.
-enum { S_HES = 0, S_RES = 8, S_RR0 = 24, S_TRI = 32, S_DOT = 48, S_ESTAGE = 56, S_COUNT = 72 };
+enum { S_HES = 0, S_RES = 8, S_RR0 = 24, S_TRI = 32, S_DOT = 48, S_ESTAGE = 56, S_TAIL = 72,
+       S_USTAGE = 80, S_COUNT = 96 };
 
 // y = L^+ x (the passes are skipped once skip->done is set)
 hfe_status green(hfe_ctx* c, const double* x, double* y, const hfe::CgState* skip = nullptr) {
@@ -414,15 +432,25 @@ hfe_status green(hfe_ctx* c, const double* x, double* y, const hfe::CgState* ski
 
 // out = K v at the current state. Totals (d.Kd, |Dd|^2) to hscal[S_HES..], or,
 // inside the CG, the curvature decision on the device state.
-hfe_status stiffness(hfe_ctx* c, const double* v, double* out, bool in_cg) {
+// U (device 3x3, may be null): the uniform part of v under mean-stress
+// control; its point sums of B : (D v + U) go to hscal[S_TAIL..] (Voigt).
+hfe_status stiffness(hfe_ctx* c, const double* v, double* out, bool in_cg,
+                     const double* U = nullptr) {
   hfe::ElemArgs A = elem_args(c);
   A.v = v;
   A.f = out;
+  A.U = U;
   if (in_cg) A.cg = c->cg;
   int nb = 0;
   {
     Prof p(c, "stiffness");
     HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
+  }
+  if (U && !in_cg) {
+    hfe::Reducer r;
+    r.partials = c->partials3;
+    Prof p(c, "finish");
+    HIPCHK(c, hfe::finish(hfe::FIN_OUT, r, nb, 6, c->dscal + S_TAIL, c->cg, c->trace, c->stream));
   }
   return in_cg ? finish(c, hfe::FIN_CURVATURE, nb, hfe::HES_NV, nullptr)
                : finish(c, hfe::FIN_OUT, nb, hfe::HES_NV, c->dscal + S_HES);
@@ -443,6 +471,32 @@ hfe_status upload_E(hfe_ctx* c) {
   double* stage = c->hscal + S_ESTAGE;
   for (int k = 0; k < 9; ++k) stage[k] = c->E[k];
   HIPCHK(c, hipMemcpyAsync(c->Edev, stage, 9 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HFE_OK;
+}
+
+// Tails of the residual under mean-stress control, g0_m = sum_q sigma : B_m
+// (from the stress sums), and r_eq = ||G_M sigma|| / ||sigma|| with
+// ||G_M sigma||^2 = y0 . g0 + sum_m g0_m^2 / N_qp.
+void refresh_tails(hfe_ctx* c) {
+  // stress sums are (xx, yy, zz, xy, xz, yz); tails use Voigt (xx, yy, zz, yz, xz, xy)
+  const double* s = c->sigma_sum;
+  const double voigt[6] = {s[0], s[1], s[2], s[5], s[4], s[3]};
+  const double nqp = (double)c->g.N * c->g.nq;
+  c->rr0 = c->rr0_nodal;
+  for (int m = 0; m < c->ne; ++m) {
+    c->g0e[m] = hfe::tail_pair(c->comp[m], voigt);
+    c->rr0 += c->g0e[m] * c->g0e[m] / nqp;
+  }
+  c->r_eq = c->sig_norm2 > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(c->sig_norm2) : 0.0;
+}
+
+// Upload a 3x3 (a uniform field) to the device through the pinned staging
+// area (synchronous, rare).
+hfe_status upload_3x3(hfe_ctx* c, const double* U, double* dev) {
+  double* stage = c->hscal + S_USTAGE;
+  for (int k = 0; k < 9; ++k) stage[k] = U[k];
+  HIPCHK(c, hipMemcpyAsync(dev, stage, 9 * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HFE_OK;
 }
@@ -475,10 +529,10 @@ hfe_status evaluate_residual(hfe_ctx* c) {
   for (int k = 0; k < 6; ++k) c->sigma_sum[k] = h[S_RES + k];
   c->sig_norm2 = h[S_RES + hfe::RES_SS];
   c->n_soft = h[S_RES + hfe::RES_NSOFT];
-  c->rr0 = h[S_RR0];
-  if (!std::isfinite(c->rr0) || !std::isfinite(c->sig_norm2))
+  c->rr0_nodal = h[S_RR0];
+  if (!std::isfinite(c->rr0_nodal) || !std::isfinite(c->sig_norm2))
     return fail(c, HFE_ENUMERIC, "non-finite stress or residual");
-  c->r_eq = c->sig_norm2 > 0.0 ? std::sqrt(std::max(c->rr0, 0.0)) / std::sqrt(c->sig_norm2) : 0.0;
+  refresh_tails(c);
   c->have_state = true;
   c->state32_fresh = false;
   return HFE_OK;
@@ -532,6 +586,8 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
   H.red = reducer(c);
   H.cg = in_cg ? c->cg : nullptr;
   H.brick_shape = c->brick_shape32;
+  H.U = nullptr;                 // mean-stress control runs in FP64 only
+  H.red_tail.partials = nullptr;
   return H;
 }
 
@@ -594,6 +650,7 @@ hfe::CgFuse<R> fuse_args(hfe_ctx* c, int nb_hes, const R* d, R* z, R* g, R* y) {
   f.nb_dir = c->nb_dir;
   f.rows_hes = c->partials;
   f.nb_hes = nb_hes;
+  f.rows_tail = c->ne > 0 ? c->partials3 : nullptr;
   f.trace = c->trace;
   f.d = d;
   f.z = z;
@@ -644,6 +701,8 @@ hfe_status cg_iteration(hfe_ctx* c) {
   A.v = c->d;
   A.f = c->Kd;
   A.cg = c->cg;
+  // mean-stress control: the direction's uniform part, kept in the CG state
+  if (c->ne > 0) A.U = c->cg->dU;
   int nb = 0;
   {
     Prof p(c, "stiffness");
@@ -792,6 +851,16 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, do
   init.rr_ref = c->rr0;
   init.j_ref = 0;
   init.stall = stall;
+  // mean-stress control: z_e = 0, g_e = g0_e, y_e = g0_e / N_qp, d_e = -y_e
+  init.ne = c->ne;
+  init.nqp = (double)c->g.N * c->g.nq;
+  for (int m = 0; m < c->ne; ++m) {
+    init.comp[m] = c->comp[m];
+    init.ge[m] = c->g0e[m];
+    init.ye[m] = c->g0e[m] / init.nqp;
+    init.de[m] = -init.ye[m];
+  }
+  hfe::tail_tensor(&init, init.de, init.dU);
   init.jmax = j_max;
   init.flag = hfe::CG_RUN;
   init.trace_cap = kTraceCap;
@@ -854,6 +923,41 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, do
         if (st) return st;
         HIPCHK(c, hfe::cg_resume(c->cg, c->stream));
         st = direction32(c);
+      } else if (c->ne > 0) {
+        // with the tails of mean-stress control: K z with z's uniform part,
+        // then r = K z + g on both parts, y = L^+ r (nodal) and r_e / N_qp,
+        // beta = 0, d_e = -y_e; the resumed state is written from the host
+        double Uz[9];
+        hfe::tail_tensor(&h, h.ze, Uz);
+        st = upload_3x3(c, Uz, c->Udev);
+        if (st) return st;
+        st = stiffness(c, c->z, c->tmp, false, c->Udev);
+        if (st) return st;
+        HIPCHK(c, hfe::vec_axpy_to(n, c->tmp, 1.0, c->g0, c->gv, c->stream));
+        st = green(c, c->gv, c->y);
+        if (st) return st;
+        st = dot(c, c->y, c->gv, c->dscal + S_DOT);
+        if (st) return st;
+        st = sync(c);
+        if (st) return st;
+        hfe::CgState r = h;
+        double rr = c->hscal[S_DOT];
+        for (int m = 0; m < c->ne; ++m) {
+          r.ge[m] = hfe::tail_pair(c->comp[m], c->hscal + S_TAIL) + c->g0e[m];
+          r.ye[m] = r.ge[m] / r.nqp;
+          r.de[m] = -r.ye[m];
+          rr += r.ge[m] * r.ye[m];
+        }
+        hfe::tail_tensor(&r, r.de, r.dU);
+        r.rr_new = rr;
+        r.beta = 0.0;
+        r.restart = 0;
+        r.done = 0;
+        r.flag = hfe::CG_RUN;
+        *c->hcg = r;
+        HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice,
+                                 c->stream));
+        st = direction(c);
       } else {
         st = stiffness(c, c->z, c->tmp, false);
         if (st) return st;
@@ -870,6 +974,7 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, do
       enq = h.iters;
       continue;
     }
+    for (int m = 0; m < c->ne; ++m) c->ze[m] = h.ze[m];   // the step's tail
     info->iters = h.iters;
     info->restarts = restarts;
     c->cg_predict = std::max(h.iters, 1);
@@ -977,6 +1082,9 @@ hfe_status hfe_create(const hfe_grid* grid, void* workspace, size_t ws_bytes, vo
   c->spec = (double2*)(c->ws + L.spec);
   c->partials = D(L.partials);
   c->partials2 = D(L.partials2);
+  c->partials3 = D(L.partials3);
+  c->Udev = D(L.Udev);
+  c->Pudev = D(L.Pudev);
   c->cg = (hfe::CgState*)(c->ws + L.cgstate);
   c->cg_mid = (hfe::CgState*)(c->ws + L.cgmid);
   c->trace = D(L.trace);
@@ -1125,6 +1233,21 @@ hfe_status hfe_set_eigenstrain(hfe_ctx* c, int phase, const double eig[9]) {
   return HFE_OK;
 }
 
+hfe_status hfe_set_mean_stress_control(hfe_ctx* c, int free_mask) {
+  if (!c) return HFE_EINVAL;
+  if (free_mask < 0 || free_mask > 63) return fail(c, HFE_EINVAL, "free_mask has bits 0..5");
+  if (free_mask != 0 && c->g.dim != 3)
+    return fail(c, HFE_EINVAL, "mean-stress control is implemented for 3D grids");
+  hfe_status st = sync(c);
+  if (st) return st;
+  destroy_graphs(c);   // captured iterations hold the tail buffers (or none)
+  c->ne = 0;
+  for (int v = 0; v < 6; ++v)
+    if (free_mask & (1 << v)) c->comp[c->ne++] = v;
+  if (c->have_state) refresh_tails(c);
+  return HFE_OK;
+}
+
 hfe_status hfe_apply_load_step(hfe_ctx* c, const double dE[9]) {
   if (!c) return HFE_EINVAL;
   if (!dE) return fail(c, HFE_EINVAL, "dE is NULL");
@@ -1187,6 +1310,9 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
     return fail(c, HFE_EINVAL, "precision must be HFE_FP64 or HFE_MIXED");
   if (p.precision == HFE_MIXED && c->g.dim != 3)
     return fail(c, HFE_EINVAL, "HFE_MIXED is implemented for 3D grids");
+  if (p.precision == HFE_MIXED && c->ne > 0)
+    return fail(c, HFE_EINVAL, "mean-stress control runs in FP64 (HFE_FP64)");
+  refresh_tails(c);   // the free components may have changed since the evaluation
   if (!c->R_init) {
     c->R = p.R0 > 0.0 ? p.R0 : c->R0_default;
     c->Rmax = p.Rmax > 0.0 ? p.Rmax : c->Rmax_default;
@@ -1221,6 +1347,17 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       // trial evaluation at u + z (Algorithm 2: model change, trial stress, FAIEF)
       hfe::ElemArgs A = elem_args(c);
       A.v = c->z;
+      double Pu[9] = {0};
+      if (c->ne > 0) {
+        // the step's uniform part moves the free macroscopic strain
+        hfe::CgState t;
+        t.ne = c->ne;
+        for (int m = 0; m < c->ne; ++m) t.comp[m] = c->comp[m];
+        hfe::tail_tensor(&t, c->ze, Pu);
+        st = upload_3x3(c, Pu, c->Pudev);
+        if (st) return st;
+        A.Pu = c->Pudev;
+      }
       int nb = 0;
       {
         Prof pr(c, "trial");
@@ -1246,6 +1383,7 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
       rec.dW = dW;
       rec.rho = rho;
       rec.R_before = c->R;
+      rec.p_norm = std::sqrt(std::max(h[hfe::TRI_PP], 0.0));
       rec.accepted = 0;
       rep.rho_last = rho;
       const bool on_boundary = flag == HFE_CG_BOUNDARY || flag == HFE_CG_NEGCURV;
@@ -1257,7 +1395,12 @@ hfe_status hfe_solve_increment(hfe_ctx* c, const hfe_solver_params* prm, hfe_sol
         // (g0 = D^T sigma, y0 = L^+ g0) are evaluated there in FP64, in
         // place, so captured CG graphs stay valid
         HIPCHK(c, hfe::vec_axpy(n, 1.0, c->z, c->u, c->stream));
-        st = evaluate_residual(c);
+        if (c->ne > 0) {
+          for (int k = 0; k < 9; ++k) c->E[k] += Pu[k];
+          st = evaluate_state(c);
+        } else {
+          st = evaluate_residual(c);
+        }
         if (st) return st;
         const double pp = h[hfe::TRI_PP], hh = h[hfe::TRI_HH];
         const double r_nr = hh > 0.0 ? std::sqrt(pp) / std::sqrt(hh) : 0.0;
@@ -1303,6 +1446,7 @@ hfe_status hfe_solve_increment_lbfgs(hfe_ctx* c, const hfe_lbfgs_params* prm, vo
                                      size_t ws_bytes, hfe_lbfgs_report* out) {
   if (!c) return HFE_EINVAL;
   if (!c->have_state) return fail(c, HFE_ESTATE, "apply a load step first");
+  if (c->ne > 0) return fail(c, HFE_EINVAL, "the L-BFGS increment runs under strain control");
   const auto t0 = std::chrono::steady_clock::now();
   hfe_lbfgs_params p;
   p.eta_eq = 1e-8; p.eta_nr = 1e-8; p.max_iters = 500; p.m = 5; p.c1 = 1e-4;

@@ -90,6 +90,13 @@ struct ElemArgs {
   Reducer red;
   CgState* cg;           // Hessian in a CG iteration: skipped once cg->done
   int brick_shape;       // brick shape of the Q1 element passes (see launch_brick)
+  // mean-stress control (Q1, FP64): U (device, 3x3) is the uniform part of the
+  // Hessian's direction, added to D v at every point, and the Hessian writes
+  // the point sums of B : (D v + U) (Voigt xx yy zz yz xz xy) to red_tail;
+  // Pu (device, 3x3) is the uniform part of the trial step. Null: none.
+  const double* U;
+  Reducer red_tail;
+  const double* Pu;
 };
 
 // Residual: f = D^T sigma(E + D u), writes a_out and cp_out (P1 pairs) or
@@ -117,6 +124,8 @@ struct HessArgs {
   Reducer red;           // rows HES_* (FP64)
   CgState* cg;           // skipped once cg->done when set
   int brick_shape;
+  const double* U;       // mean-stress control (FP64 only): as in ElemArgs, or null
+  Reducer red_tail;
 };
 // Hessian launch shapes: bricks 0..kBrickOnly-1, marching columns up to
 // kHessianShapes-1 (valid where the grid's nx, ny are multiples of the column).
@@ -208,6 +217,8 @@ struct CgFuse {
   int nb_dir;
   const double* rows_hes;   // forward pass only
   int nb_hes;
+  const double* rows_tail;  // forward pass, mean-stress control: the Hessian's rows of the
+                            // point sums of B : D d (Voigt, 6 per row), else null
   double* trace;            // forward pass only
   const R* d;
   R* z;

@@ -12,6 +12,8 @@
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
 
+#include <type_traits>
+
 namespace hfe {
 namespace {
 
@@ -1027,7 +1029,7 @@ __global__ void __launch_bounds__(BX * BY * BZ) k_trial(ElemArgs A) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           H[i][j] = A.E[3 * i + j];
-          p[i][j] = 0.0;
+          p[i][j] = A.Pu ? A.Pu[3 * i + j] : 0.0;   // the step's uniform part (mean-stress control)
         }
       tile_grad<kTile>(su, q, t0, sy, sz, H);
       tile_grad<kTile>(sv, q, t0, sy, sz, p);
@@ -1090,12 +1092,17 @@ template <typename R> constexpr int hessian_waves_per_eu() { return sizeof(R) ==
 // sum-factorised divergence into f[c][corner]. tile(c, i) reads component c
 // of staged node i; corner a = ax + 2 ay + 4 az sits at t0 + ax + ay sy + az sz.
 // dd receives sum |D v|^2 over the element's points if `owned` (else 0).
-template <typename R, bool NS, typename Tile>
+// MS (mean-stress control): the uniform U (3x3) is added to D v at every
+// point, and tv receives the element's point sums of the tangent's output
+// (Voigt xx yy zz yz xz xy) if `owned`.
+template <typename R, bool NS, bool MS = false, typename Tile>
 __device__ __forceinline__ void hess_element(const Tile& tile, int t0, int sy, int sz, R lam, R mu,
                                              const R (&aq)[8], unsigned soft,
                                              const double* __restrict__ w_e,
                                              const double* __restrict__ n_e, long long N,
-                                             R (&f)[3][8], double& dd, bool owned) {
+                                             R (&f)[3][8], double& dd, bool owned,
+                                             const double* __restrict__ U = nullptr,
+                                             double* tv = nullptr) {
   R G[3][3][2][2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1133,6 +1140,12 @@ __device__ __forceinline__ void hess_element(const Tile& tile, int t0, int sy, i
       dH[c][1] = G[c][1][gx][gz];
       dH[c][2] = G[c][2][gx][gy];
     }
+    if constexpr (MS) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dH[c][j] += (R)U[3 * c + j];
+    }
     // tau = a C : e - (w : e) w with e = sym(dH); h_ij = 2 e_ij
     const R h01 = dH[0][1] + dH[1][0], h02 = dH[0][2] + dH[2][0], h12 = dH[1][2] + dH[2][1];
     const R al = aq[q] * lam, am = aq[q] * mu;
@@ -1169,6 +1182,21 @@ __device__ __forceinline__ void hess_element(const Tile& tile, int t0, int sy, i
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) q1_div_sf(T[c], f[c]);
+  if constexpr (MS) {
+    if (owned) {
+      // sum over the 8 points of tau_ij: T[i][j] already sums along j
+      auto total = [&](int i, int j) {
+        return (double)T[i][j][0][0] + (double)T[i][j][0][1] + (double)T[i][j][1][0] +
+               (double)T[i][j][1][1];
+      };
+      tv[0] += total(0, 0);
+      tv[1] += total(1, 1);
+      tv[2] += total(2, 2);
+      tv[3] += total(1, 2);
+      tv[4] += total(0, 2);
+      tv[5] += total(0, 1);
+    }
+  }
 }
 
 // The element state the Hessian reads: phase and softening mask from the
@@ -1194,7 +1222,7 @@ __device__ __forceinline__ void hess_state(const HessArgs<R>& A, long long eg, i
 // ((f0 + f1) + f2) + f3, then the two group sums added. It is what lets the
 // column kernel carry the az = 1 sums from one layer to the next.
 
-template <typename R, int BX, int BY, int BZ, bool FULL, bool NS>
+template <typename R, int BX, int BY, int BZ, bool FULL, bool NS, bool MS>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
     k_hessian(HessArgs<R> A) {
   constexpr int kTile = BrickShape<BX, BY, BZ>::tile, kOwn = BrickShape<BX, BY, BZ>::own;
@@ -1265,12 +1293,14 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
 #pragma unroll
     for (int a = 0; a < 8; ++a) f[i][a] = R(0);
   double dd = 0.0;
+  double tv[MS ? 6 : 1] = {};
   if (active) {
     const R lam = (R)A.mat.lam[ph], mu = (R)A.mat.mu[ph];
     const int t0 = ex + tx * (ey + ty * ez);
     auto tile = [&](int c, int i) { return sv[c][i]; };
-    hess_element<R, NS>(tile, t0, tx, tx * ty, lam, mu, aq, soft, A.sw + eg,
-                        NS ? A.sn + eg : nullptr, g.N, f, dd, ex >= 1 && ey >= 1 && ez >= 1);
+    hess_element<R, NS, MS>(tile, t0, tx, tx * ty, lam, mu, aq, soft, A.sw + eg,
+                            NS ? A.sn + eg : nullptr, g.N, f, dd, ex >= 1 && ey >= 1 && ez >= 1,
+                            A.U, tv);
   }
   // Assembly. Every owned node adds the forces of its 8 elements in the
   // fixed order of corner_sum (the same for every Hessian kernel). The
@@ -1320,6 +1350,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   red[HES_DKD] = dkd;
   red[HES_DD] = dd;
   block_reduce_store<HES_NV>(red, A.red.partials);
+  if constexpr (MS) block_reduce_store<6>(tv, A.red_tail.partials);
 }
 
 // ---- column-marching Hessian (Q1) -----------------------------------------
@@ -1346,7 +1377,7 @@ template <int CX, int CY> struct ColumnShape {
   static constexpr int pre = (layer + threads - 1) / threads;
 };
 
-template <typename R, int CX, int CY, bool NS>
+template <typename R, int CX, int CY, bool NS, bool MS>
 __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_per_eu<R>())
     k_hessian_col(HessArgs<R> A, int bz) {
   using S = ColumnShape<CX, CY>;
@@ -1412,6 +1443,7 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
   __syncthreads();
   R top[3] = {R(0), R(0), R(0)};        // az = 1 sums of the layer below, for node layer k
   double dkd = 0.0, dd = 0.0;
+  double tv[MS ? 6 : 1] = {};
   for (int k = 0; k <= nzl; ++k) {
     // element layer k: nodes k (bottom) and k + 1 (top); this step's loads
     // ahead of the arithmetic: node layer k + 2 and the next mask word
@@ -1438,8 +1470,9 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
       const int sz = (k & 1) ? -S::layer : S::layer;       // to the other ring slot
       auto tile = [&](int c, int i) { return (&sv[c][0][0])[i]; };
       double de = 0.0;
-      hess_element<R, NS>(tile, t0, S::tx, sz, lam, mu, aq, soft, A.sw + eg,
-                          NS ? A.sn + eg : nullptr, N, f, de, k >= 1 && ex >= 1 && ey >= 1);
+      hess_element<R, NS, MS>(tile, t0, S::tx, sz, lam, mu, aq, soft, A.sw + eg,
+                              NS ? A.sn + eg : nullptr, N, f, de, k >= 1 && ex >= 1 && ey >= 1,
+                              A.U, tv);
       dd += de;
 #pragma unroll
       for (int a = 0; a < 8; ++a)
@@ -1481,6 +1514,7 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
   red[HES_DKD] = dkd;
   red[HES_DD] = dd;
   block_reduce_store<HES_NV>(red, A.red.partials);
+  if constexpr (MS) block_reduce_store<6>(tv, A.red_tail.partials);
 }
 
 template <int MODE, int NV, int BX, int BY, int BZ>
@@ -1514,12 +1548,25 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
   *nblocks = nb;
   const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
   const dim3 grid(nb), block(BrickShape<BX, BY, BZ>::threads);
+  if constexpr (std::is_same<R, double>::value) {
+    if (A.U) {
+      // mean-stress control: whole and ragged bricks of either law
+      if (A.tens) {
+        if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true, true>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true, true>), grid, block, 0, s, A);
+      } else {
+        if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false, true>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false, true>), grid, block, 0, s, A);
+      }
+      return hipGetLastError();
+    }
+  }
   if (A.tens) {
-    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true>), grid, block, 0, s, A);
+    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true, false>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true, false>), grid, block, 0, s, A);
   } else {
-    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false>), grid, block, 0, s, A);
+    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false, false>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false, false>), grid, block, 0, s, A);
   }
   return hipGetLastError();
 }
@@ -1538,8 +1585,15 @@ hipError_t launch_hessian_col(const HessArgs<R>& A, int bz, hipStream_t s, int* 
   const int nb = (g.nx / CX) * (g.ny / CY) * ((g.nz + bz - 1) / bz);
   *nblocks = nb;
   const dim3 grid(nb), block(ColumnShape<CX, CY>::threads);
-  if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true>), grid, block, 0, s, A, bz);
-  else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false>), grid, block, 0, s, A, bz);
+  if constexpr (std::is_same<R, double>::value) {
+    if (A.U) {
+      if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true, true>), grid, block, 0, s, A, bz);
+      else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false, true>), grid, block, 0, s, A, bz);
+      return hipGetLastError();
+    }
+  }
+  if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true, false>), grid, block, 0, s, A, bz);
+  else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false, false>), grid, block, 0, s, A, bz);
   return hipGetLastError();
 }
 
@@ -1552,7 +1606,7 @@ hipError_t launch_hessian_col(const HessArgs<R>& A, int bz, hipStream_t s, int* 
 template <typename R>
 hipError_t launch_hessian_brick(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
   if (!A.v || !A.f || !A.a || !A.sw || !A.emask || !A.E || !A.red.partials ||
-      (A.tens && !A.sn))
+      (A.tens && !A.sn) || (A.U && !A.red_tail.partials))
     return hipErrorInvalidValue;
   if (A.brick_shape >= kBrickOnly) {
     if (A.brick_shape >= kHessianShapes) return hipErrorInvalidValue;
@@ -1622,6 +1676,8 @@ hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks) {
   H.mat = A.mat;
   H.E = A.E;
   H.emask = A.emask;
+  H.U = A.U;
+  H.red_tail = A.red_tail;
   H.sw = A.sw;
   H.sn = A.sn;
   H.tens = A.tens;

@@ -354,14 +354,16 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   if constexpr (MODE == PLANE_FWD_CG) {
     if (!cf.st_in->done) {
       load_round(0);
-      double td[2], tc[2];
+      double td[2], tc[2], tt[6];
       block_sum_rows<2>(cf.rows_dir, cf.nb_dir, td);
       block_sum_rows<2>(cf.rows_hes, cf.nb_hes, tc);
+      if (cf.rows_tail) block_sum_rows<6>(cf.rows_tail, cf.nb_hes, tt);
       if (tid == 0) {
         const bool first = blockIdx.x == 0 && blockIdx.y == 0;
         sst = *cf.st_in;
         cg_decide_direction(&sst, td[0], td[1]);
-        cg_decide_curvature(&sst, first ? cf.trace : nullptr, tc[0], tc[1]);
+        cg_decide_curvature(&sst, first ? cf.trace : nullptr, tc[0], tc[1],
+                            cf.rows_tail ? tt : nullptr);
       }
     } else if (tid == 0) {
       sst = *cf.st_in;

@@ -132,6 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restric
       if (threadIdx.x == 0) {
         sst = *st;
         cg_decide_residual(&sst, blockIdx.x == 0 ? trace : nullptr, t[0], t[1]);
+        cg_tail_direction(&sst);
       }
     } else if (threadIdx.x == 0) {
       sst = *st;

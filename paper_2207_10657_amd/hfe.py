@@ -73,7 +73,8 @@ LBFGS_DEFAULTS = {"eta_eq": 1e-8, "eta_nr": 1e-8, "max_iters": 500, "m": 5, "c1"
 class _Record(ctypes.Structure):
     _fields_ = [("flag", ctypes.c_int), ("cg_iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("accepted", ctypes.c_int), ("dm", ctypes.c_double), ("dW", ctypes.c_double),
-                ("rho", ctypes.c_double), ("R_before", ctypes.c_double)]
+                ("rho", ctypes.c_double), ("R_before", ctypes.c_double),
+                ("p_norm", ctypes.c_double)]
 
 
 EXPORTS = {
@@ -106,6 +107,7 @@ EXPORTS = {
     "hfe_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
     "hfe_set_eigenstrain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "hfe_set_mean_stress_control": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     # learned warm start (paper_2207_10657_amd.warmstart)
     "hfe_nn_conv3d": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -349,6 +351,20 @@ class Solver:
         a = np.ascontiguousarray(np.asarray(eig, dtype=np.float64).reshape(3, 3))
         self._check(self.lib.hfe_set_eigenstrain(self.ctx, int(phase),
                                                  a.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_mean_stress_control(self, free):
+        """Free macroscopic strain components with zero mean stress: a
+        symmetric boolean 3x3 (or an int mask, Voigt bits xx yy zz yz xz xy)."""
+        if isinstance(free, (int, np.integer)):
+            mask = int(free)
+        else:
+            f = np.asarray(free, dtype=bool).reshape(3, 3)
+            f = f | f.T
+            mask = 0
+            for v, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))):
+                if f[i, j]:
+                    mask |= 1 << v
+        self._check(self.lib.hfe_set_mean_stress_control(self.ctx, mask))
 
     # -- Algorithm 2 -----------------------------------------------------
     def apply_load_step(self, dE):

@@ -140,6 +140,80 @@ def test_batch_of_uneven_cells_matches_single_solves():
         s.close()
 
 
+def test_batch_of_uneven_cells_against_the_oracle():
+    """A batch of cells of uneven sizes (8^3, 12^3, 16^3 and a 8x12x16 box of
+    the workload recipe), each under its own unit load case, two increments
+    solved with hfe_solve_batch, each cell against its own oracle: the same
+    Newton decisions and the homogenized stress at 1e-10 of the load scale,
+    the damage at 1e-10 (Sec. 3.3's stiffness cells, strain control)."""
+    require_gpu()
+    announce("batch of uneven cells vs the oracle")
+    from oracle.solver import CellSolver
+    from paper_2207_10657_amd import Solver, solve_batch
+    from synthetic import inclusion_microstructure
+    cases = _load_cases(2e-4)
+    w16 = workload("c1_3d16")
+    shapes = [(8, 8, 8), (12, 12, 12), (16, 16, 16), (8, 12, 16)]
+    cells = []
+    for k, shape in enumerate(shapes):
+        n = max(shape)
+        phase = inclusion_microstructure(shape, 4.0 * n / 64, 8.0 * n / 64, 0.25, 31 + k)[0]
+        cells.append((shape, phase, cases[(2 * k + 1) % 6]))
+    batch = [Solver(sh, "q1", own_stream=True) for sh, _, _ in cells]
+    oracles = [CellSolver(ph, w16.materials, "q1") for _, ph, _ in cells]
+    for s, (_, ph, _) in zip(batch, cells):
+        s.setup(ph, w16.materials)
+    for step in range(2):
+        for s, o, (_, _, dE) in zip(batch, oracles, cells):
+            s.apply_load_step(dE)
+            o.apply_load_step(dE)
+        reps = solve_batch(batch)
+        for k, (s, o, r) in enumerate(zip(batch, oracles, reps)):
+            ro = o.solve_increment()
+            assert [x["flag"] for x in s.newton_log()] == ro["flags"], (step, k)
+            assert [x["cg_iters"] for x in s.newton_log()] == ro["cg_per_newton"], (step, k)
+            assert r["converged"] == ro["converged"]
+            lam, mu = 10.0 * 0.3 / (1.3 * 0.4), 10.0 / 2.6
+            scale = np.linalg.norm(lam * np.trace(o.E) * np.eye(3) + 2 * mu * o.E)
+            dS = np.linalg.norm(s.homogenized_stress() - o.homogenized_stress()) / scale
+            dd = float(np.abs(s.damage() - o.damage()).max())
+            print("[batch] cell %s step %d: Newton %d, |dSigma|/scale %.2e, damage %.2e"
+                  % (cells[k][0], step, r["newton_iters"], dS, dd), flush=True)
+            assert dS < 1e-10 and dd < 1e-10, (step, k, dS, dd)
+
+
+@pytest.mark.parametrize("n", [48, 96])
+def test_projected_hessian_48_and_96_against_the_displacement_oracle(n):
+    """The cell sizes of uneven batches with radix-3 FFT lengths (48 = 16 x 3,
+    96 = 32 x 3): one projected-Hessian application at a softening state
+    against the displacement-space oracle (oracle/uspace.py, itself pinned to
+    the strain-space projector), element by element at 1e-12."""
+    torch = require_gpu()
+    announce("projected hessian vs displacement oracle", n)
+    from oracle import material
+    from oracle.uspace import UOperator
+    from paper_2207_10657_amd import Solver
+    from tests.gpu_util import max_err
+    w = workload("c1_3d%d" % n)
+    rng = np.random.default_rng(12)
+    u = 4e-4 * rng.normal(size=(3,) + w.shape)
+    E = np.zeros((3, 3))
+    E[0, 0] = 2e-3
+    s = Solver(w.shape, "q1")
+    s.setup(w.phase, w.materials)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    d = rng.normal(size=(3,) + w.shape)
+    out = s.apply_projected_hessian(torch.tensor(d, device="cuda"))[0].cpu().numpy()
+    s.close()
+    kh = material.MaterialField(w.phase, w.materials, 8).initial_history()
+    ref = UOperator(w.phase, w.materials, "q1", E, u, kh).apply(d)
+    err = max_err(out, ref)
+    print("[batch] %d^3 projected Hessian vs displacement oracle: max err %.2e" % (n, err),
+          flush=True)
+    assert err < 1e-12
+
+
 # ---- effective stiffness (six unit load cases as one batch) -------------------
 
 VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))

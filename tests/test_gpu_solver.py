@@ -359,3 +359,30 @@ def test_eigenstrain_laminate_on_gpu():
     S = g.homogenized_stress()
     assert abs(S[0, 0] - sxx) < 1e-10 * abs(syy)
     assert abs(S[1, 1] - syy) < 1e-10 * abs(syy) and abs(S[2, 2] - syy) < 1e-10 * abs(syy)
+
+
+def test_step_norm_recurrences_at_64cubed():
+    """The CG of Algorithm 1 tracks ||z||^2 and <z, d> in displacement
+    coordinates by recurrences (no stencil pass); the trust-region exits put
+    the step on ||p|| = R with them. On the 64^3 workload's damage-onset
+    load steps (hundreds of boundary exits at a growing iteration count),
+    the step norm the trial pass sums directly over the 2,097,152 points
+    must equal R at every boundary and negative-curvature exit to 1e-10."""
+    require_gpu()
+    from paper_2207_10657_amd import Solver
+    w = workload("c1_3d64", steps=4)
+    s = Solver(w.shape, w.element)
+    s.setup(w.phase, w.materials)
+    worst, exits = 0.0, 0
+    for n, dE in enumerate(w.load_path):
+        announce("step norm recurrences 64^3, step", n)
+        s.apply_load_step(dE)
+        s.solve_increment({"i_nr_max": 60})
+        for r in s.newton_log():
+            if r["flag"] in (2, 3):
+                exits += 1
+                worst = max(worst, abs(r["p_norm"] - r["R_before"]) / r["R_before"])
+    print("[recurrence] 64^3: %d exits on the sphere, max | ||p|| - R | / R = %.2e" % (exits, worst),
+          flush=True)
+    assert exits >= 20
+    assert worst < 1e-10

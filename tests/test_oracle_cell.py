@@ -385,3 +385,24 @@ def test_oracle_eigenstrain_laminate_closed_form():
     assert abs(S[0, 0] - sxx) < 1e-10 * scale
     assert abs(S[1, 1] - syy) < 1e-10 * scale and abs(S[2, 2] - syy) < 1e-10 * scale
     assert np.abs(S - np.diag(np.diag(S))).max() < 1e-10 * scale
+
+
+def test_oracle_restore_continues_the_path():
+    """checkpoint() / restore() resume a load path: the steps after a restore
+    reach the results of the uninterrupted run (the displacement is recovered
+    through the Green's function, so to rounding)."""
+    from synthetic import workload
+    w = workload("c1_3d8", steps=3)
+    a = CellSolver(w.phase, w.materials, "q1")
+    for dE in w.load_path[:2]:
+        a.apply_load_step(dE)
+        a.solve_increment()
+    ck = a.checkpoint()
+    b = CellSolver(w.phase, w.materials, "q1")
+    b.restore(ck)
+    for s in (a, b):
+        s.apply_load_step(w.load_path[2])
+        assert s.solve_increment()["converged"]
+    Sa, Sb = a.homogenized_stress(), b.homogenized_stress()
+    assert np.linalg.norm(Sa - Sb) <= 1e-10 * np.linalg.norm(Sa)
+    assert np.max(np.abs(a.damage() - b.damage())) <= 1e-10
