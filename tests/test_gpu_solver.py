@@ -210,9 +210,17 @@ def test_free_running_2d_workload_full_path():
 
 
 def test_lockstep_3d_workload_16():
-    """3D Q1 inclusion cell at 16^3, first 10 steps of the 0.6% path."""
+    """3D Q1 inclusion cell at 16^3, first 5 steps of the 0.6% path (through
+    the damage onset; the later steps take the oracle minutes each)."""
     require_gpu()
-    _lockstep("c1_3d16", 10)
+    _lockstep("c1_3d16", 5)
+
+
+def test_lockstep_3d_workload_8_into_full_damage():
+    """The same cell at 8^3, first 15 steps: the damage reaches 1 at step 3
+    and the later steps solve the cracked cell with long CG runs."""
+    require_gpu()
+    _lockstep("c1_3d8", 15)
 
 
 def test_lockstep_3d_workload_16_solved_to_tolerance():
