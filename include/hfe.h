@@ -436,6 +436,19 @@ hfe_status hfe_nn_conv3d_backward_weights(const float* gout, int cout, const flo
 size_t hfe_nn_mse_partials(long long n);
 hfe_status hfe_nn_mse(const float* pred, const float* target, long long n, float* grad,
                       double* partials, double* loss, void* stream);
+/* hfe_nn_mse for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the partial sums in a
+ * library-owned array of 4096 doubles (32 KiB) per device, held until the
+ * process ends; any n >= 1 fits (the loss kernel's grid never exceeds 4096
+ * blocks). No allocation of any kind. The first call on a device resolves the
+ * array's address (do not make that first call inside a graph capture).
+ * Every call on a device shares the array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Each call rewrites every row it reads. HFE_EINVAL for null pointers or
+ * n < 1, HFE_EDEVICE if the address or a launch fails. */
+hfe_status hfe_nn_mse_noalloc(const float* pred, const float* target, long long n, float* grad,
+                              double* loss, void* stream);
 /* One Adam step (step = 1, 2, ...) on FP32 master weights w with moments m,
  * v; writes the BF16 copy when w_bf16 is not NULL. */
 hfe_status hfe_nn_adam(float* w, float* m, float* v, const float* g, long long n, float lr,

@@ -14,6 +14,7 @@
 // a fixed order, so training runs give the same bits every time.
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <mutex>
 
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
@@ -324,9 +325,11 @@ hipError_t conv_bwd_data_cin(int cout, const float* g, const float* act, const u
   }
 }
 
+constexpr int kGridMax = 4096;      // blocks of a grid-stride 1D launch
+
 int grid_1d(long long n) {
   long long b = (n + kNnBlock - 1) / kNnBlock;
-  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+  return (int)(b < 1 ? 1 : (b > kGridMax ? kGridMax : b));
 }
 
 bool dims_ok(const int n[3]) { return n && n[0] >= 1 && n[1] >= 1 && n[2] >= 1; }
@@ -335,6 +338,36 @@ bool dims_ok(const int n[3]) { return n && n[0] >= 1 && n[1] >= 1 && n[2] >= 1; 
 }  // namespace hfe
 
 using namespace hfe;
+
+// Library-owned scratch of hfe_nn_mse_noalloc: one row of partial sums per
+// block of the loss kernel, whose grid never exceeds kGridMax blocks, so the
+// array fits every n (32 KiB per device, held until the process ends). Host
+// code uses the per-device address from hipGetSymbolAddress, never the
+// array's name.
+static __device__ __align__(256) double scratch[kGridMax];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, resolved once per device.
+hipError_t scratch_rows(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
 
 extern "C" {
 
@@ -386,6 +419,22 @@ hfe_status hfe_nn_conv3d_backward_weights(const float* gout, int cout, const flo
 }
 
 size_t hfe_nn_mse_partials(long long n) { return (size_t)grid_1d(n); }
+
+hfe_status hfe_nn_mse_noalloc(const float* pred, const float* target, long long n, float* grad,
+                              double* loss, void* stream) {
+  if (!pred || !target || !grad || !loss || n < 1) return HFE_EINVAL;
+  const int nb = grid_1d(n);
+  static_assert(sizeof(scratch) / sizeof(double) >= (size_t)kGridMax, "scratch holds every row");
+  if (nb > kGridMax) return HFE_EINVAL;
+  double* rows = nullptr;
+  if (scratch_rows(&rows) != hipSuccess) return HFE_EDEVICE;
+  // every row the sum reads is written by this call's first kernel: nothing
+  // to clear between calls
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kNnBlock), 0, (hipStream_t)stream, pred, target, n, grad,
+                     rows);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kNnBlock), 0, (hipStream_t)stream, rows, nb, n, loss);
+  return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+}
 
 hfe_status hfe_nn_mse(const float* pred, const float* target, long long n, float* grad,
                       double* partials, double* loss, void* stream) {

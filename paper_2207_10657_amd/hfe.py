@@ -123,6 +123,8 @@ EXPORTS = {
                                                       ctypes.c_void_p, ctypes.c_void_p,
                                                       ctypes.c_void_p]),
     "hfe_nn_mse_partials": (ctypes.c_size_t, [ctypes.c_longlong]),
+    "hfe_nn_mse_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hfe_nn_mse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
