@@ -652,6 +652,9 @@ def main():
                     help="skip the Hessian-alone line at 64^3 and 128^3")
     ap.add_argument("--no-tensile", action="store_true",
                     help="skip the tensile-masking law (Appendix A) line")
+    ap.add_argument("--stall-study", action="store_true",
+                    help="also run the timed steps with the CG stall exit in both precisions "
+                         "(minutes: the exit leaves Newton steps unconverged)")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the learned warm-start run (16^3 cells)")
     ap.add_argument("--probe", action="store_true",
@@ -703,7 +706,7 @@ def main():
     tuning = s.autotune()
     ck = s.get_state()
 
-    detail, sigmas, step_s, states = [], [], [], []
+    detail, sigmas, step_s, states, damages = [], [], [], [], []
 
     def record(rep):
         return {k: rep[k] for k in ("newton_iters", "rejected", "cg_iters", "restarts",
@@ -729,6 +732,7 @@ def main():
             detail.append(record(rep))
             sigmas.append(s.homogenized_stress())
             if keep_states:
+                damages.append(s.damage())
                 progress("replay step %d: Newton %d, CG %d" % (n, rep["newton_iters"], rep["cg_iters"]))
         return matvecs, newton, cg, converged
 
@@ -736,7 +740,7 @@ def main():
         """Each timed load step once more, each from the FP64 state before it
         (restarts are bit-exact): per step its time and result, and the
         homogenized stress against the FP64 step from the same state."""
-        per, errs, mv, secs = [], [], 0, 0.0
+        per, errs, ddmg, mv, secs = [], [], [], 0, 0.0
         for j, st in enumerate(states):
             s.set_state(st["u"], st["kappa_hist"], st["E"], st["R"], st["Rmax"])
             torch.cuda.synchronize()
@@ -748,6 +752,7 @@ def main():
             per.append(record(rep))
             S = s.homogenized_stress()
             errs.append(float(np.linalg.norm(S - sig64[j]) / max(np.linalg.norm(sig64[j]), 1e-300)))
+            ddmg.append(float(np.abs(s.damage() - damages[j]).max()))
             progress("%s step %d: Newton %d, CG %d, %.2f s, stress error %.1e"
                      % (label, W + j, rep["newton_iters"], rep["cg_iters"],
                         time.perf_counter() - ts, errs[-1]))
@@ -762,6 +767,7 @@ def main():
                 "unconverged_steps": unconverged,
                 "sigma_rel_err_vs_fp64_same_state": errs,
                 "sigma_rel_err_max": max(errs) if errs else None,
+                "damage_max_diff_vs_fp64_same_state": ddmg,
                 "per_step": per}
 
     progress("setup and autotuning done")
@@ -822,14 +828,28 @@ def main():
                          "the FP64 solve of the same step from the same state (the FP64 path is "
                          "checked against the oracle); bound %.0e" % MIXED_SIGMA_BOUND)
         mixed["within_bound"] = bool(mixed["sigma_rel_err_max"] <= MIXED_SIGMA_BOUND)
-        stall = {"window": STALL_WINDOW,
-                 "fp64": from_states(dict(SOLVE, cg_stall=STALL_WINDOW), "fp64 stall"),
-                 "mixed": from_states(dict(SOLVE, precision="mixed", cg_stall=STALL_WINDOW),
-                                      "mixed stall"),
-                 "note": "the CG returns its iterate once its residual has not halved in "
-                         "`window` iterations (an exit this library adds to Algorithm 1; off "
-                         "by default); each step from the FP64 state before it"}
-        progress("mixed precision and stall exit done")
+        # a step over the bound where both solves meet the FP64 equilibrium
+        # test (the mixed path evaluates residual and r_eq in FP64) ended at
+        # two equilibria of the same softening increment
+        over = []
+        for j, e in enumerate(mixed["sigma_rel_err_vs_fp64_same_state"]):
+            if e > MIXED_SIGMA_BOUND:
+                over.append({"step": W + j, "sigma_rel_err": e,
+                             "damage_max_diff": mixed["damage_max_diff_vs_fp64_same_state"][j],
+                             "r_eq_mixed": mixed["per_step"][j]["r_eq"],
+                             "r_eq_fp64": step_detail[j]["r_eq"],
+                             "both_converged": bool(mixed["per_step"][j]["converged"]
+                                                    and step_detail[j]["converged"])})
+        mixed["steps_over_bound"] = over
+        if args.stall_study:
+            stall = {"window": STALL_WINDOW,
+                     "fp64": from_states(dict(SOLVE, cg_stall=STALL_WINDOW), "fp64 stall"),
+                     "mixed": from_states(dict(SOLVE, precision="mixed", cg_stall=STALL_WINDOW),
+                                          "mixed stall"),
+                     "note": "the CG returns its iterate once its residual has not halved in "
+                             "`window` iterations (an exit this library adds to Algorithm 1; "
+                             "off by default); each step from the FP64 state before it"}
+        progress("mixed precision done")
 
     # the paper's quasi-Newton remark: the first LBFGS_STEPS timed increments
     # from the same checkpoint by L-BFGS on the approximate energy increment
@@ -904,7 +924,7 @@ def main():
                                     "a time per 50 Newton iterations where a step does not "
                                     "converge"},
         "mixed_precision": mixed,
-        "cg_stall_exit": stall,
+        "cg_stall_exit": stall if stall is not None else "not run (bench.py --stall-study)",
         "lbfgs": lbfgs,
     }
     if not args.no_batch:

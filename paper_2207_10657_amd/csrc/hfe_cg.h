@@ -51,6 +51,18 @@ struct CgState {
   int trace_cap;            // capacity of the trace (entries)
 };
 
+// Copy a CgState between global memory and LDS with the block's lanes, one
+// 4-byte word each: copied by one lane, the whole struct (about 130 words)
+// would pass through that lane's registers and push the kernel into spills.
+// The caller's next barrier completes it.
+__device__ __forceinline__ void copy_state_block(CgState* dst, const CgState* src) {
+  static_assert(sizeof(CgState) % 4 == 0, "CgState is copied in 4-byte words");
+  constexpr int kWords = (int)(sizeof(CgState) / 4);
+  const unsigned* s = reinterpret_cast<const unsigned*>(src);
+  unsigned* d = reinterpret_cast<unsigned*>(dst);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) d[i] = s[i];
+}
+
 // Roots of ||z + t d||^2 = R^2 with ||z|| < R, without cancellation.
 __device__ __forceinline__ void cg_roots(double zz, double zd, double dd, double R, double* tm,
                                          double* tp) {

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   const int npairs = M * ny;   // the plane's reals in pairs (x even, x odd)
   // The fused CG passes read vectors of the plane that do not depend on the
   // decisions or on the transform: their first kPre pairs per thread are
-  // loaded before the row sums (forward) or the spectrum (inverse), so that
+  // loaded before the decisions (forward) or the spectrum (inverse), so that
   // these memory latencies overlap.
   constexpr int kPre = 4;
   constexpr bool kFused = MODE == PLANE_FWD_CG || MODE == PLANE_INV_CG;
@@ -352,24 +352,26 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   // rows in the same order, so all copies agree); the inverse pass reads it
   __shared__ CgState sst;
   if constexpr (MODE == PLANE_FWD_CG) {
-    if (!cf.st_in->done) {
-      load_round(0);
+    const bool run = !cf.st_in->done;
+    copy_state_block(&sst, cf.st_in);
+    if (run) {
+      // (the barriers of the row sums complete the copy)
       double td[2], tc[2], tt[6];
       block_sum_rows<2>(cf.rows_dir, cf.nb_dir, td);
       block_sum_rows<2>(cf.rows_hes, cf.nb_hes, tc);
       if (cf.rows_tail) block_sum_rows<6>(cf.rows_tail, cf.nb_hes, tt);
+      // the plane's vectors are in flight while one lane takes the decisions
+      // (issued after the row sums, whose unrolled loads need the registers)
+      load_round(0);
       if (tid == 0) {
         const bool first = blockIdx.x == 0 && blockIdx.y == 0;
-        sst = *cf.st_in;
         cg_decide_direction(&sst, td[0], td[1]);
         cg_decide_curvature(&sst, first ? cf.trace : nullptr, tc[0], tc[1],
                             cf.rows_tail ? tt : nullptr);
       }
-    } else if (tid == 0) {
-      sst = *cf.st_in;
     }
     __syncthreads();
-    if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) *cf.st_out = sst;
+    if (blockIdx.x == 0 && blockIdx.y == 0) copy_state_block(cf.st_out, &sst);
     if (sst.done) {
       // the CG stopped on the trust-region sphere in this iteration: p = z + tau d
       if (sst.apply_tau && !cf.st_in->done) {

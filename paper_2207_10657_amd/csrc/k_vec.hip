@@ -125,25 +125,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_d(long long n, const R* __restric
     }
   };
   if (!st->done) load_round(first);
+  copy_state_block(&sst, st);
+  __syncthreads();
   if (rows_res) {
-    if (!st->done) {
+    if (!sst.done) {
       double t[2];
       block_sum_rows<2>(rows_res, nb_res, t);
       if (threadIdx.x == 0) {
-        sst = *st;
         cg_decide_residual(&sst, blockIdx.x == 0 ? trace : nullptr, t[0], t[1]);
         cg_tail_direction(&sst);
       }
     } else if (threadIdx.x == 0) {
-      sst = *st;
       sst.apply_tau = 0;   // the exit step was formed by the forward plane pass
     }
     __syncthreads();
-    if (threadIdx.x == 0 && blockIdx.x == 0) *st_out = sst;
-  } else if (threadIdx.x == 0) {
-    sst = *st;
+    if (blockIdx.x == 0) copy_state_block(st_out, &sst);
   }
-  __syncthreads();
   if (sst.done) return;
   const R beta = (R)sst.beta;
   double acc[2] = {0.0, 0.0};
