@@ -251,56 +251,104 @@ def batch_bench(w, steps):
             "same_results_as_sequential": bool(same and mv_seq == mv_bat),
             "autotuned_launch": tuned}
 
-def uneven_batch_bench(sizes=(32, 48, 64, 96), per_size=2, steps=1):
-    """Many cells of uneven sizes (the recipe's seeds 11, 12, ... at each size,
-    `per_size` cells per size), each under the six unit load cases: one
-    increment of 2e-4 solved one context after the other, then as one batch
-    (one context per cell and case, each on its own stream), from the same
-    states. Launch shapes stay at the library's defaults."""
+VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+
+
+def population_batch_bench(n_cells=64, sizes=(32, 48, 64, 96), strain=1e-4, seed=2207,
+                           log=None):
+    """A population of cells of uneven sizes, each under the six unit load
+    cases: n_cells cells of the 3D recipe (vf 0.25, radii 4-8 voxels scaled
+    with the grid, microstructure seed 3000 + i), sizes drawn uniformly from
+    `sizes` by `seed`; per cell the increment `strain` along each Voigt
+    direction (xx, yy, zz, yz, xz, xy; engineering shears) from the fresh
+    state, 6 n_cells solves, and the cell's effective stiffness
+    C_IJ = Sigma_I / strain_J. Six contexts per size (each on its own stream)
+    serve all cells of that size. Batched: one cell per size at a time, its
+    6 solves and those of the other sizes' cells in one hfe_solve_batch call
+    (up to 6 len(sizes) solves); sequential: the same solves one context at
+    a time. Times count the solves only (not setup), and both runs must give
+    the same bits."""
     import torch
     from paper_2207_10657_amd import Solver, solve_batch
     from synthetic import inclusion_microstructure, MATRIX_DAMAGE, INCLUSION_ELASTIC
     mats = [dict(MATRIX_DAMAGE), dict(INCLUSION_ELASTIC)]
-    cases = unit_load_cases(2e-4)
-    jobs = []
-    seed = 11
-    for n in sizes:
-        for _ in range(per_size):
-            phase = inclusion_microstructure((n, n, n), 4.0 * n / 64, 8.0 * n / 64, 0.25, seed)[0]
-            seed += 1
-            for dE in cases:
-                s = Solver(phase.shape, "q1", own_stream=True)
-                s.setup(phase, mats)
-                jobs.append((s, dE, phase.size))
-    cks = [s.get_state() for s, _, _ in jobs]
+    draw = np.random.default_rng(seed).integers(0, len(sizes), n_cells)
+    cells = [(sizes[k], 3000 + i) for i, k in enumerate(draw)]
+    pool = {n: [Solver((n, n, n), "q1", own_stream=True) for _ in range(6)] for n in sizes}
+    cases = []
+    for (i, j) in VOIGT:
+        dE = np.zeros((3, 3))
+        dE[i, j] = dE[j, i] = strain if i == j else strain / 2
+        cases.append(dE)
+
+    def phase_of(n, sd):
+        return inclusion_microstructure((n, n, n), 4.0 * n / 64, 8.0 * n / 64, 0.25, sd)[0]
+
+    def prepare(group):
+        for n, sd in group:
+            ph = phase_of(n, sd)
+            for s, dE in zip(pool[n], cases):
+                s.setup(ph, mats)
+                s.apply_load_step(dE)
+
+    def stiffness_of(n):
+        C = np.zeros((6, 6))
+        for J, s in enumerate(pool[n]):
+            S = s.homogenized_stress()
+            for I, (i, j) in enumerate(VOIGT):
+                C[I, J] = S[i, j] / strain
+        return C
 
     def run(batched):
-        vm = 0.0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            for s, dE, _ in jobs:
-                s.apply_load_step(dE)
-            solvers = [s for s, _, _ in jobs]
+        by_size = {n: [c for c in cells if c[0] == n] for n in sizes}
+        rounds = []
+        while any(by_size.values()):
+            rounds.append([by_size[n].pop(0) for n in sizes if by_size[n]])
+        if not batched:
+            rounds = [[c] for r in rounds for c in r]
+        secs, vm, conv, Cs = 0.0, 0.0, 0, {}
+        for r in rounds:
+            prepare(r)
+            solvers = [s for n, _ in r for s in pool[n]]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             reps = solve_batch(solvers) if batched else [s.solve_increment() for s in solvers]
-            vm += sum(r["matvecs"] * nv for r, (_, _, nv) in zip(reps, jobs))
-        torch.cuda.synchronize()
-        return vm, time.perf_counter() - t0, reps
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            vm += sum(rep["matvecs"] * int(np.prod(s.shape)) for rep, s in zip(reps, solvers))
+            conv += sum(int(rep["converged"]) for rep in reps)
+            for n, sd in r:
+                Cs[sd] = stiffness_of(n)
+            if log:
+                log("population %s: %d cells done" % ("batch" if batched else "one by one",
+                                                      len(Cs)))
+        return secs, vm, conv, Cs
 
-    vm_seq, dt_seq, reps = run(False)
-    out_seq = [s.homogenized_stress() for s, _, _ in jobs]
-    for (s, _, _), ck in zip(jobs, cks):
-        s.set_state(ck["u"], ck["kappa_hist"], ck["E"], ck["R"], ck["Rmax"])
-    vm_bat, dt_bat, _ = run(True)
-    same = all(np.array_equal(a, s.homogenized_stress()) for a, (s, _, _) in zip(out_seq, jobs))
-    for s, _, _ in jobs:
-        s.close()
-    return {"cells": len(sizes) * per_size, "sizes": list(sizes), "solves": len(jobs),
-            "converged": sum(int(r["converged"]) for r in reps),
-            "sequential": {"value": vm_seq / dt_seq / 1e9, "ms": dt_seq * 1e3},
+    dt_seq, vm_seq, conv_seq, C_seq = run(False)
+    dt_bat, vm_bat, conv_bat, C_bat = run(True)
+    for ss in pool.values():
+        for s in ss:
+            s.close()
+    same = all(np.array_equal(C_seq[k], C_bat[k]) for k in C_seq)
+    per_size = {}
+    for n in sizes:
+        Cn = [C_bat[sd] for m, sd in cells if m == n]
+        if Cn:
+            per_size["%d^3" % n] = {"cells": len(Cn),
+                                    "C11_mean": float(np.mean([C[0, 0] for C in Cn])),
+                                    "C44_mean": float(np.mean([C[3, 3] for C in Cn])),
+                                    "C11_spread": float(np.std([C[0, 0] for C in Cn]))}
+    return {"cells": n_cells, "sizes": list(sizes), "solves": 6 * n_cells,
+            "converged": conv_bat,
+            "sequential": {"value": vm_seq / dt_seq / 1e9, "ms": dt_seq * 1e3,
+                           "converged": conv_seq},
             "batched": {"value": vm_bat / dt_bat / 1e9, "ms": dt_bat * 1e3},
             "unit": "Gvoxel-matvec/s", "speedup": dt_seq / dt_bat,
-            "same_results_as_sequential": bool(same)}
+            "same_results_as_sequential": bool(same and vm_seq == vm_bat),
+            "effective_stiffness": per_size,
+            "note": "increment %.0e from the fresh cell along each Voigt direction; C from the "
+                    "homogenized stress; solve time only (context setup excluded); launch "
+                    "shapes at the library's defaults" % strain}
 
 
 # Counter summaries written by `--pmc-summary` (one per grid); read back for
@@ -327,7 +375,7 @@ PMC_KERNELS = [("k_hessian<double,", "stiffness"), ("k_hessian_col<double,", "st
                ("k_plane<1,double>", "fft_plane_inv"), ("copyBuffer", "copy")]
 PROBE_REPS = 5
 LBFGS_STEPS = 2
-PROBE_STEPS = 3
+PROBE_STEPS = 2
 # Hessian launch shapes by tuning index: bricks of nodes (x, y, z), and
 # marching columns of CX x CY nodes over BZ node layers (cx, cy, bz)
 BRICKS = {0: (8, 8, 4), 1: (8, 8, 8), 2: (16, 8, 4), 3: (16, 4, 4), 4: (8, 4, 4)}
@@ -438,10 +486,10 @@ def hessian_scaling(grids=(64, 128), launches=50):
                     "launch_shapes": tuning}
 
         res = {}
-        for k in range(2):
+        for k in range(PROBE_STEPS):
             s.apply_load_step(w.load_path[k])
             s.solve_increment()
-        s.apply_load_step(w.load_path[2])
+        s.apply_load_step(w.load_path[PROBE_STEPS])
         res["onset"] = timed("load steps 0-1 solved (i_NR,max 50), step 2 applied")
         E = np.zeros((3, 3))
         E[0, 0] = 2e-3
@@ -580,8 +628,9 @@ def load_traffic(kernel, shape, tuning):
 def probe(n, tuning_out=None, tuning_in=None):
     """Kernels for counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
 
-    The first PROBE_STEPS load increments of the workload recipe at n^3,
-    solved (the state of the benchmark's first timed steps at 64^3), the
+    The damage-onset state of the workload recipe at n^3 that
+    hessian_scaling times (the first PROBE_STEPS load increments solved
+    under the library's default Newton limit, the next one applied), the
     autotuner (the launch shapes the benchmark uses), then, for every Hessian
     brick shape,
     PROBE_REPS projected-Hessian applications at that state, and PROBE_REPS
@@ -597,6 +646,7 @@ def probe(n, tuning_out=None, tuning_in=None):
     for k in range(PROBE_STEPS):
         s.apply_load_step(w.load_path[k])
         s.solve_increment()
+    s.apply_load_step(w.load_path[PROBE_STEPS])
     if tuning_in:
         with open(tuning_in) as fh:
             t = json.load(fh)
@@ -652,6 +702,10 @@ def main():
                     help="skip the Hessian-alone line at 64^3 and 128^3")
     ap.add_argument("--no-tensile", action="store_true",
                     help="skip the tensile-masking law (Appendix A) line")
+    ap.add_argument("--tuning", metavar="FILE",
+                    help="launch shapes (JSON, as config.launch_shapes of a bench line) for the "
+                         "timed steps instead of the autotuner's choice, e.g. to profile the "
+                         "shapes an unprofiled run chose")
     ap.add_argument("--stall-study", action="store_true",
                     help="also run the timed steps with the CG stall exit in both precisions "
                          "(minutes: the exit leaves Newton steps unconverged)")
@@ -703,7 +757,14 @@ def main():
         s.apply_load_step(w.load_path[n])
         s.solve_increment(SOLVE)
     # launch shapes for this grid and state, chosen by measurement (setup)
-    tuning = s.autotune()
+    if args.tuning:
+        with open(args.tuning) as fh:
+            t = json.load(fh)
+        t = t.get("config", {}).get("launch_shapes", t)
+        s.set_tuning(**{k: int(v) for k, v in t.items() if k != "soft_points"})
+        tuning = s.tuning()
+    else:
+        tuning = s.autotune()
     ck = s.get_state()
 
     detail, sigmas, step_s, states, damages = [], [], [], [], []
@@ -929,7 +990,7 @@ def main():
     }
     if not args.no_batch:
         out["batch_six_load_cases"] = batch_bench(w, 2)
-        out["batch_uneven_cells"] = uneven_batch_bench()
+        out["batch_population"] = population_batch_bench(log=progress)
         progress("batches done")
     if not args.no_tensile:
         out["tensile_law"] = tensile_bench()
