@@ -162,14 +162,15 @@ def warm_start_bench(n=16, train_seeds=tuple(range(101, 149)), test_seed=201, st
         s.setup(phase, w.materials)
         u_prev = np.zeros((3,) + phase.shape)
         du_prev = None
-        newton = cg = conv = 0
+        newton = cg = conv = taken = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             s.apply_load_step(dE)
-            if guess and du_prev is not None:
-                du = du_prev if guess == "extrapolate" else ws.predict(phase, s.damage(), du_prev, scale)
-                s.set_displacement(u_prev + du)
+            if guess == "extrapolate" and du_prev is not None:
+                s.set_displacement(u_prev + du_prev)
+            elif guess == "learned" and du_prev is not None:
+                taken += int(ws.warm_start(s, phase, u_prev, du_prev, scale))
             r = s.solve_increment(params)
             newton += r["newton_iters"]
             cg += r["cg_iters"]
@@ -181,8 +182,11 @@ def warm_start_bench(n=16, train_seeds=tuple(range(101, 149)), test_seed=201, st
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         s.close()
-        return {"newton_iters": newton, "cg_iters": cg, "converged_steps": conv,
-                "ms_per_step": dt / steps * 1e3}
+        out = {"newton_iters": newton, "cg_iters": cg, "converged_steps": conv,
+               "ms_per_step": dt / steps * 1e3}
+        if guess == "learned":
+            out["learned_guess_taken"] = taken   # else the previous fluctuation (lower r_eq)
+        return out
 
     ws = WarmStart(seed=0)
     t0 = time.perf_counter()

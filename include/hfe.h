@@ -271,6 +271,13 @@ hfe_status hfe_solve_increment_lbfgs(hfe_ctx* ctx, const hfe_lbfgs_params* param
  * plane strain) at the last evaluated state. */
 hfe_status hfe_homogenized_stress(const hfe_ctx* ctx, double out[9]);
 
+/* Relative equilibrium residual of the last evaluated state, Algorithm 2's
+ * r_eq = ||G sigma|| / ||sigma|| (G_M under mean-stress control; 0 when
+ * sigma = 0), as the convergence test uses it. Lets a caller compare initial
+ * guesses (hfe_set_displacement) before solving. *out (host) receives it;
+ * HFE_ESTATE before a state is evaluated. */
+hfe_status hfe_residual(const hfe_ctx* ctx, double* out);
+
 /* Copy a field (HFE_FIELD_*) to host memory; n = number of doubles in out. */
 hfe_status hfe_get_field(const hfe_ctx* ctx, int which, double* host_out, size_t n);
 

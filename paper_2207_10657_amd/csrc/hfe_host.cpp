@@ -1661,6 +1661,14 @@ hfe_status hfe_effective_stiffness(hfe_ctx* const* ctxs, double strain,
   return HFE_OK;
 }
 
+hfe_status hfe_residual(const hfe_ctx* cc, double* out) {
+  hfe_ctx* c = const_cast<hfe_ctx*>(cc);
+  if (!c || !out) return HFE_EINVAL;
+  if (!c->have_state) return fail(c, HFE_ESTATE, "no evaluated state");
+  *out = c->r_eq;
+  return HFE_OK;
+}
+
 hfe_status hfe_homogenized_stress(const hfe_ctx* cc, double out[9]) {
   hfe_ctx* c = const_cast<hfe_ctx*>(cc);
   if (!c || !out) return HFE_EINVAL;

@@ -88,6 +88,7 @@ EXPORTS = {
     "hfe_solve_increment": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params),
                                            ctypes.POINTER(_Report)]),
     "hfe_homogenized_stress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hfe_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "hfe_get_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]),
     "hfe_get_newton_log": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Record), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]),
@@ -436,6 +437,12 @@ class Solver:
         Rr = np.array([R, Rmax], dtype=np.float64)
         self._check(self.lib.hfe_set_state(self.ctx, *(a.ctypes.data_as(ctypes.c_void_p)
                                                        for a in (u, kh, Em, Rr))))
+
+    def residual(self):
+        """r_eq of the last evaluated state (hfe_residual)."""
+        out = ctypes.c_double(0.0)
+        self._check(self.lib.hfe_residual(self.ctx, ctypes.byref(out)))
+        return out.value
 
     def homogenized_stress(self):
         out = np.zeros(9)

@@ -359,3 +359,17 @@ class WarmStart:
         f = features(phase, damage, du_prev, scale)
         corr = self.net.predict(self._x16(f), phase.shape).double().cpu().numpy()
         return du_prev + scale * corr
+
+    def warm_start(self, solver, phase, u_prev, du_prev, scale):
+        """Set the solver's initial guess for the increment just applied
+        (after apply_load_step): the learned one, u_prev + predict(...), if
+        its equilibrium residual r_eq is below that of Algorithm 2's plain
+        guess (the previous fluctuation u_prev, which the solver holds on
+        entry); otherwise the plain guess is kept. Returns True if the learned
+        guess was taken."""
+        r_plain = solver.residual()
+        solver.set_displacement(u_prev + self.predict(phase, solver.damage(), du_prev, scale))
+        if solver.residual() < r_plain:
+            return True
+        solver.set_displacement(u_prev)
+        return False

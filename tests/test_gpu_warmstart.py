@@ -153,10 +153,9 @@ def _run(phase, materials, steps, dE, guess=None, ws=None):
         s.apply_load_step(dE)
         if guess is not None and du_prev is not None:
             if guess == "extrapolate":
-                du = du_prev
+                s.set_displacement(u_prev + du_prev)
             else:
-                du = ws.predict(phase, s.damage(), du_prev, scale)
-            s.set_displacement(u_prev + du)
+                ws.warm_start(s, phase, u_prev, du_prev, scale)
         r = s.solve_increment()
         u = s.get_state()["u"]
         reps.append(r)
@@ -214,6 +213,57 @@ def test_warm_started_solves_reach_the_same_results():
                   % (guess, k, dS, d[k], d0[k]), flush=True)
             if d0[k] == 0.0 and d[k] == 0.0:
                 assert dS < 1e-7, (guess, k, dS)
+
+
+def test_warm_start_keeps_the_guess_with_the_lower_residual():
+    """WarmStart.warm_start compares r_eq (hfe_residual) at the learned guess
+    with Algorithm 2's plain guess, the previous fluctuation. A prediction of
+    the exact converged increment is taken and starts the solve converged. A
+    large random prediction is refused: the state returns to the plain
+    guess bit for bit, and the solve gives the plain solve's bits."""
+    require_gpu()
+    announce("warm start fallback")
+    from paper_2207_10657_amd import Solver
+    from paper_2207_10657_amd.warmstart import WarmStart
+    w = workload("c1_3d8", steps=2)
+    dE = w.load_path[0]
+    scale = np.linalg.norm(dE) * 8
+
+    def first_step():
+        s = Solver(w.shape, "q1")
+        s.setup(w.phase, w.materials)
+        s.apply_load_step(dE)
+        assert s.solve_increment()["converged"]
+        return s
+
+    ref = first_step()
+    u0 = ref.get_state()["u"]
+    ref.apply_load_step(dE)
+    r_plain = ref.residual()
+    rep_ref = ref.solve_increment()
+    du_true = ref.get_state()["u"] - u0
+    ws = WarmStart(seed=0)
+    rng = np.random.default_rng(4)
+    for name, pred, expect in (("exact", du_true, True),
+                               ("random", 1e3 * scale * rng.normal(size=du_true.shape), False)):
+        s = first_step()
+        s.apply_load_step(dE)
+        assert s.residual() == r_plain
+        ws.predict = lambda *a, _p=pred: _p
+        taken = ws.warm_start(s, w.phase, u0, u0, scale)
+        print("[warmstart] %s prediction: taken %s, r_eq %.3e (plain %.3e)"
+              % (name, taken, s.residual(), r_plain), flush=True)
+        assert taken == expect
+        if taken:
+            assert s.residual() < 1e-6 * r_plain
+            assert s.solve_increment()["newton_iters"] == 0
+        else:
+            assert s.residual() == r_plain
+            rep = s.solve_increment()
+            assert rep["newton_iters"] == rep_ref["newton_iters"]
+            np.testing.assert_array_equal(s.homogenized_stress(), ref.homogenized_stress())
+        s.close()
+    ref.close()
 
 
 def _bf16_to_f64(t16):
