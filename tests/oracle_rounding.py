@@ -197,7 +197,7 @@ def loading_tie(g, o_start, params, i):
                 % (nd, i, dstate, "straddle" if ok else "do NOT all straddle", float(gap.max())))
 
 
-def step_verdict(g, rg, o_start, ro, olog, params=None, eta_cg=1e-6):
+def step_outcome(g, rg, o_start, ro, olog, params=None, eta_cg=1e-6):
     """(same, certified, text) for one load step solved by the GPU solver g
     (report rg) and the oracle (report ro, log olog; o_start a copy of the
     oracle right after apply_load_step, before the solve). same: identical

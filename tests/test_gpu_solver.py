@@ -305,7 +305,7 @@ def test_expanding_sites_16_against_oracle():
     by O(1e-8) in relative terms, so such steps are compared at 10x the
     tolerance (stress 1e-8 of the load scale, damage and gradient 1e-7)."""
     import copy
-    from tests.oracle_rounding import step_verdict
+    from tests.oracle_rounding import step_outcome
     require_gpu()
     w = workload("gel_3d16", steps=6)
     g, o = _pair(w.shape, w.phase, w.materials)
@@ -328,7 +328,7 @@ def test_expanding_sites_16_against_oracle():
         dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
         dd = float(np.abs(g.damage() - o.damage()).max())
         dH = rel_err(g.gradient(), o.H)
-        same, certified, what = step_verdict(g, rg, o_start, ro, olog)   # may restart g
+        same, certified, what = step_outcome(g, rg, o_start, ro, olog)   # may restart g
         print("[gel] step %d: converged %s/%s, Newton %d/%d, %s, |dSigma|/scale %.2e, damage "
               "%.2e, grad %.2e, max damage %.3f"
               % (n, rg["converged"], ro["converged"], rg["newton_iters"], len(ro["flags"]), what,

@@ -21,7 +21,7 @@ from oracle import material
 from oracle.solver import CellSolver
 from synthetic import laminate_microstructure, workload
 from tests.gpu_util import require_gpu, announce, rel_err
-from tests.oracle_rounding import step_verdict
+from tests.oracle_rounding import step_outcome
 
 pytestmark = pytest.mark.gpu
 
@@ -140,7 +140,7 @@ def test_free_expansion_of_the_expanding_site_workload_against_oracle():
         dE_rel = np.max(np.abs(g.get_state()["E"] - o.E)) / max(np.max(np.abs(o.E)), 1e-300)
         dd = float(np.abs(g.damage() - o.damage()).max())
         dH = rel_err(g.gradient(), o.H)
-        same, certified, what = step_verdict(g, rg, o_start, ro, olog)   # may restart g
+        same, certified, what = step_outcome(g, rg, o_start, ro, olog)   # may restart g
         print("[stress] gel free expansion step %d: Newton %d/%d, %s, |dSigma|/scale %.2e, "
               "E %.2e, damage %.2e, grad %.2e, E_xx %.3e, max damage %.3f"
               % (n, rg["newton_iters"], ro["newton_iters"], what, dS, dE_rel, dd, dH, o.E[0, 0],

@@ -13,7 +13,7 @@ from oracle.projection import Projector
 from oracle.solver import CellSolver
 from synthetic import inclusion_microstructure, MATRIX_TENSILE, INCLUSION_ELASTIC
 from tests.gpu_util import require_gpu, announce, rel_err
-from tests.oracle_rounding import step_verdict
+from tests.oracle_rounding import step_outcome
 
 pytestmark = pytest.mark.gpu
 
@@ -135,7 +135,7 @@ def test_tensile_increments_against_oracle(shape, steps, precision):
         dd = float(np.abs(g.damage() - o.damage()).max())
         dH = rel_err(g.gradient(), o.H)
         if precision == "fp64":   # (may restart g)
-            same, certified, what = step_verdict(g, rg, o_start, ro, olog, prm)
+            same, certified, what = step_outcome(g, rg, o_start, ro, olog, prm)
         else:
             same, certified, what = False, True, "mixed precision"
         print("[tensile] %s %s step %d: Newton %d/%d, CG %d/%d, %s, |dSigma|/scale %.2e, "
@@ -213,7 +213,7 @@ def test_asr_expanding_sites_16_against_oracle():
         dS = np.linalg.norm(g.homogenized_stress() - o.homogenized_stress()) / scale
         dd = float(np.abs(g.damage() - o.damage()).max())
         dH = rel_err(g.gradient(), o.H)
-        same, certified, what = step_verdict(g, rg, o_start, ro, olog)   # may restart g
+        same, certified, what = step_outcome(g, rg, o_start, ro, olog)   # may restart g
         print("[tensile] asr step %d: Newton %d/%d, CG %d/%d, %s, |dSigma|/scale %.2e, damage "
               "%.2e, grad %.2e, max damage %.3f"
               % (n, rg["newton_iters"], ro["newton_iters"], rg["cg_iters"], ro["cg_iters"], what,
