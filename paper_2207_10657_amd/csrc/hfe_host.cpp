@@ -297,10 +297,6 @@ struct Prof {
   Prof(hfe_ctx* ctx, const char* name) : c(ctx) {
     if (!c->profiling) return;
     id = kernel_id(c, name);
-    if (std::strncmp(name, "stiffness", 9) == 0) {
-      c->prof_soft_sum += c->n_soft;
-      ++c->prof_soft_n;
-    }
     s = take_event(c);
     if (s) hipEventRecord(s, c->stream);
   }
@@ -309,6 +305,43 @@ struct Prof {
     hipEvent_t e = take_event(c);
     if (!e) return;
     hipEventRecord(e, c->stream);
+    (c->prof_sink ? c->prof_sink : &c->pending)->push_back({id, s, e});
+  }
+};
+
+// Profiling of a Hessian launch. In 3D the launch records the events at the
+// kernel's own start and end (hfe::arm_kernel_events), so the interval is
+// the kernel's execution; events recorded on the stream around a launch
+// (Prof) also hold its dispatch, a few microseconds per launch at 64^3. The
+// 2D Hessian is timed as Prof does.
+struct ProfKernel {
+  hfe_ctx* c;
+  int id = -1;
+  hipEvent_t s = nullptr, e = nullptr;
+  bool armed = false;
+  ProfKernel(hfe_ctx* ctx, const char* name) : c(ctx) {
+    if (!c->profiling) return;
+    id = kernel_id(c, name);
+    c->prof_soft_sum += c->n_soft;
+    ++c->prof_soft_n;
+    s = take_event(c);
+    e = s ? take_event(c) : nullptr;
+    if (!e) {
+      if (s) c->pool.push_back(s);
+      s = nullptr;
+      return;
+    }
+    if (c->g.dim == 3) {
+      hfe::arm_kernel_events(s, e);
+      armed = true;
+    } else {
+      hipEventRecord(s, c->stream);
+    }
+  }
+  ~ProfKernel() {
+    if (!c->profiling || !s || !e) return;
+    if (armed) hfe::arm_kernel_events(nullptr, nullptr);   // if the launch did not happen
+    else hipEventRecord(e, c->stream);
     (c->prof_sink ? c->prof_sink : &c->pending)->push_back({id, s, e});
   }
 };
@@ -443,7 +476,7 @@ hfe_status stiffness(hfe_ctx* c, const double* v, double* out, bool in_cg,
   if (in_cg) A.cg = c->cg;
   int nb = 0;
   {
-    Prof p(c, "stiffness");
+    ProfKernel p(c, "stiffness");
     HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
   }
   if (U && !in_cg) {
@@ -595,7 +628,7 @@ hfe::HessArgs<float> hess_args32(hfe_ctx* c, const float* v, float* out, bool in
 hfe_status stiffness32(hfe_ctx* c, const float* v, float* out, bool in_cg) {
   int nb = 0;
   {
-    Prof p(c, "stiffness_f32");
+    ProfKernel p(c, "stiffness_f32");
     HIPCHK(c, hfe::launch_hessian_f32(hess_args32(c, v, out, in_cg), c->stream, &nb));
   }
   return in_cg ? finish(c, hfe::FIN_CURVATURE, nb, hfe::HES_NV, nullptr)
@@ -664,7 +697,7 @@ hfe::CgFuse<R> fuse_args(hfe_ctx* c, int nb_hes, const R* d, R* z, R* g, R* y) {
 hfe_status cg_iteration32(hfe_ctx* c) {
   int nb = 0;
   {
-    Prof p(c, "stiffness_f32");
+    ProfKernel p(c, "stiffness_f32");
     HIPCHK(c, hfe::launch_hessian_f32(hess_args32(c, c->d32, c->Kd32, true), c->stream, &nb));
   }
   hfe::CgFuse<float> f = fuse_args<float>(c, nb, c->d32, c->z32, c->g32, c->y32);
@@ -705,7 +738,7 @@ hfe_status cg_iteration(hfe_ctx* c) {
   if (c->ne > 0) A.U = c->cg->dU;
   int nb = 0;
   {
-    Prof p(c, "stiffness");
+    ProfKernel p(c, "stiffness");
     HIPCHK(c, hfe::launch_hessian(A, c->stream, &nb));
   }
   if (c->g.dim == 3) {

@@ -107,6 +107,11 @@ hipError_t launch_trial(const ElemArgs& A, hipStream_t s, int* nblocks);
 // Hessian: f = D^T B D v at the state (a and the softening term), rows HES_*
 // (no-op once A.cg->done when A.cg is set).
 hipError_t launch_hessian(const ElemArgs& A, hipStream_t s, int* nblocks);
+// Profiling: a start / stop event pair that the next Hessian launch on this
+// host thread records around the kernel itself (hipExtLaunchKernelGGL), so
+// that their interval is the kernel's execution without its dispatch. The
+// launch consumes the pair; (nullptr, nullptr) disarms it.
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop);
 // Hessian operands in one precision (the FP32 copies of the state serve the
 // mixed-precision CG; Q1 only).
 template <typename R>

@@ -12,6 +12,7 @@
 #include "hfe_internal.h"
 #include "hfe_reduce.h"
 
+#include <hip/hip_ext.h>
 #include <type_traits>
 
 namespace hfe {
@@ -1542,6 +1543,22 @@ hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
   return launch_brick_shape<MODE, NV, 8, 8, 4>(A, s, nblocks);
 }
 
+// Events armed for the next Hessian launch of this host thread (profiling).
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+// Launch a Hessian kernel; with events armed, through hipExtLaunchKernelGGL,
+// which records them at the kernel's own start and end.
+template <typename K, typename... Args>
+void launch_hess(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (g_ev_start && g_ev_stop) {
+    const hipEvent_t a = g_ev_start, b = g_ev_stop;
+    g_ev_start = g_ev_stop = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+}
+
 template <typename R, int BX, int BY, int BZ>
 hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
@@ -1552,21 +1569,21 @@ hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblock
     if (A.U) {
       // mean-stress control: whole and ragged bricks of either law
       if (A.tens) {
-        if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true, true>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true, true>), grid, block, 0, s, A);
+        if (full) launch_hess(k_hessian<R, BX, BY, BZ, true, true, true>, grid, block, s, A);
+        else launch_hess(k_hessian<R, BX, BY, BZ, false, true, true>, grid, block, s, A);
       } else {
-        if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false, true>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false, true>), grid, block, 0, s, A);
+        if (full) launch_hess(k_hessian<R, BX, BY, BZ, true, false, true>, grid, block, s, A);
+        else launch_hess(k_hessian<R, BX, BY, BZ, false, false, true>, grid, block, s, A);
       }
       return hipGetLastError();
     }
   }
   if (A.tens) {
-    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, true, false>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, true, false>), grid, block, 0, s, A);
+    if (full) launch_hess(k_hessian<R, BX, BY, BZ, true, true, false>, grid, block, s, A);
+    else launch_hess(k_hessian<R, BX, BY, BZ, false, true, false>, grid, block, s, A);
   } else {
-    if (full) hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, true, false, false>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_hessian<R, BX, BY, BZ, false, false, false>), grid, block, 0, s, A);
+    if (full) launch_hess(k_hessian<R, BX, BY, BZ, true, false, false>, grid, block, s, A);
+    else launch_hess(k_hessian<R, BX, BY, BZ, false, false, false>, grid, block, s, A);
   }
   return hipGetLastError();
 }
@@ -1587,13 +1604,13 @@ hipError_t launch_hessian_col(const HessArgs<R>& A, int bz, hipStream_t s, int* 
   const dim3 grid(nb), block(ColumnShape<CX, CY>::threads);
   if constexpr (std::is_same<R, double>::value) {
     if (A.U) {
-      if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true, true>), grid, block, 0, s, A, bz);
-      else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false, true>), grid, block, 0, s, A, bz);
+      if (A.tens) launch_hess(k_hessian_col<R, CX, CY, true, true>, grid, block, s, A, bz);
+      else launch_hess(k_hessian_col<R, CX, CY, false, true>, grid, block, s, A, bz);
       return hipGetLastError();
     }
   }
-  if (A.tens) hipLaunchKernelGGL((k_hessian_col<R, CX, CY, true, false>), grid, block, 0, s, A, bz);
-  else hipLaunchKernelGGL((k_hessian_col<R, CX, CY, false, false>), grid, block, 0, s, A, bz);
+  if (A.tens) launch_hess(k_hessian_col<R, CX, CY, true, false>, grid, block, s, A, bz);
+  else launch_hess(k_hessian_col<R, CX, CY, false, false>, grid, block, s, A, bz);
   return hipGetLastError();
 }
 
@@ -1636,6 +1653,11 @@ hipError_t launch_gather(const ElemArgs& A, hipStream_t s, int* nblocks) {
 }
 
 }  // namespace
+
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
 
 hipError_t launch_residual(const ElemArgs& A, hipStream_t s, int* nblocks) {
   if (A.g.element != HFE_Q1) return launch_gather<MODE_RESIDUAL, RES_NV>(A, s, nblocks);

@@ -157,3 +157,35 @@ def test_full_size_projected_hessian_64cubed():
     s.autotune()
     out2, dots2 = s.apply_projected_hessian(dt)
     assert np.array_equal(out2.cpu().numpy(), out)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16)])
+def test_profiling_times_every_hessian_launch(shape):
+    """Profiling mode times each Hessian launch: in 3D by events the launch
+    records at the kernel's own start and end, in 2D by events around the
+    launch. Every launch is counted with a positive duration, other kernels
+    keep their event pairs, and leaving profiling mode changes no result."""
+    torch = require_gpu()
+    announce("profiling of the Hessian", shape)
+    phase, mats, E, u = _state(shape, 5, 4e-4)
+    s = _solver(shape)
+    s.setup(phase, mats)
+    s.apply_load_step(E)
+    s.set_displacement(u)
+    d = torch.tensor(np.random.default_rng(2).normal(size=(len(shape),) + shape), device="cuda")
+    ref = s.apply_stiffness(d).cpu().numpy()
+    s.set_profiling(True)
+    for _ in range(7):
+        out = s.apply_stiffness(d)
+    s.apply_projected_hessian(d)
+    torch.cuda.synchronize()
+    st = s.kernel_stats()
+    s.set_profiling(False)
+    count, ms = st["stiffness"]
+    print("[profiling] %s: stiffness %d launches, %.2f us each; %s"
+          % (shape, count, 1e3 * ms / max(count, 1),
+             {k: v[0] for k, v in st.items() if v[0]}), flush=True)
+    assert count == 8 and ms > 0.0
+    assert sum(v[0] for k, v in st.items() if k.startswith("fft")) >= 1
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    np.testing.assert_array_equal(s.apply_stiffness(d).cpu().numpy(), ref)
