@@ -100,7 +100,8 @@ def upsample2_backward(g):
 def unet_forward(x, params, levels, bf16=False):
     """The encoder-decoder of the warm start (levels resolutions, 2x2x2 mean
     pooling, nearest upsampling, the decoder's input = [encoder features,
-    upsampled coarse features]); params = {"enc": [(w, b)] * levels,
+    upsampled coarse features]; the channel counts follow the weights, so a
+    level may widen); params = {"enc": [(w, b)] * levels,
     "dec": [(w, b)] * (levels - 1) (finest first), "out": (w, b)}. With bf16,
     every convolution input is rounded to BF16 first (as the kernels store
     activations). Returns the output and the intermediate values the backward
@@ -130,8 +131,9 @@ def unet_forward(x, params, levels, bf16=False):
 def unet_backward(gy, params, st, levels):
     """Gradients of <gy, y> with respect to every (w, b), for the values `st`
     of unet_forward (the BF16 roundings of the forward pass are treated as
-    identities). Returns a dict shaped like params."""
-    C = params["enc"][0][0].shape[0]
+    identities). Returns a dict shaped like params. The channel counts may
+    differ between levels (a widening network): the decoder input of level l
+    is [encoder features of level l (C_l channels), upsampled coarse features]."""
     grads = {"enc": [None] * levels, "dec": [None] * (levels - 1)}
     w, _ = params["out"]
     grads["out"] = conv3d_backward_weights(gy, st["out_in"])
@@ -142,6 +144,7 @@ def unet_backward(gy, params, st, levels):
         w, _ = params["dec"][l]
         grads["dec"][l] = conv3d_backward_weights(gm, st["cat"][l])
         gcat = conv3d_backward_data(gm, w)
+        C = params["enc"][l][0].shape[0]
         g_enc[l] = gcat[:C]
         g = upsample2_backward(gcat[C:])
     for l in range(levels - 1, -1, -1):

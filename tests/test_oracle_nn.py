@@ -1,5 +1,6 @@
 """Pins of the convolution oracle used to check the warm-start kernels."""
 import numpy as np
+import pytest
 
 from oracle import nn
 
@@ -94,30 +95,38 @@ def test_pool_and_upsample_against_index_loops_and_adjoints():
     assert abs(np.sum(nn.upsample2(p) * h) - np.sum(p * nn.upsample2_backward(h))) < 1e-12
 
 
-def _unet_params(rng, levels, cin=3, C=4, cout=2):
+def _unet_params(rng, levels, cin=3, C=4, cout=2, widths=None):
+    """Weights of a network with widths[l] channels at level l (all C by
+    default): the decoder of level l takes [encoder features of level l,
+    upsampled features of level l + 1]."""
+    wd = list(widths) if widths is not None else [C] * levels
     p = {"enc": [], "dec": []}
     for l in range(levels):
-        p["enc"].append((rng.normal(scale=0.3, size=(C, cin if l == 0 else C, 27)),
-                         rng.normal(scale=0.1, size=C)))
+        p["enc"].append((rng.normal(scale=0.3, size=(wd[l], cin if l == 0 else wd[l - 1], 27)),
+                         rng.normal(scale=0.1, size=wd[l])))
     for l in range(levels - 1):
-        p["dec"].append((rng.normal(scale=0.3, size=(C, 2 * C, 27)), rng.normal(scale=0.1, size=C)))
-    p["out"] = (rng.normal(scale=0.3, size=(cout, C, 27)), rng.normal(scale=0.1, size=cout))
+        p["dec"].append((rng.normal(scale=0.3, size=(wd[l], wd[l] + wd[l + 1], 27)),
+                         rng.normal(scale=0.1, size=wd[l])))
+    p["out"] = (rng.normal(scale=0.3, size=(cout, wd[0], 27)), rng.normal(scale=0.1, size=cout))
     return p
 
 
-def test_unet_backward_against_finite_differences():
+@pytest.mark.parametrize("levels,widths,shape", [(3, None, (3, 8, 8, 4)),
+                                                 (4, (2, 3, 4, 5), (3, 16, 8, 8))])
+def test_unet_backward_against_finite_differences(levels, widths, shape):
     """The encoder-decoder is piecewise linear in each weight (ReLU), so a
     central difference with a small step reproduces the gradient of <gy, y>
-    away from the kinks."""
+    away from the kinks; also for a network that widens level by level."""
     rng = np.random.default_rng(4)
-    levels = 3
-    p = _unet_params(rng, levels)
-    x = rng.normal(size=(3, 8, 8, 4))
+    p = _unet_params(rng, levels, widths=widths)
+    x = rng.normal(size=shape)
     y, st = nn.unet_forward(x, p, levels)
     gy = rng.normal(size=y.shape)
     g = nn.unet_backward(gy, p, st, levels)
     h = 1e-6
-    for part, idx in [("enc", 0), ("enc", 1), ("enc", 2), ("dec", 0), ("dec", 1), ("out", None)]:
+    parts = [("enc", l) for l in range(levels)] + [("dec", l) for l in range(levels - 1)] + \
+        [("out", None)]
+    for part, idx in parts:
         w, b = p[part] if idx is None else p[part][idx]
         gw, gb = g[part] if idx is None else g[part][idx]
         for k in range(3):
