@@ -418,7 +418,10 @@ const char* hfe_last_error(const hfe_ctx* ctx);
  * fastest), n = {nx, ny, nz}; filter banks [cout][cin][27] with tap
  * (dz+1)*9 + (dy+1)*3 + (dx+1); the grid is periodic. BF16 values are
  * uint16_t (the upper half of an IEEE binary32, round to nearest even).
- * Channel counts: 1, 2, 3, 4, 6, 8, 16 or 32. `stream` is a hipStream_t (NULL:
+ * Channel counts: 1 to 512. Layers whose counts are both among 1, 2, 3, 4,
+ * 6, 8, 16 and 32 hold their filter bank in LDS; the others (the 64-channel
+ * levels of a widening network) read it from global memory in tiles of 16
+ * channels. `stream` is a hipStream_t (NULL:
  * the default stream); the calls are asynchronous on it. HFE_EINVAL for bad
  * arguments, HFE_EDEVICE if a launch fails. */
 

@@ -114,6 +114,86 @@ __global__ void __launch_bounds__(kNnBlock) k_conv_bwd_data(const float* __restr
   for (int ci = 0; ci < cin; ++ci) gin[(long long)ci * N + v] = acc[ci];
 }
 
+// Wide layers, whose filter bank does not fit the LDS of the kernels above
+// (the 64-channel levels of the widening encoder-decoder): a block computes a
+// tile of CT channels (outputs of the convolution, inputs of its adjoint) for
+// its voxels, with cin and cout runtime values, and reads the weights from
+// global memory at addresses uniform across the block (they stay in the
+// caches). The additions run in the same order as in k_conv_fwd and
+// k_conv_bwd_data: taps outer, then channels.
+constexpr int kWideTile = 16;
+
+__global__ void __launch_bounds__(kNnBlock) k_conv_fwd_wide(const uint16_t* __restrict__ in,
+                                                           int cin,
+                                                           const uint16_t* __restrict__ w,
+                                                           const float* __restrict__ bias,
+                                                           int cout, int nx, int ny, int nz,
+                                                           int relu, float* __restrict__ out,
+                                                           uint16_t* __restrict__ out16) {
+  constexpr int CT = kWideTile;
+  const int co0 = blockIdx.y * CT;
+  const long long N = (long long)nx * ny * nz;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+  float acc[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) acc[c] = (bias && co0 + c < cout) ? bias[co0 + c] : 0.f;
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const long long u = (long long)wrapi(x + dx, nx) +
+                        (long long)nx * (wrapi(y + dy, ny) + (long long)ny * wrapi(z + dz, nz));
+    for (int ci = 0; ci < cin; ++ci) {
+      const float a = from_bf16(in[(long long)ci * N + u]);
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        if (co0 + c < cout) acc[c] += from_bf16(w[((co0 + c) * cin + ci) * 27 + t]) * a;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (co0 + c >= cout) break;
+    float r = acc[c];
+    if (relu) r = fmaxf(r, 0.f);
+    out[(long long)(co0 + c) * N + v] = r;
+    if (out16) out16[(long long)(co0 + c) * N + v] = to_bf16(r);
+  }
+}
+
+__global__ void __launch_bounds__(kNnBlock) k_conv_bwd_data_wide(const float* __restrict__ g,
+                                                                int cout,
+                                                                const float* __restrict__ act,
+                                                                const uint16_t* __restrict__ w,
+                                                                int cin, int nx, int ny, int nz,
+                                                                float* __restrict__ gin) {
+  constexpr int CT = kWideTile;
+  const int ci0 = blockIdx.y * CT;
+  const long long N = (long long)nx * ny * nz;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+  float acc[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) acc[c] = 0.f;
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const long long u = (long long)wrapi(x - dx, nx) +
+                        (long long)nx * (wrapi(y - dy, ny) + (long long)ny * wrapi(z - dz, nz));
+    for (int co = 0; co < cout; ++co) {
+      float gg = g[(long long)co * N + u];
+      if (act && !(act[(long long)co * N + u] > 0.f)) gg = 0.f;
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        if (ci0 + c < cin) acc[c] += from_bf16(w[(co * cin + ci0 + c) * 27 + t]) * gg;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (ci0 + c >= cin) break;
+    gin[(long long)(ci0 + c) * N + v] = acc[c];
+  }
+}
+
 // One block per (co, ci): rows of partial sums over voxels for the 27 taps,
 // gw[co][ci][t] = sum_v gm[co][v] in[ci][v + off(t)], and (ci == 0) the bias
 // gradient sum_v gm[co][v]; gm = g masked by (act > 0) when act is set.
@@ -374,11 +454,27 @@ extern "C" {
 static bool channels_ok(int c) {
   return c == 1 || c == 2 || c == 3 || c == 4 || c == 6 || c == 8 || c == 16 || c == 32;
 }
+constexpr int kMaxChannels = 512;
+static bool wide_ok(int c) { return c >= 1 && c <= kMaxChannels; }
+// the LDS kernels take the listed channel counts; any other pair of counts
+// (up to kMaxChannels) runs in the wide kernels
+static bool lds_pair(int cin, int cout) { return channels_ok(cin) && channels_ok(cout); }
+
+static dim3 wide_grid(const int n[3], int channels) {
+  const long long N = (long long)n[0] * n[1] * n[2];
+  return dim3((unsigned)((N + kNnBlock - 1) / kNnBlock),
+              (unsigned)((channels + kWideTile - 1) / kWideTile));
+}
 
 hfe_status hfe_nn_conv3d(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout,
                          const int n[3], int relu, float* out, uint16_t* out_bf16, void* stream) {
-  if (!in || !w || !out || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
-    return HFE_EINVAL;
+  if (!in || !w || !out || !dims_ok(n) || !wide_ok(cin) || !wide_ok(cout)) return HFE_EINVAL;
+  if (!lds_pair(cin, cout)) {
+    hipLaunchKernelGGL(k_conv_fwd_wide, wide_grid(n, cout), dim3(kNnBlock), 0,
+                       (hipStream_t)stream, in, cin, w, bias, cout, n[0], n[1], n[2], relu, out,
+                       out_bf16);
+    return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+  }
   hipError_t e = hipErrorInvalidValue;
   switch (cin) {
 #define HFE_NN_CIN(C)                                                                          \
@@ -394,8 +490,12 @@ hfe_status hfe_nn_conv3d(const uint16_t* in, int cin, const uint16_t* w, const f
 hfe_status hfe_nn_conv3d_backward_data(const float* gout, int cout, const float* act,
                                        const uint16_t* w, int cin, const int n[3], float* gin,
                                        void* stream) {
-  if (!gout || !w || !gin || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
-    return HFE_EINVAL;
+  if (!gout || !w || !gin || !dims_ok(n) || !wide_ok(cin) || !wide_ok(cout)) return HFE_EINVAL;
+  if (!lds_pair(cin, cout)) {
+    hipLaunchKernelGGL(k_conv_bwd_data_wide, wide_grid(n, cin), dim3(kNnBlock), 0,
+                       (hipStream_t)stream, gout, cout, act, w, cin, n[0], n[1], n[2], gin);
+    return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;
+  }
   hipError_t e = hipErrorInvalidValue;
   switch (cin) {
 #define HFE_NN_CIN(C)                                                                          \
@@ -411,8 +511,7 @@ hfe_status hfe_nn_conv3d_backward_data(const float* gout, int cout, const float*
 hfe_status hfe_nn_conv3d_backward_weights(const float* gout, int cout, const float* act,
                                           const uint16_t* in, int cin, const int n[3], float* gw,
                                           float* gb, void* stream) {
-  if (!gout || !in || !gw || !dims_ok(n) || !channels_ok(cin) || !channels_ok(cout))
-    return HFE_EINVAL;
+  if (!gout || !in || !gw || !dims_ok(n) || !wide_ok(cin) || !wide_ok(cout)) return HFE_EINVAL;
   hipLaunchKernelGGL(k_conv_bwd_w, dim3(cout * cin), dim3(kNnBlock), 0, (hipStream_t)stream, gout,
                      cout, act, in, cin, n[0], n[1], n[2], gw, gb);
   return hipGetLastError() == hipSuccess ? HFE_OK : HFE_EDEVICE;

@@ -154,29 +154,35 @@ class _Conv:
 
 class UNet:
     """Encoder-decoder on the periodic grid (row f3): `levels` resolutions,
-    each halving the grid by 2x2x2 mean pooling; 16 channels at every level;
-    the decoder upsamples (nearest) and convolves the upsampled coarse
-    features side by side with the encoder's features of the same level (32
-    channels in). conv(6->16)+ReLU at the finest level, conv(16->16)+ReLU
-    after every pooling, conv(32->16)+ReLU at every decoder level,
-    conv(16->3) out (zero-initialised, so an untrained network predicts no
-    correction). BF16 activations and weights, FP32 accumulation; every
-    operation runs in the hfe_nn_* kernels."""
+    each halving the grid by 2x2x2 mean pooling, with widths[l] channels at
+    level l (16 at every level by default; the widening network of the
+    scaled warm start uses 16, 32, 64, 64). The decoder of level l upsamples
+    (nearest) the features of level l + 1 and convolves them side by side
+    with the encoder's features of level l (widths[l] + widths[l + 1]
+    channels in). conv(in->w0)+ReLU at the finest level, conv(w[l-1]->w[l])
+    +ReLU after every pooling, conv(w[l]+w[l+1]->w[l])+ReLU at every decoder
+    level, conv(w0->out) out (zero-initialised, so an untrained network
+    predicts no correction). BF16 activations and weights, FP32 accumulation;
+    every operation runs in the hfe_nn_* kernels."""
 
     C = 16
 
-    def __init__(self, levels=3, seed=0, device="cuda:0", in_channels=6, out_channels=3):
+    def __init__(self, levels=3, seed=0, device="cuda:0", in_channels=6, out_channels=3,
+                 widths=None):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device)
         self.levels = levels
+        self.widths = tuple(int(c) for c in widths) if widths is not None else (self.C,) * levels
+        if len(self.widths) != levels:
+            raise ValueError("one width per level")
         rng = np.random.default_rng(seed)
-        C = self.C
-        self.enc = [_Conv(self, in_channels, C, rng)] + \
-            [_Conv(self, C, C, rng) for _ in range(levels - 1)]
-        self.dec = [_Conv(self, 2 * C, C, rng) for _ in range(levels - 1)]   # dec[l]: level l
-        self.out = _Conv(self, C, out_channels, rng, zero=True)
+        W = self.widths
+        self.enc = [_Conv(self, in_channels, W[0], rng)] + \
+            [_Conv(self, W[l - 1], W[l], rng) for l in range(1, levels)]
+        self.dec = [_Conv(self, W[l] + W[l + 1], W[l], rng) for l in range(levels - 1)]
+        self.out = _Conv(self, W[0], out_channels, rng, zero=True)
         self.step = 0
 
     _stream = ConvNet._stream
@@ -194,8 +200,9 @@ class UNet:
                                            self._stream()))
 
     def forward(self, x16, shape):
-        """x16: BF16 input (6, nz, ny, nx), every axis divisible by 2^(levels-1)."""
-        torch, C, L = self.torch, self.C, self.levels
+        """x16: BF16 input (in_channels, nz, ny, nx), every axis divisible by
+        2^(levels-1)."""
+        torch, W, L = self.torch, self.widths, self.levels
         f32 = dict(dtype=torch.float32, device=self.device)
         i16 = dict(dtype=torch.int16, device=self.device)
         st = {"enc": [], "cat": [], "pool16": [], "dec": []}
@@ -203,17 +210,17 @@ class UNet:
         inp = x16
         for l in range(L):
             n, dims = self._dims(shape, l)
-            e = torch.empty((C,) + dims, **f32)
-            cat = torch.empty((2 * C,) + dims, **i16) if l < L - 1 else None
+            e = torch.empty((W[l],) + dims, **f32)
+            cat = torch.empty((W[l] + W[l + 1],) + dims, **i16) if l < L - 1 else None
             if l > 0:
                 nf, _ = self._dims(shape, l - 1)
-                p16 = torch.empty((C,) + dims, **i16)
-                self._check(self.lib.hfe_nn_pool2(_ptr(st["enc"][l - 1]), C, nf, None, _ptr(p16),
-                                                  self._stream()))
+                p16 = torch.empty((W[l - 1],) + dims, **i16)
+                self._check(self.lib.hfe_nn_pool2(_ptr(st["enc"][l - 1]), W[l - 1], nf, None,
+                                                  _ptr(p16), self._stream()))
                 st["pool16"].append(p16)
                 inp = p16
-            # the encoder's BF16 copy is the first half of the decoder input
-            self._conv(self.enc[l], inp, n, True, e, cat[:C] if cat is not None else None)
+            # the encoder's BF16 copy is the first part of the decoder input
+            self._conv(self.enc[l], inp, n, True, e, cat[:W[l]] if cat is not None else None)
             st["enc"].append(e)
             st["cat"].append(cat)
         # decoder, coarse to fine
@@ -223,10 +230,10 @@ class UNet:
             n, dims = self._dims(shape, l)
             m, _ = self._dims(shape, l + 1)
             cat = st["cat"][l]
-            self._check(self.lib.hfe_nn_upsample2(_ptr(prev), C, m, None, _ptr(cat[C:]),
-                                                  self._stream()))
-            d = torch.empty((C,) + dims, **f32)
-            d16 = torch.empty((C,) + dims, **i16) if l == 0 else None
+            self._check(self.lib.hfe_nn_upsample2(_ptr(prev), W[l + 1], m, None,
+                                                  _ptr(cat[W[l]:]), self._stream()))
+            d = torch.empty((W[l],) + dims, **f32)
+            d16 = torch.empty((W[l],) + dims, **i16) if l == 0 else None
             self._conv(self.dec[l], cat, n, True, d, d16)
             dec[l] = (d, d16)
             prev = d
@@ -253,7 +260,7 @@ class UNet:
 
     def backward(self, gy, x16, st, shape):
         """Weight and bias gradients [(layer, gw, gb)] for dL/dy = gy."""
-        torch, C, L = self.torch, self.C, self.levels
+        torch, W, L = self.torch, self.widths, self.levels
         out = []
         n0, d0 = self._dims(shape, 0)
         dec0, dec0_16 = st["dec"][0]
@@ -265,11 +272,11 @@ class UNet:
             m, mdims = self._dims(shape, l + 1)
             d = st["dec"][l][0]
             out.append((self.dec[l],) + self._grads(self.dec[l], g, d, st["cat"][l], n))
-            gcat = self._gin(self.dec[l], g, d, n, dims)    # (2C, level l)
-            g_enc_part[l] = gcat[:C]
-            gc = torch.empty((C,) + mdims, dtype=torch.float32, device=self.device)
-            self._check(self.lib.hfe_nn_upsample2_backward(_ptr(gcat[C:].contiguous()), C, m,
-                                                           _ptr(gc), self._stream()))
+            gcat = self._gin(self.dec[l], g, d, n, dims)    # (W[l] + W[l+1], level l)
+            g_enc_part[l] = gcat[:W[l]]
+            gc = torch.empty((W[l + 1],) + mdims, dtype=torch.float32, device=self.device)
+            self._check(self.lib.hfe_nn_upsample2_backward(_ptr(gcat[W[l]:].contiguous()),
+                                                           W[l + 1], m, _ptr(gc), self._stream()))
             g = gc                                          # d loss / d (dec_{l+1} or enc_{L-1})
         # encoder, coarse to fine: g is d loss / d enc_{L-1}
         for l in range(L - 1, -1, -1):
@@ -282,7 +289,8 @@ class UNet:
             gp = self._gin(self.enc[l], g, e, n, dims)      # d loss / d pooled input
             nf, _ = self._dims(shape, l - 1)
             ge = g_enc_part[l - 1].contiguous()
-            self._check(self.lib.hfe_nn_pool2_backward(_ptr(gp), C, nf, _ptr(ge), self._stream()))
+            self._check(self.lib.hfe_nn_pool2_backward(_ptr(gp), W[l - 1], nf, _ptr(ge),
+                                                       self._stream()))
             g = ge
         return out
 
@@ -326,11 +334,50 @@ def features(phase, damage, du_prev, scale):
     return f
 
 
-class WarmStart:
-    """Training data from solves, training, and the warm-started solve."""
+def strain_channels(u, E):
+    """sym(grad u) + E at the element centres of the trilinear field u (3,
+    nz, ny, nx) on the unit periodic grid (per direction, the mean of the
+    element's 4 edge differences), Voigt order xx, yy, zz, yz, xz, xy:
+    (6, nz, ny, nx)."""
+    G = np.empty((3, 3) + u.shape[1:])
+    for j, ax in enumerate((3, 2, 1)):          # x, y, z axes of u
+        d = np.roll(u, -1, axis=ax) - u
+        others = [a for a in (3, 2, 1) if a != ax]
+        d = 0.5 * (d + np.roll(d, -1, axis=others[0]))
+        d = 0.5 * (d + np.roll(d, -1, axis=others[1]))
+        G[:, j] = d
+    S = 0.5 * (G + G.transpose(1, 0, 2, 3, 4)) + np.asarray(E)[:, :, None, None, None]
+    return np.stack([S[0, 0], S[1, 1], S[2, 2], S[1, 2], S[0, 2], S[0, 1]])
 
-    def __init__(self, net=None, seed=0):
-        self.net = net if net is not None else UNet(seed=seed)
+
+def features_full(phase, damage, du_prev, scale, u, E, dE):
+    """The 18 input channels of the scaled warm start: the 6 of `features`,
+    the current strain (6, over ||E|| + ||dE||) and the macroscopic increment
+    dE (6 uniform channels, Voigt order, over ||dE||)."""
+    dE = np.asarray(dE, dtype=np.float64)
+    ndE = max(float(np.linalg.norm(dE)), 1e-300)
+    f = np.empty((18,) + phase.shape, dtype=np.float32)
+    f[:6] = features(phase, damage, du_prev, scale)
+    f[6:12] = strain_channels(u, E) / (float(np.linalg.norm(E)) + ndE)
+    for k, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))):
+        f[12 + k] = dE[i, j] / ndE
+    return f
+
+
+class WarmStart:
+    """Training data from solves, training, and the warm-started solve.
+
+    full=False: the 3-level network of 16 channels on the 6 channels of
+    `features`. full=True: the 4-level network widening 16, 32, 64, 64 on the
+    18 channels of `features_full` (the current strain and the macroscopic
+    increment as well)."""
+
+    def __init__(self, net=None, seed=0, full=False):
+        self.full = full
+        if net is None:
+            net = (UNet(levels=4, widths=(16, 32, 64, 64), in_channels=18, seed=seed) if full
+                   else UNet(seed=seed))
+        self.net = net
         self.samples = []      # (features, target, shape), target = du / scale - du_prev / scale
 
     def _x16(self, f):
@@ -360,15 +407,38 @@ class WarmStart:
         corr = self.net.predict(self._x16(f), phase.shape).double().cpu().numpy()
         return du_prev + scale * corr
 
-    def warm_start(self, solver, phase, u_prev, du_prev, scale):
+    def state_features(self, solver, phase, u_prev, du_prev, scale, dE=None):
+        """The network's input at the solver's current state (right after
+        apply_load_step, before the solve)."""
+        if not self.full:
+            return features(phase, solver.damage(), du_prev, scale)
+        return features_full(phase, solver.damage(), du_prev, scale, u_prev,
+                             solver.get_state()["E"], dE)
+
+    def record_sample(self, f, du_prev, du, scale, shape):
+        """A training pair: the input f at the start of an increment and the
+        increment du of the fluctuation that the solve reached."""
+        self.samples.append((f, ((du - du_prev) / scale).astype(np.float32), tuple(shape)))
+
+    def predict_from(self, f, du_prev, scale, shape):
+        """Predicted increment of the fluctuation from the input f, float64."""
+        corr = self.net.predict(self._x16(f), tuple(shape)).double().cpu().numpy()
+        return du_prev + scale * corr
+
+    def warm_start(self, solver, phase, u_prev, du_prev, scale, dE=None):
         """Set the solver's initial guess for the increment just applied
-        (after apply_load_step): the learned one, u_prev + predict(...), if
-        its equilibrium residual r_eq is below that of Algorithm 2's plain
-        guess (the previous fluctuation u_prev, which the solver holds on
-        entry); otherwise the plain guess is kept. Returns True if the learned
-        guess was taken."""
+        (after apply_load_step): the learned one, u_prev + the predicted
+        increment, if its equilibrium residual r_eq is below that of
+        Algorithm 2's plain guess (the previous fluctuation u_prev, which the
+        solver holds on entry); otherwise the plain guess is kept. Returns
+        True if the learned guess was taken."""
         r_plain = solver.residual()
-        solver.set_displacement(u_prev + self.predict(phase, solver.damage(), du_prev, scale))
+        if self.full:
+            du = self.predict_from(self.state_features(solver, phase, u_prev, du_prev, scale, dE),
+                                   du_prev, scale, phase.shape)
+        else:
+            du = self.predict(phase, solver.damage(), du_prev, scale)
+        solver.set_displacement(u_prev + du)
         if solver.residual() < r_plain:
             return True
         solver.set_displacement(u_prev)

@@ -13,7 +13,10 @@ from tests.gpu_util import require_gpu, announce
 
 pytestmark = pytest.mark.gpu
 
-CASES = [((5, 6, 7), 6, 16), ((4, 4, 4), 16, 16), ((8, 6, 4), 16, 3), ((3, 5, 2), 3, 8)]
+CASES = [((5, 6, 7), 6, 16), ((4, 4, 4), 16, 16), ((8, 6, 4), 16, 3), ((3, 5, 2), 3, 8),
+         # wide layers (filter bank read from global memory, tiles of 16 channels; 20 and 18
+         # leave a partial tile)
+         ((6, 5, 4), 48, 16), ((4, 4, 4), 128, 64), ((5, 3, 4), 64, 20), ((4, 6, 2), 18, 16)]
 
 
 def _net_and_lib():
@@ -310,16 +313,30 @@ def test_pool_and_upsample_kernels_against_oracle():
     assert np.abs(gc.double().cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
-def test_unet_forward_and_gradients_against_oracle():
-    """The encoder-decoder (3 levels) on an 8^3 cell: output and every layer's
-    weight and bias gradients against the oracle's FP64 composition with the
-    same BF16 weights and the same BF16 rounding of every convolution input.
-    The kernels accumulate in FP32, so a BF16 rounding of an activation can
-    land one unit apart (2^-8) at a few voxels: 1e-3 of the norm allowed."""
+@pytest.mark.parametrize("levels,widths,cin,shape,tol",
+                         [(3, None, 6, (8, 8, 8), 1e-3),
+                          (4, (16, 32, 64, 64), 18, (16, 16, 16), 3e-3)])
+def test_unet_forward_and_gradients_against_oracle(levels, widths, cin, shape, tol):
+    """The encoder-decoder (3 levels of 16 channels on an 8^3 cell; 4 levels
+    widening 16, 32, 64, 64 with 18 input channels on a 16^3 cell, most of
+    whose layers run in the wide kernels): output and every layer's weight
+    and bias gradients against the oracle's FP64 composition with the same
+    BF16 weights and the same BF16 rounding of every convolution input. The
+    kernels accumulate in FP32, so a BF16 rounding of an activation can land
+    one unit apart (2^-8) at a few voxels, and later layers carry it on: 1e-3
+    of the norm allowed for the output of the 3-level network (5 rounded
+    layers), 3e-3 for the 4-level one (8 rounded layers, activations up to 4x
+    wider). A ReLU whose input lies within FP32 rounding of zero can also
+    decide differently on the two sides, and one such voxel moves a weight
+    gradient (a sum of random-sign terms over the grid) by O(1/sqrt(N)). So
+    the gradients are checked against the oracle's backward pass run on the
+    GPU's own forward values (its activations, ReLU decisions and BF16
+    inputs): only the FP32 accumulation of the backward kernels differs there,
+    1e-4 of the norm."""
     torch = require_gpu()
-    announce("nn unet parity")
+    announce("nn unet parity", levels, widths)
     from paper_2207_10657_amd.warmstart import UNet, _ptr
-    net = UNet(levels=3, seed=2)
+    net = UNet(levels=levels, seed=2, widths=widths, in_channels=cin)
     rng = np.random.default_rng(9)
     # a non-zero output layer (its initial weights are zero)
     w = rng.normal(scale=0.1, size=tuple(net.out.w.shape))
@@ -328,8 +345,7 @@ def test_unet_forward_and_gradients_against_oracle():
                                       net._stream()))
     for layer in net.enc + net.dec + [net.out]:
         layer.b.copy_(torch.tensor(rng.normal(scale=0.05, size=layer.cout), dtype=torch.float32))
-    shape = (8, 8, 8)
-    x = nn.bf16_round(rng.normal(size=(6,) + shape))
+    x = nn.bf16_round(rng.normal(size=(cin,) + shape))
     x16 = net.to_bf16(_dev(torch, x))
     y, st = net.forward(x16, shape)
     gy = rng.normal(size=tuple(y.shape)).astype(np.float32).astype(np.float64)
@@ -339,10 +355,16 @@ def test_unet_forward_and_gradients_against_oracle():
     def pw(layer):
         return _bf16_to_f64(layer.w16).reshape(layer.w.shape), layer.b.double().cpu().numpy()
     p = {"enc": [pw(l) for l in net.enc], "dec": [pw(l) for l in net.dec], "out": pw(net.out)}
-    yr, sr = nn.unet_forward(x, p, 3, bf16=True)
-    gr = nn.unet_backward(gy, p, sr, 3)
+    yr, sr = nn.unet_forward(x, p, levels, bf16=True)
     yg = y.double().cpu().numpy()
-    assert np.linalg.norm(yg - yr) <= 1e-3 * np.linalg.norm(yr)
+    assert np.linalg.norm(yg - yr) <= tol * np.linalg.norm(yr)
+    f64 = lambda t: t.double().cpu().numpy()
+    sg = {"enc": [f64(e) for e in st["enc"]],
+          "in": [x] + [_bf16_to_f64(t).reshape(t.shape) for t in st["pool16"]],
+          "dec": [f64(dd[0]) for dd in st["dec"]],
+          "cat": [_bf16_to_f64(c).reshape(c.shape) if c is not None else None for c in st["cat"]],
+          "out_in": _bf16_to_f64(st["dec"][0][1]).reshape(st["dec"][0][1].shape)}
+    gr = nn.unet_backward(gy, p, sg, levels)
     ref = {id(net.out): gr["out"]}
     for l, layer in enumerate(net.enc):
         ref[id(layer)] = gr["enc"][l]
@@ -353,8 +375,8 @@ def test_unet_forward_and_gradients_against_oracle():
         rw, rb = ref[id(layer)]
         gwn = gw.double().cpu().numpy()
         gbn = gb.double().cpu().numpy()
-        assert np.linalg.norm(gwn - rw) <= 1e-3 * np.linalg.norm(rw), (layer.cin, layer.cout)
-        assert np.linalg.norm(gbn - rb) <= 1e-3 * np.linalg.norm(rb) + 1e-12
+        assert np.linalg.norm(gwn - rw) <= 1e-4 * np.linalg.norm(rw), (layer.cin, layer.cout)
+        assert np.linalg.norm(gbn - rb) <= 1e-4 * np.linalg.norm(rb) + 1e-12
 
 
 def test_unet_training_fits_a_smoothing():
