@@ -206,6 +206,95 @@ def warm_start_bench(n=16, train_seeds=tuple(range(101, 149)), test_seed=201, st
             "held_out_steps": steps, "guesses": out}
 
 
+def warm_start_scaled_bench(n=64, train_seeds=tuple(range(4000, 4050)),
+                            test_seeds=tuple(range(4050, 4055)), steps=6, epochs=8, log=None):
+    """The learned warm start at the scale of its configuration: cells of the
+    workload recipe at n^3 (radii 4-8 voxels, vf 0.25, one cell per seed),
+    the uniaxial increments of the recipe, each solved to the 1e-8 residual.
+    The 4-level network widening 16, 32, 64, 64 channels takes 18 input
+    channels (phase, damage, previous increment, current strain, macroscopic
+    increment) recorded at the start of each increment; its target is the
+    increment the solve reached. Trained on the increments of `train_seeds`,
+    evaluated on `test_seeds` with the plain guess (the previous
+    fluctuation), the extrapolated previous increment, and the learned guess
+    (kept only where it lowers r_eq): Newton and CG iterations, ms per step."""
+    import torch
+    from paper_2207_10657_amd import Solver
+    from paper_2207_10657_amd.warmstart import WarmStart
+    from synthetic import inclusion_microstructure, workload
+    w = workload("c1_3d%d" % n)
+    dE = w.load_path[0]
+    scale = float(np.linalg.norm(dE)) * n
+    shape = (n, n, n)
+    ws = WarmStart(seed=0, full=True)
+
+    def cell(seed):
+        return inclusion_microstructure(shape, 4.0 * n / 64, 8.0 * n / 64, 0.25, seed)[0]
+
+    def run(phase, guess=None, record=False):
+        s = Solver(shape, "q1")
+        s.setup(phase, w.materials)
+        u_prev = np.zeros((3,) + shape)
+        du_prev = None
+        newton = cg = conv = taken = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.apply_load_step(dE)
+            f = None
+            if record and du_prev is not None:
+                f = ws.state_features(s, phase, u_prev, du_prev, scale, dE)
+            if guess == "extrapolate" and du_prev is not None:
+                s.set_displacement(u_prev + du_prev)
+            elif guess == "learned" and du_prev is not None:
+                taken += int(ws.warm_start(s, phase, u_prev, du_prev, scale, dE))
+            r = s.solve_increment(SOLVE)
+            newton += r["newton_iters"]
+            cg += r["cg_iters"]
+            conv += int(r["converged"])
+            u = s.get_state()["u"]
+            if f is not None and r["converged"]:
+                ws.record_sample(f, du_prev, u - u_prev, scale, shape)
+            du_prev, u_prev = u - u_prev, u
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out = {"newton_iters": newton, "cg_iters": cg, "converged_steps": conv,
+               "ms_per_step": dt / steps * 1e3}
+        if guess == "learned":
+            out["learned_guess_taken"] = taken
+        return out
+
+    t0 = time.perf_counter()
+    for k, seed in enumerate(train_seeds):
+        run(cell(seed), record=True)
+        if log and (k + 1) % 10 == 0:
+            log("scaled warm start: %d training cells solved, %d samples" % (k + 1, len(ws.samples)))
+    t1 = time.perf_counter()
+    losses = ws.train(epochs)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if log:
+        log("scaled warm start: trained, loss %.3e -> %.3e"
+            % (float(np.mean(losses[:20])), float(np.mean(losses[-20:]))))
+    guesses = {}
+    for g in (None, "extrapolate", "learned"):
+        per = [run(cell(seed), g) for seed in test_seeds]
+        agg = {k: sum(p[k] for p in per) for k in ("newton_iters", "cg_iters", "converged_steps")}
+        agg["ms_per_step"] = float(np.mean([p["ms_per_step"] for p in per]))
+        if g == "learned":
+            agg["learned_guess_taken"] = sum(p["learned_guess_taken"] for p in per)
+        guesses[g or "previous"] = agg
+        if log:
+            log("scaled warm start: %s guess done" % (g or "previous"))
+    return {"grid": n, "levels": 4, "widths": list(ws.net.widths), "in_channels": 18,
+            "train_cells": len(train_seeds), "test_cells": len(test_seeds),
+            "increments_per_cell": steps, "samples": len(ws.samples), "epochs": epochs,
+            "data_s": t1 - t0, "train_s": t2 - t1,
+            "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))],
+            "guesses": guesses}
+
+
 def batch_bench(w, steps):
     """The six unit load cases of the cell, `steps` increments each after one
     untimed increment: solved one cell after the other, then as one batch
@@ -716,6 +805,10 @@ def main():
                     help="launch shapes (JSON, as config.launch_shapes of a bench line) for the "
                          "timed steps instead of the autotuner's choice, e.g. to profile the "
                          "shapes an unprofiled run chose")
+    ap.add_argument("--warm-start-64", action="store_true",
+                    help="also run the learned warm start at its configured scale: 64^3 cells, "
+                         "the 4-level widening network, 50 training and 5 held-out cells "
+                         "(minutes)")
     ap.add_argument("--stall-study", action="store_true",
                     help="also run the timed steps with the CG stall exit in both precisions "
                          "(minutes: the exit leaves Newton steps unconverged)")
@@ -1023,6 +1116,9 @@ def main():
     if not args.no_warm_start:
         out["warm_start"] = warm_start_bench()
         progress("warm start done")
+    if args.warm_start_64:
+        out["warm_start_64"] = warm_start_scaled_bench(log=progress)
+        progress("scaled warm start done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_matvecs)
     print(json.dumps(out), flush=True)
