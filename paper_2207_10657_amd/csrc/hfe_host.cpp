@@ -126,7 +126,10 @@ Layout make_layout(const Grid& g) {
   L.soft = take((size_t)g.N);
   L.emask = take((size_t)g.N * sizeof(uint16_t));
   L.spec = take((size_t)g.dim * g.nz * g.ny * (g.nx / 2 + 1) * sizeof(double2));
-  L.partial_rows = (int)std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024);
+  // rows of partial sums: one per block of the element and vector kernels,
+  // one per canonical tile of the Hessian
+  L.partial_rows = (int)std::max<long long>(
+      std::max<long long>((g.N + hfe::kBlock - 1) / hfe::kBlock, 1024), hfe::tile_count(g));
   L.partials = take((size_t)L.partial_rows * hfe::kMaxPartials * sizeof(double));
   L.partials2 = take((size_t)L.partial_rows * 2 * sizeof(double));
   L.partials3 = take((size_t)L.partial_rows * 6 * sizeof(double));

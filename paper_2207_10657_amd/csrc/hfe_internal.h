@@ -31,6 +31,24 @@ struct Grid {
   long long N;        // nodes = elements
 };
 
+// Canonical tiles of the node grid (3D): 8 x 4 x 4 nodes from the origin,
+// cut by the grid at its far faces. The Hessian sums over nodes (and over the
+// elements, each counted at its anchor node, the one with the lowest x, y,
+// z) per tile in one fixed order and writes one partial row per tile:
+// row = tx + ntx (ty + nty tz). Every Hessian launch shape covers whole
+// tiles, so the rows, and every total formed from them, have the same bits
+// under every shape.
+constexpr int kTileX = 8, kTileY = 4, kTileZ = 4, kTileQ = kTileX * kTileY;
+__host__ __device__ inline int tiles_x(const Grid& g) { return (g.nx + kTileX - 1) / kTileX; }
+__host__ __device__ inline int tiles_y(const Grid& g) { return (g.ny + kTileY - 1) / kTileY; }
+__host__ __device__ inline int tiles_z(const Grid& g) { return (g.nz + kTileZ - 1) / kTileZ; }
+__host__ __device__ inline int tile_count(const Grid& g) {
+  return tiles_x(g) * tiles_y(g) * tiles_z(g);
+}
+__host__ __device__ inline int tile_row(const Grid& g, int tx, int ty, int tz) {
+  return tx + tiles_x(g) * (ty + tiles_y(g) * tz);
+}
+
 struct Macro {        // macroscopic strain E, full 3x3 row-major
   double e[9];
 };

@@ -1,7 +1,8 @@
-// Deterministic block reductions: every block writes one row of NV partial
-// sums; a single-block kernel later adds the rows in a fixed order. The order
-// of every addition is fixed by the launch shape, so repeated runs give the
-// same bits.
+// Deterministic reductions: every block (or, for the Hessian, every
+// canonical tile) writes one row of NV partial sums; a single block later
+// adds the rows in a fixed order. Where a kernel has launch shapes to choose
+// from (the Hessian, the fused FFT passes), the order of every addition is
+// independent of the shape, so every shape gives the same bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,6 +15,16 @@ namespace hfe {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of a canonical tile's 32 column sums (hfe_internal.h): the lanes whose
+// bits 0..4 are q = x + 8 y hold them, and the butterfly pairs q with q ^ 16,
+// then q ^ 8, ..., q ^ 1. Every lane of each 32-lane half of the wave must
+// take part; the halves do not mix.
+__device__ __forceinline__ double tile_butterfly(double v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 

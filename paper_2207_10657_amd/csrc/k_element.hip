@@ -1223,6 +1223,56 @@ __device__ __forceinline__ void hess_state(const HessArgs<R>& A, long long eg, i
 // ((f0 + f1) + f2) + f3, then the two group sums added. It is what lets the
 // column kernel carry the az = 1 sums from one layer to the next.
 
+// The canonical tile sums of a brick (hfe_internal.h). The values are staged
+// by thread: st[t] is d.Kd of node thread t (t = x + bx (y + by z)), and
+// st[BX*BY*BZ + k * E + t] value k (|Dd|^2, then the NE - 1 tails) of element
+// thread t (t = (x+1) + (bx+1) ((y+1) + (by+1) (z+1)) for the element anchored
+// at node x, y, z; E elements per brick). One thread per tile position q adds
+// its column in ascending z onto 0.0, the tile's 32 columns are added by
+// tile_butterfly, and lane q = 0 writes the tile's row: d.Kd and |Dd|^2 to
+// rows, the tails to tail_rows (6 per row). The brick's extents are
+// multiples of the tile's, so its tiles are whole canonical tiles or those
+// the grid cuts.
+template <int BX, int BY, int BZ, int NE>
+__device__ __forceinline__ void brick_tile_rows(const double* st, int bx, int by, int bz, int x0,
+                                                int y0, int z0, const Grid& g, double* rows,
+                                                double* tail_rows) {
+  static_assert(BX % kTileX == 0 && BY % kTileY == 0 && BZ % kTileZ == 0, "whole tiles");
+  static_assert(HES_DKD == 0 && HES_DD == 1 && HES_NV == 2, "row layout");
+  constexpr int TX = BX / kTileX, TY = BY / kTileY, TZ = BZ / kTileZ, NV = 1 + NE;
+  constexpr int kOwn = BX * BY * BZ, kElems = (BX + 1) * (BY + 1) * (BZ + 1);
+  constexpr int nsum = TX * TY * TZ * kTileQ;
+  const int tid = threadIdx.x;
+  if (tid >= (nsum + 63) / 64 * 64) return;
+  const int q = tid & (kTileQ - 1), tl = tid / kTileQ;
+  const int ix = tl % TX, iy = (tl / TX) % TY, iz = tl / (TX * TY);
+  const int x = ix * kTileX + (q % kTileX), y = iy * kTileY + q / kTileX;
+  double c[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) c[k] = 0.0;
+  if (tid < nsum && x < bx && y < by) {
+#pragma unroll
+    for (int zz = 0; zz < kTileZ; ++zz) {
+      const int z = iz * kTileZ + zz;
+      if (z < bz) {
+        c[0] += st[x + bx * (y + by * z)];
+        const int e = (x + 1) + (bx + 1) * ((y + 1) + (by + 1) * (z + 1));
+#pragma unroll
+        for (int k = 0; k < NE; ++k) c[1 + k] += st[kOwn + k * kElems + e];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) c[k] = tile_butterfly(c[k]);
+  if (tid < nsum && q == 0 && ix * kTileX < bx && iy * kTileY < by && iz * kTileZ < bz) {
+    const long long row = tile_row(g, x0 / kTileX + ix, y0 / kTileY + iy, z0 / kTileZ + iz);
+    rows[row * HES_NV + HES_DKD] = c[0];
+    rows[row * HES_NV + HES_DD] = c[1];
+#pragma unroll
+    for (int k = 2; k < NV; ++k) tail_rows[row * 6 + (k - 2)] = c[k];
+  }
+}
+
 template <typename R, int BX, int BY, int BZ, bool FULL, bool NS, bool MS>
 __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_waves_per_eu<R>())
     k_hessian(HessArgs<R> A) {
@@ -1233,7 +1283,7 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
   // as the element forces F[8][3][kElems] (corner, component, element).
   constexpr int kElems = BrickShape<BX, BY, BZ>::elems;
   constexpr int kLds = 3 * kTile > 24 * kElems ? 3 * kTile : 24 * kElems;
-  __shared__ R lds[kLds];
+  __shared__ __align__(16) R lds[kLds];
   R (*sv)[kTile] = reinterpret_cast<R (*)[kTile]>(lds);
   const int nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY;
   const int brick = xcd_brick(blockIdx.x, gridDim.x);
@@ -1347,11 +1397,23 @@ __global__ void __launch_bounds__((BrickShape<BX, BY, BZ>::threads), hessian_wav
       dkd += (double)v * (double)vn[c];
     }
   }
-  double red[HES_NV];
-  red[HES_DKD] = dkd;
-  red[HES_DD] = dd;
-  block_reduce_store<HES_NV>(red, A.red.partials);
-  if constexpr (MS) block_reduce_store<6>(tv, A.red_tail.partials);
+  // the per-tile sums: node and element values staged by thread in the LDS
+  // area (its element forces are read), then summed per tile
+  constexpr int kNe = MS ? 7 : 1;
+  static_assert((kOwn + kNe * kElems) * sizeof(double) <= sizeof(lds), "tile staging fits");
+  __syncthreads();
+  double* st = reinterpret_cast<double*>(lds);
+  if (tid < nown) st[tid] = dkd;
+  if (active) {
+    st[kOwn + tid] = dd;
+    if constexpr (MS) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) st[kOwn + (1 + k) * kElems + tid] = tv[k];
+    }
+  }
+  __syncthreads();
+  brick_tile_rows<BX, BY, BZ, kNe>(st, bx, by, bz, x0, y0, z0, g, A.red.partials,
+                                   A.red_tail.partials);
 }
 
 // ---- column-marching Hessian (Q1) -----------------------------------------
@@ -1385,7 +1447,7 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
   const Grid& g = A.g;
   if (A.cg && A.cg->done) return;
   __shared__ R sv[3][2][S::layer];       // direction: component, ring slot, node
-  __shared__ R F[24][S::elems];          // element forces: corner * 3 + component, element
+  __shared__ __align__(16) R F[24][S::elems];   // element forces: corner * 3 + component, element
   const int ncx = g.nx / CX, ncy = g.ny / CY;
   const int blk = xcd_brick(blockIdx.x, gridDim.x);
   const int cxi = blk % ncx, cyi = (blk / ncx) % ncy, czi = blk / (ncx * ncy);
@@ -1443,6 +1505,8 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
   }
   __syncthreads();
   R top[3] = {R(0), R(0), R(0)};        // az = 1 sums of the layer below, for node layer k
+  // column sums of the current tile layer group (canonical tiles, 4 node
+  // layers): this thread's node, and its element if the column owns it
   double dkd = 0.0, dd = 0.0;
   double tv[MS ? 6 : 1] = {};
   for (int k = 0; k <= nzl; ++k) {
@@ -1471,10 +1535,15 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
       const int sz = (k & 1) ? -S::layer : S::layer;       // to the other ring slot
       auto tile = [&](int c, int i) { return (&sv[c][0][0])[i]; };
       double de = 0.0;
+      double te[MS ? 6 : 1] = {};
       hess_element<R, NS, MS>(tile, t0, S::tx, sz, lam, mu, aq, soft, A.sw + eg,
                               NS ? A.sn + eg : nullptr, N, f, de, k >= 1 && ex >= 1 && ey >= 1,
-                              A.U, tv);
+                              A.U, te);
       dd += de;
+      if constexpr (MS) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tv[i] += te[i];
+      }
 #pragma unroll
       for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -1489,6 +1558,7 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
     }
     __syncthreads();
     if (node) {
+      double pn = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         R lo = R(0), hi = R(0);
@@ -1503,19 +1573,59 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
           // then the top sums carried from element layer k - 1
           const R v = lo + top[c];
           A.f[c * N + (long long)(z0 + k - 1) * nxy + oxy] = v;
-          dkd += (double)v * (double)vn[c];
+          pn += (double)v * (double)vn[c];
         }
         top[c] = hi;
       }
+      dkd += pn;
     }
     if (more) store_layer(k + 2, rn);    // slot k & 1: node layer k is done
     __syncthreads();
+    // node layer z0 + k - 1 ends a canonical tile layer group (z0 is a
+    // multiple of 4): the column sums go through F (free until the next
+    // element layer) in tile order, and each tile's 32 columns are added as
+    // in the brick kernels
+    if (k >= 1 && (((k - 1) & (kTileZ - 1)) == kTileZ - 1 || k == nzl)) {
+      constexpr int kNe = MS ? 7 : 1, kTx = CX / kTileX;
+      static_assert(CX % kTileX == 0 && CY % kTileY == 0, "whole tiles");
+      static_assert((S::own + kNe * S::elems) * sizeof(double) <= sizeof(F), "tile staging fits");
+      // staged by thread: node thread t = x + CX y, element thread
+      // t = (x+1) + (CX+1) (y+1) for the element anchored at node x, y
+      double* st = reinterpret_cast<double*>(&F[0][0]);
+      if (node) st[tid] = dkd;
+      if (active) {
+        st[S::own + tid] = dd;
+        if constexpr (MS) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) st[S::own + (1 + i) * S::elems + tid] = tv[i];
+        }
+      }
+      __syncthreads();
+      if (tid < S::own) {     // S::own is a multiple of 64; lane bits 0..4 are q
+        const int q = tid & (kTileQ - 1), tl = tid / kTileQ;
+        const int x = (tl % kTx) * kTileX + q % kTileX, y = (tl / kTx) * kTileY + q / kTileX;
+        double cs[1 + kNe];
+        cs[0] = tile_butterfly(st[x + CX * y]);
+#pragma unroll
+        for (int i = 0; i < kNe; ++i)
+          cs[1 + i] = tile_butterfly(st[S::own + i * S::elems + (x + 1) + S::ex * (y + 1)]);
+        if (q == 0) {
+          const long long row = tile_row(g, x0 / kTileX + tl % kTx, y0 / kTileY + tl / kTx,
+                                         (z0 + k - 1) / kTileZ);
+          A.red.partials[row * HES_NV + HES_DKD] = cs[0];
+          A.red.partials[row * HES_NV + HES_DD] = cs[1];
+          if constexpr (MS) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) A.red_tail.partials[row * 6 + i] = cs[2 + i];
+          }
+        }
+      }
+      __syncthreads();
+      dkd = dd = 0.0;
+#pragma unroll
+      for (int i = 0; i < (MS ? 6 : 1); ++i) tv[i] = 0.0;
+    }
   }
-  double red[HES_NV];
-  red[HES_DKD] = dkd;
-  red[HES_DD] = dd;
-  block_reduce_store<HES_NV>(red, A.red.partials);
-  if constexpr (MS) block_reduce_store<6>(tv, A.red_tail.partials);
 }
 
 template <int MODE, int NV, int BX, int BY, int BZ>
@@ -1534,12 +1644,11 @@ hipError_t launch_brick_shape(const ElemArgs& A, hipStream_t s, int* nblocks) {
   return hipGetLastError();
 }
 
-// Brick shapes of the residual and trial passes: 8x8x4 (448 threads), or
-// 16x4x4 (448) for shapes 2 and 3.
+// Brick shape of the residual pass: 8x8x4 (448 threads) whatever Hessian
+// shape is tuned, so that its block sums, and the Newton decisions taken on
+// them, are the same under every tuning.
 template <int MODE, int NV>
 hipError_t launch_brick(const ElemArgs& A, hipStream_t s, int* nblocks) {
-  const int shape = A.brick_shape;
-  if (shape == 2 || shape == 3) return launch_brick_shape<MODE, NV, 16, 4, 4>(A, s, nblocks);
   return launch_brick_shape<MODE, NV, 8, 8, 4>(A, s, nblocks);
 }
 
@@ -1562,7 +1671,7 @@ void launch_hess(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
 template <typename R, int BX, int BY, int BZ>
 hipError_t launch_hessian_shape(const HessArgs<R>& A, hipStream_t s, int* nblocks) {
   const int nb = ((A.g.nx + BX - 1) / BX) * ((A.g.ny + BY - 1) / BY) * ((A.g.nz + BZ - 1) / BZ);
-  *nblocks = nb;
+  *nblocks = tile_count(A.g);   // partial rows: one per canonical tile
   const bool full = A.g.nx % BX == 0 && A.g.ny % BY == 0 && A.g.nz % BZ == 0;
   const dim3 grid(nb), block(BrickShape<BX, BY, BZ>::threads);
   if constexpr (std::is_same<R, double>::value) {
@@ -1598,9 +1707,9 @@ constexpr ColShape kColShapes[kHessianShapes - kBrickOnly] = {
 template <typename R, int CX, int CY>
 hipError_t launch_hessian_col(const HessArgs<R>& A, int bz, hipStream_t s, int* nblocks) {
   const Grid& g = A.g;
-  if (g.nx % CX != 0 || g.ny % CY != 0 || bz < 1) return hipErrorInvalidValue;
+  if (g.nx % CX != 0 || g.ny % CY != 0 || bz < 1 || bz % kTileZ != 0) return hipErrorInvalidValue;
   const int nb = (g.nx / CX) * (g.ny / CY) * ((g.nz + bz - 1) / bz);
-  *nblocks = nb;
+  *nblocks = tile_count(g);   // partial rows: one per canonical tile
   const dim3 grid(nb), block(ColumnShape<CX, CY>::threads);
   if constexpr (std::is_same<R, double>::value) {
     if (A.U) {

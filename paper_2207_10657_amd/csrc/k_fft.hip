@@ -462,30 +462,60 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
   lds_fft<true>(ny, lds, P, 1, P, twy);
   merge_c2r(lds, M, ny, P, twp);
   lds_fft<true>(M, lds, ny, P, 1, twx);
-  if (MODE == PLANE_INV_CG) {
-    // y += alpha w and the residual inner products (accumulated in FP64),
-    // w never leaves LDS
+  if constexpr (MODE == PLANE_INV_CG) {
+    // y += alpha w and the residual inner products (in FP64), w never leaves
+    // LDS. The products are added in an order that does not depend on the
+    // block size: pair i is lane i % 64 of the wave that handles the run of
+    // 64 pairs holding it (block sizes are multiples of 64), each run is
+    // summed by a butterfly over its lanes, and the runs in ascending order.
+    constexpr int kMaxRuns = 15 * 1024 / 64;   // npairs < 15 * 1024 (fft_plane_fits)
+    __shared__ double runs[2][kMaxRuns];
     const R alpha = (R)cf.st_in->alpha;
     V* y2 = reinterpret_cast<V*>(cf.y + plane);
-    double acc[2] = {0.0, 0.0};
+    const int lane = tid & 63;
     for (int base = 0; base < npairs; base += kPre * nt) {
       if (base > 0) load_round(base);
 #pragma unroll
       for (int u = 0; u < kPre; ++u) {
         const int i = base + u * nt + tid;
-        if (i < npairs) {
-          const int yy = i / M, m = i - yy * M;
-          const V w = lds[yy * P + m];
-          const V yo = pa[u];
-          const V gi = pb[u];
-          const V yn = mk<V>(yo.x + alpha * w.x, yo.y + alpha * w.y);
-          y2[i] = yn;
-          acc[0] += (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
-          acc[1] += (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
+        const int run0 = i - lane;             // the same for the whole wave
+        if (run0 < npairs) {
+          double p0 = 0.0, p1 = 0.0;
+          if (i < npairs) {
+            const int yy = i / M, m = i - yy * M;
+            const V w = lds[yy * P + m];
+            const V yo = pa[u];
+            const V gi = pb[u];
+            const V yn = mk<V>(yo.x + alpha * w.x, yo.y + alpha * w.y);
+            y2[i] = yn;
+            p0 = (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
+            p1 = (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
+          }
+          p0 = wave_sum(p0);
+          p1 = wave_sum(p1);
+          if (lane == 0) {
+            runs[0][run0 / 64] = p0;
+            runs[1][run0 / 64] = p1;
+          }
         }
       }
     }
-    block_reduce_store<2>(acc, cf.partials, (int)(blockIdx.y * gridDim.x + blockIdx.x));
+    __syncthreads();
+    if (tid < 64) {
+      const int nruns = (npairs + 63) / 64;
+      double s0 = 0.0, s1 = 0.0;
+      for (int r = tid; r < nruns; r += 64) {
+        s0 += runs[0][r];
+        s1 += runs[1][r];
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (tid == 0) {
+        const size_t row = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        cf.partials[row * 2] = s0;
+        cf.partials[row * 2 + 1] = s1;
+      }
+    }
     return;
   }
   V* dst = reinterpret_cast<V*>(out + plane);
@@ -673,8 +703,10 @@ size_t fft_plane_lds_bytes(const Grid& g) {
 
 template <typename R>
 bool fft_plane_fits(const Grid& g) {
-  // LDS of one CU, and at most 15 staged values per thread of a 1024-thread block
-  return fft_plane_lds_bytes<R>(g) <= 160 * 1024 && (long long)(g.nx / 2 + 1) * g.ny <= 15 * 1024;
+  // LDS of one CU less 4 KiB for the passes' static LDS (the run sums of the
+  // fused inverse pass), and at most 15 staged values per thread of a
+  // 1024-thread block
+  return fft_plane_lds_bytes<R>(g) <= 156 * 1024 && (long long)(g.nx / 2 + 1) * g.ny <= 15 * 1024;
 }
 
 namespace {

@@ -1,8 +1,10 @@
 """GPU checks of the batched solve and of the launch-shape autotuner.
 
 Launch shapes change which block computes a value, not the arithmetic of
-that value (every FFT value and every nodal sum of the Hessian is formed in
-the same order whatever the shape), so the Green's operator and K d must be
+that value: every FFT value and every nodal sum of the Hessian is formed in
+the same order whatever the shape, the Hessian's sums are formed per
+canonical 8x4x4 tile of nodes, and the fused inverse FFT pass sums runs of 64
+values. So the Green's operator, K d and a whole Newton solve must be
 bit-identical under every shape the tuner may pick. A batch of solvers on
 their own streams must give, per solver, the bits of the same solve run
 alone."""
@@ -71,6 +73,77 @@ def test_every_launch_shape_gives_the_same_bits(shape):
     announce("autotuned", shape, tuned)
     np.testing.assert_array_equal(s.apply_green(d).cpu().numpy(), ref[0])
     np.testing.assert_array_equal(s.apply_stiffness(d).cpu().numpy(), ref[1])
+
+
+def _spread_tunings(solver):
+    """Every Hessian shape the grid allows, each with other FFT launch shapes,
+    and every plane block size with the 8x8x8 brick."""
+    combos = _shapes(solver)
+    by_shape = {}
+    for sh in combos:
+        by_shape.setdefault(sh[3], []).append(sh)
+    picked = []
+    for j, bs in enumerate(sorted(by_shape)):
+        lst = by_shape[bs]
+        picked.append(lst[(7 * j + 3) % len(lst)])
+    for pt in (256, 512, 1024):
+        for sh in combos:
+            if sh[0] == pt and sh[3] == 1 and sh not in picked:
+                picked.append(sh)
+                break
+    return picked
+
+
+@pytest.mark.parametrize("shape,precision,control", [
+    ((32, 32, 24), "fp64", False),   # bricks and every column, columns cut along z
+    ((24, 12, 6), "fp64", False),    # ragged bricks, tiles cut by the grid
+    ((32, 32, 24), "mixed", False),
+    ((16, 16, 12), "fp64", True),    # mean-stress control: the Hessian's tail rows
+])
+def test_every_launch_shape_gives_the_same_solve(shape, precision, control):
+    """A softening increment (Newton with Steihaug CG, its decisions taken on
+    the reductions of the Hessian and of the fused FFT passes) solved under
+    many launch shapes: the Newton log, the CG residual trace, the state and
+    the stress have the same bits under every shape."""
+    torch = require_gpu()
+    announce("same solve under every launch shape", shape, precision, control)
+    from paper_2207_10657_amd import Solver
+    w = workload("c1_3d16")
+    rng = np.random.default_rng(11)
+    phase = (rng.random(shape) < 0.3).astype(np.uint8)
+    s = Solver(shape, "q1")
+    s.setup(phase, w.materials)
+    if control:
+        free = np.zeros((3, 3), dtype=bool)
+        free[1, 1] = free[2, 2] = True
+        s.set_mean_stress_control(free)
+    ck = s.get_state()
+    u0 = 3e-4 * rng.normal(size=(3,) + shape)
+    E0 = np.zeros((3, 3))
+    E0[0, 0] = 1.2e-3
+    dE = np.zeros((3, 3))
+    dE[0, 0] = 2e-4
+    params = {"i_nr_max": 4, "precision": precision}
+    ref = None
+    tunings = _spread_tunings(s)
+    assert len(tunings) >= 6
+    for sh in tunings:
+        pt, pc, pth, bs = sh
+        s.set_tuning(plane_threads=pt, pencil_cols=pc, pencil_threads=pth, plane_threads32=pt,
+                     pencil_cols32=pc, pencil_threads32=pth, brick_shape=bs, brick_shape32=bs)
+        s.set_state(u0, ck["kappa_hist"], E0, ck["R"], ck["Rmax"])
+        s.apply_load_step(dE)
+        rep = s.solve_increment(params)
+        st = s.get_state()
+        log = s.newton_log()
+        out = (np.array([[float(r[k]) for k in sorted(r)] for r in log]), s.cg_trace(), st["u"],
+               st["kappa_hist"], st["E"], s.homogenized_stress())
+        if ref is None:
+            ref = out
+            assert rep["cg_iters"] > 20 and len(log) >= 2, rep
+            continue
+        for a, b in zip(out, ref):
+            np.testing.assert_array_equal(np.asarray(a), np.asarray(b), err_msg=str(sh))
 
 
 def _load_cases(mag):
