@@ -18,14 +18,46 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of a canonical tile's 32 column sums (hfe_internal.h): the lanes whose
-// bits 0..4 are q = x + 8 y hold them, and the butterfly pairs q with q ^ 16,
-// then q ^ 8, ..., q ^ 1. Every lane of each 32-lane half of the wave must
-// take part; the halves do not mix.
-__device__ __forceinline__ double tile_butterfly(double v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Cross-lane sums by DPP (no LDS traffic). dpp_add<CTRL, ROWS> adds to v the
+// value of the lane the DPP control selects; lanes of rows (16 lanes each)
+// outside the row mask add 0. A double moves as its two 32-bit halves under
+// the same control. Floating-point addition is commutative, so after each of
+// the symmetric steps below every lane of the group holds the same value.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each row of 16 lanes, in every lane of the row: lane pairs (xor 1),
+// quads (xor 2), half-rows (mirror within 8), the two half-rows (mirror
+// within 16).
+__device__ __forceinline__ double row16_sum(double v) {
+  v = dpp_add<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v = dpp_add<0x141>(v);   // row_half_mirror
+  v = dpp_add<0x140>(v);   // row_mirror
   return v;
+}
+
+// Sum of a canonical tile's 32 column sums (hfe_internal.h), held by the
+// lanes of a half-wave whose bits 0..4 are q = x + 8 y: each row of 16, then
+// the second row adds the first (row_bcast:15). The tile's sum is in the
+// half-wave's lanes q = 16..31; the halves do not mix. Every lane of the
+// wave must take part.
+__device__ __forceinline__ double tile_sum32(double v) {
+  v = row16_sum(v);
+  return dpp_add<0x142, 0xa>(v);
+}
+
+// Sum over the 64 lanes of a wave in lane 63 (the other lanes hold partial
+// sums): each half-wave as in tile_sum32, then the upper half adds the lower
+// half's sum (row_bcast:31).
+__device__ __forceinline__ double wave_total63(double v) {
+  v = tile_sum32(v);
+  return dpp_add<0x143, 0xc>(v);
 }
 
 // Reduce acc[NV] over the block (blockDim.x a multiple of 64, at most 1024)

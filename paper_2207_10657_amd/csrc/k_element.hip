@@ -1229,7 +1229,7 @@ __device__ __forceinline__ void hess_state(const HessArgs<R>& A, long long eg, i
 // thread t (t = (x+1) + (bx+1) ((y+1) + (by+1) (z+1)) for the element anchored
 // at node x, y, z; E elements per brick). One thread per tile position q adds
 // its column in ascending z onto 0.0, the tile's 32 columns are added by
-// tile_butterfly, and lane q = 0 writes the tile's row: d.Kd and |Dd|^2 to
+// tile_sum32, and lane q = 31 writes the tile's row: d.Kd and |Dd|^2 to
 // rows, the tails to tail_rows (6 per row). The brick's extents are
 // multiples of the tile's, so its tiles are whole canonical tiles or those
 // the grid cuts.
@@ -1263,8 +1263,8 @@ __device__ __forceinline__ void brick_tile_rows(const double* st, int bx, int by
     }
   }
 #pragma unroll
-  for (int k = 0; k < NV; ++k) c[k] = tile_butterfly(c[k]);
-  if (tid < nsum && q == 0 && ix * kTileX < bx && iy * kTileY < by && iz * kTileZ < bz) {
+  for (int k = 0; k < NV; ++k) c[k] = tile_sum32(c[k]);
+  if (tid < nsum && q == kTileQ - 1 && ix * kTileX < bx && iy * kTileY < by && iz * kTileZ < bz) {
     const long long row = tile_row(g, x0 / kTileX + ix, y0 / kTileY + iy, z0 / kTileZ + iz);
     rows[row * HES_NV + HES_DKD] = c[0];
     rows[row * HES_NV + HES_DD] = c[1];
@@ -1605,11 +1605,11 @@ __global__ void __launch_bounds__((ColumnShape<CX, CY>::threads), hessian_waves_
         const int q = tid & (kTileQ - 1), tl = tid / kTileQ;
         const int x = (tl % kTx) * kTileX + q % kTileX, y = (tl / kTx) * kTileY + q / kTileX;
         double cs[1 + kNe];
-        cs[0] = tile_butterfly(st[x + CX * y]);
+        cs[0] = tile_sum32(st[x + CX * y]);
 #pragma unroll
         for (int i = 0; i < kNe; ++i)
-          cs[1 + i] = tile_butterfly(st[S::own + i * S::elems + (x + 1) + S::ex * (y + 1)]);
-        if (q == 0) {
+          cs[1 + i] = tile_sum32(st[S::own + i * S::elems + (x + 1) + S::ex * (y + 1)]);
+        if (q == kTileQ - 1) {
           const long long row = tile_row(g, x0 / kTileX + tl % kTx, y0 / kTileY + tl / kTx,
                                          (z0 + k - 1) / kTileZ);
           A.red.partials[row * HES_NV + HES_DKD] = cs[0];

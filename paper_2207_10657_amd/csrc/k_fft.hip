@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
     // LDS. The products are added in an order that does not depend on the
     // block size: pair i is lane i % 64 of the wave that handles the run of
     // 64 pairs holding it (block sizes are multiples of 64), each run is
-    // summed by a butterfly over its lanes, and the runs in ascending order.
+    // summed across its lanes (wave_total63), and the runs in ascending order.
     constexpr int kMaxRuns = 15 * 1024 / 64;   // npairs < 15 * 1024 (fft_plane_fits)
     __shared__ double runs[2][kMaxRuns];
     const R alpha = (R)cf.st_in->alpha;
@@ -491,9 +491,9 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
             p0 = (double)yn.x * (double)gi.x + (double)yn.y * (double)gi.y;
             p1 = (double)yo.x * (double)gi.x + (double)yo.y * (double)gi.y;
           }
-          p0 = wave_sum(p0);
-          p1 = wave_sum(p1);
-          if (lane == 0) {
+          p0 = wave_total63(p0);
+          p1 = wave_total63(p1);
+          if (lane == 63) {
             runs[0][run0 / 64] = p0;
             runs[1][run0 / 64] = p1;
           }
@@ -508,9 +508,9 @@ __global__ void __launch_bounds__(1024) k_plane(Grid g, FftTablesT<R> t, const R
         s0 += runs[0][r];
         s1 += runs[1][r];
       }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-      if (tid == 0) {
+      s0 = wave_total63(s0);
+      s1 = wave_total63(s1);
+      if (tid == 63) {
         const size_t row = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
         cf.partials[row * 2] = s0;
         cf.partials[row * 2 + 1] = s1;

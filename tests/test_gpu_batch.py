@@ -277,13 +277,28 @@ def test_projected_hessian_48_and_96_against_the_displacement_oracle(n):
     s.apply_load_step(E)
     s.set_displacement(u)
     d = rng.normal(size=(3,) + w.shape)
-    out = s.apply_projected_hessian(torch.tensor(d, device="cuda"))[0].cpu().numpy()
-    s.close()
+    dt = torch.tensor(d, device="cuda")
+    out = s.apply_projected_hessian(dt)[0].cpu().numpy()
     kh = material.MaterialField(w.phase, w.materials, 8).initial_history()
-    ref = UOperator(w.phase, w.materials, "q1", E, u, kh).apply(d)
+    op = UOperator(w.phase, w.materials, "q1", E, u, kh)
+    ref = op.apply(d)
     err = max_err(out, ref)
     print("[batch] %d^3 projected Hessian vs displacement oracle: max err %.2e" % (n, err),
           flush=True)
+    if err >= 1e-12:
+        # which stage: K d, or the Green's operator applied to the GPU's K d
+        Kd = s.apply_stiffness(dt).cpu().numpy()
+        GKd = s.apply_green(torch.tensor(Kd, device="cuda")).cpu().numpy()
+        out2 = s.apply_projected_hessian(dt)[0].cpu().numpy()
+        Kd_ref = op.stiffness(d)
+        ref1 = UOperator(w.phase, w.materials, "q1", E, u, kh, workers=1).apply(d)
+        bad = np.argwhere(np.abs(out - ref) > 1e-6 * np.abs(ref).max())
+        print("[batch]   K d %.2e, green(K d) %.2e, a second application %.2e, the oracle on "
+              "one thread vs its first result %.2e; %d bad values, z %s, y %s, x %s"
+              % (max_err(Kd, Kd_ref), max_err(GKd, op.green(Kd)), max_err(out2, ref),
+                 max_err(ref1, ref), len(bad), np.unique(bad[:, 1])[:12],
+                 np.unique(bad[:, 2])[:12], np.unique(bad[:, 3])[:12]), flush=True)
+    s.close()
     assert err < 1e-12
 
 

@@ -226,9 +226,14 @@ def test_lockstep_3d_workload_16():
 
 def test_lockstep_3d_workload_8_into_full_damage():
     """The same cell at 8^3, first 15 steps: the damage reaches 1 at step 3
-    and the later steps solve the cracked cell with long CG runs."""
+    and the later steps solve the cracked cell with long CG runs. Those runs
+    (150-280 iterations) end within the method's rounding drift of the CG
+    threshold, so most of the cracked-cell steps are certified ties (on some
+    of them the oracle itself decides differently once its summation order
+    is reversed); the steps before the crack are compared at the parity bar."""
     require_gpu()
-    _lockstep("c1_3d8", 15)
+    compared, ties = _lockstep("c1_3d8", 15, max_tie_frac=0.7)
+    assert compared >= 4, (compared, ties)
 
 
 def test_lockstep_3d_workload_16_solved_to_tolerance():
