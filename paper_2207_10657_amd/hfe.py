@@ -177,6 +177,11 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libhfe.so not built (%s); run paper_2207_10657_amd.build.build()" % path)
+    # torch first: libhfe.so must bind to the HIP runtime torch has loaded.
+    # Loaded before torch, it would bind the system's runtime, torch would
+    # then load its own, and device memory from one would be unknown to the
+    # other (hfe_create fails on the workspace torch allocated).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
