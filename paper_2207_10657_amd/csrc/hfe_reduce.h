@@ -11,10 +11,48 @@
 
 namespace hfe {
 
-// Sum over the 64 lanes of a wavefront (butterfly with xor shuffles).
+
+// The value of lane i ^ 32 and of lane i ^ 16 (gfx950 permlane swaps: with
+// both operands v, the swap's second result holds the upper half-wave's
+// values in the lower lanes and its first result the lower half's in the
+// upper lanes; the 16-lane swap does the same between neighbouring rows).
+__device__ __forceinline__ unsigned int lane_xor32(unsigned int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ unsigned int lane_xor16(unsigned int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16) ? r[0] : r[1];
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront: the butterfly that adds lane i ^ 32,
+// then i ^ 16, 8, 4, 2, 1 (every lane ends with the same value). The
+// exchanges run in registers (permlane swaps for 32 and 16; DPP row_ror:8,
+// which is i ^ 8 within a row; row_ror:4, which gives the value of i ^ 4
+// once values depend on i mod 8 only; quad perms for 2 and 1), with the
+// bits of the shuffle form of the same butterfly. Every lane must take part.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  {
+    const long long b = __double_as_longlong(v);
+    const unsigned int lo = lane_xor32((unsigned int)b), hi = lane_xor32((unsigned int)(b >> 32));
+    v += __longlong_as_double(((long long)hi << 32) | lo);
+  }
+  {
+    const long long b = __double_as_longlong(v);
+    const unsigned int lo = lane_xor16((unsigned int)b), hi = lane_xor16((unsigned int)(b >> 32));
+    v += __longlong_as_double(((long long)hi << 32) | lo);
+  }
+  v += dpp_mov<0x128>(v);   // row_ror:8
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
   return v;
 }
 
