@@ -855,6 +855,35 @@ hfe_status cg_batch(hfe_ctx* c, int slot, int k) {
 }
 
 // Algorithm 1 in displacement coordinates. Result in c->z; returns the exit flag.
+// The CG state at the start of a solve at the current residual (rr0, and the
+// tails under mean-stress control).
+hfe::CgState cg_initial_state(const hfe_ctx* c, double R, double eta_cg, int j_max,
+                              double restart_c, int stall) {
+  hfe::CgState init;
+  std::memset(&init, 0, sizeof(init));
+  init.rr = init.rr0 = init.rr_new = c->rr0;
+  init.R = R;
+  init.eta_cg = eta_cg;
+  init.restart_c = restart_c;
+  init.rr_ref = c->rr0;
+  init.j_ref = 0;
+  init.stall = stall;
+  // mean-stress control: z_e = 0, g_e = g0_e, y_e = g0_e / N_qp, d_e = -y_e
+  init.ne = c->ne;
+  init.nqp = (double)c->g.N * c->g.nq;
+  for (int m = 0; m < c->ne; ++m) {
+    init.comp[m] = c->comp[m];
+    init.ge[m] = c->g0e[m];
+    init.ye[m] = c->g0e[m] / init.nqp;
+    init.de[m] = -init.ye[m];
+  }
+  hfe::tail_tensor(&init, init.de, init.dU);
+  init.jmax = j_max;
+  init.flag = hfe::CG_RUN;
+  init.trace_cap = kTraceCap;
+  return init;
+}
+
 hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, double restart_c,
                     int stall, int* flag, CgInfo* info) {
   const long long n = ndof(c);
@@ -878,29 +907,7 @@ hfe_status steihaug(hfe_ctx* c, double R, double eta_cg, int j_max, int prec, do
     HIPCHK(c, hfe::vec_to_f32(n, c->g0, c->g32, c->stream));
     HIPCHK(c, hfe::vec_to_f32(n, c->y0, c->y32, c->stream));
   }
-  hfe::CgState init;
-  std::memset(&init, 0, sizeof(init));
-  init.rr = init.rr0 = init.rr_new = c->rr0;
-  init.R = R;
-  init.eta_cg = eta_cg;
-  init.restart_c = restart_c;
-  init.rr_ref = c->rr0;
-  init.j_ref = 0;
-  init.stall = stall;
-  // mean-stress control: z_e = 0, g_e = g0_e, y_e = g0_e / N_qp, d_e = -y_e
-  init.ne = c->ne;
-  init.nqp = (double)c->g.N * c->g.nq;
-  for (int m = 0; m < c->ne; ++m) {
-    init.comp[m] = c->comp[m];
-    init.ge[m] = c->g0e[m];
-    init.ye[m] = c->g0e[m] / init.nqp;
-    init.de[m] = -init.ye[m];
-  }
-  hfe::tail_tensor(&init, init.de, init.dU);
-  init.jmax = j_max;
-  init.flag = hfe::CG_RUN;
-  init.trace_cap = kTraceCap;
-  *c->hcg = init;
+  *c->hcg = cg_initial_state(c, R, eta_cg, j_max, restart_c, stall);
   HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
   // d0 = -y0 (beta = 0) with <r0, d0> and z.g = 0; in FP64 one kernel also
   // sets z = 0, g = g0 and y = y0
@@ -1931,6 +1938,30 @@ hfe_status hfe_set_tuning(hfe_ctx* c, const hfe_tuning* in) {
   return HFE_OK;
 }
 
+// A CG solve started only to time its iterations, at the current state: a
+// radius and tolerance that never stop it (a negative curvature still can),
+// the reset constant of the defaults. The next solve starts its own.
+hfe_status cg_probe_start(hfe_ctx* c) {
+  *c->hcg = cg_initial_state(c, 1e150, 0.0, 1 << 30, 0.2, 0);
+  HIPCHK(c, hipMemcpyAsync(c->cg, c->hcg, sizeof(hfe::CgState), hipMemcpyHostToDevice, c->stream));
+  hfe::Reducer r;
+  r.partials = c->partials2;
+  HIPCHK(c, hfe::cg_start(ndof(c), c->g0, c->y0, c->z, c->gv, c->y, c->d, r, c->stream, &c->nb_dir));
+  return HFE_OK;
+}
+
+// Whether the probe solve was still running (its timed iterations all did
+// their work).
+bool cg_probe_running(hfe_ctx* c) {
+  int done = 1;
+  if (hipMemcpyAsync(&c->hcg->done, &c->cg->done, sizeof(int), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess)
+    return false;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return false;
+  done = c->hcg->done;
+  return done == 0;
+}
+
 hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
   if (!c) return HFE_EINVAL;
   if (c->profiling) return fail(c, HFE_ESTATE, "switch profiling off before tuning");
@@ -1971,10 +2002,17 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
   const int pencils[][2] = {{dc, dt}, {4, 64}, {4, 128}, {8, 64}, {8, 128}, {8, 256}, {16, 128},
                             {16, 256}, {32, 256}};
   const bool q1 = c->g.dim == 3;
+  // The FP64 shapes of a 3D cell with a state are timed on the CG iteration
+  // itself (the Hessian and the fused passes, whose best shapes differ from
+  // those of the plain Green's operator), each from a fresh probe solve. If
+  // a probe stops (negative curvature) the FP64 shapes are timed again on
+  // the Green's operator.
+  bool iter_timing = q1 && c->have_state && c->rr0 > 0.0;
   for (int prec = 0; prec < (q1 ? 2 : 1); ++prec) {
     const size_t rb = prec ? 4 : 8;
     double best = INFINITY;
     int bp = 0, bc = 0, bt = 0;
+    bool stopped = false;
     for (int pt : planes)
       for (const auto& pc : pencils) {
         if (!hfe::fft_launch_valid(c->g, pt, pc[0], pc[1], rb)) continue;
@@ -1983,7 +2021,13 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
           c->tabs.plane_threads = pt;
           c->tabs.pencil_cols = pc[0];
           c->tabs.pencil_threads = pc[1];
-          t = time_us([&]() { return green(c, c->g0, c->w); });
+          if (iter_timing) {
+            t = cg_probe_start(c) == HFE_OK ? time_us([&]() { return cg_iteration(c); })
+                                            : INFINITY;
+            if (!cg_probe_running(c)) stopped = true;
+          } else {
+            t = time_us([&]() { return green(c, c->g0, c->w); });
+          }
         } else {
           c->tabs32.plane_threads = pt;
           c->tabs32.pencil_cols = pc[0];
@@ -1997,6 +2041,11 @@ hfe_status hfe_autotune(hfe_ctx* c, hfe_tuning* out) {
           bt = pc[1];
         }
       }
+    if (prec == 0 && iter_timing && stopped) {
+      iter_timing = false;
+      --prec;            // the FP64 shapes again, on the Green's operator
+      continue;
+    }
     if (!(best < INFINITY)) {
       hipEventDestroy(e0);
       hipEventDestroy(e1);
