@@ -359,7 +359,8 @@ typedef struct {
                            CX x CY nodes marching over BZ node layers (nx a multiple
                            of CX, ny of CY): 5 = 16x16x16, 6 = 16x16x8, 7 = 16x8x16,
                            8 = 16x8x8, 9 = 8x8x8, 10 = 8x8x16, 11 = 16x8x32,
-                           12 = 16x16x32. Every shape gives the same K d bits. */
+                           12 = 16x16x32. Every shape gives the same K d bits,
+                           and the same sums (formed per canonical tile). */
   int plane_threads32, pencil_cols32, pencil_threads32, brick_shape32;
 } hfe_tuning;
 
@@ -370,12 +371,16 @@ hfe_status hfe_get_tuning(const hfe_ctx* ctx, hfe_tuning* out);
  * pencil block pencil_cols * nz values at 15 per thread in 64 KiB of LDS, a
  * Hessian column must divide nx and ny. */
 hfe_status hfe_set_tuning(hfe_ctx* ctx, const hfe_tuning* in);
-/* Autotuner: times every valid plane / pencil shape on this grid's Green's
- * operator (FP64 and FP32) and, once a load step has been applied, the brick
- * shapes on the Hessian at the current state (all five, FP64 and FP32);
- * keeps the fastest and
- * returns them in `out` (may be NULL). Results do not depend on the shapes
- * (the arithmetic per value is the same), only the time does. */
+/* Autotuner: times every valid plane / pencil shape and, once a load step
+ * has been applied, every valid Hessian shape at the current state (FP64 and
+ * FP32); keeps the fastest and returns them in `out` (may be NULL). With a 3D
+ * state, the FP64 plane / pencil shapes are timed on CG iterations of a probe
+ * solve started at that state (the fused passes the solver runs), otherwise
+ * (2D, no state, or a probe that stops on negative curvature) on the Green's
+ * operator; the FP32 ones on the FP32 Green's operator. The probe overwrites
+ * the CG work vectors, which every solve initialises itself. Results do not
+ * depend on the shapes (every value and every sum is formed in the same
+ * order), only the time does. */
 hfe_status hfe_autotune(hfe_ctx* ctx, hfe_tuning* out);
 
 /* The two halves of the matvec, for operator tests: out = K d (device
