@@ -146,6 +146,36 @@ def test_every_launch_shape_gives_the_same_solve(shape, precision, control):
             np.testing.assert_array_equal(np.asarray(a), np.asarray(b), err_msg=str(sh))
 
 
+def test_autotune_between_load_steps_changes_no_result():
+    """The autotuner times CG iterations of a probe solve at the current
+    state (its FP64 FFT shapes): tuning between two load steps must leave
+    every later result as it is, bit for bit, against the same steps solved
+    without tuning."""
+    require_gpu()
+    announce("autotune between load steps", (16, 16, 16))
+    from paper_2207_10657_amd import Solver
+    w = workload("c1_3d16", steps=4)
+    runs = []
+    for tune in (False, True):
+        s = Solver(w.shape, "q1")
+        s.setup(w.phase, w.materials)
+        out = []
+        for n, dE in enumerate(w.load_path):
+            if tune and n == 2:
+                s.autotune()
+            s.apply_load_step(dE)
+            s.solve_increment()
+            log = s.newton_log()
+            st = s.get_state()
+            out.append((np.array([[float(r[k]) for k in sorted(r)] for r in log]), s.cg_trace(),
+                        st["u"], st["kappa_hist"], s.homogenized_stress()))
+        s.close()
+        runs.append(out)
+    for n, (a, b) in enumerate(zip(*runs)):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(np.asarray(x), np.asarray(y), err_msg="step %d" % n)
+
+
 def _load_cases(mag):
     cases = []
     for (i, j) in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
