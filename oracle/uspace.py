@@ -22,13 +22,16 @@ this module is validated against (tests/test_oracle_uspace.py).
 
 The grid is split into slabs of element layers along its first axis (z in
 3D, y in 2D), evaluated on a thread pool (numpy's array loops release the
-GIL); the nodal sums of the slabs are added in slab order, so the result
-does not depend on the number of threads. FFTs run on scipy.fft with
+GIL), with BLAS held to one thread meanwhile (its own thread pool is not safe
+under concurrent callers); the nodal sums of the slabs are added in slab
+order, so the result does not depend on the number of threads. FFTs run on scipy.fft with
 `workers` threads. This is the oracle the CPU baseline times on every host
 core.
 """
 import os
 from concurrent.futures import ThreadPoolExecutor
+
+from threadpoolctl import threadpool_limits
 
 import numpy as np
 import scipy.fft as sfft
@@ -76,7 +79,9 @@ class UOperator:
         Em = np.asarray(E, dtype=np.float64)[:self.dim, :self.dim]
         self._mf = []
         self._st = []
-        with ThreadPoolExecutor(self.workers) as pool:
+        # one BLAS thread per slab: a threaded BLAS called from several
+        # threads at once can return wrong products
+        with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(self.workers) as pool:
             def evaluate(sl):
                 z0, z1 = sl
                 mf = material.MaterialField(self.phase[z0:z1], materials, self.nq)
@@ -123,7 +128,7 @@ class UOperator:
             tau = material.apply_tangent(self._mf[k], self._st[k], self._gradient(d, z0, z1))
             return self._divergence(tau)
 
-        with ThreadPoolExecutor(self.workers) as pool:
+        with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(self.workers) as pool:
             parts = list(pool.map(slab, range(len(self.slabs))))
         f = np.zeros_like(d)
         n0 = self.grid[0]
