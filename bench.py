@@ -789,7 +789,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-matvecs", type=int, default=3)
+    ap.add_argument("--cpu-matvecs", type=int, default=100,
+                    help="oracle applications timed for cpu_baseline (about 10 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run of the same steps")
